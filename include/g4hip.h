@@ -1,0 +1,188 @@
+/*
+ * g4hip.h -- C ABI of libg4hip.so, the MI355X (gfx950) gravity hot path of
+ * Springel, Pakmor, Zier & Reinecke, "Simulating cosmic structure formation
+ * with the GADGET-4 code" (arXiv:2010.03567).
+ *
+ * Conventions for every entry point:
+ *  - Array arguments are DEVICE pointers owned by the caller unless a comment
+ *    says "host".  The library never allocates device memory: the caller
+ *    queries a workspace size and passes the buffer in.
+ *  - Work is enqueued on the stream bound to the context and is asynchronous
+ *    unless the call returns host-side results (stats, counts, status of a
+ *    device-side check), in which case it synchronises that stream.
+ *  - Return value: G4_OK (0) or a negative g4_status; g4_last_error() gives a
+ *    message.  No C++ exception crosses the ABI.
+ *  - Particles are given in the caller's order; outputs are written in the
+ *    caller's order.  Positions are the integer fixed-point coordinates of the
+ *    paper's Sec. "Integer coordinates" (see g4_quantize).
+ *  - One context is bound to one stream and one device and is not re-entrant.
+ */
+#ifndef G4HIP_H
+#define G4HIP_H
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct g4_ctx g4_ctx;
+typedef struct g4_tree g4_tree;
+
+typedef enum {
+    G4_OK = 0,
+    G4_EINVAL = -1,  /* invalid argument */
+    G4_ENOMEM = -2,  /* workspace too small */
+    G4_EHIP = -3,    /* HIP runtime error */
+    G4_ESTATE = -4,  /* call out of order (e.g. moments not computed) */
+    G4_EROOT = -5    /* a particle lies outside an isolated root cube */
+} g4_status;
+
+/* Root geometry and tree shape (paper Sec. "Geometry of the tree").
+ * periodic = 1: cube [origin, origin+box)^3 with periodic wrap; integer
+ *               coordinates span the full 2^32 range (one step = box/2^32).
+ * periodic = 0: isolated; the root cube [origin, origin+box)^3 maps onto
+ *               [2^30, 3*2^30) so coordinate differences never wrap
+ *               (Sec. "Non-periodic potentials"); one step = box/2^31.
+ * leaf_max  = B: a node is split only while it holds more than B particles.
+ * max_depth: deepest level (<= 21); leaves there may hold more than B. */
+typedef struct {
+    int periodic;
+    double box;
+    double origin[3];
+    int leaf_max;
+    int max_depth;
+} g4_tree_params;
+
+/* Particle set in the caller's order: integer coordinates and masses. */
+typedef struct {
+    int64_t n;
+    const uint32_t *x, *y, *z;
+    const float *mass;
+} g4_particles;
+
+/* One-sided walk (Sec. "One-sided multipole expansion", "Tree walk and
+ * opening criterion", "TreePM approach").
+ * kernel:    0 softened Newtonian, 1 TreePM short-range (eq. eqnpo4 force).
+ * criterion: 0 geometric l/r < theta; 1 relative M l^p < alpha |a| r^(p+2)
+ *            (eq. eqnrelcriterion) with |a| from a_seed, or, when a_seed is
+ *            NULL, from a geometric pre-walk with theta_seed.
+ * order:     p = 2 (monopole force) or 3 (monopole + quadrupole force;
+ *            octupole enters the potential).
+ * exclusion: 1 = never accept a node whose cube of side 2l centred on the
+ *            node holds the target.  Nodes closer than h = 2.8 eps0 are
+ *            always opened.  TreePM drops nodes whose nearest edge is farther
+ *            than r_cut.  alpha_split = 1/(2 r_s).
+ * group_size: particles per 64-lane wavefront group (1..64).
+ * a_seed:    device, caller order, |a| per particle (nullable).
+ * seed_from_tree: with a_seed NULL, 1 = use the |a| that the previous
+ *            geometric (criterion 0) call left in this tree instead of
+ *            running a pre-walk (lets a caller time the two walks apart). */
+typedef struct {
+    int kernel;
+    int criterion;
+    int order;
+    int exclusion;
+    double G, eps0, r_s, r_cut, theta, alpha, theta_seed;
+    const float *a_seed;
+    int group_size;
+    int seed_from_tree;
+} g4_walk_params;
+
+/* FMM (Sec. "Fast multipole method", "The FMM-PM approach"), p = 3.
+ * Node pairs interact when (l_A + l_B)/r < theta and the cubes do not touch
+ * and r >= h; kernel 1 drops pairs whose nearest sides are farther apart than
+ * r_cut. */
+typedef struct {
+    int kernel;
+    double G, eps0, r_s, r_cut, theta;
+} g4_fmm_params;
+
+/* Counters filled by the force calls (host struct). */
+typedef struct {
+    uint64_t n_p2p;      /* particle-particle interactions */
+    uint64_t n_p2m;      /* particle-node (one-sided) interactions */
+    uint64_t n_visit;    /* node visits by active lanes (criterion evaluations) */
+    uint64_t n_seed_p2p, n_seed_p2m, n_seed_visit;  /* same, geometric pre-walk (if run) */
+    uint64_t n_pp, n_pn, n_nn;   /* FMM interaction counts */
+    uint64_t n_nodes;    /* nodes in the tree */
+    uint32_t flags;      /* bit 0: a leaf at max_depth holds more than leaf_max particles */
+} g4_stats;
+
+/* ---------------------------------------------------------------- context */
+/* Bind a context to device `device` and HIP stream `hip_stream` (a
+ * hipStream_t, or NULL for the default stream).  Host allocation only. */
+int g4_ctx_create(int device, void *hip_stream, g4_ctx **out);
+int g4_ctx_destroy(g4_ctx *ctx);
+/* Message of the last error on this context (static storage of the ctx). */
+const char *g4_last_error(const g4_ctx *ctx);
+
+/* ---------------------------------------------------------- integer mapping */
+/* pos: device, n x 3 float64 row-major (physical).  Writes x, y, z (device,
+ * n uint32 each) per the mapping of g4_tree_params (periodic: floor(x/L 2^32)
+ * mod 2^32; isolated: 2^30 + floor((x-origin)/box 2^31)).  Synchronises and
+ * returns G4_EROOT if an isolated particle lies outside the root cube
+ * (coordinates are then clamped to the root).  `flag` is a device int32
+ * scratch word supplied by the caller. */
+int g4_quantize(g4_ctx *ctx, const double *pos, int64_t n, const g4_tree_params *tp,
+                uint32_t *x, uint32_t *y, uint32_t *z, int32_t *flag);
+
+/* ---------------------------------------------------------------- tree */
+/* Workspace bytes for a tree over n particles (node storage sized for the
+ * worst case N + max_depth * N/(B+1) nodes, key sort buffers, moments). */
+int g4_workspace_bytes(const g4_tree_params *tp, int64_t n, size_t *bytes);
+
+/* Build the octree over Morton-sorted particles (Sec. "Geometry of the
+ * tree"): quantised coordinates -> 63-bit Morton keys -> stable radix sort ->
+ * level-synchronous node splitting.  ws: device buffer of ws_bytes (kept by
+ * the tree until g4_tree_free; the particle arrays are copied into it).
+ * *out receives a host handle. */
+int g4_build_tree(g4_ctx *ctx, const g4_particles *p, const g4_tree_params *tp, void *ws, size_t ws_bytes,
+                  g4_tree **out);
+
+/* Multipole moments up to octupole about each node's centre of mass
+ * (Sec. "One-sided multipole expansion"; upward pass as in the first FMM
+ * phase): leaves from their particles, parents from their children by the
+ * parallel-axis shift.  FP64 accumulation at levels <= 8, FP32 below. */
+int g4_compute_multipoles(g4_ctx *ctx, g4_tree *tree, int order);
+
+/* Node count and level ranges of a built tree (host outputs; synchronises).
+ * level_start: host array of max_depth + 2 int64 (may be NULL). */
+int g4_tree_info(g4_ctx *ctx, const g4_tree *tree, int64_t *nnodes, int64_t *level_start);
+
+/* Copy node data to caller device buffers (any pointer may be NULL):
+ * level (int32), cell (3 x uint32 per node: integer cube index at its level),
+ * count (int64 particles), leaf (int32), mass (f64), com (3 x f64 physical,
+ * relative to the root's lower corner), q2 (6 x f64: xx xy xz yy yz zz), q3 (10 x f64:
+ * xxx xxy xxz xyy xyz xzz yyy yyz yzz zzz).  Moments need g4_compute_multipoles. */
+int g4_tree_export(g4_ctx *ctx, const g4_tree *tree, int32_t *level, uint32_t *cell, int64_t *count,
+                   int32_t *leaf, double *mass, double *com, double *q2, double *q3);
+
+int g4_tree_free(g4_ctx *ctx, g4_tree *tree);
+
+/* --------------------------------------------------------------- forces */
+/* One-sided tree walk (kernel per params).  ax, ay, az: device, n float64,
+ * caller order.  pot: device n float64 or NULL.  counts: device n x 2 uint32
+ * (particle-particle, particle-node per particle) or NULL.  a_out: device n
+ * float32 |a| (caller order) or NULL.  stats: host or NULL (synchronises).
+ * A geometric call (criterion 0) also keeps |a| inside the tree for a later
+ * relative call with seed_from_tree = 1. */
+int g4_tree_force(g4_ctx *ctx, g4_tree *tree, const g4_walk_params *wp, double *ax, double *ay, double *az,
+                  double *pot, uint32_t *counts, float *a_out, g4_stats *stats);
+
+/* The TreePM short-range force (kernel forced to 1). */
+int g4_treepm_shortrange(g4_ctx *ctx, g4_tree *tree, const g4_walk_params *wp, double *ax, double *ay,
+                         double *az, double *pot, uint32_t *counts, float *a_out, g4_stats *stats);
+
+/* Direct summation on the device (the exact reference of Sec. "Softened
+ * potential in periodic systems"): forces on `ntargets` particles (device
+ * int64 indices into the caller order, or NULL for all) from all n particles,
+ * FP64 arithmetic.  kernel/eps0/r_s from wp; r_cut used only if truncate. */
+int g4_direct_force(g4_ctx *ctx, const g4_particles *p, const g4_tree_params *tp, const g4_walk_params *wp,
+                    int truncate, const int64_t *targets, int64_t ntargets, double *ax, double *ay, double *az,
+                    double *pot);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

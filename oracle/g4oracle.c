@@ -527,7 +527,8 @@ static void walk_node(const walk_job *J, int64_t i, double aseed, int64_t q, dou
         if (P->criterion == 0)
             accept = l < P->theta * r;
         else
-            accept = nd->mass * l * l * l < P->alpha * aseed * r2 * r2 * r;
+            accept = P->order >= 3 ? nd->mass * l * l * l < P->alpha * aseed * r2 * r2 * r
+                                   : nd->mass * l * l < P->alpha * aseed * r2 * r2;
     }
     if (accept) {
         p2m_one(P, nd, rv, a, phi);

@@ -1,0 +1,234 @@
+// api.hip -- the extern "C" entry points of libg4hip.so declared in
+// include/g4hip.h: argument checks, workspace carving, and the order of the
+// kernel launches on the context's stream.
+#include <new>
+
+#include "g4_internal.h"
+
+static int check_tp(g4_ctx *ctx, const g4_tree_params *tp)
+{
+    if (!tp) return g4_set_err(ctx, G4_EINVAL, "null tree params");
+    if (!(tp->box > 0)) return g4_set_err(ctx, G4_EINVAL, "box must be positive");
+    if (tp->leaf_max < 1) return g4_set_err(ctx, G4_EINVAL, "leaf_max must be >= 1");
+    if (tp->max_depth < 1 || tp->max_depth > G4_MAXLEV)
+        return g4_set_err(ctx, G4_EINVAL, "max_depth must be in [1, 21]");
+    return G4_OK;
+}
+
+extern "C" {
+
+int g4_ctx_create(int device, void *hip_stream, g4_ctx **out)
+{
+    if (!out) return G4_EINVAL;
+    g4_ctx *c = new (std::nothrow) g4_ctx;
+    if (!c) return G4_ENOMEM;
+    c->device = device;
+    c->stream = (hipStream_t)hip_stream;
+    c->err[0] = 0;
+    *out = c;
+    return G4_OK;
+}
+
+int g4_ctx_destroy(g4_ctx *ctx)
+{
+    delete ctx;
+    return G4_OK;
+}
+
+const char *g4_last_error(const g4_ctx *ctx) { return ctx ? ctx->err : "null context"; }
+
+int g4_quantize(g4_ctx *ctx, const double *pos, int64_t n, const g4_tree_params *tp, uint32_t *x, uint32_t *y,
+                uint32_t *z, int32_t *flag)
+{
+    if (!ctx) return G4_EINVAL;
+    int st = check_tp(ctx, tp);
+    if (st) return st;
+    if (n < 0 || (n > 0 && (!pos || !x || !y || !z)) || !flag) return g4_set_err(ctx, G4_EINVAL, "bad quantize args");
+    return g4_launch_quantize(ctx, pos, n, tp, x, y, z, flag);
+}
+
+int g4_workspace_bytes(const g4_tree_params *tp, int64_t n, size_t *bytes)
+{
+    if (!tp || !bytes || n < 1 || n > 0xFFFFFFF0ll) return G4_EINVAL;
+    if (check_tp(nullptr, tp)) return G4_EINVAL;
+    WsLayout L;
+    int st = g4_layout(tp, n, &L);
+    if (st) return st;
+    *bytes = L.total;
+    return G4_OK;
+}
+
+int g4_build_tree(g4_ctx *ctx, const g4_particles *p, const g4_tree_params *tp, void *ws, size_t ws_bytes,
+                  g4_tree **out)
+{
+    if (!ctx) return G4_EINVAL;
+    int st = check_tp(ctx, tp);
+    if (st) return st;
+    if (!p || !out || !ws) return g4_set_err(ctx, G4_EINVAL, "null argument");
+    if (p->n < 1 || p->n > 0xFFFFFFF0ll) return g4_set_err(ctx, G4_EINVAL, "particle count out of range");
+    if (!p->x || !p->y || !p->z || !p->mass) return g4_set_err(ctx, G4_EINVAL, "null particle array");
+    if (((uintptr_t)ws & 255) != 0) return g4_set_err(ctx, G4_EINVAL, "workspace must be 256-byte aligned");
+    WsLayout L;
+    st = g4_layout(tp, p->n, &L);
+    if (st) return g4_set_err(ctx, st, "workspace layout failed");
+    if (ws_bytes < L.total) return g4_set_err(ctx, G4_ENOMEM, "workspace too small");
+    g4_tree *t = new (std::nothrow) g4_tree;
+    if (!t) return g4_set_err(ctx, G4_ENOMEM, "host allocation failed");
+    char *b = (char *)ws;
+    t->n = p->n;
+    t->tp = *tp;
+    t->S = tp->periodic ? 32 : 31;
+    t->corner = tp->periodic ? 0u : (1u << 30);
+    t->unit = tp->box / (tp->periodic ? 4294967296.0 : 2147483648.0);
+    t->cap = L.cap;
+    t->moments_order = 0;
+    t->seed_valid = 0;
+    t->ctr = (DevCounters *)(b + L.ctr);
+    t->keys0 = (uint64_t *)(b + L.keys0);
+    t->keys1 = (uint64_t *)(b + L.keys1);
+    t->perm0 = (uint32_t *)(b + L.perm0);
+    t->perm1 = (uint32_t *)(b + L.perm1);
+    t->parts = (uint4 *)(b + L.parts);
+    t->bfirst = (uint32_t *)(b + L.bfirst);
+    t->bcount = (uint32_t *)(b + L.bcount);
+    t->wn = (WNode *)(b + L.wn);
+    t->q3 = (float *)(b + L.q3);
+    t->mom = (double *)(b + L.mom);
+    t->aseed = (float *)(b + L.aseed);
+    t->sort_tmp = b + L.sort_tmp;
+    t->sort_tmp_bytes = L.sort_bytes;
+    st = g4_launch_build(ctx, t, p);
+    if (st) {
+        delete t;
+        return st;
+    }
+    *out = t;
+    return G4_OK;
+}
+
+int g4_compute_multipoles(g4_ctx *ctx, g4_tree *tree, int order)
+{
+    if (!ctx || !tree) return G4_EINVAL;
+    if (order != 2 && order != 3) return g4_set_err(ctx, G4_EINVAL, "order must be 2 or 3");
+    int st = g4_launch_moments(ctx, tree);
+    if (st) return st;
+    tree->moments_order = order;
+    tree->seed_valid = 0;
+    return G4_OK;
+}
+
+int g4_tree_info(g4_ctx *ctx, const g4_tree *tree, int64_t *nnodes, int64_t *level_start)
+{
+    if (!ctx || !tree) return G4_EINVAL;
+    DevCounters h;
+    G4_HIP(ctx, hipMemcpyAsync(&h, tree->ctr, sizeof(h), hipMemcpyDeviceToHost, ctx->stream));
+    G4_HIP(ctx, hipStreamSynchronize(ctx->stream));
+    if (nnodes) *nnodes = h.node_count;
+    if (level_start) {
+        const int maxd = tree->tp.max_depth;
+        for (int l = 0; l <= maxd; l++) level_start[l] = h.lvl_start[l];
+        level_start[maxd + 1] = h.lvl_start[maxd] + h.lvl_count[maxd];
+    }
+    if (h.flags & 2u) return g4_set_err(ctx, G4_ENOMEM, "node capacity exceeded");
+    return G4_OK;
+}
+
+int g4_tree_export(g4_ctx *ctx, const g4_tree *tree, int32_t *level, uint32_t *cell, int64_t *count, int32_t *leaf,
+                   double *mass, double *com, double *q2, double *q3)
+{
+    if (!ctx || !tree) return G4_EINVAL;
+    if ((mass || com || q2 || q3) && !tree->moments_order)
+        return g4_set_err(ctx, G4_ESTATE, "moments not computed");
+    return g4_launch_export(ctx, tree, level, cell, count, leaf, mass, com, q2, q3);
+}
+
+int g4_tree_free(g4_ctx *ctx, g4_tree *tree)
+{
+    (void)ctx;
+    delete tree;
+    return G4_OK;
+}
+
+static int tree_force_impl(g4_ctx *ctx, g4_tree *tree, const g4_walk_params *wp, int kernel, double *ax,
+                           double *ay, double *az, double *pot, uint32_t *counts, float *a_out, g4_stats *stats)
+{
+    if (!ctx || !tree || !wp) return G4_EINVAL;
+    if (!ax || !ay || !az) return g4_set_err(ctx, G4_EINVAL, "null output");
+    if (!tree->moments_order) return g4_set_err(ctx, G4_ESTATE, "moments not computed");
+    if (wp->order != 2 && wp->order != 3) return g4_set_err(ctx, G4_EINVAL, "order must be 2 or 3");
+    if (wp->order > tree->moments_order) return g4_set_err(ctx, G4_ESTATE, "moments computed at a lower order");
+    if (wp->criterion != 0 && wp->criterion != 1) return g4_set_err(ctx, G4_EINVAL, "criterion must be 0 or 1");
+    if (kernel == 1 && !(wp->r_s > 0)) return g4_set_err(ctx, G4_EINVAL, "r_s must be positive");
+    if (kernel == 1 && !(wp->r_cut > 0)) return g4_set_err(ctx, G4_EINVAL, "r_cut must be positive");
+    if (wp->eps0 < 0) return g4_set_err(ctx, G4_EINVAL, "eps0 must be >= 0");
+    if (wp->group_size < 0 || wp->group_size > 64) return g4_set_err(ctx, G4_EINVAL, "group_size must be 0..64");
+    if (!tree->tp.periodic && kernel == 1) return g4_set_err(ctx, G4_EINVAL, "short-range kernel needs a periodic box");
+    if (stats) G4_HIP(ctx, hipMemsetAsync(tree->ctr->stat, 0, sizeof(tree->ctr->stat), ctx->stream));
+    int st;
+    if (wp->criterion == 1) {
+        if (wp->a_seed) {
+            st = g4_launch_gather_seed(ctx, tree, wp->a_seed);
+        } else if (wp->seed_from_tree) {
+            if (!tree->seed_valid) return g4_set_err(ctx, G4_ESTATE, "no geometric walk has left |a| in this tree");
+            st = G4_OK;
+        } else {
+            if (!(wp->theta_seed > 0)) return g4_set_err(ctx, G4_EINVAL, "theta_seed must be positive");
+            // geometric pre-walk (first-force footnote of eq. eqnrelcriterion): |a| estimate
+            // written into the tree's sorted seed buffer; its forces are scratch and go to ax..az
+            st = g4_launch_walk(ctx, tree, wp, kernel, 0, ax, ay, az, nullptr, nullptr, nullptr, tree->aseed, 3);
+        }
+        if (st) return st;
+    }
+    st = g4_launch_walk(ctx, tree, wp, kernel, wp->criterion, ax, ay, az, pot, counts, a_out,
+                        wp->criterion == 0 ? tree->aseed : nullptr, 0);
+    if (st) return st;
+    if (wp->criterion == 0) tree->seed_valid = 1;
+    if (stats) {
+        DevCounters h;
+        G4_HIP(ctx, hipMemcpyAsync(&h, tree->ctr, sizeof(h), hipMemcpyDeviceToHost, ctx->stream));
+        G4_HIP(ctx, hipStreamSynchronize(ctx->stream));
+        stats->n_p2p = h.stat[0];
+        stats->n_p2m = h.stat[1];
+        stats->n_visit = h.stat[2];
+        stats->n_seed_p2p = h.stat[3];
+        stats->n_seed_p2m = h.stat[4];
+        stats->n_seed_visit = h.stat[5];
+        stats->n_pp = stats->n_pn = stats->n_nn = 0;
+        stats->n_nodes = h.node_count;
+        stats->flags = h.flags;
+    }
+    return G4_OK;
+}
+
+int g4_tree_force(g4_ctx *ctx, g4_tree *tree, const g4_walk_params *wp, double *ax, double *ay, double *az,
+                  double *pot, uint32_t *counts, float *a_out, g4_stats *stats)
+{
+    if (!wp) return G4_EINVAL;
+    if (wp->kernel != 0 && wp->kernel != 1) return g4_set_err(ctx, G4_EINVAL, "kernel must be 0 or 1");
+    return tree_force_impl(ctx, tree, wp, wp->kernel, ax, ay, az, pot, counts, a_out, stats);
+}
+
+int g4_treepm_shortrange(g4_ctx *ctx, g4_tree *tree, const g4_walk_params *wp, double *ax, double *ay, double *az,
+                         double *pot, uint32_t *counts, float *a_out, g4_stats *stats)
+{
+    if (!wp) return G4_EINVAL;
+    g4_walk_params w = *wp;
+    w.kernel = 1;
+    return tree_force_impl(ctx, tree, &w, 1, ax, ay, az, pot, counts, a_out, stats);
+}
+
+int g4_direct_force(g4_ctx *ctx, const g4_particles *p, const g4_tree_params *tp, const g4_walk_params *wp,
+                    int truncate, const int64_t *targets, int64_t ntargets, double *ax, double *ay, double *az,
+                    double *pot)
+{
+    if (!ctx) return G4_EINVAL;
+    int st = check_tp(ctx, tp);
+    if (st) return st;
+    if (!p || !wp || !ax || !ay || !az) return g4_set_err(ctx, G4_EINVAL, "null argument");
+    if (p->n < 1 || !p->x || !p->y || !p->z || !p->mass) return g4_set_err(ctx, G4_EINVAL, "bad particles");
+    if (targets && ntargets < 0) return g4_set_err(ctx, G4_EINVAL, "negative target count");
+    if (wp->kernel == 1 && !(wp->r_s > 0)) return g4_set_err(ctx, G4_EINVAL, "r_s must be positive");
+    return g4_launch_direct(ctx, p, tp, wp, truncate, targets, ntargets, ax, ay, az, pot);
+}
+
+}  // extern "C"

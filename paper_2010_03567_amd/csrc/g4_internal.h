@@ -1,0 +1,108 @@
+// g4_internal.h -- device data layout and launch helpers shared by the HIP
+// sources of libg4hip.so (not part of the public ABI).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/g4hip.h"
+
+#define G4_MAXLEV 21  // 63-bit Morton keys: 21 bits per axis
+
+struct g4_ctx {
+    int device;
+    hipStream_t stream;
+    char err[512];
+};
+
+// Walk record of one node, 64 bytes, read by a whole wavefront through the
+// scalar cache (the node index is wave-uniform during traversal).
+struct __attribute__((aligned(16))) WNode {
+    uint32_t cx, cy, cz;   // centre of mass on the integer grid (nearest point)
+    float mass;
+    float q[6];            // Q2 about the centre of mass: xx xy xz yy yz zz (physical units)
+    uint32_t gx, gy, gz;   // integer geometric centre of the node's cube
+    uint32_t next;         // internal: first child node; leaf: first particle (sorted order)
+    uint32_t num;          // internal: number of children; leaf: number of particles
+    uint32_t meta;         // bits 0-7 level, bit 8 leaf
+};
+static_assert(sizeof(WNode) == 64, "WNode must be 64 bytes");
+
+#define WN_LEAF (1u << 8)
+
+// Full-precision moments of one node (double storage for the upward pass):
+// [0] mass, [1..3] centre of mass minus geometric centre (physical),
+// [4..9] Q2 packed, [10..19] Q3 packed (xxx xxy xxz xyy xyz xzz yyy yyz yzz zzz).
+#define MOM_STRIDE 20
+
+// Device counters at the head of the tree workspace.
+struct DevCounters {
+    uint32_t node_count;      // total nodes (written by the last split pass)
+    uint32_t pad0;
+    uint32_t flags;           // bit 0: depth-capped leaf above leaf_max; bit 1: node overflow
+    uint32_t pad;
+    uint32_t lvl_start[G4_MAXLEV + 4];  // first node of each level
+    uint32_t lvl_count[G4_MAXLEV + 4];  // nodes of each level (children allocated by atomics)
+    unsigned long long stat[16];  // [0..2] walk p2p/p2m/visits, [3..5] seed walk, [6..8] FMM pp/pn/nn
+};
+
+struct g4_tree {
+    int64_t n;
+    g4_tree_params tp;
+    int S;              // bits spanned by the root: 32 periodic, 31 isolated
+    uint32_t corner;    // integer lower corner of the root
+    double unit;        // physical length of one integer step
+    int64_t cap;        // node capacity
+    int moments_order;  // 0 until g4_compute_multipoles
+    int seed_valid;     // aseed holds |a| of a geometric walk over this tree
+    // workspace views
+    DevCounters *ctr;
+    uint64_t *keys0, *keys1;
+    uint32_t *perm0, *perm1;  // perm1[i] = caller index of sorted particle i
+    uint4 *parts;             // sorted particles: x, y, z, mass bits
+    uint32_t *bfirst, *bcount;
+    WNode *wn;
+    float *q3;                // 10 floats per node (potential only)
+    double *mom;              // MOM_STRIDE doubles per node
+    float *aseed;             // n floats, sorted order
+    void *sort_tmp;
+    size_t sort_tmp_bytes;
+};
+
+// Layout of a tree workspace (byte offsets).
+struct WsLayout {
+    size_t ctr, keys0, keys1, perm0, perm1, parts, bfirst, bcount, wn, q3, mom, aseed, sort_tmp, sort_bytes, total;
+    int64_t cap;
+};
+
+int g4_layout(const g4_tree_params *tp, int64_t n, WsLayout *L);
+
+static inline int g4_set_err(g4_ctx *ctx, int code, const char *msg)
+{
+    if (ctx) {
+        int i = 0;
+        for (; msg[i] && i < 511; i++) ctx->err[i] = msg[i];
+        ctx->err[i] = 0;
+    }
+    return code;
+}
+
+#define G4_HIP(ctx, call)                                                       \
+    do {                                                                        \
+        hipError_t e_ = (call);                                                 \
+        if (e_ != hipSuccess) return g4_set_err((ctx), G4_EHIP, hipGetErrorString(e_)); \
+    } while (0)
+
+// host launchers implemented in the .hip files
+int g4_launch_build(g4_ctx *ctx, g4_tree *t, const g4_particles *p);
+int g4_launch_moments(g4_ctx *ctx, g4_tree *t);
+int g4_launch_walk(g4_ctx *ctx, g4_tree *t, const g4_walk_params *wp, int kernel, int criterion,
+                   double *ax, double *ay, double *az, double *pot, uint32_t *counts, float *aout_caller,
+                   float *aout_sorted, int stat_slot);
+int g4_launch_export(g4_ctx *ctx, const g4_tree *t, int32_t *level, uint32_t *cell, int64_t *count,
+                     int32_t *leaf, double *mass, double *com, double *q2, double *q3);
+int g4_launch_direct(g4_ctx *ctx, const g4_particles *p, const g4_tree_params *tp, const g4_walk_params *wp,
+                     int truncate, const int64_t *targets, int64_t ntargets, double *ax, double *ay, double *az,
+                     double *pot);
+int g4_launch_quantize(g4_ctx *ctx, const double *pos, int64_t n, const g4_tree_params *tp, uint32_t *x,
+                       uint32_t *y, uint32_t *z, int32_t *flag);
+int g4_launch_gather_seed(g4_ctx *ctx, g4_tree *t, const float *a_seed_caller);

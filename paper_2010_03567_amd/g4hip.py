@@ -1,0 +1,270 @@
+"""Thin ctypes binding of libg4hip.so (argument marshalling only).
+
+Every function of ``include/g4hip.h`` is exposed under the same name.  Device
+arrays are passed as torch CUDA (HIP) tensors; PyTorch provides memory and the
+current stream, every step of the solver runs in the library's HIP kernels.
+The library must be built (``python -m paper_2010_03567_amd.build``); a
+missing library is an ImportError, never a fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from dataclasses import dataclass
+
+import torch
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libg4hip.so")
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_2010_03567_amd.build`")
+
+_L = C.CDLL(LIB_PATH)
+
+G4_OK, G4_EINVAL, G4_ENOMEM, G4_EHIP, G4_ESTATE, G4_EROOT = 0, -1, -2, -3, -4, -5
+
+
+class g4_tree_params(C.Structure):
+    _fields_ = [("periodic", C.c_int), ("box", C.c_double), ("origin", C.c_double * 3),
+                ("leaf_max", C.c_int), ("max_depth", C.c_int)]
+
+
+class g4_particles(C.Structure):
+    _fields_ = [("n", C.c_int64), ("x", C.c_void_p), ("y", C.c_void_p), ("z", C.c_void_p),
+                ("mass", C.c_void_p)]
+
+
+class g4_walk_params(C.Structure):
+    _fields_ = [("kernel", C.c_int), ("criterion", C.c_int), ("order", C.c_int), ("exclusion", C.c_int),
+                ("G", C.c_double), ("eps0", C.c_double), ("r_s", C.c_double), ("r_cut", C.c_double),
+                ("theta", C.c_double), ("alpha", C.c_double), ("theta_seed", C.c_double),
+                ("a_seed", C.c_void_p), ("group_size", C.c_int), ("seed_from_tree", C.c_int)]
+
+
+class g4_fmm_params(C.Structure):
+    _fields_ = [("kernel", C.c_int), ("G", C.c_double), ("eps0", C.c_double), ("r_s", C.c_double),
+                ("r_cut", C.c_double), ("theta", C.c_double)]
+
+
+class g4_stats(C.Structure):
+    _fields_ = [("n_p2p", C.c_uint64), ("n_p2m", C.c_uint64), ("n_visit", C.c_uint64),
+                ("n_seed_p2p", C.c_uint64), ("n_seed_p2m", C.c_uint64), ("n_seed_visit", C.c_uint64),
+                ("n_pp", C.c_uint64), ("n_pn", C.c_uint64), ("n_nn", C.c_uint64),
+                ("n_nodes", C.c_uint64), ("flags", C.c_uint32)]
+
+    def as_dict(self):
+        return {k: int(getattr(self, k)) for k, _ in self._fields_}
+
+
+_p, _i64, _i32, _sz = C.c_void_p, C.c_int64, C.c_int, C.c_size_t
+_SIGS = {
+    "g4_ctx_create": [_i32, _p, C.POINTER(C.c_void_p)],
+    "g4_ctx_destroy": [_p],
+    "g4_quantize": [_p, _p, _i64, C.POINTER(g4_tree_params), _p, _p, _p, _p],
+    "g4_workspace_bytes": [C.POINTER(g4_tree_params), _i64, C.POINTER(_sz)],
+    "g4_build_tree": [_p, C.POINTER(g4_particles), C.POINTER(g4_tree_params), _p, _sz, C.POINTER(C.c_void_p)],
+    "g4_compute_multipoles": [_p, _p, _i32],
+    "g4_tree_info": [_p, _p, C.POINTER(_i64), _p],
+    "g4_tree_export": [_p, _p, _p, _p, _p, _p, _p, _p, _p, _p],
+    "g4_tree_free": [_p, _p],
+    "g4_tree_force": [_p, _p, C.POINTER(g4_walk_params), _p, _p, _p, _p, _p, _p, C.POINTER(g4_stats)],
+    "g4_treepm_shortrange": [_p, _p, C.POINTER(g4_walk_params), _p, _p, _p, _p, _p, _p, C.POINTER(g4_stats)],
+    "g4_direct_force": [_p, C.POINTER(g4_particles), C.POINTER(g4_tree_params), C.POINTER(g4_walk_params), _i32,
+                        _p, _i64, _p, _p, _p, _p],
+}
+for _name, _args in _SIGS.items():
+    f = getattr(_L, _name)
+    f.argtypes = _args
+    f.restype = C.c_int
+_L.g4_last_error.argtypes = [_p]
+_L.g4_last_error.restype = C.c_char_p
+
+OPTIONAL_SYMBOLS = []  # filled by extensions below when present
+
+
+def exported_symbols():
+    """Names of the entry points this binding found in the library."""
+    return sorted(_SIGS) + ["g4_last_error"] + OPTIONAL_SYMBOLS
+
+
+class G4Error(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"g4 status {code}: {msg}")
+        self.code = code
+
+
+def _ptr(t):
+    if t is None:
+        return None
+    if not t.is_cuda:
+        raise ValueError("device tensor expected")
+    if not t.is_contiguous():
+        raise ValueError("contiguous tensor expected")
+    return C.c_void_p(t.data_ptr())
+
+
+class Context:
+    """g4_ctx bound to the current device and torch's current stream."""
+
+    def __init__(self, device=None, stream=None):
+        if not torch.cuda.is_available():
+            raise RuntimeError("libg4hip needs a HIP device")
+        self.device = torch.device("cuda", torch.cuda.current_device() if device is None else device)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        h = C.c_void_p()
+        self._check(_L.g4_ctx_create(self.device.index, C.c_void_p(self.stream.cuda_stream), C.byref(h)), None)
+        self.h = h
+
+    def _check(self, code, h=None):
+        if code != G4_OK:
+            msg = _L.g4_last_error(h if h is not None else getattr(self, "h", None))
+            raise G4Error(code, msg.decode() if msg else "")
+
+    def check(self, code):
+        self._check(code, self.h)
+
+    def __del__(self):
+        h = getattr(self, "h", None)
+        if h:
+            _L.g4_ctx_destroy(h)
+            self.h = None
+
+
+def tree_params(periodic, box, origin=(0.0, 0.0, 0.0), leaf_max=8, max_depth=21):
+    tp = g4_tree_params()
+    tp.periodic = int(periodic)
+    tp.box = float(box)
+    for k in range(3):
+        tp.origin[k] = float(origin[k])
+    tp.leaf_max = int(leaf_max)
+    tp.max_depth = int(max_depth)
+    return tp
+
+
+def walk_params(kernel=0, criterion=0, order=3, exclusion=1, G=1.0, eps0=0.0, r_s=1.0, r_cut=1e30, theta=0.7,
+                alpha=0.005, theta_seed=0.7, a_seed=None, group_size=64, seed_from_tree=0):
+    wp = g4_walk_params()
+    wp.kernel, wp.criterion, wp.order, wp.exclusion = int(kernel), int(criterion), int(order), int(exclusion)
+    wp.G, wp.eps0, wp.r_s, wp.r_cut = float(G), float(eps0), float(r_s), float(r_cut)
+    wp.theta, wp.alpha, wp.theta_seed = float(theta), float(alpha), float(theta_seed)
+    wp.a_seed = None if a_seed is None else a_seed.data_ptr()
+    wp.group_size = int(group_size)
+    wp.seed_from_tree = int(seed_from_tree)
+    wp._keep = a_seed
+    return wp
+
+
+def particles(x, y, z, mass):
+    p = g4_particles()
+    p.n = x.numel()
+    p.x, p.y, p.z, p.mass = x.data_ptr(), y.data_ptr(), z.data_ptr(), mass.data_ptr()
+    p._keep = (x, y, z, mass)
+    return p
+
+
+# ------------------------------------------------------------------ calls
+def g4_quantize(ctx, pos, tp):
+    """pos: (n, 3) float64 device tensor -> (x, y, z) uint32 device tensors (int32 storage)."""
+    n = pos.shape[0]
+    dev = pos.device
+    x = torch.empty(n, dtype=torch.int32, device=dev)
+    y = torch.empty_like(x)
+    z = torch.empty_like(x)
+    flag = torch.zeros(1, dtype=torch.int32, device=dev)
+    ctx.check(_L.g4_quantize(ctx.h, _ptr(pos), n, C.byref(tp), _ptr(x), _ptr(y), _ptr(z), _ptr(flag)))
+    return x, y, z
+
+
+def g4_workspace_bytes(tp, n):
+    b = C.c_size_t()
+    code = _L.g4_workspace_bytes(C.byref(tp), int(n), C.byref(b))
+    if code != G4_OK:
+        raise G4Error(code, "workspace size query failed")
+    return int(b.value)
+
+
+class Tree:
+    """Handle of a built tree; owns its workspace tensor."""
+
+    def __init__(self, ctx, h, ws, tp, n, parts):
+        self.ctx, self.h, self.ws, self.tp, self.n, self._parts = ctx, h, ws, tp, n, parts
+
+    def __del__(self):
+        h = getattr(self, "h", None)
+        if h:
+            _L.g4_tree_free(self.ctx.h, h)
+            self.h = None
+
+
+def g4_build_tree(ctx, p, tp, ws=None):
+    nbytes = g4_workspace_bytes(tp, p.n)
+    if ws is None:
+        ws = torch.empty(nbytes + 256, dtype=torch.uint8, device=ctx.device)
+    off = (-ws.data_ptr()) % 256
+    wsv = ws[off:]
+    h = C.c_void_p()
+    ctx.check(_L.g4_build_tree(ctx.h, C.byref(p), C.byref(tp), C.c_void_p(wsv.data_ptr()), wsv.numel(), C.byref(h)))
+    return Tree(ctx, h, ws, tp, int(p.n), p)
+
+
+def g4_compute_multipoles(ctx, tree, order=3):
+    ctx.check(_L.g4_compute_multipoles(ctx.h, tree.h, int(order)))
+
+
+def g4_tree_info(ctx, tree):
+    nn = C.c_int64()
+    ls = (C.c_int64 * (tree.tp.max_depth + 2))()
+    ctx.check(_L.g4_tree_info(ctx.h, tree.h, C.byref(nn), C.cast(ls, C.c_void_p)))
+    return int(nn.value), list(ls)
+
+
+def g4_tree_export(ctx, tree, moments=True):
+    nn, _ = g4_tree_info(ctx, tree)
+    dev = ctx.device
+    out = dict(level=torch.empty(nn, dtype=torch.int32, device=dev),
+               cell=torch.empty((nn, 3), dtype=torch.int32, device=dev),
+               count=torch.empty(nn, dtype=torch.int64, device=dev),
+               leaf=torch.empty(nn, dtype=torch.int32, device=dev))
+    if moments:
+        out.update(mass=torch.empty(nn, dtype=torch.float64, device=dev),
+                   com=torch.empty((nn, 3), dtype=torch.float64, device=dev),
+                   q2=torch.empty((nn, 6), dtype=torch.float64, device=dev),
+                   q3=torch.empty((nn, 10), dtype=torch.float64, device=dev))
+    g = lambda k: _ptr(out[k]) if k in out else None
+    ctx.check(_L.g4_tree_export(ctx.h, tree.h, g("level"), g("cell"), g("count"), g("leaf"), g("mass"), g("com"),
+                                g("q2"), g("q3")))
+    return out
+
+
+def _force_outputs(n, dev, want_pot, want_counts, want_amag):
+    ax = torch.empty(n, dtype=torch.float64, device=dev)
+    ay = torch.empty_like(ax)
+    az = torch.empty_like(ax)
+    pot = torch.empty_like(ax) if want_pot else None
+    cnt = torch.empty((n, 2), dtype=torch.int32, device=dev) if want_counts else None
+    am = torch.empty(n, dtype=torch.float32, device=dev) if want_amag else None
+    return ax, ay, az, pot, cnt, am
+
+
+def g4_tree_force(ctx, tree, wp, want_pot=False, want_counts=False, want_amag=False, want_stats=False, out=None,
+                  shortrange=False):
+    ax, ay, az, pot, cnt, am = out if out is not None else _force_outputs(tree.n, ctx.device, want_pot, want_counts,
+                                                                            want_amag)
+    st = g4_stats() if want_stats else None
+    fn = _L.g4_treepm_shortrange if shortrange else _L.g4_tree_force
+    ctx.check(fn(ctx.h, tree.h, C.byref(wp), _ptr(ax), _ptr(ay), _ptr(az), _ptr(pot), _ptr(cnt), _ptr(am),
+                 C.byref(st) if st is not None else None))
+    return dict(ax=ax, ay=ay, az=az, pot=pot, counts=cnt, amag=am, stats=st.as_dict() if st is not None else None)
+
+
+def g4_treepm_shortrange(ctx, tree, wp, **kw):
+    return g4_tree_force(ctx, tree, wp, shortrange=True, **kw)
+
+
+def g4_direct_force(ctx, p, tp, wp, targets=None, truncate=False, want_pot=True):
+    nt = p.n if targets is None else targets.numel()
+    ax, ay, az, pot, _, _ = _force_outputs(nt, ctx.device, want_pot, False, False)
+    ctx.check(_L.g4_direct_force(ctx.h, C.byref(p), C.byref(tp), C.byref(wp), int(truncate), _ptr(targets), int(nt),
+                                 _ptr(ax), _ptr(ay), _ptr(az), _ptr(pot)))
+    return dict(ax=ax, ay=ay, az=az, pot=pot)

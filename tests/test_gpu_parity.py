@@ -1,0 +1,280 @@
+"""Parity of the HIP path (through the C ABI) with the FP64 oracle.
+
+Integer work (quantisation, node sets) must match bit for bit.  Forces must
+match at identical opening decisions: the relative walk on the GPU is given the
+oracle's own |a| seeds, so both sides evaluate the same criterion; per-particle
+relative force differences must have median <= 1e-5 and 99.9th percentile
+<= 1e-3, and at least 99.9 % of the particles must have identical interaction
+counts (the decision-agreement rate; the rest are FP32-vs-FP64 threshold flips).
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import workloads
+
+pytestmark = pytest.mark.gpu
+
+MEDIAN_TOL = 1e-5
+P999_TOL = 1e-3
+AGREE_MIN = 0.999
+
+
+@pytest.fixture(scope="module")
+def g():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2010_03567_amd.g4hip as g
+    return g
+
+
+@pytest.fixture(scope="module")
+def ctx(g):
+    return g.Context()
+
+
+class Case:
+    pass
+
+
+def make_case(g, ctx, ps, periodic, B, max_depth=21):
+    c = Case()
+    if periodic:
+        org, box = (0.0, 0.0, 0.0), ps.box
+    else:
+        org, box = workloads.isolated_root(ps.pos)
+    c.tp = g.tree_params(periodic, box, org, leaf_max=B, max_depth=max_depth)
+    x, y, z = g.g4_quantize(ctx, torch.from_numpy(ps.pos).cuda(), c.tp)
+    st, X, Y, Z = oracle.quantize(ps.pos, periodic, box, org)
+    assert st == 0
+    for a, b in ((x, X), (y, Y), (z, Z)):
+        assert np.array_equal(a.cpu().numpy().view(np.uint32), b), "quantisation differs"
+    c.mass32 = ps.mass.astype(np.float32)
+    c.m = torch.from_numpy(c.mass32).cuda()
+    c.x, c.y, c.z = x, y, z
+    c.p = g.particles(x, y, z, c.m)
+    c.tree = g.g4_build_tree(ctx, c.p, c.tp)
+    g.g4_compute_multipoles(ctx, c.tree, 3)
+    c.ot = oracle.Tree(X, Y, Z, c.mass32.astype(np.float64), periodic, box, B, max_depth)
+    c.ot.compute_moments()
+    c.X, c.Y, c.Z = X, Y, Z
+    c.box, c.periodic, c.n = box, periodic, ps.pos.shape[0]
+    return c
+
+
+def stack3(out):
+    return np.stack([out["ax"].cpu().numpy(), out["ay"].cpu().numpy(), out["az"].cpu().numpy()], axis=1)
+
+
+def assert_parity(a_gpu, a_orc, cnt_gpu=None, cnt_orc=None, label=""):
+    err = workloads.relative_errors(a_gpu, a_orc)
+    med, p999 = np.median(err), np.percentile(err, 99.9)
+    msg = f"{label}: median {med:.3e} p99.9 {p999:.3e} max {err.max():.3e}"
+    if cnt_gpu is not None:
+        agree = np.mean(np.all(cnt_gpu.astype(np.int64) == cnt_orc, axis=1))
+        msg += f" decision agreement {agree:.5f}"
+        assert agree >= AGREE_MIN, msg
+    print(msg)
+    assert med <= MEDIAN_TOL and p999 <= P999_TOL, msg
+
+
+# ---------------------------------------------------------------- integer work
+def test_quantize_isolated_outside_root(g, ctx):
+    tp = g.tree_params(False, 1.0, (0.0, 0.0, 0.0))
+    pos = torch.tensor([[0.5, 0.5, 0.5], [1.5, 0.2, 0.2]], dtype=torch.float64, device="cuda")
+    with pytest.raises(g.G4Error) as e:
+        g.g4_quantize(ctx, pos, tp)
+    assert e.value.code == g.G4_EROOT
+
+
+def node_set(level, cell, count, leaf):
+    return {(int(l), int(c[0]), int(c[1]), int(c[2]), int(k), int(f)) for l, c, k, f in zip(level, cell, count, leaf)}
+
+
+@pytest.mark.parametrize("kind,n,B", [("plummer", 8192, 8), ("box", 30001, 8), ("box", 65, 4), ("plummer", 1, 8),
+                                      ("box", 4096, 16)])
+def test_tree_node_set_bit_exact(g, ctx, kind, n, B):
+    ps = workloads.plummer(n, seed=3) if kind == "plummer" else workloads.clustered_box(n, seed=4, nhalo=max(2, n // 500))
+    c = make_case(g, ctx, ps, kind == "box", B)
+    ex = g.g4_tree_export(ctx, c.tree, moments=False)
+    mine = node_set(ex["level"].cpu().numpy(), ex["cell"].cpu().numpy().view(np.uint32), ex["count"].cpu().numpy(),
+                    ex["leaf"].cpu().numpy())
+    ref = node_set(*c.ot.nodes())
+    assert mine == ref
+
+
+def test_tree_depth_cap_coincident(g, ctx):
+    pos = np.full((40, 3), 0.3)
+    pos[20:] = 0.7
+    ps = workloads.ParticleSet(pos, np.full(40, 1 / 40), 1.0, {})
+    c = make_case(g, ctx, ps, True, 8)
+    ex = g.g4_tree_export(ctx, c.tree, moments=False)
+    mine = node_set(ex["level"].cpu().numpy(), ex["cell"].cpu().numpy().view(np.uint32), ex["count"].cpu().numpy(),
+                    ex["leaf"].cpu().numpy())
+    assert mine == node_set(*c.ot.nodes())
+    assert max(k[0] for k in mine) == 21
+
+
+# ---------------------------------------------------------------- moments
+@pytest.mark.parametrize("kind", ["plummer", "box"])
+def test_moments_parity(g, ctx, kind):
+    ps = workloads.plummer(8192, seed=5) if kind == "plummer" else workloads.clustered_box(30001, seed=6, nhalo=60)
+    c = make_case(g, ctx, ps, kind == "box", 8)
+    ex = g.g4_tree_export(ctx, c.tree, moments=True)
+    key = lambda l, cc: (int(l), int(cc[0]), int(cc[1]), int(cc[2]))
+    lv, ce = ex["level"].cpu().numpy(), ex["cell"].cpu().numpy().view(np.uint32)
+    gi = {key(l, cc): i for i, (l, cc) in enumerate(zip(lv, ce))}
+    olv, oce, _, _ = c.ot.nodes()
+    om, ocom, oq2, oq3 = c.ot.moments()
+    order = np.array([gi[key(l, cc)] for l, cc in zip(olv, oce)])
+    m = ex["mass"].cpu().numpy()[order]
+    com = ex["com"].cpu().numpy()[order]
+    q2 = ex["q2"].cpu().numpy()[order]
+    q3 = ex["q3"].cpu().numpy()[order]
+    side = c.box / 2.0 ** olv
+    np.testing.assert_allclose(m, om, rtol=2e-6)
+    assert np.all(np.abs(com - ocom).max(axis=1) <= 1e-6 * side + 1e-12 * c.box)
+    assert np.all(np.abs(q2 - oq2).max(axis=1) <= 1e-5 * om * side ** 2)
+    assert np.all(np.abs(q3 - oq3).max(axis=1) <= 1e-5 * om * side ** 3)
+
+
+# ---------------------------------------------------------------- walks
+PLUMMER_EPS = 0.01
+
+
+@pytest.fixture(scope="module")
+def plummer_case(g, ctx):
+    return make_case(g, ctx, workloads.plummer(8192, seed=1), False, 8)
+
+
+def test_walk_geometric_parity_plummer(g, ctx, plummer_case):
+    c = plummer_case
+    wp = g.walk_params(kernel=0, criterion=0, theta=0.7, eps0=PLUMMER_EPS)
+    out = g.g4_tree_force(ctx, c.tree, wp, want_pot=True, want_counts=True)
+    acc, pot, cnt = c.ot.walk(kernel=0, criterion=0, theta=0.7, eps0=PLUMMER_EPS, nthreads=16)
+    assert_parity(stack3(out), acc, out["counts"].cpu().numpy(), cnt, "plummer geometric")
+    perr = np.abs(out["pot"].cpu().numpy() - pot) / np.abs(pot)
+    assert np.median(perr) < 1e-5
+
+
+@pytest.mark.parametrize("order", [3, 2])
+def test_walk_relative_parity_plummer(g, ctx, plummer_case, order):
+    """Relative criterion at alpha = 0.005, |a| seeds from the oracle's geometric pre-walk."""
+    c = plummer_case
+    a0, _, _ = c.ot.walk(kernel=0, criterion=0, theta=0.7, eps0=PLUMMER_EPS, nthreads=16)
+    seed = np.linalg.norm(a0, axis=1)
+    wp = g.walk_params(kernel=0, criterion=1, order=order, alpha=0.005, eps0=PLUMMER_EPS,
+                       a_seed=torch.from_numpy(seed.astype(np.float32)).cuda())
+    out = g.g4_tree_force(ctx, c.tree, wp, want_pot=True, want_counts=True, want_stats=True)
+    acc, pot, cnt = c.ot.walk(kernel=0, criterion=1, order=order, alpha=0.005, aseed=seed.astype(np.float32),
+                              eps0=PLUMMER_EPS, nthreads=16)
+    assert_parity(stack3(out), acc, out["counts"].cpu().numpy(), cnt, f"plummer relative p={order}")
+    st = out["stats"]
+    assert st["n_p2p"] == int(out["counts"].cpu().numpy()[:, 0].astype(np.int64).sum())
+    assert st["n_p2m"] == int(out["counts"].cpu().numpy()[:, 1].astype(np.int64).sum())
+
+
+def test_walk_relative_own_prewalk_plummer(g, ctx, plummer_case):
+    """With a_seed = NULL the library runs its own geometric pre-walk; its |a| must
+    match the oracle's pre-walk and the final forces stay at parity."""
+    c = plummer_case
+    a0, _, _ = c.ot.walk(kernel=0, criterion=0, theta=0.7, eps0=PLUMMER_EPS, nthreads=16)
+    wp0 = g.walk_params(kernel=0, criterion=0, theta=0.7, eps0=PLUMMER_EPS)
+    pre = g.g4_tree_force(ctx, c.tree, wp0, want_amag=True)
+    np.testing.assert_allclose(pre["amag"].cpu().numpy(), np.linalg.norm(a0, axis=1), rtol=1e-4)
+    wp = g.walk_params(kernel=0, criterion=1, alpha=0.005, theta_seed=0.7, eps0=PLUMMER_EPS)
+    out = g.g4_tree_force(ctx, c.tree, wp, want_counts=True)
+    acc, _, cnt = c.ot.walk(kernel=0, criterion=1, alpha=0.005, aseed=np.linalg.norm(a0, axis=1), eps0=PLUMMER_EPS,
+                            nthreads=16)
+    assert_parity(stack3(out), acc, out["counts"].cpu().numpy(), cnt, "plummer relative, own pre-walk")
+
+
+def sr_params(n):
+    """Config-2 TreePM parameters scaled to n particles in a unit box (same
+    r_s and softening relative to the mean spacing)."""
+    scale = (128 ** 3 / n) ** (1.0 / 3.0)
+    rs = 1.25 / 256 * scale
+    return dict(r_s=rs, r_cut=4.5 * rs, eps0=scale / (40 * 128))
+
+
+@pytest.fixture(scope="module")
+def box_case(g, ctx):
+    return make_case(g, ctx, workloads.clustered_box(30001, seed=7, nhalo=60), True, 8)
+
+
+def test_treepm_geometric_parity(g, ctx, box_case):
+    c = box_case
+    kw = sr_params(c.n)
+    wp = g.walk_params(kernel=1, criterion=0, theta=0.7, **kw)
+    out = g.g4_treepm_shortrange(ctx, c.tree, wp, want_pot=True, want_counts=True)
+    acc, pot, cnt = c.ot.walk(kernel=1, criterion=0, theta=0.7, nthreads=16, **kw)
+    assert_parity(stack3(out), acc, out["counts"].cpu().numpy(), cnt, "treepm geometric")
+    perr = np.abs(out["pot"].cpu().numpy() - pot) / np.abs(pot)
+    assert np.median(perr) < 1e-5
+
+
+def test_treepm_relative_parity(g, ctx, box_case):
+    c = box_case
+    kw = sr_params(c.n)
+    a0, _, _ = c.ot.walk(kernel=1, criterion=0, theta=0.7, nthreads=16, **kw)
+    seed = np.linalg.norm(a0, axis=1).astype(np.float32)
+    wp = g.walk_params(kernel=1, criterion=1, alpha=0.005, a_seed=torch.from_numpy(seed).cuda(), **kw)
+    out = g.g4_treepm_shortrange(ctx, c.tree, wp, want_counts=True)
+    acc, _, cnt = c.ot.walk(kernel=1, criterion=1, alpha=0.005, aseed=seed, nthreads=16, **kw)
+    assert_parity(stack3(out), acc, out["counts"].cpu().numpy(), cnt, "treepm relative")
+
+
+@pytest.mark.parametrize("group", [1, 17, 64])
+def test_walk_group_sizes(g, ctx, box_case, group):
+    """Group size changes only how lanes are packed, never the per-particle decisions."""
+    c = box_case
+    kw = sr_params(c.n)
+    wp = g.walk_params(kernel=1, criterion=0, theta=0.5, group_size=group, **kw)
+    out = g.g4_treepm_shortrange(ctx, c.tree, wp, want_counts=True)
+    acc, _, cnt = c.ot.walk(kernel=1, criterion=0, theta=0.5, nthreads=16, **kw)
+    assert_parity(stack3(out), acc, out["counts"].cpu().numpy(), cnt, f"group {group}")
+
+
+def test_single_particle_has_zero_force(g, ctx):
+    c = make_case(g, ctx, workloads.plummer(1, seed=2), False, 8)
+    out = g.g4_tree_force(ctx, c.tree, g.walk_params(kernel=0, criterion=0, eps0=0.01), want_pot=True)
+    assert np.all(stack3(out) == 0) and np.all(out["pot"].cpu().numpy() == 0)
+
+
+# ---------------------------------------------------------------- direct sums
+@pytest.mark.parametrize("kernel", [0, 1])
+def test_direct_kernel_parity(g, ctx, kernel):
+    if kernel == 0:
+        c = make_case(g, ctx, workloads.plummer(3000, seed=8), False, 8)
+        kw = dict(eps0=0.01)
+    else:
+        c = make_case(g, ctx, workloads.clustered_box(3000, seed=9, nhalo=10), True, 8)
+        kw = sr_params(3000)
+    tg = torch.arange(0, c.n, 7, dtype=torch.int64, device="cuda")
+    wp = g.walk_params(kernel=kernel, **kw)
+    out = g.g4_direct_force(ctx, c.p, c.tp, wp, targets=tg)
+    ref, pref = oracle.direct(c.X, c.Y, c.Z, c.mass32.astype(np.float64), c.ot.unit, kernel=kernel,
+                              targets=tg.cpu().numpy(), nthreads=16, **{k: v for k, v in kw.items() if k != "r_cut"})
+    np.testing.assert_allclose(stack3(out), ref, rtol=1e-11, atol=1e-13 * np.abs(ref).max())
+    np.testing.assert_allclose(out["pot"].cpu().numpy(), pref, rtol=1e-11)
+
+
+# ---------------------------------------------------------------- full size
+@pytest.mark.slow
+def test_treepm_full_size_sampled_parity(g, ctx):
+    """The clustered 128^3 box at its real size, in the launch configuration the
+    benchmark times (GPU pre-walk seeds): 2000 sampled particles against the
+    oracle walking the same tree one particle at a time."""
+    n = 128 ** 3
+    ps = workloads.clustered_box(n, seed=2)
+    c = make_case(g, ctx, ps, True, 8)
+    kw = dict(r_s=1.25 / 256, r_cut=4.5 * 1.25 / 256, eps0=1.0 / (40 * 128))
+    wp = g.walk_params(kernel=1, criterion=1, alpha=0.005, theta_seed=0.7, **kw)
+    out = g.g4_treepm_shortrange(ctx, c.tree, wp, want_counts=True)
+    tg = workloads.sample_indices(n, 2000, seed=77)
+    a0, _, _ = c.ot.walk(kernel=1, criterion=0, theta=0.7, targets=tg, nthreads=16, **kw)
+    seed = np.zeros(n)
+    seed[tg] = np.linalg.norm(a0, axis=1)
+    acc, _, cnt = c.ot.walk(kernel=1, criterion=1, alpha=0.005, aseed=seed, targets=tg, nthreads=16, **kw)
+    assert_parity(stack3(out)[tg], acc, out["counts"].cpu().numpy()[tg], cnt, "treepm 128^3 sampled")

@@ -144,6 +144,8 @@ def isolated_root(pos, margin: float = 1e-3):
     """Shrink-wrapped cubic root for an isolated set: (origin[3], side)."""
     lo = pos.min(axis=0); hi = pos.max(axis=0)
     side = float((hi - lo).max()) * (1.0 + margin)
+    if not side > 0.0:  # a single particle (or all coincident): any positive cube holds it
+        side = 1.0
     centre = 0.5 * (lo + hi)
     origin = centre - 0.5 * side
     return origin.astype(np.float64), side
