@@ -106,6 +106,10 @@ typedef struct {
     uint64_t n_seed_p2p, n_seed_p2m, n_seed_visit;  /* same, geometric pre-walk (if run) */
     uint64_t n_pp, n_pn, n_nn;   /* FMM interaction counts */
     uint64_t n_nodes;    /* nodes in the tree */
+    /* wavefront-level iterations of the walk (64 lanes each): node pops,
+     * particle-node passes, particle-particle source iterations; lane
+     * utilisation = lane count / (64 x wavefront count) */
+    uint64_t w_pop, w_p2m, w_p2p;
     uint32_t flags;      /* bit 0: a leaf at max_depth holds more than leaf_max particles */
 } g4_stats;
 
@@ -181,6 +185,47 @@ int g4_treepm_shortrange(g4_ctx *ctx, g4_tree *tree, const g4_walk_params *wp, d
 int g4_direct_force(g4_ctx *ctx, const g4_particles *p, const g4_tree_params *tp, const g4_walk_params *wp,
                     int truncate, const int64_t *targets, int64_t ntargets, double *ax, double *ay, double *az,
                     double *pot);
+
+/* ------------------------------------------------------- learned |a| seed */
+/* The relative criterion needs |a| before the first force; the paper gets it
+ * from a geometric pre-walk (footnote to eq. eqnrelcriterion).  These calls
+ * predict log10 |a| instead with a perceptron 8 -> 64 -> 64 -> 1 (SiLU), BF16
+ * weights (4801 values, layout W1[64][8], b1[64], W2[64][64], b2[64], w3[64],
+ * b3), FP32 arithmetic. */
+
+/* Per-particle features from the particle's leaf L, its parent P and its
+ * grandparent (caller order, n x 8 float): log10 M_L, log10 l_L, level of L,
+ * log10(|x - s_L|/l_L + 1e-3), log10(|x - s_P|/l_P + 1e-3), log10 M_P,
+ * log10 M_grandparent, log10 |a_near| (pair forces of the other particles of
+ * L plus monopoles of the siblings of L and of P, with the softened kernel of
+ * wp: kernel, eps0, r_s).  norm: device 16 floats (mean[8], 1/std[8]) applied
+ * as (f - mean) / std, or NULL for raw features.  Needs
+ * g4_compute_multipoles. */
+int g4_mlp_features(g4_ctx *ctx, const g4_tree *tree, const g4_walk_params *wp, const float *norm, float *feat);
+
+/* out[i] = y_i (mode 0) or 10^(y_i + shift) (mode 1, directly usable as
+ * g4_walk_params.a_seed); w_bf16: device 4801 bf16; feat: device n x 8. */
+int g4_mlp_forward(g4_ctx *ctx, const void *w_bf16, const float *feat, int64_t n, float *out, float shift, int mode);
+
+/* Gradient of the loss with respect to the 4801 parameters (device float
+ * grad[4801], overwritten) and the loss itself (device float).  tau <= 0:
+ * L = (1/n) sum (y_i - target_i)^2; 0 < tau < 1: pinball loss
+ * L = (1/n) sum rho_tau(target_i - y_i), rho_tau(u) = u (tau - [u < 0]),
+ * which fits the tau-quantile (a conservative, low seed for small tau). */
+int g4_mlp_grad(g4_ctx *ctx, const void *w_bf16, const float *feat, const float *target, int64_t n, float tau,
+                float *grad, float *loss);
+
+/* One Adam step (Kingma & Ba 2015) on FP32 master weights with moment buffers
+ * m, v (device float[4801] each); rewrites w_bf16 as the rounded master
+ * weights.  step counts from 1. */
+int g4_mlp_adam(g4_ctx *ctx, void *w_bf16, float *w_master, float *m, float *v, const float *grad, float lr,
+                float beta1, float beta2, float eps, int64_t step);
+
+/* grad + Adam in one call: adam_state = m[4801] followed by v[4801]; grad is
+ * caller scratch of 4801 floats; loss receives L before the update. */
+int g4_mlp_train_step(g4_ctx *ctx, void *w_bf16, float *w_master, float *adam_state, float *grad,
+                      const float *feat, const float *target, int64_t n, float tau, float lr, int64_t step,
+                      float *loss);
 
 #ifdef __cplusplus
 }

@@ -71,9 +71,11 @@ def lib():
         L.orc_fmm.argtypes = [p, C.POINTER(FmmParams), p, p, p]
         L.orc_mlp_forward.argtypes = [p, p, i64, p]
         L.orc_mlp_loss_grad.restype = d
-        L.orc_mlp_loss_grad.argtypes = [p, p, p, i64, p]
+        L.orc_mlp_loss_grad.argtypes = [p, p, p, i64, d, p]
         L.orc_adam.argtypes = [p, p, p, p, i64, d, d, d, d, i64]
         L.orc_two_groups.argtypes = [i64, p, p, i64, p, p, p, p, p, p]
+        L.orc_features.restype = i32
+        L.orc_features.argtypes = [p, C.POINTER(WalkParams), p]
         _lib = L
     return _lib
 
@@ -190,6 +192,16 @@ class Tree:
             raise RuntimeError(f"orc_walk failed with status {st}")
         return acc, pot, cnt
 
+    def features(self, kernel=0, eps0=0.0, r_s=1.0):
+        """Learned-seed features, n x 8 (caller order)."""
+        if not self.has_moments:
+            self.compute_moments()
+        f = np.zeros((self.n, 8))
+        P = WalkParams(int(kernel), 0, 3, 1, 1.0, float(eps0), float(r_s), 0.0, 0.0, 0.0)
+        if lib().orc_features(self._h, C.byref(P), _ptr(f)) != 0:
+            raise RuntimeError("orc_features failed")
+        return f
+
     def fmm(self, kernel=0, G=1.0, eps0=0.0, r_s=1.0, r_cut=np.inf, theta=0.5):
         if not self.has_moments:
             self.compute_moments()
@@ -235,10 +247,10 @@ def mlp_forward(w, feat):
     return out
 
 
-def mlp_loss_grad(w, feat, target):
+def mlp_loss_grad(w, feat, target, tau=0.0):
     w = _f64(w); feat = _f64(feat); target = _f64(target)
     g = np.zeros(NPARAM)
-    loss = lib().orc_mlp_loss_grad(_ptr(w), _ptr(feat), _ptr(target), feat.shape[0], _ptr(g))
+    loss = lib().orc_mlp_loss_grad(_ptr(w), _ptr(feat), _ptr(target), feat.shape[0], float(tau), _ptr(g))
     return loss, g
 
 

@@ -977,9 +977,11 @@ void orc_mlp_forward(const double *w, const double *feat, int64_t n, double *out
     }
 }
 
-/* Mean-squared-error loss L = (1/n) sum (y - target)^2 and its gradient
- * with respect to all 4801 parameters (backpropagation). */
-double orc_mlp_loss_grad(const double *w, const double *feat, const double *target, int64_t n, double *grad)
+/* Loss and its gradient with respect to all 4801 parameters
+ * (backpropagation).  tau <= 0: mean squared error L = (1/n) sum (y - t)^2;
+ * 0 < tau < 1: pinball loss L = (1/n) sum rho(t - y), rho(u) = u (tau - [u<0]). */
+double orc_mlp_loss_grad(const double *w, const double *feat, const double *target, int64_t n, double tau,
+                         double *grad)
 {
     const double *W1 = w, *b1 = w + 512, *W2 = w + 576, *b2 = w + 4672, *w3 = w + 4736, *b3 = w + 4800;
     double *gW1 = grad, *gb1 = grad + 512, *gW2 = grad + 576, *gb2 = grad + 4672, *gw3 = grad + 4736,
@@ -1002,9 +1004,15 @@ double orc_mlp_loss_grad(const double *w, const double *feat, const double *targ
         }
         double y = b3[0];
         for (int i = 0; i < 64; i++) y += w3[i] * h2[i];
-        double e = y - target[p];
-        loss += e * e;
-        double dy = 2.0 * e / (double)n;
+        double e = y - target[p], dy;
+        if (tau > 0.0) {
+            double u = -e;  /* target - y */
+            loss += u >= 0.0 ? tau * u : (tau - 1.0) * u;
+            dy = (u >= 0.0 ? -tau : 1.0 - tau) / (double)n;
+        } else {
+            loss += e * e;
+            dy = 2.0 * e / (double)n;
+        }
         gb3[0] += dy;
         double dz2[64], dh1[64];
         for (int i = 0; i < 64; i++) {
@@ -1124,4 +1132,90 @@ void orc_two_groups(int64_t nA, const double *posA, const double *mA, int64_t nB
         p2m_one(&P, &nA_, r, acc, &phi);
         memcpy(accB_tree + 3 * i, acc, sizeof(acc));
     }
+}
+
+/* ======================================================================
+ * 11. Features of the learned |a| seed, per particle, from the leaf L that
+ *     holds it, its parent P and grandparent Q (a missing ancestor is
+ *     replaced by the node itself):
+ *       log10 M_L, log10 l_L, level of L,
+ *       log10(|x - s_L|/l_L + 1e-3), log10(|x - s_P|/l_P + 1e-3),
+ *       log10 M_P, log10 M_Q,
+ *       log10 |a_near|, a_near = pair forces of the other particles of L
+ *       + point-mass forces of the siblings of L (other children of P) and
+ *       of the siblings of P (other children of Q), with the pair kernel
+ *       of the walk (softened, short-range for kernel 1).
+ *     feat: n x 8, caller order.
+ * ====================================================================== */
+
+/* force factor of a point mass at distance r, as in p2p_one */
+static double pair_K(const orc_walk_params *P, double r)
+{
+    double h = 2.8 * P->eps0;
+    if (P->kernel == 0) return orc_soft_K(r, h);
+    return orc_sr_K(r, h, 0.5 / P->r_s);
+}
+
+static void features_rec(const orc_tree *t, const orc_walk_params *P, int64_t q, int64_t par, int64_t gpar,
+                         double *feat)
+{
+    const onode *nd = &t->nodes[q];
+    if (!nd->leaf) {
+        for (int c = 0; c < nd->nchild; c++) features_rec(t, P, nd->child0 + c, q, par, feat);
+        return;
+    }
+    const onode *np = &t->nodes[par >= 0 ? par : q];
+    const onode *ng = gpar >= 0 ? &t->nodes[gpar] : np;
+    double l = node_side(t, nd->level), lp = node_side(t, np->level);
+    for (int64_t s = 0; s < nd->count; s++) {
+        int64_t j = t->idx[nd->first + s];
+        double *f = feat + 8 * j;
+        uint32_t xj[3] = {t->X[j], t->Y[j], t->Z[j]};
+        double dL = 0.0, dP = 0.0;
+        for (int k = 0; k < 3; k++) {
+            double a = (double)(int32_t)(xj[k] - nd->gc[k]) * t->unit - nd->dcom[k];
+            double b = (double)(int32_t)(xj[k] - np->gc[k]) * t->unit - np->dcom[k];
+            dL += a * a;
+            dP += b * b;
+        }
+        double acc[3] = {0, 0, 0};
+        for (int64_t u = 0; u < nd->count; u++) {
+            int64_t k = t->idx[nd->first + u];
+            if (k == j) continue;
+            double d[3] = {(double)(int32_t)(t->X[k] - xj[0]) * t->unit, (double)(int32_t)(t->Y[k] - xj[1]) * t->unit,
+                           (double)(int32_t)(t->Z[k] - xj[2]) * t->unit};
+            double K = pair_K(P, sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]));
+            for (int c = 0; c < 3; c++) acc[c] += t->m[k] * d[c] * K;
+        }
+        int64_t selfs[2] = {q, par}, ups[2] = {par, gpar};
+        for (int lev = 0; lev < 2; lev++) {
+            if (selfs[lev] < 0 || ups[lev] < 0) break;
+            const onode *up = &t->nodes[ups[lev]];
+            for (int c = 0; c < up->nchild; c++) {
+                int64_t sib = up->child0 + c;
+                if (sib == selfs[lev]) continue;
+                const onode *sn = &t->nodes[sib];
+                double d[3];
+                for (int k = 0; k < 3; k++) d[k] = (double)(int32_t)(sn->gc[k] - xj[k]) * t->unit + sn->dcom[k];
+                double K = pair_K(P, sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]));
+                for (int k = 0; k < 3; k++) acc[k] += sn->mass * d[k] * K;
+            }
+        }
+        double am = sqrt(acc[0] * acc[0] + acc[1] * acc[1] + acc[2] * acc[2]);
+        f[0] = log10(nd->mass);
+        f[1] = log10(l);
+        f[2] = nd->level;
+        f[3] = log10(sqrt(dL) / l + 1e-3);
+        f[4] = log10(sqrt(dP) / lp + 1e-3);
+        f[5] = log10(np->mass);
+        f[6] = log10(ng->mass);
+        f[7] = log10(am > 1e-30 ? am : 1e-30);
+    }
+}
+
+int orc_features(const orc_tree *t, const orc_walk_params *P, double *feat)
+{
+    if (!t->has_moments) return -4;
+    features_rec(t, P, 0, -1, -1, feat);
+    return 0;
 }

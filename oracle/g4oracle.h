@@ -64,7 +64,8 @@ int orc_fmm(const orc_tree *t, const orc_fmm_params *P, double *acc, double *pot
 
 /* MLP 8 -> 64 -> 64 -> 1 (SiLU), 4801 parameters */
 void orc_mlp_forward(const double *w, const double *feat, int64_t n, double *out);
-double orc_mlp_loss_grad(const double *w, const double *feat, const double *target, int64_t n, double *grad);
+double orc_mlp_loss_grad(const double *w, const double *feat, const double *target, int64_t n, double tau,
+                         double *grad);
 void orc_adam(double *w, const double *g, double *m, double *v, int64_t np, double lr, double b1, double b2,
               double eps, int64_t step);
 
@@ -72,6 +73,10 @@ void orc_adam(double *w, const double *g, double *m, double *v, int64_t np, doub
  * particles of each group from the other, FMM (p = 3) and one-sided tree */
 void orc_two_groups(int64_t nA, const double *posA, const double *mA, int64_t nB, const double *posB,
                     const double *mB, double *accA_fmm, double *accB_fmm, double *accA_tree, double *accB_tree);
+
+/* learned-seed features of every particle (n x 8, caller order); P gives
+ * the pair kernel (kernel, eps0, r_s) of the near-field force feature */
+int orc_features(const orc_tree *t, const orc_walk_params *P, double *feat);
 
 #ifdef __cplusplus
 }

@@ -91,6 +91,7 @@ int g4_build_tree(g4_ctx *ctx, const g4_particles *p, const g4_tree_params *tp, 
     t->parts = (uint4 *)(b + L.parts);
     t->bfirst = (uint32_t *)(b + L.bfirst);
     t->bcount = (uint32_t *)(b + L.bcount);
+    t->parent = (uint32_t *)(b + L.parent);
     t->wn = (WNode *)(b + L.wn);
     t->q3 = (float *)(b + L.q3);
     t->mom = (double *)(b + L.mom);
@@ -195,6 +196,9 @@ static int tree_force_impl(g4_ctx *ctx, g4_tree *tree, const g4_walk_params *wp,
         stats->n_seed_visit = h.stat[5];
         stats->n_pp = stats->n_pn = stats->n_nn = 0;
         stats->n_nodes = h.node_count;
+        stats->w_pop = h.stat[9];
+        stats->w_p2m = h.stat[10];
+        stats->w_p2p = h.stat[11];
         stats->flags = h.flags;
     }
     return G4_OK;
@@ -229,6 +233,48 @@ int g4_direct_force(g4_ctx *ctx, const g4_particles *p, const g4_tree_params *tp
     if (targets && ntargets < 0) return g4_set_err(ctx, G4_EINVAL, "negative target count");
     if (wp->kernel == 1 && !(wp->r_s > 0)) return g4_set_err(ctx, G4_EINVAL, "r_s must be positive");
     return g4_launch_direct(ctx, p, tp, wp, truncate, targets, ntargets, ax, ay, az, pot);
+}
+
+int g4_mlp_features(g4_ctx *ctx, const g4_tree *tree, const g4_walk_params *wp, const float *norm, float *feat)
+{
+    if (!ctx || !tree || !feat || !wp) return G4_EINVAL;
+    if (!tree->moments_order) return g4_set_err(ctx, G4_ESTATE, "moments not computed");
+    if (wp->kernel == 1 && !(wp->r_s > 0)) return g4_set_err(ctx, G4_EINVAL, "r_s must be positive");
+    return g4_launch_mlp_features(ctx, tree, wp, norm, feat);
+}
+
+int g4_mlp_forward(g4_ctx *ctx, const void *w_bf16, const float *feat, int64_t n, float *out, float shift, int mode)
+{
+    if (!ctx) return G4_EINVAL;
+    if (!w_bf16 || !feat || !out || n < 0) return g4_set_err(ctx, G4_EINVAL, "bad mlp_forward args");
+    if (((uintptr_t)feat & 15) != 0) return g4_set_err(ctx, G4_EINVAL, "feat must be 16-byte aligned");
+    return g4_launch_mlp_forward(ctx, (const uint16_t *)w_bf16, feat, n, out, shift, mode ? 1 : 0);
+}
+
+int g4_mlp_grad(g4_ctx *ctx, const void *w_bf16, const float *feat, const float *target, int64_t n, float tau,
+                float *grad, float *loss)
+{
+    if (!ctx) return G4_EINVAL;
+    if (!w_bf16 || !feat || !target || !grad || !loss || n < 1) return g4_set_err(ctx, G4_EINVAL, "bad mlp_grad args");
+    if (!(tau < 1.0f)) return g4_set_err(ctx, G4_EINVAL, "tau must be < 1");
+    return g4_launch_mlp_grad(ctx, (const uint16_t *)w_bf16, feat, target, n, tau, grad, loss);
+}
+
+int g4_mlp_adam(g4_ctx *ctx, void *w_bf16, float *w_master, float *m, float *v, const float *grad, float lr,
+                float beta1, float beta2, float eps, int64_t step)
+{
+    if (!ctx) return G4_EINVAL;
+    if (!w_bf16 || !w_master || !m || !v || !grad || step < 1) return g4_set_err(ctx, G4_EINVAL, "bad adam args");
+    return g4_launch_mlp_adam(ctx, (uint16_t *)w_bf16, w_master, m, v, grad, lr, beta1, beta2, eps, step);
+}
+
+int g4_mlp_train_step(g4_ctx *ctx, void *w_bf16, float *w_master, float *adam_state, float *grad, const float *feat,
+                      const float *target, int64_t n, float tau, float lr, int64_t step, float *loss)
+{
+    if (!ctx || !adam_state) return G4_EINVAL;
+    int st = g4_mlp_grad(ctx, w_bf16, feat, target, n, tau, grad, loss);
+    if (st) return st;
+    return g4_mlp_adam(ctx, w_bf16, w_master, adam_state, adam_state + 4801, grad, lr, 0.9f, 0.999f, 1e-8f, step);
 }
 
 }  // extern "C"

@@ -57,6 +57,7 @@ int g4_layout(const g4_tree_params *tp, int64_t n, WsLayout *L)
     L->parts = take((size_t)n * 16);
     L->bfirst = take((size_t)cap * 4);
     L->bcount = take((size_t)cap * 4);
+    L->parent = take((size_t)cap * 4);
     L->wn = take((size_t)cap * sizeof(WNode));
     L->q3 = take((size_t)cap * 10 * 4);
     L->mom = take((size_t)cap * MOM_STRIDE * 8);
@@ -151,7 +152,7 @@ __global__ void k_gather(const uint32_t *__restrict__ X, const uint32_t *__restr
     }
 }
 
-__global__ void k_init(DevCounters *C, uint32_t *bfirst, uint32_t *bcount, uint32_t n)
+__global__ void k_init(DevCounters *C, uint32_t *bfirst, uint32_t *bcount, uint32_t *parent, uint32_t n)
 {
     if (threadIdx.x == 0 && blockIdx.x == 0) {
         C->node_count = 1;
@@ -165,6 +166,7 @@ __global__ void k_init(DevCounters *C, uint32_t *bfirst, uint32_t *bcount, uint3
         for (int s = 0; s < 16; s++) C->stat[s] = 0;
         bfirst[0] = 0;
         bcount[0] = n;
+        parent[0] = 0xffffffffu;
     }
 }
 
@@ -184,7 +186,8 @@ __device__ __forceinline__ uint32_t lower_bound_u64(const uint64_t *__restrict__
 // above the depth cap) gets its non-empty octants as children, found by
 // binary search for the octant digit boundaries in its sorted key range.
 __global__ void k_split(DevCounters *C, const uint64_t *__restrict__ keys, const uint4 *__restrict__ parts,
-                        uint32_t *__restrict__ bfirst, uint32_t *__restrict__ bcount, WNode *__restrict__ wn,
+                        uint32_t *__restrict__ bfirst, uint32_t *__restrict__ bcount, uint32_t *__restrict__ parent,
+                        WNode *__restrict__ wn,
                         int level, int B, int maxd, int S, uint32_t corner, int64_t cap)
 {
     // level l is complete (pass l-1 has finished); level l+1 starts right after it
@@ -232,6 +235,7 @@ __global__ void k_split(DevCounters *C, const uint64_t *__restrict__ keys, const
                     if (bnd[d + 1] > bnd[d]) {
                         bfirst[c] = bnd[d];
                         bcount[c] = bnd[d + 1] - bnd[d];
+                        parent[c] = q;
                         c++;
                     }
                 }
@@ -262,11 +266,11 @@ int g4_launch_build(g4_ctx *ctx, g4_tree *t, const g4_particles *p)
                                           63, s));
     // sorted keys now live in keys1; keep that name for the split kernels
     k_gather<<<grid_for(n), kBlock, 0, s>>>(p->x, p->y, p->z, p->mass, t->perm1, n, t->parts);
-    k_init<<<1, 64, 0, s>>>(t->ctr, t->bfirst, t->bcount, (uint32_t)n);
+    k_init<<<1, 64, 0, s>>>(t->ctr, t->bfirst, t->bcount, t->parent, (uint32_t)n);
     G4_HIP(ctx, hipGetLastError());
     for (int l = 0; l <= maxd; l++) {
         // a fixed grid; the grid-stride loop reads the true range of the level
-        k_split<<<grid_for(n, 1024), kBlock, 0, s>>>(t->ctr, t->keys1, t->parts, t->bfirst, t->bcount, t->wn, l,
+        k_split<<<grid_for(n, 1024), kBlock, 0, s>>>(t->ctr, t->keys1, t->parts, t->bfirst, t->bcount, t->parent, t->wn, l,
                                                       t->tp.leaf_max, maxd, t->S, t->corner, t->cap);
     }
     G4_HIP(ctx, hipGetLastError());

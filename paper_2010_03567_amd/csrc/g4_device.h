@@ -1,0 +1,98 @@
+// g4_device.h -- device functions shared by the HIP kernels: fast hardware
+// reciprocals, an erfc approximation, the spline-softening factors and the
+// softened (short-range) pair kernel.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#define INV_SQRTPI 0.564189583547756287f
+
+__device__ __forceinline__ float rsq(float x) { return __builtin_amdgcn_rsqf(x); }
+__device__ __forceinline__ uint32_t uabs(int32_t d) { return d < 0 ? 0u - (uint32_t)d : (uint32_t)d; }
+__device__ __forceinline__ float rcp(float x) { return __builtin_amdgcn_rcpf(x); }
+__device__ __forceinline__ float expneg(float x2) { return __builtin_amdgcn_exp2f(-1.44269504088896341f * x2); }
+
+// erfc(x) for x >= 0 by Abramowitz & Stegun 7.1.26 (Hastings' rational
+// approximation, |error| <= 1.5e-7): erfc(x) = t P(t) exp(-x^2), t = 1/(1+px).
+// ex = exp(-x^2) is passed in because the kernel needs it anyway.
+__device__ __forceinline__ float erfc_hastings(float x, float ex)
+{
+    float t = rcp(1.0f + 0.3275911f * x);
+    float p = fmaf(t, 1.061405429f, -1.453152027f);
+    p = fmaf(t, p, 1.421413741f);
+    p = fmaf(t, p, -0.284496736f);
+    p = fmaf(t, p, 0.254829592f);
+    return t * p * ex;
+}
+
+// Spline-softened force factor K(u)/h^3 and potential W(u)/h, u = r/h < 1.
+__device__ __forceinline__ float soft_force(float u, float hinv)
+{
+    float h3 = hinv * hinv * hinv, u2 = u * u;
+    if (u < 0.5f) return h3 * (10.666666666666667f + u2 * (-38.4f + 32.0f * u));
+    return h3 * (21.333333333333333f - 48.0f * u + 38.4f * u2 - 10.666666666666667f * u2 * u -
+                 0.066666666666666667f * rcp(u2 * u));
+}
+__device__ __forceinline__ float soft_pot(float u, float hinv)
+{
+    float u2 = u * u;
+    if (u < 0.5f) return hinv * (2.8f + u2 * (-5.333333333333333f + u2 * (9.6f - 6.4f * u)));
+    return hinv * (3.2f - 0.066666666666666667f * rcp(u) +
+                   u2 * (-10.666666666666667f + u * (16.0f + u * (-9.6f + 2.1333333333333333f * u))));
+}
+
+// Long-range pair factors for x = alpha r, needed only inside the softening edge:
+//   lrf(x) = (erf x - 2x e^{-x^2}/sqrt(pi)) / x^3,   erfx(x) = erf(x)/x.
+__device__ __forceinline__ float lr_force_x3(float x)
+{
+    if (x < 0.5f) {
+        float x2 = x * x;
+        float s = 1.0f / 3 + x2 * (-1.0f / 5 + x2 * (1.0f / 14 + x2 * (-1.0f / 54 + x2 * (1.0f / 264 - x2 / 1560))));
+        return 4.0f * INV_SQRTPI * s;
+    }
+    float ex = expneg(x * x);
+    float erfv = 1.0f - erfc_hastings(x, ex);
+    return (erfv - 2.0f * INV_SQRTPI * x * ex) * rcp(x * x * x);
+}
+__device__ __forceinline__ float erf_over_x(float x)
+{
+    if (x < 0.5f) {
+        float x2 = x * x;
+        float s = 1.0f + x2 * (-1.0f / 3 + x2 * (1.0f / 10 + x2 * (-1.0f / 42 + x2 * (1.0f / 216 - x2 / 1320))));
+        return 2.0f * INV_SQRTPI * s;
+    }
+    return (1.0f - erfc_hastings(x, expneg(x * x))) * rcp(x);
+}
+
+// Pair interaction (softened, optionally short-range): returns the force
+// factor K (a += m K d) and the potential factor W (phi -= m W).
+template <int KER, bool POT>
+__device__ __forceinline__ void pair_kernel(float r2, float asplit, float h2, float hinv, float &K, float &W)
+{
+    float rinv = r2 > 0.f ? rsq(r2) : 0.f;
+    float rinv2 = rinv * rinv;
+    if (KER == 0) {
+        K = rinv * rinv2;
+        if (POT) W = rinv;
+    } else {
+        float r = r2 * rinv;
+        float x = asplit * r;
+        float ex = expneg(x * x);
+        float ec = erfc_hastings(x, ex);
+        K = (ec + 2.0f * INV_SQRTPI * x * ex) * rinv * rinv2;
+        if (POT) W = ec * rinv;
+    }
+    if (r2 < h2) {
+        float r = r2 * rinv;
+        float u = r * hinv;
+        K = soft_force(u, hinv);
+        if (POT) W = soft_pot(u, hinv);
+        if (KER == 1) {
+            float x = asplit * r;
+            float a3 = asplit * asplit * asplit;
+            K -= a3 * lr_force_x3(x);
+            if (POT) W -= asplit * erf_over_x(x);
+        }
+    }
+}
+

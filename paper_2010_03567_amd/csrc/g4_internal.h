@@ -60,6 +60,7 @@ struct g4_tree {
     uint32_t *perm0, *perm1;  // perm1[i] = caller index of sorted particle i
     uint4 *parts;             // sorted particles: x, y, z, mass bits
     uint32_t *bfirst, *bcount;
+    uint32_t *parent;         // parent node (0xffffffff for the root)
     WNode *wn;
     float *q3;                // 10 floats per node (potential only)
     double *mom;              // MOM_STRIDE doubles per node
@@ -70,7 +71,8 @@ struct g4_tree {
 
 // Layout of a tree workspace (byte offsets).
 struct WsLayout {
-    size_t ctr, keys0, keys1, perm0, perm1, parts, bfirst, bcount, wn, q3, mom, aseed, sort_tmp, sort_bytes, total;
+    size_t ctr, keys0, keys1, perm0, perm1, parts, bfirst, bcount, parent, wn, q3, mom, aseed, sort_tmp, sort_bytes,
+        total;
     int64_t cap;
 };
 
@@ -106,3 +108,11 @@ int g4_launch_direct(g4_ctx *ctx, const g4_particles *p, const g4_tree_params *t
 int g4_launch_quantize(g4_ctx *ctx, const double *pos, int64_t n, const g4_tree_params *tp, uint32_t *x,
                        uint32_t *y, uint32_t *z, int32_t *flag);
 int g4_launch_gather_seed(g4_ctx *ctx, g4_tree *t, const float *a_seed_caller);
+int g4_launch_mlp_features(g4_ctx *ctx, const g4_tree *t, const g4_walk_params *wp, const float *norm,
+                           float *feat);
+int g4_launch_mlp_forward(g4_ctx *ctx, const uint16_t *w, const float *feat, int64_t n, float *out, float shift,
+                          int mode);
+int g4_launch_mlp_grad(g4_ctx *ctx, const uint16_t *w, const float *feat, const float *target, int64_t n,
+                       float tau, float *grad, float *loss);
+int g4_launch_mlp_adam(g4_ctx *ctx, uint16_t *w, float *master, float *m, float *v, const float *grad, float lr,
+                       float b1, float b2, float eps, int64_t step);

@@ -17,6 +17,7 @@
 // of lanes that open the node (pushed with the children) or use its
 // multipoles.  Interactions are FP32 arithmetic on int32 nearest-image
 // differences; partial sums are flushed into per-lane FP64 accumulators.
+#include "g4_device.h"
 #include "g4_internal.h"
 
 struct WalkArgs {
@@ -41,99 +42,9 @@ struct WalkArgs {
     double *ax, *ay, *az, *pot;
     uint32_t *counts;
     float *aout_caller, *aout_sorted;
-    unsigned long long *stat;  // 3 counters: p2p, p2m, visits
+    unsigned long long *stat;   // 3 counters: p2p, p2m, visits
+    unsigned long long *wstat;  // 3 counters: node pops, P2M passes, P2P source iterations (per wavefront)
 };
-
-#define INV_SQRTPI 0.564189583547756287f
-
-__device__ __forceinline__ float rsq(float x) { return __builtin_amdgcn_rsqf(x); }
-__device__ __forceinline__ uint32_t uabs(int32_t d) { return d < 0 ? 0u - (uint32_t)d : (uint32_t)d; }
-__device__ __forceinline__ float rcp(float x) { return __builtin_amdgcn_rcpf(x); }
-__device__ __forceinline__ float expneg(float x2) { return __builtin_amdgcn_exp2f(-1.44269504088896341f * x2); }
-
-// erfc(x) for x >= 0 by Abramowitz & Stegun 7.1.26 (Hastings' rational
-// approximation, |error| <= 1.5e-7): erfc(x) = t P(t) exp(-x^2), t = 1/(1+px).
-// ex = exp(-x^2) is passed in because the kernel needs it anyway.
-__device__ __forceinline__ float erfc_hastings(float x, float ex)
-{
-    float t = rcp(1.0f + 0.3275911f * x);
-    float p = fmaf(t, 1.061405429f, -1.453152027f);
-    p = fmaf(t, p, 1.421413741f);
-    p = fmaf(t, p, -0.284496736f);
-    p = fmaf(t, p, 0.254829592f);
-    return t * p * ex;
-}
-
-// Spline-softened force factor K(u)/h^3 and potential W(u)/h, u = r/h < 1.
-__device__ __forceinline__ float soft_force(float u, float hinv)
-{
-    float h3 = hinv * hinv * hinv, u2 = u * u;
-    if (u < 0.5f) return h3 * (10.666666666666667f + u2 * (-38.4f + 32.0f * u));
-    return h3 * (21.333333333333333f - 48.0f * u + 38.4f * u2 - 10.666666666666667f * u2 * u -
-                 0.066666666666666667f * rcp(u2 * u));
-}
-__device__ __forceinline__ float soft_pot(float u, float hinv)
-{
-    float u2 = u * u;
-    if (u < 0.5f) return hinv * (2.8f + u2 * (-5.333333333333333f + u2 * (9.6f - 6.4f * u)));
-    return hinv * (3.2f - 0.066666666666666667f * rcp(u) +
-                   u2 * (-10.666666666666667f + u * (16.0f + u * (-9.6f + 2.1333333333333333f * u))));
-}
-
-// Long-range pair factors for x = alpha r, needed only inside the softening edge:
-//   lrf(x) = (erf x - 2x e^{-x^2}/sqrt(pi)) / x^3,   erfx(x) = erf(x)/x.
-__device__ __forceinline__ float lr_force_x3(float x)
-{
-    if (x < 0.5f) {
-        float x2 = x * x;
-        float s = 1.0f / 3 + x2 * (-1.0f / 5 + x2 * (1.0f / 14 + x2 * (-1.0f / 54 + x2 * (1.0f / 264 - x2 / 1560))));
-        return 4.0f * INV_SQRTPI * s;
-    }
-    float ex = expneg(x * x);
-    float erfv = 1.0f - erfc_hastings(x, ex);
-    return (erfv - 2.0f * INV_SQRTPI * x * ex) * rcp(x * x * x);
-}
-__device__ __forceinline__ float erf_over_x(float x)
-{
-    if (x < 0.5f) {
-        float x2 = x * x;
-        float s = 1.0f + x2 * (-1.0f / 3 + x2 * (1.0f / 10 + x2 * (-1.0f / 42 + x2 * (1.0f / 216 - x2 / 1320))));
-        return 2.0f * INV_SQRTPI * s;
-    }
-    return (1.0f - erfc_hastings(x, expneg(x * x))) * rcp(x);
-}
-
-// Pair interaction: returns the force factor K (a += m K d) and the potential
-// factor W (phi -= m W).
-template <int KER, bool POT>
-__device__ __forceinline__ void pair_kernel(float r2, const WalkArgs &A, float &K, float &W)
-{
-    float rinv = r2 > 0.f ? rsq(r2) : 0.f;
-    float rinv2 = rinv * rinv;
-    if (KER == 0) {
-        K = rinv * rinv2;
-        if (POT) W = rinv;
-    } else {
-        float r = r2 * rinv;
-        float x = A.asplit * r;
-        float ex = expneg(x * x);
-        float ec = erfc_hastings(x, ex);
-        K = (ec + 2.0f * INV_SQRTPI * x * ex) * rinv * rinv2;
-        if (POT) W = ec * rinv;
-    }
-    if (r2 < A.h2) {
-        float r = r2 * rinv;
-        float u = r * A.hinv;
-        K = soft_force(u, A.hinv);
-        if (POT) W = soft_pot(u, A.hinv);
-        if (KER == 1) {
-            float x = A.asplit * r;
-            float a3 = A.asplit * A.asplit * A.asplit;
-            K -= a3 * lr_force_x3(x);
-            if (POT) W -= A.asplit * erf_over_x(x);
-        }
-    }
-}
 
 // g1, g2, g3 (and g0) of the interaction kernel at r (r2, rinv given), r >= h.
 template <int KER>
@@ -178,6 +89,7 @@ __global__ __launch_bounds__(256) void k_walk(const WalkArgs A)
     double dax = 0.0, day = 0.0, daz = 0.0, dpot = 0.0;
     float fx = 0.f, fy = 0.f, fz = 0.f, fp = 0.f;
     uint32_t n_pp = 0, n_pm = 0, n_visit = 0;
+    uint32_t w_pop = 0, w_pm = 0, w_pp = 0;  // wavefront-level work (uniform counters)
     int pending = 0;
 
     const uint64_t amask = __ballot(act);
@@ -198,6 +110,7 @@ __global__ __launch_bounds__(256) void k_walk(const WalkArgs A)
             sp--;
         }
         const WNode nd = A.wn[node];
+        w_pop++;
         const int level = (int)(nd.meta & 0xffu);
         const bool leaf = (nd.meta & WN_LEAF) != 0;
         bool mine = (mask >> lane) & 1ull;
@@ -237,6 +150,7 @@ __global__ __launch_bounds__(256) void k_walk(const WalkArgs A)
         const bool use = mine && accept;
         const uint64_t openm = __ballot(mine && !accept);
         if (__ballot(use)) {
+            w_pm++;
             if (use) {
                 float g0, g1, g2, g3;
                 gfun<KER>(r2, rinv, A, g0, g1, g2, g3);
@@ -286,6 +200,7 @@ __global__ __launch_bounds__(256) void k_walk(const WalkArgs A)
         }
         if (openm) {
             if (leaf) {
+                w_pp += nd.num;
                 const bool op = (openm >> lane) & 1ull;
                 for (uint32_t j = nd.next; j < nd.next + nd.num; j++) {
                     const uint4 src = A.parts[j];
@@ -295,7 +210,7 @@ __global__ __launch_bounds__(256) void k_walk(const WalkArgs A)
                     const float sz = (float)(int32_t)(src.z - me.z) * A.unit;
                     const float s2 = fmaf(sx, sx, fmaf(sy, sy, sz * sz));
                     float K, W;
-                    pair_kernel<KER, POT>(s2, A, K, W);
+                    pair_kernel<KER, POT>(s2, A.asplit, A.h2, A.hinv, K, W);
                     const float mk = mj * K;
                     fx = fmaf(mk, sx, fx);
                     fy = fmaf(mk, sy, fy);
@@ -344,6 +259,12 @@ __global__ __launch_bounds__(256) void k_walk(const WalkArgs A)
             atomicAdd(&A.stat[0], s0);
             atomicAdd(&A.stat[1], s1);
             atomicAdd(&A.stat[2], s2);
+            // wavefront-level iterations (slots 9..11 of the counter block, walk call only)
+            if (A.wstat) {
+                atomicAdd(&A.wstat[0], (unsigned long long)w_pop);
+                atomicAdd(&A.wstat[1], (unsigned long long)w_pm);
+                atomicAdd(&A.wstat[2], (unsigned long long)w_pp);
+            }
         }
     }
 }
@@ -391,6 +312,7 @@ int g4_launch_walk(g4_ctx *ctx, g4_tree *t, const g4_walk_params *wp, int kernel
     A.aout_caller = aout_caller;
     A.aout_sorted = aout_sorted;
     A.stat = t->ctr->stat + stat_slot;
+    A.wstat = stat_slot == 0 ? t->ctr->stat + 9 : nullptr;
     hipStream_t s = ctx->stream;
     const bool P = pot != nullptr;
     if (kernel == 0) {

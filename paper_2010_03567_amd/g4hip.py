@@ -51,7 +51,8 @@ class g4_stats(C.Structure):
     _fields_ = [("n_p2p", C.c_uint64), ("n_p2m", C.c_uint64), ("n_visit", C.c_uint64),
                 ("n_seed_p2p", C.c_uint64), ("n_seed_p2m", C.c_uint64), ("n_seed_visit", C.c_uint64),
                 ("n_pp", C.c_uint64), ("n_pn", C.c_uint64), ("n_nn", C.c_uint64),
-                ("n_nodes", C.c_uint64), ("flags", C.c_uint32)]
+                ("n_nodes", C.c_uint64), ("w_pop", C.c_uint64), ("w_p2m", C.c_uint64), ("w_p2p", C.c_uint64),
+                ("flags", C.c_uint32)]
 
     def as_dict(self):
         return {k: int(getattr(self, k)) for k, _ in self._fields_}
@@ -72,6 +73,11 @@ _SIGS = {
     "g4_treepm_shortrange": [_p, _p, C.POINTER(g4_walk_params), _p, _p, _p, _p, _p, _p, C.POINTER(g4_stats)],
     "g4_direct_force": [_p, C.POINTER(g4_particles), C.POINTER(g4_tree_params), C.POINTER(g4_walk_params), _i32,
                         _p, _i64, _p, _p, _p, _p],
+    "g4_mlp_features": [_p, _p, C.POINTER(g4_walk_params), _p, _p],
+    "g4_mlp_forward": [_p, _p, _p, _i64, _p, C.c_float, _i32],
+    "g4_mlp_grad": [_p, _p, _p, _p, _i64, C.c_float, _p, _p],
+    "g4_mlp_adam": [_p, _p, _p, _p, _p, _p, C.c_float, C.c_float, C.c_float, C.c_float, _i64],
+    "g4_mlp_train_step": [_p, _p, _p, _p, _p, _p, _p, _i64, C.c_float, C.c_float, _i64, _p],
 }
 for _name, _args in _SIGS.items():
     f = getattr(_L, _name)
@@ -268,3 +274,39 @@ def g4_direct_force(ctx, p, tp, wp, targets=None, truncate=False, want_pot=True)
     ctx.check(_L.g4_direct_force(ctx.h, C.byref(p), C.byref(tp), C.byref(wp), int(truncate), _ptr(targets), int(nt),
                                  _ptr(ax), _ptr(ay), _ptr(az), _ptr(pot)))
     return dict(ax=ax, ay=ay, az=az, pot=pot)
+
+
+# ------------------------------------------------------------------ learned seed
+MLP_NPARAM = 4801
+
+
+def g4_mlp_features(ctx, tree, wp, norm=None, out=None):
+    feat = out if out is not None else torch.empty((tree.n, 8), dtype=torch.float32, device=ctx.device)
+    ctx.check(_L.g4_mlp_features(ctx.h, tree.h, C.byref(wp), _ptr(norm), _ptr(feat)))
+    return feat
+
+
+def g4_mlp_forward(ctx, w_bf16, feat, shift=0.0, mode=0, out=None):
+    n = feat.shape[0]
+    if out is None:
+        out = torch.empty(n, dtype=torch.float32, device=ctx.device)
+    ctx.check(_L.g4_mlp_forward(ctx.h, _ptr(w_bf16), _ptr(feat), n, _ptr(out), float(shift), int(mode)))
+    return out
+
+
+def g4_mlp_grad(ctx, w_bf16, feat, target, tau=0.0):
+    grad = torch.empty(MLP_NPARAM, dtype=torch.float32, device=ctx.device)
+    loss = torch.empty(1, dtype=torch.float32, device=ctx.device)
+    ctx.check(_L.g4_mlp_grad(ctx.h, _ptr(w_bf16), _ptr(feat), _ptr(target), feat.shape[0], float(tau), _ptr(grad),
+                             _ptr(loss)))
+    return grad, loss
+
+
+def g4_mlp_adam(ctx, w_bf16, master, m, v, grad, lr, step, beta1=0.9, beta2=0.999, eps=1e-8):
+    ctx.check(_L.g4_mlp_adam(ctx.h, _ptr(w_bf16), _ptr(master), _ptr(m), _ptr(v), _ptr(grad), float(lr),
+                             float(beta1), float(beta2), float(eps), int(step)))
+
+
+def g4_mlp_train_step(ctx, w_bf16, master, adam_state, grad, feat, target, lr, step, loss, tau=0.0):
+    ctx.check(_L.g4_mlp_train_step(ctx.h, _ptr(w_bf16), _ptr(master), _ptr(adam_state), _ptr(grad), _ptr(feat),
+                                   _ptr(target), feat.shape[0], float(tau), float(lr), int(step), _ptr(loss)))

@@ -1,0 +1,139 @@
+"""Train the learned |a| seed on accelerations the solver itself computes.
+
+For each training snapshot (a clustered periodic box drawn with its own seed)
+the library builds the tree, runs the plain relative walk (geometric pre-walk
+seed) and keeps log10 |a| of every particle as the target, plus the raw leaf
+features.  The network is then trained full-batch, one snapshot per Adam step,
+with the library's own gradient and Adam kernels (BF16 weights, FP32 master
+copy).  The result is saved as an .npz (bf16 bits, feature standardisation,
+seed shift, metadata).
+
+    python -m paper_2010_03567_amd.train_seed --n 2097152 --out paper_2010_03567_amd/weights/seed_mlp_2097152.npz
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+import torch
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+ROOT = os.path.dirname(HERE)
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+import workloads  # noqa: E402
+import paper_2010_03567_amd.g4hip as g  # noqa: E402
+
+
+def treepm_params(n):
+    """Split scale, softening of the clustered-box workload at n particles."""
+    scale = (128 ** 3 / n) ** (1.0 / 3.0)
+    return 1.25 / 256 * scale, scale / (40 * 128)
+
+
+def snapshot(ctx, n, seed, rcut_f, alpha, B=8):
+    """(raw features n x 8, log10 |a| target n) of one clustered box on the device."""
+    r_s, eps0 = treepm_params(n)
+    ps = workloads.clustered_box(n, seed=seed)
+    dev = ctx.device
+    tp = g.tree_params(True, ps.box, leaf_max=B)
+    x, y, z = g.g4_quantize(ctx, torch.from_numpy(ps.pos).to(dev), tp)
+    p = g.particles(x, y, z, torch.from_numpy(ps.mass.astype(np.float32)).to(dev))
+    tree = g.g4_build_tree(ctx, p, tp)
+    g.g4_compute_multipoles(ctx, tree, 3)
+    wp = g.walk_params(kernel=1, criterion=1, alpha=alpha, theta_seed=0.7, r_s=r_s, r_cut=rcut_f * r_s, eps0=eps0)
+    out = g.g4_treepm_shortrange(ctx, tree, wp, want_amag=True)
+    feat = g.g4_mlp_features(ctx, tree, wp)
+    target = torch.log10(out["amag"].clamp_min(1e-30))
+    del tree
+    return feat, target
+
+
+def train(n, seeds, rcut_f, alpha, steps, lr, tau=0.0, log=print):
+    ctx = g.Context()
+    t0 = time.time()
+    feats, targets = [], []
+    for s in seeds:
+        f, t = snapshot(ctx, n, s, rcut_f, alpha)
+        feats.append(f)
+        targets.append(t)
+        log(f"[train] snapshot seed {s} ready ({time.time() - t0:.1f} s)")
+    allf = torch.cat(feats)
+    mu = allf.mean(0)
+    sd = allf.std(0).clamp_min(1e-6)
+    norm = torch.cat([mu, 1.0 / sd]).float().contiguous()
+    feats = [((f - mu) / sd).float().contiguous() for f in feats]
+    del allf
+    rng = np.random.default_rng(0)
+    w0 = rng.normal(size=g.MLP_NPARAM).astype(np.float32)
+    # fan-in scaled initialisation: W1 ~ 1/sqrt(8), W2 ~ 1/sqrt(64), w3 ~ 1/sqrt(64); biases 0,
+    # output bias at the mean target
+    w0[:512] *= 1 / math.sqrt(8)
+    w0[512:576] = 0
+    w0[576:4672] *= 1 / math.sqrt(64)
+    w0[4672:4736] = 0
+    w0[4736:4800] *= 1 / math.sqrt(64)
+    w0[4800] = float(torch.cat(targets).mean())
+    master = torch.from_numpy(w0).to(ctx.device)
+    w = master.to(torch.bfloat16).contiguous()
+    state = torch.zeros(2 * g.MLP_NPARAM, dtype=torch.float32, device=ctx.device)
+    grad = torch.empty(g.MLP_NPARAM, dtype=torch.float32, device=ctx.device)
+    loss = torch.empty(1, dtype=torch.float32, device=ctx.device)
+    hist = []
+    for step in range(1, steps + 1):
+        k = (step - 1) % len(feats)
+        lr_t = lr * 0.5 * (1 + math.cos(math.pi * (step - 1) / steps))
+        g.g4_mlp_train_step(ctx, w, master, state, grad, feats[k], targets[k], lr_t, step, loss, tau=tau)
+        if step % 100 == 0 or step == 1:
+            hist.append((step, float(loss.item())))
+            log(f"[train] step {step} loss {hist[-1][1]:.4e}")
+    # residuals on the training set: the seed shift makes the predicted |a| a
+    # low quantile of the truth, so the relative criterion stays conservative
+    res = []
+    for f, t in zip(feats, targets):
+        y = g.g4_mlp_forward(ctx, w, f)
+        res.append((y - t).cpu().numpy())
+    res = np.concatenate(res)
+    return dict(w=w, norm=norm, residual_quantiles={q: float(np.percentile(res, q)) for q in (1, 10, 50, 90, 99)},
+                residual_rms=float(np.sqrt(np.mean(res ** 2))), history=hist)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--n", type=int, default=128 ** 3)
+    ap.add_argument("--seeds", type=str, default="1001-1020")
+    ap.add_argument("--rcut", type=float, default=7.0)
+    ap.add_argument("--alpha", type=float, default=0.001)
+    ap.add_argument("--steps", type=int, default=1000)
+    ap.add_argument("--lr", type=float, default=3e-3)
+    ap.add_argument("--tau", type=float, default=0.0, help="pinball-loss quantile (0: mean squared error)")
+    ap.add_argument("--out", type=str, required=True)
+    a = ap.parse_args()
+    lo, hi = (int(v) for v in a.seeds.split("-"))
+    r = train(a.n, list(range(lo, hi + 1)), a.rcut, a.alpha, a.steps, a.lr, a.tau,
+              log=lambda m: print(m, file=sys.stderr, flush=True))
+    os.makedirs(os.path.dirname(os.path.abspath(a.out)), exist_ok=True)
+    meta = dict(n=a.n, seeds=a.seeds, rcut=a.rcut, alpha=a.alpha, steps=a.steps, lr=a.lr, tau=a.tau,
+                residual_quantiles=r["residual_quantiles"], residual_rms=r["residual_rms"], history=r["history"])
+    np.savez(a.out, w_bf16=r["w"].view(torch.int16).cpu().numpy().view(np.uint16), norm=r["norm"].cpu().numpy(),
+             meta=np.frombuffer(json.dumps(meta).encode(), dtype=np.uint8))
+    print(json.dumps(meta))
+
+
+def load(path, device):
+    """(bf16 weights, norm, meta) from a file written by main()."""
+    d = np.load(path, allow_pickle=False)
+    w = torch.from_numpy(d["w_bf16"].view(np.int16).copy()).view(torch.bfloat16).to(device)
+    norm = torch.from_numpy(d["norm"].astype(np.float32)).to(device)
+    meta = json.loads(bytes(d["meta"]).decode())
+    return w, norm, meta
+
+
+if __name__ == "__main__":
+    main()

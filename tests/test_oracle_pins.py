@@ -518,18 +518,21 @@ def test_tree_is_not_momentum_conserving():
 
 
 # ---------------------------------------------------------------- MLP
-def test_mlp_gradient_finite_differences():
+@pytest.mark.parametrize("tau", [0.0, 0.3])
+def test_mlp_gradient_finite_differences(tau):
     rng = np.random.default_rng(5)
     w = rng.normal(scale=0.3, size=oracle.NPARAM)
     feat = rng.normal(size=(7, 8))
     target = rng.normal(size=7)
-    loss, g = oracle.mlp_loss_grad(w, feat, target)
+    loss, g = oracle.mlp_loss_grad(w, feat, target, tau)
     y = oracle.mlp_forward(w, feat)
-    assert loss == pytest.approx(np.mean((y - target) ** 2), rel=1e-13)
+    u = target - y
+    ref = np.mean((y - target) ** 2) if tau == 0 else np.mean(np.where(u >= 0, tau * u, (tau - 1) * u))
+    assert loss == pytest.approx(ref, rel=1e-13)
     for i in list(range(0, 512, 37)) + list(range(512, 4801, 211)) + [4800, 4736, 4672]:
         e = np.zeros(oracle.NPARAM); e[i] = 1e-6
-        lp, _ = oracle.mlp_loss_grad(w + e, feat, target)
-        lm, _ = oracle.mlp_loss_grad(w - e, feat, target)
+        lp, _ = oracle.mlp_loss_grad(w + e, feat, target, tau)
+        lm, _ = oracle.mlp_loss_grad(w - e, feat, target, tau)
         assert g[i] == pytest.approx((lp - lm) / 2e-6, rel=1e-5, abs=1e-9)
 
 
