@@ -227,6 +227,23 @@ int g4_mlp_train_step(g4_ctx *ctx, void *w_bf16, float *w_master, float *adam_st
                       const float *feat, const float *target, int64_t n, float tau, float lr, int64_t step,
                       float *loss);
 
+/* ------------------------------------------------------------------ FMM */
+/* Workspace for g4_fmm_force on this tree: pair frontier and interaction
+ * lists sized list_factor x (48, 96, 160) x n entries, field expansions (20
+ * floats per node), sort scratch.  list_factor <= 0 means 1. */
+int g4_fmm_workspace_bytes(const g4_tree *tree, double list_factor, size_t *bytes);
+
+/* Symmetric FMM at p = 3 (Sec. "Fast multipole method"): dual walk from
+ * (root, root), field expansions in both nodes of every accepted pair,
+ * particle-node and particle-particle interactions, downward shift and
+ * evaluation at the particles.  Needs g4_compute_multipoles(order 3).
+ * ax, ay, az (pot nullable): device n float64, caller order.  Synchronises
+ * (list sizes are read back); returns G4_ENOMEM when the lists exceed the
+ * workspace of list_factor (retry with a larger factor).  Sums are ordered
+ * by target, so results do not depend on the order of list construction. */
+int g4_fmm_force(g4_ctx *ctx, g4_tree *tree, const g4_fmm_params *fp, double list_factor, void *ws, size_t ws_bytes,
+                 double *ax, double *ay, double *az, double *pot, g4_stats *stats);
+
 #ifdef __cplusplus
 }
 #endif

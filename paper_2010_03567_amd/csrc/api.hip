@@ -235,6 +235,27 @@ int g4_direct_force(g4_ctx *ctx, const g4_particles *p, const g4_tree_params *tp
     return g4_launch_direct(ctx, p, tp, wp, truncate, targets, ntargets, ax, ay, az, pot);
 }
 
+int g4_fmm_workspace_bytes(const g4_tree *tree, double list_factor, size_t *bytes)
+{
+    if (!tree || !bytes) return G4_EINVAL;
+    return g4_fmm_layout_bytes(tree, list_factor, bytes);
+}
+
+int g4_fmm_force(g4_ctx *ctx, g4_tree *tree, const g4_fmm_params *fp, double list_factor, void *ws, size_t ws_bytes,
+                 double *ax, double *ay, double *az, double *pot, g4_stats *stats)
+{
+    if (!ctx || !tree || !fp || !ws) return G4_EINVAL;
+    if (!ax || !ay || !az) return g4_set_err(ctx, G4_EINVAL, "null output");
+    if (tree->moments_order < 3) return g4_set_err(ctx, G4_ESTATE, "FMM needs moments to order 3");
+    if (fp->kernel != 0 && fp->kernel != 1) return g4_set_err(ctx, G4_EINVAL, "kernel must be 0 or 1");
+    if (fp->kernel == 1 && (!(fp->r_s > 0) || !(fp->r_cut > 0)))
+        return g4_set_err(ctx, G4_EINVAL, "r_s and r_cut must be positive");
+    if (fp->kernel == 1 && !tree->tp.periodic) return g4_set_err(ctx, G4_EINVAL, "short-range kernel needs a periodic box");
+    if (!(fp->theta > 0) || fp->eps0 < 0) return g4_set_err(ctx, G4_EINVAL, "bad theta or eps0");
+    if (((uintptr_t)ws & 255) != 0) return g4_set_err(ctx, G4_EINVAL, "workspace must be 256-byte aligned");
+    return g4_launch_fmm(ctx, tree, fp, list_factor, ws, ws_bytes, ax, ay, az, pot, stats);
+}
+
 int g4_mlp_features(g4_ctx *ctx, const g4_tree *tree, const g4_walk_params *wp, const float *norm, float *feat)
 {
     if (!ctx || !tree || !feat || !wp) return G4_EINVAL;

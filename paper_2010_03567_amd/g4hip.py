@@ -74,6 +74,8 @@ _SIGS = {
     "g4_direct_force": [_p, C.POINTER(g4_particles), C.POINTER(g4_tree_params), C.POINTER(g4_walk_params), _i32,
                         _p, _i64, _p, _p, _p, _p],
     "g4_mlp_features": [_p, _p, C.POINTER(g4_walk_params), _p, _p],
+    "g4_fmm_workspace_bytes": [_p, C.c_double, C.POINTER(_sz)],
+    "g4_fmm_force": [_p, _p, C.POINTER(g4_fmm_params), C.c_double, _p, _sz, _p, _p, _p, _p, C.POINTER(g4_stats)],
     "g4_mlp_forward": [_p, _p, _p, _i64, _p, C.c_float, _i32],
     "g4_mlp_grad": [_p, _p, _p, _p, _i64, C.c_float, _p, _p],
     "g4_mlp_adam": [_p, _p, _p, _p, _p, _p, C.c_float, C.c_float, C.c_float, C.c_float, _i64],
@@ -310,3 +312,41 @@ def g4_mlp_adam(ctx, w_bf16, master, m, v, grad, lr, step, beta1=0.9, beta2=0.99
 def g4_mlp_train_step(ctx, w_bf16, master, adam_state, grad, feat, target, lr, step, loss, tau=0.0):
     ctx.check(_L.g4_mlp_train_step(ctx.h, _ptr(w_bf16), _ptr(master), _ptr(adam_state), _ptr(grad), _ptr(feat),
                                    _ptr(target), feat.shape[0], float(tau), float(lr), int(step), _ptr(loss)))
+
+
+# ------------------------------------------------------------------ FMM
+def fmm_params(kernel=0, G=1.0, eps0=0.0, r_s=1.0, r_cut=1e30, theta=0.5):
+    fp = g4_fmm_params()
+    fp.kernel, fp.G, fp.eps0, fp.r_s, fp.r_cut, fp.theta = int(kernel), float(G), float(eps0), float(r_s), float(r_cut), float(theta)
+    return fp
+
+
+def g4_fmm_workspace_bytes(tree, list_factor=1.0):
+    b = C.c_size_t()
+    code = _L.g4_fmm_workspace_bytes(tree.h, float(list_factor), C.byref(b))
+    if code != G4_OK:
+        raise G4Error(code, "fmm workspace size query failed")
+    return int(b.value)
+
+
+def g4_fmm_force(ctx, tree, fp, list_factor=1.0, ws=None, want_pot=False, want_stats=False, out=None, retries=4):
+    """FMM forces; on G4_ENOMEM (interaction lists larger than the workspace)
+    the list factor grows 4x and the call is repeated."""
+    ax, ay, az, pot, _, _ = out if out is not None else _force_outputs(tree.n, ctx.device, want_pot, False, False)
+    st = g4_stats() if want_stats else None
+    for attempt in range(retries + 1):
+        nbytes = g4_fmm_workspace_bytes(tree, list_factor)
+        if ws is None or ws.numel() < nbytes + 256:
+            ws = torch.empty(nbytes + 256, dtype=torch.uint8, device=ctx.device)
+        off = (-ws.data_ptr()) % 256
+        wsv = ws[off:]
+        code = _L.g4_fmm_force(ctx.h, tree.h, C.byref(fp), float(list_factor), C.c_void_p(wsv.data_ptr()),
+                               wsv.numel(), _ptr(ax), _ptr(ay), _ptr(az), _ptr(pot),
+                               C.byref(st) if st is not None else None)
+        if code == G4_ENOMEM and attempt < retries:
+            list_factor *= 4.0
+            continue
+        ctx.check(code)
+        break
+    return dict(ax=ax, ay=ay, az=az, pot=pot, stats=st.as_dict() if st is not None else None, ws=ws,
+                list_factor=list_factor)

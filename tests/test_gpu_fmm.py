@@ -1,0 +1,130 @@
+"""Parity of the GPU FMM (p = 3) with the FP64 oracle's dual-tree FMM, momentum
+conservation, and the theta -> 0 limit (every interaction exact)."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import workloads
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def g():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2010_03567_amd.g4hip as g
+    return g
+
+
+@pytest.fixture(scope="module")
+def ctx(g):
+    return g.Context()
+
+
+def build(g, ctx, ps, periodic, B=16):
+    if periodic:
+        org, box = (0.0, 0.0, 0.0), ps.box
+    else:
+        org, box = workloads.isolated_root(ps.pos)
+    tp = g.tree_params(periodic, box, org, leaf_max=B)
+    x, y, z = g.g4_quantize(ctx, torch.from_numpy(ps.pos).cuda(), tp)
+    m32 = ps.mass.astype(np.float32)
+    p = g.particles(x, y, z, torch.from_numpy(m32).cuda())
+    tree = g.g4_build_tree(ctx, p, tp)
+    g.g4_compute_multipoles(ctx, tree, 3)
+    st, X, Y, Z = oracle.quantize(ps.pos, periodic, box, org)
+    ot = oracle.Tree(X, Y, Z, m32.astype(np.float64), periodic, box, B)
+    return tree, ot, p, tp, m32
+
+
+def st3(o):
+    return np.stack([o["ax"].cpu().numpy(), o["ay"].cpu().numpy(), o["az"].cpu().numpy()], 1)
+
+
+def sr(n):
+    scale = (128 ** 3 / n) ** (1.0 / 3.0)
+    rs = 1.25 / 256 * scale
+    return dict(r_s=rs, r_cut=4.5 * rs, eps0=scale / (40 * 128))
+
+
+def check(a, ref, label, med=1e-5, p999=1e-3):
+    e = workloads.relative_errors(a, ref)
+    msg = f"{label}: median {np.median(e):.2e} p99.9 {np.percentile(e, 99.9):.2e} max {e.max():.2e}"
+    print(msg)
+    assert np.median(e) <= med and np.percentile(e, 99.9) <= p999, msg
+
+
+@pytest.mark.parametrize("kind,n", [("plummer", 3000), ("box", 30001), ("box", 131072)])
+def test_fmm_parity(g, ctx, kind, n):
+    if kind == "plummer":
+        ps = workloads.plummer(n, seed=51)
+        kw = dict(kernel=0, eps0=0.01)
+    else:
+        ps = workloads.clustered_box(n, seed=52, nhalo=max(10, n // 500))
+        kw = dict(kernel=1, **sr(n))
+    tree, ot, p, tp, m32 = build(g, ctx, ps, kind == "box")
+    out = g.g4_fmm_force(ctx, tree, g.fmm_params(theta=0.5, **kw), want_pot=True, want_stats=True)
+    acc, pot, stt = ot.fmm(theta=0.5, **kw)
+    check(st3(out), acc, f"fmm {kind} {n}")
+    perr = np.abs(out["pot"].cpu().numpy() - pot) / np.abs(pot)
+    assert np.median(perr) < 1e-5
+    s = out["stats"]
+    for k, v in zip(("n_pp", "n_pn", "n_nn"), stt):
+        assert abs(s[k] - int(v)) <= 1e-3 * max(1, int(v)), (k, s[k], int(v))
+
+
+@pytest.mark.parametrize("kind", ["plummer", "box"])
+def test_fmm_momentum_conservation(g, ctx, kind):
+    """Sec. "Fast multipole method": the symmetric expansion conserves momentum;
+    on the GPU the net force is FP32 round-off of the total force magnitude."""
+    if kind == "plummer":
+        ps = workloads.plummer(20000, seed=53)
+        kw = dict(kernel=0, eps0=0.01)
+    else:
+        ps = workloads.clustered_box(100000, seed=54, nhalo=200)
+        kw = dict(kernel=1, **sr(100000))
+    tree, ot, p, tp, m32 = build(g, ctx, ps, kind == "box")
+    a = st3(g.g4_fmm_force(ctx, tree, g.fmm_params(theta=0.5, **kw)))
+    net = np.abs((m32[:, None].astype(np.float64) * a).sum(0)).max()
+    tot = (m32[:, None] * np.abs(a)).sum()
+    assert net <= 1e-6 * tot, (net, tot)
+    # the one-sided walk on the same tree is far from momentum conserving
+    wp = g.walk_params(kernel=kw["kernel"], criterion=0, theta=0.7, eps0=kw["eps0"], r_s=kw.get("r_s", 1.0),
+                       r_cut=kw.get("r_cut", 1e30))
+    aw = st3(g.g4_tree_force(ctx, tree, wp))
+    assert np.abs((m32[:, None] * aw).sum(0)).max() > 10 * net
+
+
+def test_fmm_theta_to_zero_is_direct_sum(g, ctx):
+    ps = workloads.clustered_box(4000, seed=55, nhalo=10)
+    kw = sr(4000)
+    kw["r_cut"] = 1e30
+    tree, ot, p, tp, m32 = build(g, ctx, ps, True)
+    out = g.g4_fmm_force(ctx, tree, g.fmm_params(kernel=1, theta=1e-6, **kw), want_stats=True)
+    assert out["stats"]["n_pn"] == 0 and out["stats"]["n_nn"] == 0
+    assert out["stats"]["n_pp"] == 4000 * 3999 // 2
+    ref = g.g4_direct_force(ctx, p, tp, g.walk_params(kernel=1, **kw))
+    check(st3(out), st3(ref), "fmm theta->0")
+
+
+@pytest.mark.slow
+def test_fmm_full_size(g, ctx):
+    """The clustered 128^3 box at full size: net force at round-off, and errors
+    against FP64 direct summation on a 10^4 sample at the level the oracle's FMM
+    shows at smaller N (dominated by the r_cut truncation)."""
+    n = 128 ** 3
+    ps = workloads.clustered_box(n, seed=3)
+    kw = sr(n)
+    tree, ot, p, tp, m32 = build(g, ctx, ps, True)
+    out = g.g4_fmm_force(ctx, tree, g.fmm_params(kernel=1, theta=0.5, **kw), want_stats=True)
+    a = st3(out)
+    net = np.abs((m32[:, None].astype(np.float64) * a).sum(0)).max()
+    assert net <= 1e-6 * (m32[:, None] * np.abs(a)).sum()
+    tg = workloads.sample_indices(n, 10000, seed=7)
+    ref = st3(g.g4_direct_force(ctx, p, tp, g.walk_params(kernel=1, r_s=kw["r_s"], eps0=kw["eps0"]),
+                                targets=torch.from_numpy(tg).cuda(), want_pot=False))
+    e = workloads.relative_errors(a[tg], ref)
+    print("fmm 128^3 vs direct:", workloads.percentiles(e), out["stats"])
+    assert np.median(e) < 2e-3 and np.percentile(e, 90) < 2e-2
