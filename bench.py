@@ -49,6 +49,8 @@ def parse():
     ap.add_argument("--no-as-stated", action="store_true")
     ap.add_argument("--no-learned", action="store_true")
     ap.add_argument("--weights", type=str, default="", help="learned-seed weights (.npz); default by particle count")
+    ap.add_argument("--no-fmm", action="store_true")
+    ap.add_argument("--no-forest", action="store_true")
     ap.add_argument("--cpu-sample", type=int, default=20000)
     ap.add_argument("--err-sample", type=int, default=10000)
     ap.add_argument("--group", type=int, default=64)
@@ -219,9 +221,88 @@ def main():
         result["as_stated_rcut4.5_alpha0.005"] = {"forces_per_s": n / (ms45 * 1e-3), "ms_per_step": ms45,
                                                   "prewalk_ms": s45, "walk_ms": w45, "errors_vs_direct": e45}
         log(f"[bench] as stated: {ms45:.3f} ms/step, errors {e45}")
+    if not args.no_fmm:
+        result["fmm"] = bench_fmm(args, g, ctx, n)
+    if not args.no_forest:
+        result["forest"] = bench_forest(args, g, ctx)
     if not args.no_cpu_baseline:
         result["cpu_baseline"] = cpu_baseline(ps, n, B, r_s, args.rcut * r_s, eps0, alpha, args)
     print(json.dumps(result), flush=True)
+
+
+def bench_fmm(args, g, ctx, n):
+    """Symmetric FMM (p = 3, theta = 0.5, leaf 16) on the clustered box drawn
+    with its own seed, short-range kernel at the same split, R_cut = 4.5 r_s."""
+    import torch
+    import workloads
+    scale = (128 ** 3 / n) ** (1.0 / 3.0)
+    r_s, eps0 = 1.25 / 256 * scale, scale / (40 * 128)
+    ps = workloads.clustered_box(n, seed=3)
+    dev = ctx.device
+    pos = torch.from_numpy(ps.pos).to(dev)
+    m32 = ps.mass.astype(np.float32)
+    mass = torch.from_numpy(m32).to(dev)
+    tp = g.tree_params(True, 1.0, leaf_max=16)
+    ws = torch.empty(g.g4_workspace_bytes(tp, n) + 256, dtype=torch.uint8, device=dev)
+    fp = g.fmm_params(kernel=1, theta=0.5, r_s=r_s, r_cut=4.5 * r_s, eps0=eps0)
+    state = {"factor": 1.0, "fws": None}
+
+    def step(ev=None):
+        x, y, z = g.g4_quantize(ctx, pos, tp)
+        p = g.particles(x, y, z, mass)
+        t = g.g4_build_tree(ctx, p, tp, ws=ws)
+        g.g4_compute_multipoles(ctx, t, 3)
+        if ev is not None:
+            ev[0].record()
+        o = g.g4_fmm_force(ctx, t, fp, list_factor=state["factor"], ws=state["fws"])
+        if ev is not None:
+            ev[1].record()
+        state["factor"], state["fws"], state["out"], state["p"] = o["list_factor"], o["ws"], o, p
+
+    step()
+    steps = max(3, args.steps // 2)
+    evs = [[torch.cuda.Event(enable_timing=True) for _ in range(2)] for _ in range(steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(steps):
+        step(evs[k])
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / steps
+    fmm_ms = float(np.mean([e[0].elapsed_time(e[1]) for e in evs]))
+    o = state["out"]
+    a = np.stack([o["ax"].cpu().numpy(), o["ay"].cpu().numpy(), o["az"].cpu().numpy()], 1)
+    net = float(np.abs((m32[:, None].astype(np.float64) * a).sum(0)).max() / (m32[:, None] * np.abs(a)).sum())
+    tg = workloads.sample_indices(n, args.err_sample, seed=98)
+    ref = g.g4_direct_force(ctx, state["p"], tp, g.walk_params(kernel=1, r_s=r_s, eps0=eps0),
+                            targets=torch.from_numpy(tg).to(dev), want_pot=False)
+    ref = np.stack([ref["ax"].cpu().numpy(), ref["ay"].cpu().numpy(), ref["az"].cpu().numpy()], 1)
+    log(f"[bench] fmm: {ms:.3f} ms/step (fmm {fmm_ms:.3f} ms), net force {net:.2e}")
+    return {"workload": "fmm_clustered_box_128^3 (seed 3), p=3, theta=0.5, leaf 16, R_cut 4.5 r_s",
+            "forces_per_s": n / (ms * 1e-3), "ms_per_step": ms, "fmm_ms": fmm_ms,
+            "net_force_over_sum_abs": net, "list_factor": state["factor"],
+            "errors_vs_direct": workloads.percentiles(workloads.relative_errors(a[tg], ref))}
+
+
+def bench_forest(args, g, ctx):
+    """Batched persistent walk over 64 independent clustered boxes (N log-uniform
+    in [32768, 1048576], seeds 3000+b, concentration spread x3), leaf and group
+    size from the autotuner's table when present."""
+    import workloads
+    from paper_2010_03567_amd.autotune import ForestStep
+    boxes = workloads.forest(64, seed=3000)
+    r_s = 1.25 / 256
+    tf = os.path.join(ROOT, "paper_2010_03567_amd", "weights", "autotune_forest.json")
+    B, G, tuned = 8, 64, False
+    if os.path.exists(tf):
+        with open(tf) as fh:
+            t = json.load(fh)
+        B, G, tuned = int(t["B"]), int(t["G"]), True
+    step = ForestStep(ctx, boxes, r_s, args.rcut * r_s, 1.0 / (40 * 128), 0.001)
+    ms, pre, walk = step.time(B, G, steps=max(3, args.steps // 2))
+    log(f"[bench] forest: {step.n} particles in 64 boxes, {ms:.3f} ms/step (B={B}, G={G})")
+    return {"workload": "forest of 64 clustered boxes", "n": step.n, "forces_per_s": step.n / (ms * 1e-3),
+            "ms_per_step": ms, "prewalk_ms": pre, "walk_ms": walk, "leaf_max": B, "group_size": G,
+            "autotuned": tuned, "R_cut": args.rcut, "alpha": 0.001}
 
 
 def learned_variant(args, g, ctx, n, r_s, eps0, tp, ws, pos, mass, out, outs, stream, state, tg, ref, plain_ms):

@@ -144,6 +144,17 @@ int g4_workspace_bytes(const g4_tree_params *tp, int64_t n, size_t *bytes);
 int g4_build_tree(g4_ctx *ctx, const g4_particles *p, const g4_tree_params *tp, void *ws, size_t ws_bytes,
                   g4_tree **out);
 
+/* Forest of nbox independent periodic boxes of side tp->box (batching):
+ * box b holds the caller's particles [box_offsets[b], box_offsets[b+1])
+ * (host array of nbox + 1, starting at 0 and ending at n, every box
+ * non-empty).  One node array with one root per box (nodes 0..nbox-1);
+ * multipoles and walks work on it as on a single tree, the walk running as
+ * one persistent launch over (box, particle group) work items, largest boxes
+ * first.  Workspace from g4_forest_workspace_bytes. */
+int g4_forest_workspace_bytes(const g4_tree_params *tp, int nbox, int64_t n, size_t *bytes);
+int g4_build_forest(g4_ctx *ctx, int nbox, const int64_t *box_offsets, const g4_particles *p,
+                    const g4_tree_params *tp, void *ws, size_t ws_bytes, g4_tree **out);
+
 /* Multipole moments up to octupole about each node's centre of mass
  * (Sec. "One-sided multipole expansion"; upward pass as in the first FMM
  * phase): leaves from their particles, parents from their children by the
@@ -239,8 +250,9 @@ int g4_fmm_workspace_bytes(const g4_tree *tree, double list_factor, size_t *byte
  * evaluation at the particles.  Needs g4_compute_multipoles(order 3).
  * ax, ay, az (pot nullable): device n float64, caller order.  Synchronises
  * (list sizes are read back); returns G4_ENOMEM when the lists exceed the
- * workspace of list_factor (retry with a larger factor).  Sums are ordered
- * by target, so results do not depend on the order of list construction. */
+ * workspace of list_factor (retry with a larger factor).  Each target sums
+ * its sources in the order of their first particle and level, so results do
+ * not depend on list construction or node numbering.  n < 2^27. */
 int g4_fmm_force(g4_ctx *ctx, g4_tree *tree, const g4_fmm_params *fp, double list_factor, void *ws, size_t ws_bytes,
                  double *ax, double *ay, double *az, double *pot, g4_stats *stats);
 

@@ -15,6 +15,9 @@ static int check_tp(g4_ctx *ctx, const g4_tree_params *tp)
     return G4_OK;
 }
 
+static int g4_build_tree_views(g4_ctx *ctx, const g4_particles *p, const g4_tree_params *tp, void *ws,
+                               const WsLayout *Lp, g4_tree **out);
+
 extern "C" {
 
 int g4_ctx_create(int device, void *hip_stream, g4_ctx **out)
@@ -72,6 +75,23 @@ int g4_build_tree(g4_ctx *ctx, const g4_particles *p, const g4_tree_params *tp, 
     st = g4_layout(tp, p->n, &L);
     if (st) return g4_set_err(ctx, st, "workspace layout failed");
     if (ws_bytes < L.total) return g4_set_err(ctx, G4_ENOMEM, "workspace too small");
+    g4_tree *t = nullptr;
+    st = g4_build_tree_views(ctx, p, tp, ws, &L, &t);
+    if (st) return st;
+    st = g4_launch_build(ctx, t, p);
+    if (st) {
+        delete t;
+        return st;
+    }
+    *out = t;
+    return G4_OK;
+}
+
+// host handle with views into a workspace laid out by L
+static int g4_build_tree_views(g4_ctx *ctx, const g4_particles *p, const g4_tree_params *tp, void *ws,
+                               const WsLayout *Lp, g4_tree **out)
+{
+    const WsLayout &L = *Lp;
     g4_tree *t = new (std::nothrow) g4_tree;
     if (!t) return g4_set_err(ctx, G4_ENOMEM, "host allocation failed");
     char *b = (char *)ws;
@@ -83,6 +103,13 @@ int g4_build_tree(g4_ctx *ctx, const g4_particles *p, const g4_tree_params *tp, 
     t->cap = L.cap;
     t->moments_order = 0;
     t->seed_valid = 0;
+    t->nbox = 1;
+    t->items = nullptr;
+    t->nitems = 0;
+    t->items_group = 0;
+    t->box_off = nullptr;
+    t->items_host = nullptr;
+    t->items_cap = 0;
     t->ctr = (DevCounters *)(b + L.ctr);
     t->keys0 = (uint64_t *)(b + L.keys0);
     t->keys1 = (uint64_t *)(b + L.keys1);
@@ -98,11 +125,6 @@ int g4_build_tree(g4_ctx *ctx, const g4_particles *p, const g4_tree_params *tp, 
     t->aseed = (float *)(b + L.aseed);
     t->sort_tmp = b + L.sort_tmp;
     t->sort_tmp_bytes = L.sort_bytes;
-    st = g4_launch_build(ctx, t, p);
-    if (st) {
-        delete t;
-        return st;
-    }
     *out = t;
     return G4_OK;
 }
@@ -145,8 +167,75 @@ int g4_tree_export(g4_ctx *ctx, const g4_tree *tree, int32_t *level, uint32_t *c
 
 int g4_tree_free(g4_ctx *ctx, g4_tree *tree)
 {
-    (void)ctx;
+    if (tree) {
+        // the items may still be in flight to the device: wait before releasing their host copy
+        if (ctx && tree->items_host) hipStreamSynchronize(ctx->stream);
+        delete[] tree->box_off;
+        delete[] tree->items_host;
+    }
     delete tree;
+    return G4_OK;
+}
+
+int g4_forest_workspace_bytes(const g4_tree_params *tp, int nbox, int64_t n, size_t *bytes)
+{
+    if (!tp || !bytes || nbox < 1 || n < nbox) return G4_EINVAL;
+    size_t b = 0;
+    int st = g4_workspace_bytes(tp, n, &b);
+    if (st) return st;
+    // box offsets, two box-key arrays, work items (one per particle at worst)
+    b += (((size_t)(nbox + 1) * 8 + 255) & ~(size_t)255) + 2 * (((size_t)n * 4 + 255) & ~(size_t)255) +
+         (((size_t)(n + nbox) * 16 + 255) & ~(size_t)255);
+    *bytes = b;
+    return G4_OK;
+}
+
+int g4_build_forest(g4_ctx *ctx, int nbox, const int64_t *box_offsets, const g4_particles *p,
+                    const g4_tree_params *tp, void *ws, size_t ws_bytes, g4_tree **out)
+{
+    if (!ctx) return G4_EINVAL;
+    int st = check_tp(ctx, tp);
+    if (st) return st;
+    if (!tp->periodic && nbox > 1) return g4_set_err(ctx, G4_EINVAL, "a forest needs periodic boxes");
+    if (nbox < 1 || !box_offsets || !p || !out || !ws) return g4_set_err(ctx, G4_EINVAL, "bad forest args");
+    if (box_offsets[0] != 0 || box_offsets[nbox] != p->n) return g4_set_err(ctx, G4_EINVAL, "offsets must span [0, n]");
+    for (int b = 0; b < nbox; b++)
+        if (box_offsets[b + 1] <= box_offsets[b]) return g4_set_err(ctx, G4_EINVAL, "every box needs a particle");
+    size_t need = 0;
+    st = g4_forest_workspace_bytes(tp, nbox, p->n, &need);
+    if (st) return g4_set_err(ctx, st, "forest layout failed");
+    if (ws_bytes < need) return g4_set_err(ctx, G4_ENOMEM, "workspace too small");
+    if (((uintptr_t)ws & 255) != 0) return g4_set_err(ctx, G4_EINVAL, "workspace must be 256-byte aligned");
+    WsLayout L;
+    g4_layout(tp, p->n, &L);
+    g4_tree *t = nullptr;
+    // carve the single-tree part, then the forest extras behind it
+    st = g4_build_tree_views(ctx, p, tp, ws, &L, &t);
+    if (st) return st;
+    char *extra = (char *)ws + L.total;
+    int64_t *off_dev = (int64_t *)extra;
+    extra += (((size_t)(nbox + 1) * 8 + 255) & ~(size_t)255);
+    uint32_t *bkey0 = (uint32_t *)extra;
+    extra += (((size_t)p->n * 4 + 255) & ~(size_t)255);
+    uint32_t *bkey1 = (uint32_t *)extra;
+    extra += (((size_t)p->n * 4 + 255) & ~(size_t)255);
+    t->items = (uint4 *)extra;
+    t->items_cap = p->n + nbox;
+    t->nbox = nbox;
+    t->box_off = new (std::nothrow) int64_t[nbox + 1];
+    if (!t->box_off) {
+        delete t;
+        return g4_set_err(ctx, G4_ENOMEM, "host allocation failed");
+    }
+    for (int b = 0; b <= nbox; b++) t->box_off[b] = box_offsets[b];
+    G4_HIP(ctx, hipMemcpyAsync(off_dev, t->box_off, (size_t)(nbox + 1) * 8, hipMemcpyHostToDevice, ctx->stream));
+    st = g4_launch_build_forest(ctx, t, p, off_dev, bkey0, bkey1);
+    if (st) {
+        g4_tree_free(ctx, t);
+        return st;
+    }
+    // the offsets copy reads host memory owned by the tree; it completes before any later call returns
+    *out = t;
     return G4_OK;
 }
 
@@ -253,6 +342,7 @@ int g4_fmm_force(g4_ctx *ctx, g4_tree *tree, const g4_fmm_params *fp, double lis
     if (fp->kernel == 1 && !tree->tp.periodic) return g4_set_err(ctx, G4_EINVAL, "short-range kernel needs a periodic box");
     if (!(fp->theta > 0) || fp->eps0 < 0) return g4_set_err(ctx, G4_EINVAL, "bad theta or eps0");
     if (((uintptr_t)ws & 255) != 0) return g4_set_err(ctx, G4_EINVAL, "workspace must be 256-byte aligned");
+    if (tree->n >= (1ll << 27)) return g4_set_err(ctx, G4_EINVAL, "FMM supports up to 2^27 particles per call");
     return g4_launch_fmm(ctx, tree, fp, list_factor, ws, ws_bytes, ax, ay, az, pot, stats);
 }
 

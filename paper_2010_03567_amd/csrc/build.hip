@@ -440,3 +440,88 @@ int g4_launch_gather_seed(g4_ctx *ctx, g4_tree *t, const float *a_seed_caller)
     G4_HIP(ctx, hipGetLastError());
     return G4_OK;
 }
+
+// ------------------------------------------------------------------ forest
+// Many independent boxes in one node array: particles sorted by (box, Morton
+// key), one root per box at level 0 (nodes 0..nbox-1), then the same
+// level-synchronous split and upward pass as a single tree.
+
+// box of each Morton-sorted particle (caller index -> box by binary search)
+__global__ void k_boxkey(const uint32_t *__restrict__ perm, int64_t n, const int64_t *__restrict__ off, int nbox,
+                         uint32_t *__restrict__ bkey)
+{
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t c = perm[i];
+        int lo = 0, hi = nbox - 1;
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (off[mid] <= c) lo = mid;
+            else hi = mid - 1;
+        }
+        bkey[i] = (uint32_t)lo;
+    }
+}
+
+// Morton keys in the final (box, key) order
+__global__ void k_keys_perm(const uint32_t *__restrict__ X, const uint32_t *__restrict__ Y,
+                            const uint32_t *__restrict__ Z, const uint32_t *__restrict__ perm, int64_t n, int drop,
+                            uint32_t corner, uint64_t *__restrict__ keys)
+{
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        const uint32_t p = perm[i];
+        const uint32_t rx = (X[p] - corner) >> drop, ry = (Y[p] - corner) >> drop, rz = (Z[p] - corner) >> drop;
+        keys[i] = (spread3(rx) << 2) | (spread3(ry) << 1) | spread3(rz);
+    }
+}
+
+__global__ void k_init_forest(DevCounters *C, uint32_t *bfirst, uint32_t *bcount, uint32_t *parent,
+                              const int64_t *__restrict__ off, int nbox)
+{
+    const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b == 0) {
+        C->node_count = (uint32_t)nbox;
+        C->flags = 0;
+        for (int l = 0; l < G4_MAXLEV + 4; l++) {
+            C->lvl_start[l] = 0;
+            C->lvl_count[l] = 0;
+        }
+        C->lvl_count[0] = (uint32_t)nbox;
+        for (int s = 0; s < 16; s++) C->stat[s] = 0;
+    }
+    if (b < nbox) {
+        bfirst[b] = (uint32_t)off[b];
+        bcount[b] = (uint32_t)(off[b + 1] - off[b]);
+        parent[b] = 0xffffffffu;
+    }
+}
+
+int g4_launch_build_forest(g4_ctx *ctx, g4_tree *t, const g4_particles *p, const int64_t *off_dev, uint32_t *bkey0,
+                           uint32_t *bkey1)
+{
+    hipStream_t s = ctx->stream;
+    const int64_t n = t->n;
+    const int maxd = t->tp.max_depth < 1 ? 1 : (t->tp.max_depth > G4_MAXLEV ? G4_MAXLEV : t->tp.max_depth);
+    k_keys<<<grid_for(n), kBlock, 0, s>>>(p->x, p->y, p->z, n, t->S - G4_MAXLEV, t->corner, t->keys0, t->perm0);
+    G4_HIP(ctx, hipGetLastError());
+    size_t sb = t->sort_tmp_bytes;
+    G4_HIP(ctx, rocprim::radix_sort_pairs(t->sort_tmp, sb, t->keys0, t->keys1, t->perm0, t->perm1, (size_t)n, 0,
+                                          63, s));
+    k_boxkey<<<grid_for(n), kBlock, 0, s>>>(t->perm1, n, off_dev, t->nbox, bkey0);
+    int bits = 1;
+    while ((1 << bits) < t->nbox) bits++;
+    sb = t->sort_tmp_bytes;
+    // stable: particles of a box keep their Morton order
+    G4_HIP(ctx, rocprim::radix_sort_pairs(t->sort_tmp, sb, bkey0, bkey1, t->perm1, t->perm0, (size_t)n, 0, bits, s));
+    uint32_t *tmp = t->perm0;
+    t->perm0 = t->perm1;
+    t->perm1 = tmp;
+    k_keys_perm<<<grid_for(n), kBlock, 0, s>>>(p->x, p->y, p->z, t->perm1, n, t->S - G4_MAXLEV, t->corner, t->keys1);
+    k_gather<<<grid_for(n), kBlock, 0, s>>>(p->x, p->y, p->z, p->mass, t->perm1, n, t->parts);
+    k_init_forest<<<(t->nbox + 255) / 256, 256, 0, s>>>(t->ctr, t->bfirst, t->bcount, t->parent, off_dev, t->nbox);
+    G4_HIP(ctx, hipGetLastError());
+    for (int l = 0; l <= maxd; l++)
+        k_split<<<grid_for(n, 1024), kBlock, 0, s>>>(t->ctr, t->keys1, t->parts, t->bfirst, t->bcount, t->parent,
+                                                      t->wn, l, t->tp.leaf_max, maxd, t->S, t->corner, t->cap);
+    G4_HIP(ctx, hipGetLastError());
+    return G4_OK;
+}

@@ -15,13 +15,15 @@
 // pairs (nodes, or single particles once a leaf is opened).  Each pass
 // classifies every pair and appends, with one atomic per wavefront per list,
 // (a) new pairs to the next frontier or (b) per-target entries
-// (target, source): a node target collects the field of a node (M2L) or a
+// (target, source) entries: a node target collects the field of a node (M2L) or a
 // particle (P2L); a particle target collects the force of a node (M2P), of a
 // single particle, or of all particles of a leaf (P2P).  Both sides of every
-// symmetric interaction become an entry, so after sorting the entries by
-// target each target sums its own list: no floating-point atomics, and the
-// order of every sum is fixed.  Then L2L runs level by level and one pass
-// per particle does M2P + P2P + L2P with FP64 accumulation.
+// symmetric interaction become an entry; entries are sorted by target and,
+// within a target, by the source's first particle and level, so each target
+// sums its own list in an order that depends neither on the order of
+// appends nor on node numbering: no floating-point atomics, bitwise
+// reproducible.  Then L2L runs level by level and one pass per particle does
+// M2P + P2P + L2P with FP64 accumulation.
 #include <cstring>
 
 #include <rocprim/rocprim.hpp>
@@ -38,6 +40,7 @@
 
 struct FmmArgs {
     const WNode *wn;
+    const uint32_t *bfirst;  // first particle of each node
     const uint4 *parts;
     const float *q3;
     const DevCounters *ctr;
@@ -51,9 +54,12 @@ struct FmmArgs {
     uint2 *fout;
     uint32_t *cnt;   // [0] in-count (read), [1] out-count, [2] node entries, [3] particle entries, [4] overflow
     uint32_t cap_pairs;
-    uint32_t *nkey, *nval;
+    // entries: key = target << 32 | order key of the source, value = source (type bits | index)
+    uint64_t *nkey;
+    uint32_t *nval;
     uint32_t cap_node;
-    uint32_t *pkey, *pval;
+    uint64_t *pkey;
+    uint32_t *pval;
     uint32_t cap_part;
     unsigned long long *stat;  // pp, pn, nn
 };
@@ -188,6 +194,22 @@ __device__ Act classify(const FmmArgs &A, uint32_t ea, uint32_t eb)
     return X;
 }
 
+// Order key of a source that does not depend on how nodes were numbered:
+// its first particle (sorted order) and its level (31 for a single particle).
+__device__ __forceinline__ uint32_t src_order(const FmmArgs &A, uint32_t src)
+{
+    const uint32_t id = ENT_IDX(src);
+    if (ENT_TYPE(src) == ENT_PART) return (id << 5) | 31u;
+    return (A.bfirst[id] << 5) | (A.wn[id].meta & 0x1fu);
+}
+
+__device__ __forceinline__ void put(uint64_t *key, uint32_t *val, uint32_t at, const FmmArgs &A, uint32_t target,
+                                    uint32_t src)
+{
+    key[at] = ((uint64_t)target << 32) | src_order(A, src);
+    val[at] = src;
+}
+
 // wavefront-aggregated append: returns this lane's base index
 __device__ __forceinline__ uint32_t wave_append(uint32_t *counter, uint32_t n)
 {
@@ -246,10 +268,7 @@ __global__ __launch_bounds__(256) void k_fmm_traverse(FmmArgs A)
         }
         switch (X.kind) {
         case ACT_SELF_LEAF:
-            for (uint32_t k = 0; k < X.a.num; k++) {
-                A.pkey[ok + k] = X.a.next + k;
-                A.pval[ok + k] = ENT_LEAF | X.ea;
-            }
+            for (uint32_t k = 0; k < X.a.num; k++) put(A.pkey, A.pval, ok + k, A, X.a.next + k, ENT_LEAF | X.ea);
             break;
         case ACT_SELF_SPLIT: {
             uint32_t o = op;
@@ -258,23 +277,17 @@ __global__ __launch_bounds__(256) void k_fmm_traverse(FmmArgs A)
             break;
         }
         case ACT_PP:
-            A.pkey[ok] = X.ea & ~PF;
-            A.pval[ok] = ENT_PART | (X.eb & ~PF);
-            A.pkey[ok + 1] = X.eb & ~PF;
-            A.pval[ok + 1] = ENT_PART | (X.ea & ~PF);
+            put(A.pkey, A.pval, ok, A, X.ea & ~PF, ENT_PART | (X.eb & ~PF));
+            put(A.pkey, A.pval, ok + 1, A, X.eb & ~PF, ENT_PART | (X.ea & ~PF));
             break;
         case ACT_NN:
-            A.nkey[on] = X.ea;
-            A.nval[on] = ENT_NODE | X.eb;
-            A.nkey[on + 1] = X.eb;
-            A.nval[on + 1] = ENT_NODE | X.ea;
+            put(A.nkey, A.nval, on, A, X.ea, ENT_NODE | X.eb);
+            put(A.nkey, A.nval, on + 1, A, X.eb, ENT_NODE | X.ea);
             break;
         case ACT_PN: {
             const uint32_t node = X.a.part ? X.eb : X.ea, part = (X.a.part ? X.ea : X.eb) & ~PF;
-            A.nkey[on] = node;
-            A.nval[on] = ENT_PART | part;
-            A.pkey[ok] = part;
-            A.pval[ok] = ENT_NODE | node;
+            put(A.nkey, A.nval, on, A, node, ENT_PART | part);
+            put(A.pkey, A.pval, ok, A, part, ENT_NODE | node);
             break;
         }
         case ACT_OPEN_PP: {
@@ -282,14 +295,8 @@ __global__ __launch_bounds__(256) void k_fmm_traverse(FmmArgs A)
             const uint32_t srcb = X.b.part ? (ENT_PART | (X.eb & ~PF)) : (ENT_LEAF | X.eb);
             const uint32_t srca = X.a.part ? (ENT_PART | (X.ea & ~PF)) : (ENT_LEAF | X.ea);
             uint32_t o = ok;
-            for (uint32_t k = 0; k < X.na; k++) {
-                A.pkey[o] = open_item(X.a, X.ea, k) & ~PF;
-                A.pval[o++] = srcb;
-            }
-            for (uint32_t k = 0; k < X.nb; k++) {
-                A.pkey[o] = open_item(X.b, X.eb, k) & ~PF;
-                A.pval[o++] = srca;
-            }
+            for (uint32_t k = 0; k < X.na; k++) put(A.pkey, A.pval, o++, A, open_item(X.a, X.ea, k) & ~PF, srcb);
+            for (uint32_t k = 0; k < X.nb; k++) put(A.pkey, A.pval, o++, A, open_item(X.b, X.eb, k) & ~PF, srca);
             break;
         }
         case ACT_OPEN: {
@@ -314,24 +321,26 @@ __global__ void k_fmm_rotate(uint32_t *cnt)
     }
 }
 
-__global__ void k_fmm_init(uint32_t *cnt, uint2 *f0, unsigned long long *stat)
+// the walk starts from the self-pair of every root (one root per box of a forest)
+__global__ void k_fmm_init(uint32_t *cnt, uint2 *f0, unsigned long long *stat, int nroot)
 {
-    if (threadIdx.x == 0 && blockIdx.x == 0) {
-        f0[0] = make_uint2(0u, 0u);
-        cnt[0] = 1;
+    const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b < nroot) f0[b] = make_uint2((uint32_t)b, (uint32_t)b);
+    if (b == 0) {
+        cnt[0] = (uint32_t)nroot;
         for (int k = 1; k < 8; k++) cnt[k] = 0;
         stat[0] = stat[1] = stat[2] = 0;
     }
 }
 
 // ------------------------------------------------------------ CSR of entries
-__global__ void k_fmm_csr(const uint32_t *__restrict__ key, uint32_t n, uint32_t *__restrict__ start,
+__global__ void k_fmm_csr(const uint64_t *__restrict__ key, uint32_t n, uint32_t *__restrict__ start,
                           uint32_t *__restrict__ end)
 {
     for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
-        const uint32_t k = key[i];
-        if (i == 0 || key[i - 1] != k) start[k] = i;
-        if (i == n - 1 || key[i + 1] != k) end[k] = i + 1;
+        const uint32_t k = (uint32_t)(key[i] >> 32);
+        if (i == 0 || (uint32_t)(key[i - 1] >> 32) != k) start[k] = i;
+        if (i == n - 1 || (uint32_t)(key[i + 1] >> 32) != k) end[k] = i + 1;
     }
 }
 
@@ -642,7 +651,7 @@ __global__ __launch_bounds__(256) void k_fmm_particles(FmmArgs A, const uint32_t
 
 // ------------------------------------------------------------------ host side
 struct FmmLayout {
-    size_t cnt, f0, f1, nkey, nval, nkey2, nval2, pkey, pval, pkey2, pval2, nstart, nend, pstart, pend, F, leafid,
+    size_t cnt, f0, f1, nkey, nkey2, nval, nval2, pkey, pkey2, pval, pval2, nstart, nend, pstart, pend, F, leafid,
         sort_tmp, sort_bytes, total;
     uint32_t cap_pairs, cap_node, cap_part;
 };
@@ -662,13 +671,13 @@ static int fmm_layout(int64_t n, int64_t cap_nodes, double factor, FmmLayout *L)
     L->cnt = take(64);
     L->f0 = take((size_t)L->cap_pairs * 8);
     L->f1 = take((size_t)L->cap_pairs * 8);
-    L->nkey = take((size_t)L->cap_node * 4);
+    L->nkey = take((size_t)L->cap_node * 8);
+    L->nkey2 = take((size_t)L->cap_node * 8);
     L->nval = take((size_t)L->cap_node * 4);
-    L->nkey2 = take((size_t)L->cap_node * 4);
     L->nval2 = take((size_t)L->cap_node * 4);
-    L->pkey = take((size_t)L->cap_part * 4);
+    L->pkey = take((size_t)L->cap_part * 8);
+    L->pkey2 = take((size_t)L->cap_part * 8);
     L->pval = take((size_t)L->cap_part * 4);
-    L->pkey2 = take((size_t)L->cap_part * 4);
     L->pval2 = take((size_t)L->cap_part * 4);
     L->nstart = take((size_t)cap_nodes * 4);
     L->nend = take((size_t)cap_nodes * 4);
@@ -677,11 +686,11 @@ static int fmm_layout(int64_t n, int64_t cap_nodes, double factor, FmmLayout *L)
     L->F = take((size_t)cap_nodes * 20 * 4);
     L->leafid = take((size_t)n * 4);
     size_t sb1 = 0, sb2 = 0;
-    if (rocprim::radix_sort_pairs((void *)nullptr, sb1, (uint32_t *)nullptr, (uint32_t *)nullptr,
-                                  (uint32_t *)nullptr, (uint32_t *)nullptr, (size_t)L->cap_node, 0, 32) != hipSuccess)
+    if (rocprim::radix_sort_pairs((void *)nullptr, sb1, (uint64_t *)nullptr, (uint64_t *)nullptr,
+                                  (uint32_t *)nullptr, (uint32_t *)nullptr, (size_t)L->cap_node, 0, 64) != hipSuccess)
         return G4_EHIP;
-    if (rocprim::radix_sort_pairs((void *)nullptr, sb2, (uint32_t *)nullptr, (uint32_t *)nullptr,
-                                  (uint32_t *)nullptr, (uint32_t *)nullptr, (size_t)L->cap_part, 0, 32) != hipSuccess)
+    if (rocprim::radix_sort_pairs((void *)nullptr, sb2, (uint64_t *)nullptr, (uint64_t *)nullptr,
+                                  (uint32_t *)nullptr, (uint32_t *)nullptr, (size_t)L->cap_part, 0, 64) != hipSuccess)
         return G4_EHIP;
     L->sort_bytes = std::max(sb1, sb2);
     L->sort_tmp = take(L->sort_bytes);
@@ -732,15 +741,17 @@ int g4_launch_fmm(g4_ctx *ctx, g4_tree *t, const g4_fmm_params *fp, double facto
     A.kernel = fp->kernel;
     A.cnt = (uint32_t *)(b + L.cnt);
     A.cap_pairs = L.cap_pairs;
-    A.nkey = (uint32_t *)(b + L.nkey);
+    A.nkey = (uint64_t *)(b + L.nkey);
     A.nval = (uint32_t *)(b + L.nval);
     A.cap_node = L.cap_node;
-    A.pkey = (uint32_t *)(b + L.pkey);
+    A.pkey = (uint64_t *)(b + L.pkey);
     A.pval = (uint32_t *)(b + L.pval);
     A.cap_part = L.cap_part;
+    A.bfirst = t->bfirst;
     A.stat = t->ctr->stat + 6;
     uint2 *fr[2] = {(uint2 *)(b + L.f0), (uint2 *)(b + L.f1)};
-    k_fmm_init<<<1, 64, 0, s>>>(A.cnt, fr[0], A.stat);
+    if ((uint64_t)t->nbox > L.cap_pairs) return g4_set_err(ctx, G4_ENOMEM, "fmm frontier smaller than the root count");
+    k_fmm_init<<<(t->nbox + 255) / 256, 256, 0, s>>>(A.cnt, fr[0], A.stat, t->nbox);
     G4_HIP(ctx, hipGetLastError());
     // dual walk: passes until the frontier is empty (checked every 8 passes)
     int cur = 0;
@@ -772,18 +783,18 @@ int g4_launch_fmm(g4_ctx *ctx, g4_tree *t, const g4_fmm_params *fp, double facto
         G4_HIP(ctx, hipStreamSynchronize(s));
         nn_host = hc.node_count;
     }
-    // sort entries by target
-    uint32_t *nk = A.nkey, *nv = A.nval, *pk = A.pkey, *pv = A.pval;
-    uint32_t *nk2 = (uint32_t *)(b + L.nkey2), *nv2 = (uint32_t *)(b + L.nval2);
-    uint32_t *pk2 = (uint32_t *)(b + L.pkey2), *pv2 = (uint32_t *)(b + L.pval2);
+    // sort the entries by (target, source): each target's sum then runs in source order,
+    // independent of the order in which the walk appended its entries
+    uint64_t *nk2 = (uint64_t *)(b + L.nkey2), *pk2 = (uint64_t *)(b + L.pkey2);
+    uint32_t *nv2 = (uint32_t *)(b + L.nval2), *pv2 = (uint32_t *)(b + L.pval2);
     size_t sb = L.sort_bytes;
     if (n_node)
-        G4_HIP(ctx, rocprim::radix_sort_pairs((void *)(b + L.sort_tmp), sb, nk, nk2, nv, nv2, (size_t)n_node, 0,
-                                              bits_for((uint64_t)nn_host), s));
+        G4_HIP(ctx, rocprim::radix_sort_pairs((void *)(b + L.sort_tmp), sb, A.nkey, nk2, A.nval, nv2, (size_t)n_node,
+                                              0, 32 + bits_for((uint64_t)nn_host), s));
     sb = L.sort_bytes;
     if (n_part)
-        G4_HIP(ctx, rocprim::radix_sort_pairs((void *)(b + L.sort_tmp), sb, pk, pk2, pv, pv2, (size_t)n_part, 0,
-                                              bits_for((uint64_t)t->n), s));
+        G4_HIP(ctx, rocprim::radix_sort_pairs((void *)(b + L.sort_tmp), sb, A.pkey, pk2, A.pval, pv2, (size_t)n_part,
+                                              0, 32 + bits_for((uint64_t)t->n), s));
     uint32_t *nstart = (uint32_t *)(b + L.nstart), *nend = (uint32_t *)(b + L.nend);
     uint32_t *pstart = (uint32_t *)(b + L.pstart), *pend = (uint32_t *)(b + L.pend);
     G4_HIP(ctx, hipMemsetAsync(nstart, 0, (size_t)t->cap * 4, s));

@@ -37,7 +37,7 @@ static_assert(sizeof(WNode) == 64, "WNode must be 64 bytes");
 // Device counters at the head of the tree workspace.
 struct DevCounters {
     uint32_t node_count;      // total nodes (written by the last split pass)
-    uint32_t pad0;
+    uint32_t item_ctr;        // work-item counter of the persistent walk
     uint32_t flags;           // bit 0: depth-capped leaf above leaf_max; bit 1: node overflow
     uint32_t pad;
     uint32_t lvl_start[G4_MAXLEV + 4];  // first node of each level
@@ -65,6 +65,14 @@ struct g4_tree {
     float *q3;                // 10 floats per node (potential only)
     double *mom;              // MOM_STRIDE doubles per node
     float *aseed;             // n floats, sorted order
+    // forest of independent boxes: one root per box (nodes 0..nbox-1)
+    int nbox;
+    uint4 *items;             // device work items of the walk (first, count, root), 0 for a single tree
+    uint32_t nitems;
+    int items_group;          // group size the items were made for
+    int64_t *box_off;         // host copy of the box offsets (nbox + 1)
+    uint4 *items_host;        // host staging of the items
+    int64_t items_cap;
     void *sort_tmp;
     size_t sort_tmp_bytes;
 };
@@ -97,6 +105,8 @@ static inline int g4_set_err(g4_ctx *ctx, int code, const char *msg)
 // host launchers implemented in the .hip files
 int g4_launch_build(g4_ctx *ctx, g4_tree *t, const g4_particles *p);
 int g4_launch_moments(g4_ctx *ctx, g4_tree *t);
+int g4_launch_build_forest(g4_ctx *ctx, g4_tree *t, const g4_particles *p, const int64_t *off_dev, uint32_t *bkey0,
+                           uint32_t *bkey1);
 int g4_launch_walk(g4_ctx *ctx, g4_tree *t, const g4_walk_params *wp, int kernel, int criterion,
                    double *ax, double *ay, double *az, double *pot, uint32_t *counts, float *aout_caller,
                    float *aout_sorted, int stat_slot);

@@ -17,6 +17,10 @@
 // of lanes that open the node (pushed with the children) or use its
 // multipoles.  Interactions are FP32 arithmetic on int32 nearest-image
 // differences; partial sums are flushed into per-lane FP64 accumulators.
+#include <algorithm>
+#include <new>
+#include <vector>
+
 #include "g4_device.h"
 #include "g4_internal.h"
 
@@ -44,6 +48,9 @@ struct WalkArgs {
     float *aout_caller, *aout_sorted;
     unsigned long long *stat;   // 3 counters: p2p, p2m, visits
     unsigned long long *wstat;  // 3 counters: node pops, P2M passes, P2P source iterations (per wavefront)
+    const uint4 *items;         // work items (first particle, count, root node), or null: groups of `group`
+    uint32_t nitems;
+    uint32_t *item_ctr;         // zeroed before the launch
 };
 
 // g1, g2, g3 (and g0) of the interaction kernel at r (r2, rinv given), r >= h.
@@ -79,22 +86,40 @@ __global__ __launch_bounds__(256) void k_walk(const WalkArgs A)
     __shared__ uint4 stk[4][32];
     const int lane = threadIdx.x & 63;
     const int wv = threadIdx.x >> 6;
-    const int64_t i0 = ((int64_t)blockIdx.x * 4 + wv) * A.group;
-    if (i0 >= A.n) return;
+    uint32_t t_pp = 0, t_pm = 0, t_visit = 0;  // per-lane totals over all items
+    uint32_t w_pop = 0, w_pm = 0, w_pp = 0;    // wavefront-level work (uniform counters)
+
+    // persistent wavefront: pull work items (a group of particles of one tree) until none are left
+    for (;;) {
+    uint32_t it = 0;
+    if (lane == 0) it = atomicAdd(A.item_ctr, 1u);
+    it = (uint32_t)__shfl((int)it, 0);
+    if (it >= A.nitems) break;
+    int64_t i0;
+    uint32_t gcount, root;
+    if (A.items) {
+        const uint4 w = A.items[it];
+        i0 = w.x;
+        gcount = w.y;
+        root = w.z;
+    } else {
+        i0 = (int64_t)it * A.group;
+        gcount = (uint32_t)min((int64_t)A.group, A.n - i0);
+        root = 0;
+    }
     const int64_t i = i0 + lane;
-    const bool act = lane < A.group && i < A.n;
+    const bool act = (uint32_t)lane < gcount;
     const uint4 me = A.parts[act ? i : i0];
     const float arel = CRIT == 1 ? A.alpha * (act ? A.aseed[i] : 0.f) : 0.f;
 
     double dax = 0.0, day = 0.0, daz = 0.0, dpot = 0.0;
     float fx = 0.f, fy = 0.f, fz = 0.f, fp = 0.f;
     uint32_t n_pp = 0, n_pm = 0, n_visit = 0;
-    uint32_t w_pop = 0, w_pm = 0, w_pp = 0;  // wavefront-level work (uniform counters)
     int pending = 0;
 
     const uint64_t amask = __ballot(act);
     int sp = 1;
-    if (lane == 0) stk[wv][0] = make_uint4(0u, 1u, (uint32_t)amask, (uint32_t)(amask >> 32));
+    if (lane == 0) stk[wv][0] = make_uint4(root, 1u, (uint32_t)amask, (uint32_t)(amask >> 32));
     __builtin_amdgcn_wave_barrier();
 
     while (sp > 0) {
@@ -247,9 +272,13 @@ __global__ __launch_bounds__(256) void k_walk(const WalkArgs A)
             A.counts[2 * (size_t)o + 1] = n_pm;
         }
     }
+    t_pp += n_pp;
+    t_pm += n_pm;
+    t_visit += n_visit;
+    }  // work items
     if (A.stat) {
         // wavefront sums of the interaction counters, one atomic per wavefront
-        unsigned long long s0 = n_pp, s1 = n_pm, s2 = n_visit;
+        unsigned long long s0 = t_pp, s1 = t_pm, s2 = t_visit;
         for (int off = 32; off > 0; off >>= 1) {
             s0 += __shfl_xor(s0, off);
             s1 += __shfl_xor(s1, off);
@@ -272,8 +301,10 @@ __global__ __launch_bounds__(256) void k_walk(const WalkArgs A)
 template <int KER, int CRIT, bool POT>
 static void launch_walk(const WalkArgs &A, hipStream_t s)
 {
-    int64_t groups = (A.n + A.group - 1) / A.group;
-    int64_t blocks = (groups + 3) / 4;
+    // persistent grid: 4 wavefronts per block, at most 8 resident wavefronts per SIMD
+    int64_t blocks = ((int64_t)A.nitems + 3) / 4;
+    if (blocks > 2048) blocks = 2048;
+    if (blocks < 1) blocks = 1;
     k_walk<KER, CRIT, POT><<<(unsigned)blocks, 256, 0, s>>>(A);
 }
 
@@ -312,6 +343,40 @@ int g4_launch_walk(g4_ctx *ctx, g4_tree *t, const g4_walk_params *wp, int kernel
     A.aout_caller = aout_caller;
     A.aout_sorted = aout_sorted;
     A.stat = t->ctr->stat + stat_slot;
+    if (t->nbox > 1 && t->items_group != A.group) {
+        // work items of a forest: every box cut into groups; largest boxes first so the
+        // persistent wavefronts finish together (longest-processing-time order)
+        if (!t->items_host) {
+            t->items_host = new (std::nothrow) uint4[t->items_cap];
+            if (!t->items_host) return g4_set_err(ctx, G4_ENOMEM, "host allocation failed");
+        }
+        std::vector<int> order(t->nbox);
+        for (int b = 0; b < t->nbox; b++) order[b] = b;
+        std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
+            return t->box_off[a + 1] - t->box_off[a] > t->box_off[b + 1] - t->box_off[b];
+        });
+        // wait for earlier work that may still read the previous items
+        G4_HIP(ctx, hipStreamSynchronize(ctx->stream));
+        int64_t k = 0;
+        for (int b : order)
+            for (int64_t f = t->box_off[b]; f < t->box_off[b + 1]; f += A.group) {
+                const int64_t c = std::min<int64_t>(A.group, t->box_off[b + 1] - f);
+                t->items_host[k++] = make_uint4((uint32_t)f, (uint32_t)c, (uint32_t)b, 0u);
+            }
+        t->nitems = (uint32_t)k;
+        t->items_group = A.group;
+        G4_HIP(ctx, hipMemcpyAsync(t->items, t->items_host, (size_t)k * sizeof(uint4), hipMemcpyHostToDevice,
+                                   ctx->stream));
+    }
+    if (t->nitems) {
+        A.items = t->items;
+        A.nitems = t->nitems;
+    } else {
+        A.items = nullptr;
+        A.nitems = (uint32_t)((A.n + A.group - 1) / A.group);
+    }
+    A.item_ctr = &t->ctr->item_ctr;
+    G4_HIP(ctx, hipMemsetAsync(A.item_ctr, 0, sizeof(uint32_t), ctx->stream));
     A.wstat = stat_slot == 0 ? t->ctr->stat + 9 : nullptr;
     hipStream_t s = ctx->stream;
     const bool P = pot != nullptr;

@@ -75,6 +75,9 @@ _SIGS = {
                         _p, _i64, _p, _p, _p, _p],
     "g4_mlp_features": [_p, _p, C.POINTER(g4_walk_params), _p, _p],
     "g4_fmm_workspace_bytes": [_p, C.c_double, C.POINTER(_sz)],
+    "g4_forest_workspace_bytes": [C.POINTER(g4_tree_params), _i32, _i64, C.POINTER(_sz)],
+    "g4_build_forest": [_p, _i32, _p, C.POINTER(g4_particles), C.POINTER(g4_tree_params), _p, _sz,
+                        C.POINTER(C.c_void_p)],
     "g4_fmm_force": [_p, _p, C.POINTER(g4_fmm_params), C.c_double, _p, _sz, _p, _p, _p, _p, C.POINTER(g4_stats)],
     "g4_mlp_forward": [_p, _p, _p, _i64, _p, C.c_float, _i32],
     "g4_mlp_grad": [_p, _p, _p, _p, _i64, C.c_float, _p, _p],
@@ -350,3 +353,30 @@ def g4_fmm_force(ctx, tree, fp, list_factor=1.0, ws=None, want_pot=False, want_s
         break
     return dict(ax=ax, ay=ay, az=az, pot=pot, stats=st.as_dict() if st is not None else None, ws=ws,
                 list_factor=list_factor)
+
+
+# ------------------------------------------------------------------ forest
+def g4_forest_workspace_bytes(tp, nbox, n):
+    b = C.c_size_t()
+    code = _L.g4_forest_workspace_bytes(C.byref(tp), int(nbox), int(n), C.byref(b))
+    if code != G4_OK:
+        raise G4Error(code, "forest workspace size query failed")
+    return int(b.value)
+
+
+def g4_build_forest(ctx, box_offsets, p, tp, ws=None):
+    """box_offsets: host sequence of nbox + 1 int64 (particles grouped by box)."""
+    import numpy as _np
+    off = _np.ascontiguousarray(_np.asarray(box_offsets, dtype=_np.int64))
+    nbox = off.shape[0] - 1
+    nbytes = g4_forest_workspace_bytes(tp, nbox, p.n)
+    if ws is None:
+        ws = torch.empty(nbytes + 256, dtype=torch.uint8, device=ctx.device)
+    o = (-ws.data_ptr()) % 256
+    wsv = ws[o:]
+    h = C.c_void_p()
+    ctx.check(_L.g4_build_forest(ctx.h, nbox, off.ctypes.data_as(C.c_void_p), C.byref(p), C.byref(tp),
+                                 C.c_void_p(wsv.data_ptr()), wsv.numel(), C.byref(h)))
+    t = Tree(ctx, h, ws, tp, int(p.n), p)
+    t.box_offsets = off
+    return t
