@@ -106,11 +106,11 @@ typedef struct {
     uint64_t n_seed_p2p, n_seed_p2m, n_seed_visit;  /* same, geometric pre-walk (if run) */
     uint64_t n_pp, n_pn, n_nn;   /* FMM interaction counts */
     uint64_t n_nodes;    /* nodes in the tree */
-    /* wavefront-level iterations of the walk (64 lanes each): node pops,
-     * particle-node passes, particle-particle source iterations; lane
-     * utilisation = lane count / (64 x wavefront count) */
+    /* 64-lane passes of the walk: node visits, particle-node interactions,
+     * particle-particle interactions; lane utilisation = count / (64 x passes) */
     uint64_t w_pop, w_p2m, w_p2p;
     uint32_t flags;      /* bit 0: a leaf at max_depth holds more than leaf_max particles */
+    uint32_t max_stack;  /* deepest traversal stack of the walk (entries; the top 48 are kept in LDS) */
 } g4_stats;
 
 /* ---------------------------------------------------------------- context */

@@ -123,6 +123,8 @@ static int g4_build_tree_views(g4_ctx *ctx, const g4_particles *p, const g4_tree
     t->q3 = (float *)(b + L.q3);
     t->mom = (double *)(b + L.mom);
     t->aseed = (float *)(b + L.aseed);
+    t->walk_spill = (uint4 *)(b + L.spill);
+    t->walk_spill_waves = L.spill_waves;
     t->sort_tmp = b + L.sort_tmp;
     t->sort_tmp_bytes = L.sort_bytes;
     *out = t;
@@ -289,6 +291,7 @@ static int tree_force_impl(g4_ctx *ctx, g4_tree *tree, const g4_walk_params *wp,
         stats->w_p2m = h.stat[10];
         stats->w_p2p = h.stat[11];
         stats->flags = h.flags;
+        stats->max_stack = (uint32_t)h.stat[12];
     }
     return G4_OK;
 }

@@ -62,6 +62,11 @@ int g4_layout(const g4_tree_params *tp, int64_t n, WsLayout *L)
     L->q3 = take((size_t)cap * 10 * 4);
     L->mom = take((size_t)cap * MOM_STRIDE * 8);
     L->aseed = take((size_t)n * 4);
+    // a walk grid never has more wavefronts than work items (<= n), rounded up to whole blocks of 4
+    int64_t waves = ((n > 0 ? n : 1) + 3) / 4 * 4;
+    if (waves > G4_WALK_MAX_WAVES) waves = G4_WALK_MAX_WAVES;
+    L->spill_waves = waves;
+    L->spill = take((size_t)waves * G4_WALK_SPILL * 16);
     size_t sb = 0;
     if (rocprim::radix_sort_pairs((void *)nullptr, sb, (uint64_t *)nullptr, (uint64_t *)nullptr,
                                   (uint32_t *)nullptr, (uint32_t *)nullptr, (size_t)(n > 0 ? n : 1), 0, 63) !=

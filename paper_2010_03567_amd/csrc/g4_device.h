@@ -47,7 +47,7 @@ __device__ __forceinline__ float lr_force_x3(float x)
 {
     if (x < 0.5f) {
         float x2 = x * x;
-        float s = 1.0f / 3 + x2 * (-1.0f / 5 + x2 * (1.0f / 14 + x2 * (-1.0f / 54 + x2 * (1.0f / 264 - x2 / 1560))));
+        float s = 1.0f / 3 + x2 * (-1.0f / 5 + x2 * (1.0f / 14 + x2 * (-1.0f / 54 + x2 * (1.0f / 264 - x2 * (1.0f / 1560)))));
         return 4.0f * INV_SQRTPI * s;
     }
     float ex = expneg(x * x);
@@ -58,7 +58,7 @@ __device__ __forceinline__ float erf_over_x(float x)
 {
     if (x < 0.5f) {
         float x2 = x * x;
-        float s = 1.0f + x2 * (-1.0f / 3 + x2 * (1.0f / 10 + x2 * (-1.0f / 42 + x2 * (1.0f / 216 - x2 / 1320))));
+        float s = 1.0f + x2 * (-1.0f / 3 + x2 * (1.0f / 10 + x2 * (-1.0f / 42 + x2 * (1.0f / 216 - x2 * (1.0f / 1320)))));
         return 2.0f * INV_SQRTPI * s;
     }
     return (1.0f - erfc_hastings(x, expneg(x * x))) * rcp(x);

@@ -8,6 +8,15 @@
 
 #define G4_MAXLEV 21  // 63-bit Morton keys: 21 bits per axis
 
+// Traversal stack of the walk: entries needed at most, entries kept in LDS
+// (fewer with the diagnostic G4_WALK_LDS_STACK environment variable), the
+// device spill area per wavefront (room for the whole stack, so any LDS share
+// is safe), and the wavefront cap of the persistent walk grid.
+#define G4_WALK_STACK (1 + 7 * (G4_MAXLEV - 1) + 8)
+#define G4_WALK_LDS_STACK 48
+#define G4_WALK_SPILL G4_WALK_STACK
+#define G4_WALK_MAX_WAVES 8192
+
 struct g4_ctx {
     int device;
     hipStream_t stream;
@@ -65,6 +74,8 @@ struct g4_tree {
     float *q3;                // 10 floats per node (potential only)
     double *mom;              // MOM_STRIDE doubles per node
     float *aseed;             // n floats, sorted order
+    uint4 *walk_spill;        // G4_WALK_SPILL stack entries per wavefront of the walk
+    int64_t walk_spill_waves; // wavefronts with a spill area (multiple of 4)
     // forest of independent boxes: one root per box (nodes 0..nbox-1)
     int nbox;
     uint4 *items;             // device work items of the walk (first, count, root), 0 for a single tree
@@ -79,9 +90,10 @@ struct g4_tree {
 
 // Layout of a tree workspace (byte offsets).
 struct WsLayout {
-    size_t ctr, keys0, keys1, perm0, perm1, parts, bfirst, bcount, parent, wn, q3, mom, aseed, sort_tmp, sort_bytes,
-        total;
+    size_t ctr, keys0, keys1, perm0, perm1, parts, bfirst, bcount, parent, wn, q3, mom, aseed, spill, sort_tmp,
+        sort_bytes, total;
     int64_t cap;
+    int64_t spill_waves;
 };
 
 int g4_layout(const g4_tree_params *tp, int64_t n, WsLayout *L);

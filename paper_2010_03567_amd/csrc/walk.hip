@@ -8,16 +8,14 @@
 // systems" (spline softening of edge h = 2.8 eps0).
 //
 // Mapping to CDNA4: one 64-lane wavefront walks the tree for a group of up to
-// 64 consecutive Morton-sorted particles, one particle per lane.  Traversal is
-// wavefront-uniform: a small LDS stack holds (first sibling, sibling count,
-// 64-bit lane mask) entries, so the node index is uniform and the 64-byte node
-// record arrives through scalar loads (one read serves all lanes).  Every lane
-// takes its own opening decision for its own particle, exactly as in the
-// per-particle walk of the paper; __ballot turns the decisions into the masks
-// of lanes that open the node (pushed with the children) or use its
-// multipoles.  Interactions are FP32 arithmetic on int32 nearest-image
-// differences; partial sums are flushed into per-lane FP64 accumulators.
+// 64 consecutive Morton-sorted particles.  Every target takes its own opening
+// decisions, exactly as in the per-particle walk of the paper, but the work is
+// packed so that lanes stay busy: (node, target) visits, particle-node and
+// particle-particle interactions are each issued 64 at a time from LDS (see
+// the kernel below).  Interactions are FP32 arithmetic on int32 nearest-image
+// differences, summed per target in FP64.
 #include <algorithm>
+#include <cstdlib>
 #include <new>
 #include <vector>
 
@@ -47,10 +45,13 @@ struct WalkArgs {
     uint32_t *counts;
     float *aout_caller, *aout_sorted;
     unsigned long long *stat;   // 3 counters: p2p, p2m, visits
-    unsigned long long *wstat;  // 3 counters: node pops, P2M passes, P2P source iterations (per wavefront)
+    unsigned long long *wstat;  // visit, P2M and P2P passes, deepest stack (slots 9..12)
     const uint4 *items;         // work items (first particle, count, root node), or null: groups of `group`
     uint32_t nitems;
     uint32_t *item_ctr;         // zeroed before the launch
+    uint4 *spill;               // per-wavefront spill area of the traversal stack
+    int64_t spill_waves;        // wavefronts the spill area has room for (a multiple of 4)
+    int lds_stk;                // stack entries kept in LDS (<= WK_LDS_STK)
 };
 
 // g1, g2, g3 (and g0) of the interaction kernel at r (r2, rinv given), r >= h.
@@ -80,28 +81,189 @@ __device__ __forceinline__ void gfun(float r2, float rinv, const WalkArgs &A, fl
     }
 }
 
+// ---------------------------------------------------------------------------
+// Decide-then-evaluate wavefront walk.
+//
+// A wavefront owns one group of up to 64 targets (one per lane) and keeps, in
+// its own slice of LDS, the targets, their FP64 accumulators, a traversal
+// stack and two rings of pending interactions.  A stack entry is a set of
+// sibling nodes [first, first + c) together with the mask of target lanes that
+// must look at them.  Every (node, target) pair of an entry gets one lane of a
+// visit pass, so a pass is full however sparse the mask; each lane takes the
+// per-target decision of the paper (drop beyond r_cut, open, or use the
+// multipoles).  Accepted pairs go to the node ring, opened leaves expand into
+// (source particle, target) pairs in the particle ring, and opened internal
+// nodes are OR-ed into per-child masks that become new stack entries.  A ring
+// is evaluated 64 pairs at a time, every lane busy, and each result is added
+// into the target's FP64 accumulator with an LDS atomic.
+// ---------------------------------------------------------------------------
+
+// Stack depth bound (entries of 16 bytes; the constants are in g4_internal.h):
+// entries hold sibling nodes of one level, 0..G4_MAXLEV; processing an entry
+// pushes at most 8, and at most 7 of them wait per level below the current
+// path, so at most 7 (G4_MAXLEV - 1) + 8 entries are live after the root's.
+// The top entries (WK_LDS_STK, or fewer if asked for) live in LDS, deeper ones
+// in a per-wavefront spill area of the tree workspace.
+#define WK_STK G4_WALK_STACK
+#define WK_LDS_STK G4_WALK_LDS_STACK
+#define WK_SPILL G4_WALK_SPILL
+#define WK_RING 128  // pending pairs per ring: < 64 before an append of <= 64
+
+// Per-child visit record, staged in LDS for the passes over one entry.
+struct __attribute__((aligned(16))) VisitRec {
+    uint32_t cx, cy, cz;
+    float crit;         // relative: M l^p; geometric: l^2
+    uint32_t gx, gy, gz;
+    uint32_t lint;      // exclusion half-size on the grid (all ones at level 0, zero if no exclusion)
+    float hl;           // half side (physical)
+    uint32_t pad[3];
+};
+
+// One wavefront's LDS: 5632 bytes without the potential (7 wavefronts per
+// SIMD fit in the 160 KiB of a CU), 6144 with it.
+#define FLAG_OPEN 1
+#define FLAG_USE 2
+template <bool POT>
+struct __attribute__((aligned(16))) WaveLds {
+    uint4 tgt[64];                 // target x, y, z (grid) and alpha |a_old| (bits)
+    double acc[POT ? 4 : 3][64];   // a_x, a_y, a_z (, potential), before the factor G, component-major
+    uint32_t pm_idx[WK_RING];      // node of each pending particle-node pair
+    uint32_t pp_idx[WK_RING];      // source particle of each pending particle-particle pair
+    uint8_t pm_tgt[WK_RING];       // target lane of each pending pair
+    uint8_t pp_tgt[WK_RING];
+    VisitRec rec[8];               // children of the current entry
+    uint8_t flag[8][64];           // flag[j][t]: FLAG_OPEN / FLAG_USE of child j for target t (t in the mask)
+    uint8_t rmap[64];              // rank within the entry mask -> lane
+    uint8_t lmap[64];              // rank within an opened leaf's mask -> lane
+    uint4 stk[WK_LDS_STK];         // (first node, count, mask lo, mask hi), top of the stack
+};
+
+__device__ __forceinline__ uint32_t lanes_below(uint64_t m)
+{
+    return __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+}
+// readfirstlane/readlane return int: go through uint32_t so no half of a mask sign-extends
+__device__ __forceinline__ uint32_t uni(uint32_t x) { return (uint32_t)__builtin_amdgcn_readfirstlane((int)x); }
+__device__ __forceinline__ uint32_t lane_val(uint32_t x, uint32_t l)
+{
+    return (uint32_t)__builtin_amdgcn_readlane((int)x, (int)l);
+}
+__device__ __forceinline__ void wave_sync_lds()
+{
+    // LDS operations of one wavefront execute in order; this only keeps the
+    // compiler from moving LDS accesses across the point.
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+}
+__device__ __forceinline__ void lds_add(double *p, double v)
+{
+    __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
+}
+
+// 64 particle-node interactions from the node ring, one per lane (lanes >= n idle).
+template <int KER, bool POT>
+__device__ __forceinline__ void eval_p2m(const WalkArgs &A, WaveLds<POT> &W, uint32_t head, uint32_t n, int lane)
+{
+    if ((uint32_t)lane >= n) return;
+    const uint32_t q = (head + lane) & (WK_RING - 1);
+    const uint32_t node = W.pm_idx[q], t = W.pm_tgt[q];
+    const uint4 T = W.tgt[t];
+    const WNode *nd = A.wn + node;
+    const uint4 c4 = *reinterpret_cast<const uint4 *>(nd);
+    const float4 qa = *reinterpret_cast<const float4 *>(&nd->q[0]);
+    const float2 qb = *reinterpret_cast<const float2 *>(&nd->q[4]);
+    const float mass = __uint_as_float(c4.w);
+    const float dx = (float)(int32_t)(c4.x - T.x) * A.unit;
+    const float dy = (float)(int32_t)(c4.y - T.y) * A.unit;
+    const float dz = (float)(int32_t)(c4.z - T.z) * A.unit;
+    const float r2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
+    const float rinv = rsq(r2);
+    float g0, g1, g2, g3;
+    gfun<KER>(r2, rinv, A, g0, g1, g2, g3);
+    float fx, fy, fz, fp = 0.f;
+    // Q2 packed xx xy xz yy yz zz
+    const float qx = fmaf(qa.x, dx, fmaf(qa.y, dy, qa.z * dz));
+    const float qy = fmaf(qa.y, dx, fmaf(qa.w, dy, qb.x * dz));
+    const float qz = fmaf(qa.z, dx, fmaf(qb.x, dy, qb.y * dz));
+    const float rqr = fmaf(dx, qx, fmaf(dy, qy, dz * qz));
+    const float tr = qa.x + qa.w + qb.y;
+    if (A.order >= 3) {
+        const float fac = fmaf(mass, g1, 0.5f * fmaf(g2, tr, g3 * rqr));
+        fx = -fmaf(fac, dx, g2 * qx);
+        fy = -fmaf(fac, dy, g2 * qy);
+        fz = -fmaf(fac, dz, g2 * qz);
+        if (POT) {
+            const float *o = A.q3 + (size_t)node * 10;
+            // Q3 . D3 = 3 g2 (t . r) + g3 Q3(r, r, r), t_k = sum_i Q3_iik
+            const float tx = o[0] + o[3] + o[5], ty = o[1] + o[6] + o[8], tz = o[2] + o[7] + o[9];
+            const float c3 = o[0] * dx * dx * dx + o[6] * dy * dy * dy + o[9] * dz * dz * dz +
+                             3.f * (o[1] * dx * dx * dy + o[2] * dx * dx * dz + o[3] * dx * dy * dy +
+                                    o[5] * dx * dz * dz + o[7] * dy * dy * dz + o[8] * dy * dz * dz) +
+                             6.f * o[4] * dx * dy * dz;
+            const float q3d3 = 3.f * g2 * (tx * dx + ty * dy + tz * dz) + g3 * c3;
+            fp = -(mass * g0 + 0.5f * (g1 * tr + g2 * rqr) + q3d3 * (1.0f / 6.0f));
+        }
+    } else {
+        const float fac = mass * g1;
+        fx = -fac * dx;
+        fy = -fac * dy;
+        fz = -fac * dz;
+        if (POT) fp = -(mass * g0 + 0.5f * (g1 * tr + g2 * rqr));
+    }
+    lds_add(&W.acc[0][t], (double)fx);
+    lds_add(&W.acc[1][t], (double)fy);
+    lds_add(&W.acc[2][t], (double)fz);
+    if constexpr (POT) lds_add(&W.acc[3][t], (double)fp);
+}
+
+// 64 particle-particle interactions from the particle ring, one per lane.
+template <int KER, bool POT>
+__device__ __forceinline__ void eval_p2p(const WalkArgs &A, WaveLds<POT> &W, uint32_t head, uint32_t n, int64_t i0,
+                                         int lane)
+{
+    if ((uint32_t)lane >= n) return;
+    const uint32_t q = (head + lane) & (WK_RING - 1);
+    const uint32_t j = W.pp_idx[q], t = W.pp_tgt[q];
+    const uint4 T = W.tgt[t];
+    const uint4 src = A.parts[j];
+    const float mj = ((int64_t)j != i0 + (int64_t)t) ? __uint_as_float(src.w) : 0.f;
+    const float sx = (float)(int32_t)(src.x - T.x) * A.unit;
+    const float sy = (float)(int32_t)(src.y - T.y) * A.unit;
+    const float sz = (float)(int32_t)(src.z - T.z) * A.unit;
+    const float s2 = fmaf(sx, sx, fmaf(sy, sy, sz * sz));
+    float K, Wp;
+    pair_kernel<KER, POT>(s2, A.asplit, A.h2, A.hinv, K, Wp);
+    const float mk = mj * K;
+    lds_add(&W.acc[0][t], (double)(mk * sx));
+    lds_add(&W.acc[1][t], (double)(mk * sy));
+    lds_add(&W.acc[2][t], (double)(mk * sz));
+    if constexpr (POT) lds_add(&W.acc[3][t], (double)(-mj * Wp));
+}
+
 template <int KER, int CRIT, bool POT>
 __global__ __launch_bounds__(256) void k_walk(const WalkArgs A)
 {
-    __shared__ uint4 stk[4][32];
+    __shared__ WaveLds<POT> lds[4];
     const int lane = threadIdx.x & 63;
-    const int wv = threadIdx.x >> 6;
-    uint32_t t_pp = 0, t_pm = 0, t_visit = 0;  // per-lane totals over all items
-    uint32_t w_pop = 0, w_pm = 0, w_pp = 0;    // wavefront-level work (uniform counters)
+    WaveLds<POT> &W = lds[threadIdx.x >> 6];
+    uint4 *const spill = A.spill + (size_t)(blockIdx.x * 4 + (threadIdx.x >> 6)) * WK_SPILL;
+    uint32_t t_pp = 0;                                 // per-lane total of particle-particle pairs
+    uint32_t u_pm = 0, u_visit = 0;                    // wavefront totals (per launch < 2^32 per wave)
+    uint32_t w_pass = 0, w_pm = 0, w_pp = 0;           // 64-lane passes of each kind
+    int max_sp = 0;                                    // deepest stack seen
 
-    // persistent wavefront: pull work items (a group of particles of one tree) until none are left
     for (;;) {
     uint32_t it = 0;
     if (lane == 0) it = atomicAdd(A.item_ctr, 1u);
-    it = (uint32_t)__shfl((int)it, 0);
+    it = uni(it);  // all lanes are active here, so the first lane is lane 0
     if (it >= A.nitems) break;
     int64_t i0;
     uint32_t gcount, root;
     if (A.items) {
         const uint4 w = A.items[it];
-        i0 = w.x;
-        gcount = w.y;
-        root = w.z;
+        i0 = uni(w.x);
+        gcount = uni(w.y);
+        root = uni(w.z);
     } else {
         i0 = (int64_t)it * A.group;
         gcount = (uint32_t)min((int64_t)A.group, A.n - i0);
@@ -109,161 +271,192 @@ __global__ __launch_bounds__(256) void k_walk(const WalkArgs A)
     }
     const int64_t i = i0 + lane;
     const bool act = (uint32_t)lane < gcount;
-    const uint4 me = A.parts[act ? i : i0];
-    const float arel = CRIT == 1 ? A.alpha * (act ? A.aseed[i] : 0.f) : 0.f;
-
-    double dax = 0.0, day = 0.0, daz = 0.0, dpot = 0.0;
-    float fx = 0.f, fy = 0.f, fz = 0.f, fp = 0.f;
-    uint32_t n_pp = 0, n_pm = 0, n_visit = 0;
-    int pending = 0;
-
+    if (act) {
+        const uint4 me = A.parts[i];
+        const float arel = CRIT == 1 ? A.alpha * A.aseed[i] : 0.f;
+        W.tgt[lane] = make_uint4(me.x, me.y, me.z, __float_as_uint(arel));
+    }
+    W.acc[0][lane] = 0.0;
+    W.acc[1][lane] = 0.0;
+    W.acc[2][lane] = 0.0;
+    if constexpr (POT) W.acc[3][lane] = 0.0;
     const uint64_t amask = __ballot(act);
+    if (lane == 0) W.stk[0] = make_uint4(root, 1u, (uint32_t)amask, (uint32_t)(amask >> 32));
+    uint32_t n_pp = 0, n_pm = 0;
     int sp = 1;
-    if (lane == 0) stk[wv][0] = make_uint4(root, 1u, (uint32_t)amask, (uint32_t)(amask >> 32));
-    __builtin_amdgcn_wave_barrier();
+    uint32_t pm_h = 0, pm_t = 0, pp_h = 0, pp_t = 0;   // ring heads and tails (uniform)
+    wave_sync_lds();
 
     while (sp > 0) {
-        const uint4 e = stk[wv][sp - 1];
-        // readfirstlane returns int: go through uint32_t so no half of the mask sign-extends
-        const uint32_t node = (uint32_t)__builtin_amdgcn_readfirstlane(e.x);
-        const uint32_t cnt = (uint32_t)__builtin_amdgcn_readfirstlane(e.y);
-        const uint64_t mask = ((uint64_t)(uint32_t)__builtin_amdgcn_readfirstlane(e.w) << 32) |
-                              (uint64_t)(uint32_t)__builtin_amdgcn_readfirstlane(e.z);
-        if (cnt > 1) {
-            if (lane == 0) stk[wv][sp - 1] = make_uint4(node + 1, cnt - 1, e.z, e.w);
+        // ---- pop an entry: nodes [first, first + c) for the lanes in mask m; stage the nodes ----
+        sp--;
+        uint4 e;
+        if (sp < A.lds_stk) {
+            e = W.stk[sp];
         } else {
-            sp--;
+            // deeper entries were written by lane 0; lane 0 reads them back
+            e = make_uint4(0u, 0u, 0u, 0u);
+            if (lane == 0) e = spill[sp - A.lds_stk];
         }
-        const WNode nd = A.wn[node];
-        w_pop++;
-        const int level = (int)(nd.meta & 0xffu);
-        const bool leaf = (nd.meta & WN_LEAF) != 0;
-        bool mine = (mask >> lane) & 1ull;
+        const uint32_t first = uni(e.x), c = uni(e.y);
+        const uint64_t m = ((uint64_t)uni(e.w) << 32) | (uint64_t)uni(e.z);
+        const uint32_t k = (uint32_t)__builtin_popcountll(m);
+        const uint32_t slots = c * k;
+        const float invk = rcp((float)k);  // hardware reciprocal: the quotients below stay exact
+        if ((m >> lane) & 1ull) W.rmap[lanes_below(m)] = (uint8_t)lane;
+        uint32_t v_next = 0, v_num = 0, v_meta = 0;   // lane j < c: fields of child j
+        if ((uint32_t)lane < c) {
+            const WNode nd = A.wn[first + lane];
+            const int level = (int)(nd.meta & 0xffu);
+            const float l = ldexpf(A.box, -level);
+            VisitRec r;
+            r.cx = nd.cx;
+            r.cy = nd.cy;
+            r.cz = nd.cz;
+            if (CRIT == 0) r.crit = l * l;
+            else r.crit = nd.mass * (A.order >= 3 ? l * l * l : l * l);
+            r.gx = nd.gx;
+            r.gy = nd.gy;
+            r.gz = nd.gz;
+            r.lint = level == 0 ? 0xffffffffu : (A.exclusion ? 1u << (A.S - level) : 0u);
+            r.hl = 0.5f * l;
+            r.pad[0] = r.pad[1] = r.pad[2] = 0u;
+            W.rec[lane] = r;
+            v_next = nd.next;
+            v_num = nd.num;
+            v_meta = nd.meta;
+        }
+        wave_sync_lds();
 
-        const float dx = (float)(int32_t)(nd.cx - me.x) * A.unit;
-        const float dy = (float)(int32_t)(nd.cy - me.y) * A.unit;
-        const float dz = (float)(int32_t)(nd.cz - me.z) * A.unit;
-        const float r2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
-        const uint32_t ex = uabs((int32_t)(nd.gx - me.x));
-        const uint32_t ey = uabs((int32_t)(nd.gy - me.y));
-        const uint32_t ez = uabs((int32_t)(nd.gz - me.z));
-        const float l = ldexpf(A.box, -level);
-        if (KER == 1) {
-            // nearest edge of the node's cube farther than r_cut: drop it
-            const float hl = 0.5f * l;
-            const float qx = fmaxf((float)ex * A.unit - hl, 0.f);
-            const float qy = fmaxf((float)ey * A.unit - hl, 0.f);
-            const float qz = fmaxf((float)ez * A.unit - hl, 0.f);
-            mine = mine && (fmaf(qx, qx, fmaf(qy, qy, qz * qz)) <= A.rcut2);
-        }
-        bool inside = level == 0;
-        if (A.exclusion && level > 0) {
-            const uint32_t lint = 1u << (A.S - level);
-            inside = ex < lint && ey < lint && ez < lint;
-        }
-        const float rinv = rsq(r2);
-        bool accept = !inside && r2 >= A.h2;
-        if (CRIT == 0) {
-            accept = accept && (l * l < A.theta2 * r2);
-        } else {
-            // M (l/r)^p / r^2 < alpha |a|  <=>  M l^p < alpha |a| r^(p+2)
-            const float lp = A.order >= 3 ? l * l * l : l * l;
-            const float rp = A.order >= 3 ? r2 * r2 * r2 * rinv : r2 * r2;
-            accept = accept && (nd.mass * lp < arel * rp);
-        }
-        n_visit += mine;
-        const bool use = mine && accept;
-        const uint64_t openm = __ballot(mine && !accept);
-        if (__ballot(use)) {
-            w_pm++;
-            if (use) {
-                float g0, g1, g2, g3;
-                gfun<KER>(r2, rinv, A, g0, g1, g2, g3);
-                if (A.order >= 3) {
-                    const float qx = fmaf(nd.q[0], dx, fmaf(nd.q[1], dy, nd.q[2] * dz));
-                    const float qy = fmaf(nd.q[1], dx, fmaf(nd.q[3], dy, nd.q[4] * dz));
-                    const float qz = fmaf(nd.q[2], dx, fmaf(nd.q[4], dy, nd.q[5] * dz));
-                    const float rqr = fmaf(dx, qx, fmaf(dy, qy, dz * qz));
-                    const float tr = nd.q[0] + nd.q[3] + nd.q[5];
-                    const float fac = fmaf(nd.mass, g1, 0.5f * fmaf(g2, tr, g3 * rqr));
-                    fx -= fmaf(fac, dx, g2 * qx);
-                    fy -= fmaf(fac, dy, g2 * qy);
-                    fz -= fmaf(fac, dz, g2 * qz);
-                    if (POT) {
-                        const float *o = A.q3 + (size_t)node * 10;
-                        // Q3 . D3 = 3 g2 (t . r) + g3 Q3(r, r, r), t_k = sum_i Q3_iik
-                        const float tx = o[0] + o[3] + o[5], ty = o[1] + o[6] + o[8], tz = o[2] + o[7] + o[9];
-                        const float c3 = o[0] * dx * dx * dx + o[6] * dy * dy * dy + o[9] * dz * dz * dz +
-                                         3.f * (o[1] * dx * dx * dy + o[2] * dx * dx * dz + o[3] * dx * dy * dy +
-                                                o[5] * dx * dz * dz + o[7] * dy * dy * dz + o[8] * dy * dz * dz) +
-                                         6.f * o[4] * dx * dy * dz;
-                        const float q3d3 = 3.f * g2 * (tx * dx + ty * dy + tz * dz) + g3 * c3;
-                        fp -= nd.mass * g0 + 0.5f * (g1 * tr + g2 * rqr) + q3d3 * (1.0f / 6.0f);
-                    }
-                } else {
-                    const float fac = nd.mass * g1;
-                    fx -= fac * dx;
-                    fy -= fac * dy;
-                    fz -= fac * dz;
-                    if (POT) {
-                        const float qx = fmaf(nd.q[0], dx, fmaf(nd.q[1], dy, nd.q[2] * dz));
-                        const float qy = fmaf(nd.q[1], dx, fmaf(nd.q[3], dy, nd.q[4] * dz));
-                        const float qz = fmaf(nd.q[2], dx, fmaf(nd.q[4], dy, nd.q[5] * dz));
-                        const float rqr = fmaf(dx, qx, fmaf(dy, qy, dz * qz));
-                        const float tr = nd.q[0] + nd.q[3] + nd.q[5];
-                        fp -= nd.mass * g0 + 0.5f * (g1 * tr + g2 * rqr);
-                    }
-                }
-                n_pm++;
+        // ---- visit passes: 64 (child, target) slots at a time ----
+        for (uint32_t base = 0; base < slots; base += 64) {
+            const uint32_t p = base + lane;
+            const bool valid = p < slots;
+            uint32_t j = (uint32_t)(((float)p + 0.5f) * invk);  // exact p / k for p < 512
+            uint32_t rank = p - j * k;
+            if (!valid) j = rank = 0;
+            const uint32_t t = W.rmap[rank];
+            const uint4 T = W.tgt[t];
+            const VisitRec R = W.rec[j];
+            const float dx = (float)(int32_t)(R.cx - T.x) * A.unit;
+            const float dy = (float)(int32_t)(R.cy - T.y) * A.unit;
+            const float dz = (float)(int32_t)(R.cz - T.z) * A.unit;
+            const float r2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
+            const uint32_t ex = uabs((int32_t)(R.gx - T.x));
+            const uint32_t ey = uabs((int32_t)(R.gy - T.y));
+            const uint32_t ez = uabs((int32_t)(R.gz - T.z));
+            bool ok = valid;
+            if (KER == 1) {
+                // nearest edge of the node's cube farther than r_cut: drop it
+                const float qx = fmaxf((float)ex * A.unit - R.hl, 0.f);
+                const float qy = fmaxf((float)ey * A.unit - R.hl, 0.f);
+                const float qz = fmaxf((float)ez * A.unit - R.hl, 0.f);
+                ok = ok && (fmaf(qx, qx, fmaf(qy, qy, qz * qz)) <= A.rcut2);
             }
-            if (++pending >= 8) {
-                dax += fx; day += fy; daz += fz;
-                if (POT) dpot += fp;
-                fx = fy = fz = fp = 0.f;
-                pending = 0;
-            }
-        }
-        if (openm) {
-            if (leaf) {
-                w_pp += nd.num;
-                const bool op = (openm >> lane) & 1ull;
-                for (uint32_t j = nd.next; j < nd.next + nd.num; j++) {
-                    const uint4 src = A.parts[j];
-                    const float mj = (op && (int64_t)j != i) ? __uint_as_float(src.w) : 0.f;
-                    const float sx = (float)(int32_t)(src.x - me.x) * A.unit;
-                    const float sy = (float)(int32_t)(src.y - me.y) * A.unit;
-                    const float sz = (float)(int32_t)(src.z - me.z) * A.unit;
-                    const float s2 = fmaf(sx, sx, fmaf(sy, sy, sz * sz));
-                    float K, W;
-                    pair_kernel<KER, POT>(s2, A.asplit, A.h2, A.hinv, K, W);
-                    const float mk = mj * K;
-                    fx = fmaf(mk, sx, fx);
-                    fy = fmaf(mk, sy, fy);
-                    fz = fmaf(mk, sz, fz);
-                    if (POT) fp = fmaf(-mj, W, fp);
-                }
-                if (op) n_pp += nd.num - ((i >= (int64_t)nd.next && i < (int64_t)(nd.next + nd.num)) ? 1u : 0u);
-                dax += fx; day += fy; daz += fz;
-                if (POT) dpot += fp;
-                fx = fy = fz = fp = 0.f;
-                pending = 0;
+            const bool inside = max(ex, max(ey, ez)) < R.lint;
+            const float rinv = rsq(r2);
+            bool accept = !inside && r2 >= A.h2;
+            if (CRIT == 0) {
+                accept = accept && (R.crit < A.theta2 * r2);
             } else {
-                if (lane == 0) stk[wv][sp] = make_uint4(nd.next, nd.num, (uint32_t)openm, (uint32_t)(openm >> 32));
-                sp++;
+                // M (l/r)^p / r^2 < alpha |a|  <=>  M l^p < alpha |a| r^(p+2)
+                const float rp = A.order >= 3 ? r2 * r2 * r2 * rinv : r2 * r2;
+                accept = accept && (R.crit < __uint_as_float(T.w) * rp);
+            }
+            const bool use = ok && accept;
+            const uint64_t um = __ballot(use);
+            if (use) {
+                const uint32_t q = (pm_t + lanes_below(um)) & (WK_RING - 1);
+                W.pm_idx[q] = first + j;
+                W.pm_tgt[q] = (uint8_t)t;
+            }
+            // every (child, target) pair of the entry has exactly one slot: no clearing needed
+            if (valid) W.flag[j][t] = (uint8_t)(use ? FLAG_USE : (ok ? FLAG_OPEN : 0));
+            const uint32_t nu = (uint32_t)__builtin_popcountll(um);
+            pm_t += nu;
+            u_pm += nu;
+            u_visit += (uint32_t)__builtin_popcountll(__ballot(ok));
+            w_pass++;
+            if (pm_t - pm_h >= 64) {
+                wave_sync_lds();
+                eval_p2m<KER, POT>(A, W, pm_h, 64u, lane);
+                pm_h += 64;
+                w_pm++;
             }
         }
-        __builtin_amdgcn_wave_barrier();
+        wave_sync_lds();
+
+        // ---- opened children: internal ones become entries, leaves expand into pairs ----
+        const bool inm = (m >> lane) & 1ull;
+        for (uint32_t jj = 0; jj < c; jj++) {
+            const uint32_t f = W.flag[jj][lane];
+            n_pm += (inm && f == FLAG_USE) ? 1u : 0u;
+            const uint64_t om = __ballot(f == FLAG_OPEN) & m;
+            if (!om) continue;
+            const uint32_t next = lane_val(v_next, jj), num = lane_val(v_num, jj), meta = lane_val(v_meta, jj);
+            if (!(meta & WN_LEAF)) {
+                if (sp < WK_STK) {
+                    const uint4 ne = make_uint4(next, num, (uint32_t)om, (uint32_t)(om >> 32));
+                    if (lane == 0) {
+                        if (sp < A.lds_stk) W.stk[sp] = ne;
+                        else spill[sp - A.lds_stk] = ne;
+                    }
+                    sp++;
+                    max_sp = max(max_sp, sp);
+                }
+                continue;
+            }
+            const uint32_t lk = (uint32_t)__builtin_popcountll(om);
+            if ((om >> lane) & 1ull) {
+                W.lmap[lanes_below(om)] = (uint8_t)lane;
+                n_pp += num - ((i >= (int64_t)next && i < (int64_t)next + num) ? 1u : 0u);
+            }
+            wave_sync_lds();
+            // chunk of ns sources x lk targets: lane -> (source offset lane / lk, target rank lane % lk)
+            const float lkinv = rcp((float)lk);
+            const uint32_t per = (uint32_t)((64.0f + 0.5f) * lkinv);  // floor(64 / lk) >= 1
+            const uint32_t soff = (uint32_t)(((float)lane + 0.5f) * lkinv);
+            const uint32_t tl = soff < per ? W.lmap[lane - soff * lk] : 0u;
+            for (uint32_t sb = 0; sb < num; sb += per) {
+                const uint32_t ns = min(per, num - sb);
+                if (soff < ns) {
+                    const uint32_t q = (pp_t + lane) & (WK_RING - 1);
+                    W.pp_idx[q] = next + sb + soff;
+                    W.pp_tgt[q] = (uint8_t)tl;
+                }
+                pp_t += ns * lk;
+                if (pp_t - pp_h >= 64) {
+                    wave_sync_lds();
+                    eval_p2p<KER, POT>(A, W, pp_h, 64u, i0, lane);
+                    pp_h += 64;
+                    w_pp++;
+                }
+            }
+        }
     }
-    dax += fx; day += fy; daz += fz;
-    if (POT) dpot += fp;
+    // ---- drain the rings ----
+    wave_sync_lds();
+    while (pm_t != pm_h) {
+        const uint32_t n = min(pm_t - pm_h, 64u);
+        eval_p2m<KER, POT>(A, W, pm_h, n, lane);
+        pm_h += n;
+        w_pm++;
+    }
+    while (pp_t != pp_h) {
+        const uint32_t n = min(pp_t - pp_h, 64u);
+        eval_p2p<KER, POT>(A, W, pp_h, n, i0, lane);
+        pp_h += n;
+        w_pp++;
+    }
+    wave_sync_lds();
 
     if (act) {
         const uint32_t o = A.perm[i];
-        const double gx = A.G * dax, gy = A.G * day, gz = A.G * daz;
+        const double gx = A.G * W.acc[0][lane], gy = A.G * W.acc[1][lane], gz = A.G * W.acc[2][lane];
         A.ax[o] = gx;
         A.ay[o] = gy;
         A.az[o] = gz;
-        if (POT && A.pot) A.pot[o] = A.G * dpot;
+        if (POT && A.pot) A.pot[o] = A.G * W.acc[3][lane];
         const float amag = (float)sqrt(gx * gx + gy * gy + gz * gz);
         if (A.aout_sorted) A.aout_sorted[i] = amag;
         if (A.aout_caller) A.aout_caller[o] = amag;
@@ -273,26 +466,23 @@ __global__ __launch_bounds__(256) void k_walk(const WalkArgs A)
         }
     }
     t_pp += n_pp;
-    t_pm += n_pm;
-    t_visit += n_visit;
+    wave_sync_lds();
     }  // work items
     if (A.stat) {
         // wavefront sums of the interaction counters, one atomic per wavefront
-        unsigned long long s0 = t_pp, s1 = t_pm, s2 = t_visit;
-        for (int off = 32; off > 0; off >>= 1) {
-            s0 += __shfl_xor(s0, off);
-            s1 += __shfl_xor(s1, off);
-            s2 += __shfl_xor(s2, off);
-        }
+        unsigned long long s0 = t_pp;
+        for (int off = 32; off > 0; off >>= 1) s0 += __shfl_xor(s0, off);
         if (lane == 0) {
             atomicAdd(&A.stat[0], s0);
-            atomicAdd(&A.stat[1], s1);
-            atomicAdd(&A.stat[2], s2);
-            // wavefront-level iterations (slots 9..11 of the counter block, walk call only)
+            atomicAdd(&A.stat[1], (unsigned long long)u_pm);
+            atomicAdd(&A.stat[2], (unsigned long long)u_visit);
+            // 64-lane passes of each kind and the deepest stack (slots 9..12 of the counter block,
+            // walk call only)
             if (A.wstat) {
-                atomicAdd(&A.wstat[0], (unsigned long long)w_pop);
+                atomicAdd(&A.wstat[0], (unsigned long long)w_pass);
                 atomicAdd(&A.wstat[1], (unsigned long long)w_pm);
                 atomicAdd(&A.wstat[2], (unsigned long long)w_pp);
+                atomicMax(&A.wstat[3], (unsigned long long)max_sp);  // slot 12
             }
         }
     }
@@ -301,9 +491,9 @@ __global__ __launch_bounds__(256) void k_walk(const WalkArgs A)
 template <int KER, int CRIT, bool POT>
 static void launch_walk(const WalkArgs &A, hipStream_t s)
 {
-    // persistent grid: 4 wavefronts per block, at most 8 resident wavefronts per SIMD
+    // persistent grid: 4 wavefronts per block, each with its own spill area
     int64_t blocks = ((int64_t)A.nitems + 3) / 4;
-    if (blocks > 2048) blocks = 2048;
+    if (blocks > A.spill_waves / 4) blocks = A.spill_waves / 4;
     if (blocks < 1) blocks = 1;
     k_walk<KER, CRIT, POT><<<(unsigned)blocks, 256, 0, s>>>(A);
 }
@@ -376,6 +566,14 @@ int g4_launch_walk(g4_ctx *ctx, g4_tree *t, const g4_walk_params *wp, int kernel
         A.nitems = (uint32_t)((A.n + A.group - 1) / A.group);
     }
     A.item_ctr = &t->ctr->item_ctr;
+    A.spill = t->walk_spill;
+    A.spill_waves = t->walk_spill_waves;
+    A.lds_stk = WK_LDS_STK;
+    if (const char *env = getenv("G4_WALK_LDS_STACK")) {
+        // diagnostic: keep fewer entries in LDS so that the spill path runs
+        const int v = atoi(env);
+        if (v >= 1 && v <= WK_LDS_STK) A.lds_stk = v;
+    }
     G4_HIP(ctx, hipMemsetAsync(A.item_ctr, 0, sizeof(uint32_t), ctx->stream));
     A.wstat = stat_slot == 0 ? t->ctr->stat + 9 : nullptr;
     hipStream_t s = ctx->stream;

@@ -190,6 +190,34 @@ def test_walk_relative_own_prewalk_plummer(g, ctx, plummer_case):
     assert_parity(stack3(out), acc, out["counts"].cpu().numpy(), cnt, "plummer relative, own pre-walk")
 
 
+def test_walk_deep_stack_spills(g, ctx, monkeypatch):
+    """theta = 0.05 on a leaf-size-1 tree of a Plummer sphere opens nearly every
+    node on the way down to the dense core, so the traversal stack gets ~46
+    entries deep; with only 8 of them kept in LDS (diagnostic environment
+    variable) the device spill area carries the rest and the forces stay at
+    parity.  About 1.7e4 criterion evaluations per particle here (against ~600
+    in the other walks) make FP32-vs-FP64 threshold flips more frequent, so the
+    decision-agreement floor is 0.99."""
+    ps = workloads.plummer(20000, seed=5)
+    c = make_case(g, ctx, ps, False, 1)
+    wp = g.walk_params(kernel=0, criterion=0, theta=0.05, eps0=PLUMMER_EPS)
+    acc, pot, cnt = c.ot.walk(kernel=0, criterion=0, theta=0.05, eps0=PLUMMER_EPS, nthreads=16)
+    results = []
+    for lds in ("48", "8"):
+        monkeypatch.setenv("G4_WALK_LDS_STACK", lds)
+        out = g.g4_tree_force(ctx, c.tree, wp, want_pot=True, want_counts=True, want_stats=True)
+        print("LDS stack", lds, "max stack", out["stats"]["max_stack"])
+        assert out["stats"]["max_stack"] > 8
+        a = stack3(out)
+        err = np.linalg.norm(a - acc, axis=1) / np.linalg.norm(acc, axis=1)
+        agree = np.mean(np.all(out["counts"].cpu().numpy() == cnt, axis=1))
+        assert np.median(err) <= MEDIAN_TOL and np.percentile(err, 99.9) <= P999_TOL and agree >= 0.99, (
+            lds, np.median(err), np.percentile(err, 99.9), agree)
+        results.append((out["counts"].cpu().numpy(), a))
+    # the spill changes where entries are kept, not the traversal: same decisions
+    assert np.array_equal(results[0][0], results[1][0])
+
+
 def sr_params(n):
     """Config-2 TreePM parameters scaled to n particles in a unit box (same
     r_s and softening relative to the mean spacing)."""
