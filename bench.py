@@ -179,6 +179,7 @@ def main():
     achieved = walk_flop / (walk_ms * 1e-3)
     util = {"pop": st["n_visit"] / max(1, 64 * st["w_pop"]), "p2m": st["n_p2m"] / max(1, 64 * st["w_p2m"]),
             "p2p": st["n_p2p"] / max(1, 64 * st["w_p2p"])}
+    passes = {k: st[k] for k in ("w_pop", "w_p2m", "w_p2p", "w_entry", "w_leaf", "w_chunk", "max_stack")}
 
     plain_value = n / (ms_per_step * 1e-3)
     best_learned = learned is not None and "forces_per_s" in learned and learned["forces_per_s"] > plain_value
@@ -211,7 +212,7 @@ def main():
                      "traffic": None, "avg_ms": walk_ms, "flop_per_launch": walk_flop},
         "breakdown_ms": {"prewalk": seed_ms, "walk": walk_ms, "rest": ms_per_step - seed_ms - walk_ms},
         "interactions": {"per_particle_p2p": st["n_p2p"] / n, "per_particle_p2m": st["n_p2m"] / n,
-                         "per_particle_visit": st["n_visit"] / n, "lane_utilisation": util,
+                         "per_particle_visit": st["n_visit"] / n, "lane_utilisation": util, "walk_passes": passes,
                          "prewalk_per_particle": {"p2p": st_seed["n_p2p"] / n, "p2m": st_seed["n_p2m"] / n}},
     }
     if not args.no_as_stated:

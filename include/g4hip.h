@@ -106,11 +106,14 @@ typedef struct {
     uint64_t n_seed_p2p, n_seed_p2m, n_seed_visit;  /* same, geometric pre-walk (if run) */
     uint64_t n_pp, n_pn, n_nn;   /* FMM interaction counts */
     uint64_t n_nodes;    /* nodes in the tree */
-    /* 64-lane passes of the walk: node visits, particle-node interactions,
-     * particle-particle interactions; lane utilisation = count / (64 x passes) */
+    /* 64-lane steps of the walk: node visits, particle-node interactions,
+     * particle-particle interactions; lane utilisation = count / (64 x steps) */
     uint64_t w_pop, w_p2m, w_p2p;
     uint32_t flags;      /* bit 0: a leaf at max_depth holds more than leaf_max particles */
-    uint32_t max_stack;  /* deepest traversal stack of the walk (entries; the top 48 are kept in LDS) */
+    uint32_t max_stack;  /* deepest traversal stack of the walk (entries; the top 32 are kept in LDS) */
+    /* walk bookkeeping: sibling sets popped, (opened leaf, target) items,
+     * particle-pair phases of the lane queue */
+    uint64_t w_entry, w_leaf, w_chunk;
 } g4_stats;
 
 /* ---------------------------------------------------------------- context */

@@ -292,6 +292,9 @@ static int tree_force_impl(g4_ctx *ctx, g4_tree *tree, const g4_walk_params *wp,
         stats->w_p2p = h.stat[11];
         stats->flags = h.flags;
         stats->max_stack = (uint32_t)h.stat[12];
+        stats->w_entry = h.stat[13];
+        stats->w_leaf = h.stat[14];
+        stats->w_chunk = h.stat[15];
     }
     return G4_OK;
 }

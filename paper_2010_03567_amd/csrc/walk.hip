@@ -45,7 +45,7 @@ struct WalkArgs {
     uint32_t *counts;
     float *aout_caller, *aout_sorted;
     unsigned long long *stat;   // 3 counters: p2p, p2m, visits
-    unsigned long long *wstat;  // visit, P2M and P2P passes, deepest stack (slots 9..12)
+    unsigned long long *wstat;  // passes, deepest stack, entries, leaves, chunks (slots 9..15)
     const uint4 *items;         // work items (first particle, count, root node), or null: groups of `group`
     uint32_t nitems;
     uint32_t *item_ctr;         // zeroed before the launch
@@ -85,17 +85,18 @@ __device__ __forceinline__ void gfun(float r2, float rinv, const WalkArgs &A, fl
 // Decide-then-evaluate wavefront walk.
 //
 // A wavefront owns one group of up to 64 targets (one per lane) and keeps, in
-// its own slice of LDS, the targets, their FP64 accumulators, a traversal
-// stack and two rings of pending interactions.  A stack entry is a set of
+// its own slice of LDS, the targets, their FP64 accumulators, the top of a
+// traversal stack and rings of pending work.  A stack entry is a set of
 // sibling nodes [first, first + c) together with the mask of target lanes that
 // must look at them.  Every (node, target) pair of an entry gets one lane of a
 // visit pass, so a pass is full however sparse the mask; each lane takes the
 // per-target decision of the paper (drop beyond r_cut, open, or use the
-// multipoles).  Accepted pairs go to the node ring, opened leaves expand into
-// (source particle, target) pairs in the particle ring, and opened internal
-// nodes are OR-ed into per-child masks that become new stack entries.  A ring
-// is evaluated 64 pairs at a time, every lane busy, and each result is added
-// into the target's FP64 accumulator with an LDS atomic.
+// multipoles).  Accepted pairs go to the node ring, evaluated 64 at a time and
+// added to the target's accumulator with an LDS atomic.  An opened leaf gives
+// a (leaf, target) item in the leaf ring; a lane-level queue then walks each
+// item's particles for its target, one pair per lane per step, refilling
+// lanes as their items run out, and adds the item's sum once.  Opened internal
+// nodes are collected per child into the masks of new stack entries.
 // ---------------------------------------------------------------------------
 
 // Stack depth bound (entries of 16 bytes; the constants are in g4_internal.h):
@@ -107,20 +108,25 @@ __device__ __forceinline__ void gfun(float r2, float rinv, const WalkArgs &A, fl
 #define WK_STK G4_WALK_STACK
 #define WK_LDS_STK G4_WALK_LDS_STACK
 #define WK_SPILL G4_WALK_SPILL
-#define WK_RING 128  // pending pairs per ring: < 64 before an append of <= 64
+#define WK_RING 128  // ring capacity: < 64 pending before an append of <= 64
+
+#define NUM_LEAF (1u << 31)  // leaf bit of VisitRec::numleaf
 
 // Per-child visit record, staged in LDS for the passes over one entry.
 struct __attribute__((aligned(16))) VisitRec {
     uint32_t cx, cy, cz;
-    float crit;         // relative: M l^p; geometric: l^2
+    float crit;         // relative: M l^p; geometric: l^2; +inf at level 0 (the root is never used)
     uint32_t gx, gy, gz;
-    uint32_t lint;      // exclusion half-size on the grid (all ones at level 0, zero if no exclusion)
+    int32_t lm1;        // exclusion: cube half-size on the grid minus 1 (-1: no exclusion zone)
     float hl;           // half side (physical)
-    uint32_t pad[3];
+    int32_t nlm1;       // -lm1
+    uint32_t next;      // first child, or first particle of a leaf
+    uint32_t numleaf;   // number of children or particles, NUM_LEAF for a leaf
 };
+static_assert(sizeof(VisitRec) == 48, "VisitRec is 48 bytes");
 
-// One wavefront's LDS: 5632 bytes without the potential (7 wavefronts per
-// SIMD fit in the 160 KiB of a CU), 6144 with it.
+// One wavefront's LDS: 5824 bytes without the potential (7 wavefronts per
+// SIMD fit in the 160 KiB of a CU), 6336 with it.
 #define FLAG_OPEN 1
 #define FLAG_USE 2
 template <bool POT>
@@ -128,16 +134,18 @@ struct __attribute__((aligned(16))) WaveLds {
     uint4 tgt[64];                 // target x, y, z (grid) and alpha |a_old| (bits)
     double acc[POT ? 4 : 3][64];   // a_x, a_y, a_z (, potential), before the factor G, component-major
     uint32_t pm_idx[WK_RING];      // node of each pending particle-node pair
-    uint32_t pp_idx[WK_RING];      // source particle of each pending particle-particle pair
-    uint8_t pm_tgt[WK_RING];       // target lane of each pending pair
-    uint8_t pp_tgt[WK_RING];
+    uint32_t lt_first[WK_RING];    // first particle of each pending opened leaf
+    uint32_t lt_num[WK_RING];      // its particle count
+    uint8_t pm_tgt[WK_RING];       // target lane of each pending particle-node pair
+    uint8_t lt_tgt[WK_RING];       // target lane of each pending opened leaf
     VisitRec rec[8];               // children of the current entry
     uint8_t flag[8][64];           // flag[j][t]: FLAG_OPEN / FLAG_USE of child j for target t (t in the mask)
     uint8_t rmap[64];              // rank within the entry mask -> lane
-    uint8_t lmap[64];              // rank within an opened leaf's mask -> lane
     uint4 stk[WK_LDS_STK];         // (first node, count, mask lo, mask hi), top of the stack
 };
 
+// mask of the active lanes for which c holds
+__device__ __forceinline__ uint64_t ballot(bool c) { return __builtin_amdgcn_ballot_w64(c); }
 __device__ __forceinline__ uint32_t lanes_below(uint64_t m)
 {
     return __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
@@ -187,11 +195,12 @@ __device__ __forceinline__ void eval_p2m(const WalkArgs &A, WaveLds<POT> &W, uin
     const float qz = fmaf(qa.z, dx, fmaf(qb.x, dy, qb.y * dz));
     const float rqr = fmaf(dx, qx, fmaf(dy, qy, dz * qz));
     const float tr = qa.x + qa.w + qb.y;
+    // the node's contribution is -(fx, fy, fz): the sign goes into the FP64 conversion below
     if (A.order >= 3) {
         const float fac = fmaf(mass, g1, 0.5f * fmaf(g2, tr, g3 * rqr));
-        fx = -fmaf(fac, dx, g2 * qx);
-        fy = -fmaf(fac, dy, g2 * qy);
-        fz = -fmaf(fac, dz, g2 * qz);
+        fx = fmaf(fac, dx, g2 * qx);
+        fy = fmaf(fac, dy, g2 * qy);
+        fz = fmaf(fac, dz, g2 * qz);
         if (POT) {
             const float *o = A.q3 + (size_t)node * 10;
             // Q3 . D3 = 3 g2 (t . r) + g3 Q3(r, r, r), t_k = sum_i Q3_iik
@@ -201,43 +210,19 @@ __device__ __forceinline__ void eval_p2m(const WalkArgs &A, WaveLds<POT> &W, uin
                                     o[5] * dx * dz * dz + o[7] * dy * dy * dz + o[8] * dy * dz * dz) +
                              6.f * o[4] * dx * dy * dz;
             const float q3d3 = 3.f * g2 * (tx * dx + ty * dy + tz * dz) + g3 * c3;
-            fp = -(mass * g0 + 0.5f * (g1 * tr + g2 * rqr) + q3d3 * (1.0f / 6.0f));
+            fp = mass * g0 + 0.5f * (g1 * tr + g2 * rqr) + q3d3 * (1.0f / 6.0f);
         }
     } else {
         const float fac = mass * g1;
-        fx = -fac * dx;
-        fy = -fac * dy;
-        fz = -fac * dz;
-        if (POT) fp = -(mass * g0 + 0.5f * (g1 * tr + g2 * rqr));
+        fx = fac * dx;
+        fy = fac * dy;
+        fz = fac * dz;
+        if (POT) fp = mass * g0 + 0.5f * (g1 * tr + g2 * rqr);
     }
-    lds_add(&W.acc[0][t], (double)fx);
-    lds_add(&W.acc[1][t], (double)fy);
-    lds_add(&W.acc[2][t], (double)fz);
-    if constexpr (POT) lds_add(&W.acc[3][t], (double)fp);
-}
-
-// 64 particle-particle interactions from the particle ring, one per lane.
-template <int KER, bool POT>
-__device__ __forceinline__ void eval_p2p(const WalkArgs &A, WaveLds<POT> &W, uint32_t head, uint32_t n, int64_t i0,
-                                         int lane)
-{
-    if ((uint32_t)lane >= n) return;
-    const uint32_t q = (head + lane) & (WK_RING - 1);
-    const uint32_t j = W.pp_idx[q], t = W.pp_tgt[q];
-    const uint4 T = W.tgt[t];
-    const uint4 src = A.parts[j];
-    const float mj = ((int64_t)j != i0 + (int64_t)t) ? __uint_as_float(src.w) : 0.f;
-    const float sx = (float)(int32_t)(src.x - T.x) * A.unit;
-    const float sy = (float)(int32_t)(src.y - T.y) * A.unit;
-    const float sz = (float)(int32_t)(src.z - T.z) * A.unit;
-    const float s2 = fmaf(sx, sx, fmaf(sy, sy, sz * sz));
-    float K, Wp;
-    pair_kernel<KER, POT>(s2, A.asplit, A.h2, A.hinv, K, Wp);
-    const float mk = mj * K;
-    lds_add(&W.acc[0][t], (double)(mk * sx));
-    lds_add(&W.acc[1][t], (double)(mk * sy));
-    lds_add(&W.acc[2][t], (double)(mk * sz));
-    if constexpr (POT) lds_add(&W.acc[3][t], (double)(-mj * Wp));
+    lds_add(&W.acc[0][t], -(double)fx);
+    lds_add(&W.acc[1][t], -(double)fy);
+    lds_add(&W.acc[2][t], -(double)fz);
+    if constexpr (POT) lds_add(&W.acc[3][t], -(double)fp);
 }
 
 template <int KER, int CRIT, bool POT>
@@ -249,8 +234,9 @@ __global__ __launch_bounds__(256) void k_walk(const WalkArgs A)
     uint4 *const spill = A.spill + (size_t)(blockIdx.x * 4 + (threadIdx.x >> 6)) * WK_SPILL;
     uint32_t t_pp = 0;                                 // per-lane total of particle-particle pairs
     uint32_t u_pm = 0, u_visit = 0;                    // wavefront totals (per launch < 2^32 per wave)
-    uint32_t w_pass = 0, w_pm = 0, w_pp = 0;           // 64-lane passes of each kind
+    uint32_t w_pass = 0, w_pm = 0, w_pp = 0;           // 64-lane steps: visits, node pairs, particle pairs
     int max_sp = 0;                                    // deepest stack seen
+    uint32_t w_entry = 0, w_leaf = 0, w_phase = 0;     // sibling sets, (leaf, target) items, pair phases
 
     for (;;) {
     uint32_t it = 0;
@@ -280,16 +266,76 @@ __global__ __launch_bounds__(256) void k_walk(const WalkArgs A)
     W.acc[1][lane] = 0.0;
     W.acc[2][lane] = 0.0;
     if constexpr (POT) W.acc[3][lane] = 0.0;
-    const uint64_t amask = __ballot(act);
+    const uint64_t amask = ballot(act);
     if (lane == 0) W.stk[0] = make_uint4(root, 1u, (uint32_t)amask, (uint32_t)(amask >> 32));
-    uint32_t n_pp = 0, n_pm = 0;
+    uint32_t n_pp = 0, n_pm = 0;                      // counts of target `lane` (only with A.counts)
     int sp = 1;
-    uint32_t pm_h = 0, pm_t = 0, pp_h = 0, pp_t = 0;   // ring heads and tails (uniform)
+    uint32_t pm_h = 0, pm_t = 0, lt_h = 0, lt_t = 0;  // ring heads and tails (uniform)
+    // this lane's (leaf, target) item: next source, sources left, target lane and position, partial sums
+    uint32_t q_src = 0, q_rem = 0, q_t = 0, q_self = 0;
+    uint32_t q_x = 0, q_y = 0, q_z = 0;
+    float q_fx = 0.f, q_fy = 0.f, q_fz = 0.f, q_fp = 0.f;
     wave_sync_lds();
+
+    // Particle pairs from the leaf ring: idle lanes take the next items in ring
+    // order; every step evaluates one pair per busy lane.  Without `drain` the
+    // phase ends as soon as a lane cannot be refilled, so every step is full;
+    // lanes keep their unfinished items for the next phase.
+    auto run_pairs = [&](bool drain) {
+        w_phase++;
+        for (;;) {
+            const uint64_t idle = ballot(q_rem == 0);
+            const uint32_t avail = lt_t - lt_h;
+            if (idle && avail) {
+                const uint32_t r = lanes_below(idle);
+                if (q_rem == 0 && r < avail) {
+                    const uint32_t q = (lt_h + r) & (WK_RING - 1);
+                    q_src = W.lt_first[q];
+                    q_rem = W.lt_num[q];
+                    q_t = W.lt_tgt[q];
+                    const uint4 T = W.tgt[q_t];
+                    q_x = T.x;
+                    q_y = T.y;
+                    q_z = T.z;
+                    q_self = (uint32_t)i0 + q_t;  // sorted index of the target itself
+                    t_pp += q_rem - ((q_self - q_src) < q_rem ? 1u : 0u);
+                }
+                lt_h += min((uint32_t)__builtin_popcountll(idle), avail);
+            }
+            const uint64_t busy = ballot(q_rem != 0);
+            if (!busy || (!drain && busy != ~0ull)) break;
+            w_pp++;
+            if (q_rem != 0) {
+                const uint4 src = A.parts[q_src];
+                const float mj = q_src != q_self ? __uint_as_float(src.w) : 0.f;
+                const float sx = (float)(int32_t)(src.x - q_x) * A.unit;
+                const float sy = (float)(int32_t)(src.y - q_y) * A.unit;
+                const float sz = (float)(int32_t)(src.z - q_z) * A.unit;
+                const float s2 = fmaf(sx, sx, fmaf(sy, sy, sz * sz));
+                float K, Wp;
+                pair_kernel<KER, POT>(s2, A.asplit, A.h2, A.hinv, K, Wp);
+                const float mk = mj * K;
+                q_fx = fmaf(mk, sx, q_fx);
+                q_fy = fmaf(mk, sy, q_fy);
+                q_fz = fmaf(mk, sz, q_fz);
+                if (POT) q_fp = fmaf(-mj, Wp, q_fp);
+                q_src++;
+                q_rem--;
+                if (q_rem == 0) {
+                    lds_add(&W.acc[0][q_t], (double)q_fx);
+                    lds_add(&W.acc[1][q_t], (double)q_fy);
+                    lds_add(&W.acc[2][q_t], (double)q_fz);
+                    if constexpr (POT) lds_add(&W.acc[3][q_t], (double)q_fp);
+                    q_fx = q_fy = q_fz = q_fp = 0.f;
+                }
+            }
+        }
+    };
 
     while (sp > 0) {
         // ---- pop an entry: nodes [first, first + c) for the lanes in mask m; stage the nodes ----
         sp--;
+        w_entry++;
         uint4 e;
         if (sp < A.lds_stk) {
             e = W.stk[sp];
@@ -302,9 +348,10 @@ __global__ __launch_bounds__(256) void k_walk(const WalkArgs A)
         const uint64_t m = ((uint64_t)uni(e.w) << 32) | (uint64_t)uni(e.z);
         const uint32_t k = (uint32_t)__builtin_popcountll(m);
         const uint32_t slots = c * k;
-        const float invk = rcp((float)k);  // hardware reciprocal: the quotients below stay exact
+        // p / k for p < 576 as the float fma(p, 1/k, 1/2k), exact with the hardware reciprocal
+        const float invk = rcp((float)k), hinvk = 0.5f * invk;
         if ((m >> lane) & 1ull) W.rmap[lanes_below(m)] = (uint8_t)lane;
-        uint32_t v_next = 0, v_num = 0, v_meta = 0;   // lane j < c: fields of child j
+        uint32_t v_next = 0, v_numleaf = 0;   // lane j < c: child j
         if ((uint32_t)lane < c) {
             const WNode nd = A.wn[first + lane];
             const int level = (int)(nd.meta & 0xffu);
@@ -313,18 +360,20 @@ __global__ __launch_bounds__(256) void k_walk(const WalkArgs A)
             r.cx = nd.cx;
             r.cy = nd.cy;
             r.cz = nd.cz;
-            if (CRIT == 0) r.crit = l * l;
+            if (level == 0) r.crit = __builtin_huge_valf();
+            else if (CRIT == 0) r.crit = l * l;
             else r.crit = nd.mass * (A.order >= 3 ? l * l * l : l * l);
             r.gx = nd.gx;
             r.gy = nd.gy;
             r.gz = nd.gz;
-            r.lint = level == 0 ? 0xffffffffu : (A.exclusion ? 1u << (A.S - level) : 0u);
+            r.lm1 = (A.exclusion && level > 0) ? (int32_t)((1u << (A.S - level)) - 1u) : -1;
             r.hl = 0.5f * l;
-            r.pad[0] = r.pad[1] = r.pad[2] = 0u;
+            r.nlm1 = -r.lm1;
+            r.next = nd.next;
+            r.numleaf = nd.num | ((nd.meta & WN_LEAF) ? NUM_LEAF : 0u);
             W.rec[lane] = r;
-            v_next = nd.next;
-            v_num = nd.num;
-            v_meta = nd.meta;
+            v_next = r.next;
+            v_numleaf = r.numleaf;
         }
         wave_sync_lds();
 
@@ -332,7 +381,7 @@ __global__ __launch_bounds__(256) void k_walk(const WalkArgs A)
         for (uint32_t base = 0; base < slots; base += 64) {
             const uint32_t p = base + lane;
             const bool valid = p < slots;
-            uint32_t j = (uint32_t)(((float)p + 0.5f) * invk);  // exact p / k for p < 512
+            uint32_t j = (uint32_t)fmaf((float)p, invk, hinvk);
             uint32_t rank = p - j * k;
             if (!valid) j = rank = 0;
             const uint32_t t = W.rmap[rank];
@@ -342,18 +391,18 @@ __global__ __launch_bounds__(256) void k_walk(const WalkArgs A)
             const float dy = (float)(int32_t)(R.cy - T.y) * A.unit;
             const float dz = (float)(int32_t)(R.cz - T.z) * A.unit;
             const float r2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
-            const uint32_t ex = uabs((int32_t)(R.gx - T.x));
-            const uint32_t ey = uabs((int32_t)(R.gy - T.y));
-            const uint32_t ez = uabs((int32_t)(R.gz - T.z));
+            // offsets from the cube centre (grid units): |d| < half-size on all axes is the
+            // exclusion zone; the nearest-edge distance is max(|d| unit - l/2, 0) per axis
+            const int32_t gx = (int32_t)(R.gx - T.x), gy = (int32_t)(R.gy - T.y), gz = (int32_t)(R.gz - T.z);
             bool ok = valid;
             if (KER == 1) {
                 // nearest edge of the node's cube farther than r_cut: drop it
-                const float qx = fmaxf((float)ex * A.unit - R.hl, 0.f);
-                const float qy = fmaxf((float)ey * A.unit - R.hl, 0.f);
-                const float qz = fmaxf((float)ez * A.unit - R.hl, 0.f);
+                const float qx = fmaxf(fabsf((float)gx) * A.unit - R.hl, 0.f);
+                const float qy = fmaxf(fabsf((float)gy) * A.unit - R.hl, 0.f);
+                const float qz = fmaxf(fabsf((float)gz) * A.unit - R.hl, 0.f);
                 ok = ok && (fmaf(qx, qx, fmaf(qy, qy, qz * qz)) <= A.rcut2);
             }
-            const bool inside = max(ex, max(ey, ez)) < R.lint;
+            const bool inside = max(gx, max(gy, gz)) <= R.lm1 && min(gx, min(gy, gz)) >= R.nlm1;
             const float rinv = rsq(r2);
             bool accept = !inside && r2 >= A.h2;
             if (CRIT == 0) {
@@ -364,18 +413,33 @@ __global__ __launch_bounds__(256) void k_walk(const WalkArgs A)
                 accept = accept && (R.crit < __uint_as_float(T.w) * rp);
             }
             const bool use = ok && accept;
-            const uint64_t um = __ballot(use);
+            const bool open = ok && !accept;
+            const uint64_t um = ballot(use);
             if (use) {
                 const uint32_t q = (pm_t + lanes_below(um)) & (WK_RING - 1);
                 W.pm_idx[q] = first + j;
                 W.pm_tgt[q] = (uint8_t)t;
             }
+            // opened leaves become (leaf, target) items
+            const bool oleaf = open && (R.numleaf & NUM_LEAF);
+            const uint64_t lm = ballot(oleaf);
+            if (lm) {
+                if (oleaf) {
+                    const uint32_t q = (lt_t + lanes_below(lm)) & (WK_RING - 1);
+                    W.lt_first[q] = R.next;
+                    W.lt_num[q] = R.numleaf & ~NUM_LEAF;
+                    W.lt_tgt[q] = (uint8_t)t;
+                }
+                const uint32_t nl = (uint32_t)__builtin_popcountll(lm);
+                lt_t += nl;
+                w_leaf += nl;
+            }
             // every (child, target) pair of the entry has exactly one slot: no clearing needed
-            if (valid) W.flag[j][t] = (uint8_t)(use ? FLAG_USE : (ok ? FLAG_OPEN : 0));
+            if (valid) W.flag[j][t] = (uint8_t)(use ? FLAG_USE : (open ? FLAG_OPEN : 0));
             const uint32_t nu = (uint32_t)__builtin_popcountll(um);
             pm_t += nu;
             u_pm += nu;
-            u_visit += (uint32_t)__builtin_popcountll(__ballot(ok));
+            u_visit += (uint32_t)__builtin_popcountll(ballot(ok));
             w_pass++;
             if (pm_t - pm_h >= 64) {
                 wave_sync_lds();
@@ -383,54 +447,36 @@ __global__ __launch_bounds__(256) void k_walk(const WalkArgs A)
                 pm_h += 64;
                 w_pm++;
             }
+            if (lt_t - lt_h >= 64) {
+                wave_sync_lds();
+                run_pairs(false);
+            }
         }
         wave_sync_lds();
 
-        // ---- opened children: internal ones become entries, leaves expand into pairs ----
+        // ---- opened internal children become entries; leaves only need counting ----
         const bool inm = (m >> lane) & 1ull;
         for (uint32_t jj = 0; jj < c; jj++) {
+            const uint32_t next = lane_val(v_next, jj), nl = lane_val(v_numleaf, jj);
+            const bool leaf = (nl & NUM_LEAF) != 0;
+            const uint32_t num = nl & ~NUM_LEAF;
+            if (leaf && !A.counts) continue;
             const uint32_t f = W.flag[jj][lane];
-            n_pm += (inm && f == FLAG_USE) ? 1u : 0u;
-            const uint64_t om = __ballot(f == FLAG_OPEN) & m;
+            if (A.counts) {
+                n_pm += (inm && f == FLAG_USE) ? 1u : 0u;
+                if (leaf && inm && f == FLAG_OPEN) n_pp += num - ((uint32_t)(i - next) < num ? 1u : 0u);
+            }
+            if (leaf) continue;
+            const uint64_t om = ballot(f == FLAG_OPEN) & m;
             if (!om) continue;
-            const uint32_t next = lane_val(v_next, jj), num = lane_val(v_num, jj), meta = lane_val(v_meta, jj);
-            if (!(meta & WN_LEAF)) {
-                if (sp < WK_STK) {
-                    const uint4 ne = make_uint4(next, num, (uint32_t)om, (uint32_t)(om >> 32));
-                    if (lane == 0) {
-                        if (sp < A.lds_stk) W.stk[sp] = ne;
-                        else spill[sp - A.lds_stk] = ne;
-                    }
-                    sp++;
-                    max_sp = max(max_sp, sp);
+            if (sp < WK_STK) {
+                const uint4 ne = make_uint4(next, num, (uint32_t)om, (uint32_t)(om >> 32));
+                if (lane == 0) {
+                    if (sp < A.lds_stk) W.stk[sp] = ne;
+                    else spill[sp - A.lds_stk] = ne;
                 }
-                continue;
-            }
-            const uint32_t lk = (uint32_t)__builtin_popcountll(om);
-            if ((om >> lane) & 1ull) {
-                W.lmap[lanes_below(om)] = (uint8_t)lane;
-                n_pp += num - ((i >= (int64_t)next && i < (int64_t)next + num) ? 1u : 0u);
-            }
-            wave_sync_lds();
-            // chunk of ns sources x lk targets: lane -> (source offset lane / lk, target rank lane % lk)
-            const float lkinv = rcp((float)lk);
-            const uint32_t per = (uint32_t)((64.0f + 0.5f) * lkinv);  // floor(64 / lk) >= 1
-            const uint32_t soff = (uint32_t)(((float)lane + 0.5f) * lkinv);
-            const uint32_t tl = soff < per ? W.lmap[lane - soff * lk] : 0u;
-            for (uint32_t sb = 0; sb < num; sb += per) {
-                const uint32_t ns = min(per, num - sb);
-                if (soff < ns) {
-                    const uint32_t q = (pp_t + lane) & (WK_RING - 1);
-                    W.pp_idx[q] = next + sb + soff;
-                    W.pp_tgt[q] = (uint8_t)tl;
-                }
-                pp_t += ns * lk;
-                if (pp_t - pp_h >= 64) {
-                    wave_sync_lds();
-                    eval_p2p<KER, POT>(A, W, pp_h, 64u, i0, lane);
-                    pp_h += 64;
-                    w_pp++;
-                }
+                sp++;
+                max_sp = max(max_sp, sp);
             }
         }
     }
@@ -442,12 +488,7 @@ __global__ __launch_bounds__(256) void k_walk(const WalkArgs A)
         pm_h += n;
         w_pm++;
     }
-    while (pp_t != pp_h) {
-        const uint32_t n = min(pp_t - pp_h, 64u);
-        eval_p2p<KER, POT>(A, W, pp_h, n, i0, lane);
-        pp_h += n;
-        w_pp++;
-    }
+    run_pairs(true);
     wave_sync_lds();
 
     if (act) {
@@ -465,7 +506,6 @@ __global__ __launch_bounds__(256) void k_walk(const WalkArgs A)
             A.counts[2 * (size_t)o + 1] = n_pm;
         }
     }
-    t_pp += n_pp;
     wave_sync_lds();
     }  // work items
     if (A.stat) {
@@ -476,13 +516,16 @@ __global__ __launch_bounds__(256) void k_walk(const WalkArgs A)
             atomicAdd(&A.stat[0], s0);
             atomicAdd(&A.stat[1], (unsigned long long)u_pm);
             atomicAdd(&A.stat[2], (unsigned long long)u_visit);
-            // 64-lane passes of each kind and the deepest stack (slots 9..12 of the counter block,
-            // walk call only)
+            // 64-lane steps of each kind, the deepest stack and the bookkeeping counts (slots 9..15
+            // of the counter block, walk call only)
             if (A.wstat) {
                 atomicAdd(&A.wstat[0], (unsigned long long)w_pass);
                 atomicAdd(&A.wstat[1], (unsigned long long)w_pm);
                 atomicAdd(&A.wstat[2], (unsigned long long)w_pp);
                 atomicMax(&A.wstat[3], (unsigned long long)max_sp);  // slot 12
+                atomicAdd(&A.wstat[4], (unsigned long long)w_entry);
+                atomicAdd(&A.wstat[5], (unsigned long long)w_leaf);
+                atomicAdd(&A.wstat[6], (unsigned long long)w_phase);
             }
         }
     }
