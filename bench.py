@@ -56,11 +56,48 @@ def parse():
     ap.add_argument("--group", type=int, default=64)
     ap.add_argument("--copy-calibration-mb", type=int, default=0,
                     help="also run a plain device copy of this size (HBM counter calibration)")
+    ap.add_argument("--profile-walk", choices=("plain", "learned"), default=None,
+                    help="only time `steps` steps of this variant at --alpha (no reference sums, no calibration), "
+                         "for counter runs of the walk")
     return ap.parse_args()
 
 
 def log(msg):
     print(msg, file=sys.stderr, flush=True)
+
+
+WALK_SOURCES = ("walk.hip", "g4_device.h", "g4_internal.h")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "walk_treepm_clustered128_traffic.txt")
+
+
+def walk_source_sha():
+    import hashlib
+    h = hashlib.sha256()
+    for f in WALK_SOURCES:
+        with open(os.path.join(ROOT, "paper_2010_03567_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def walk_traffic(variant, alpha):
+    """HBM bytes per launch of the relative walk from the committed counter
+    summary, if it was taken on the current walk sources for this variant and
+    alpha; None otherwise."""
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    kv = {}
+    with open(TRAFFIC_FILE) as fh:
+        for line in fh:
+            if ":" in line and not line.startswith("#"):
+                k, v = line.split(":", 1)
+                kv[k.strip()] = v.strip()
+    try:
+        if kv.get("source_sha256") != walk_source_sha() or kv.get("variant") != variant or \
+                abs(float(kv.get("alpha", "nan")) - alpha) > 1e-12:
+            return None
+        return float(kv["traffic_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
 
 
 def main():
@@ -122,6 +159,28 @@ def main():
         torch.cuda.synchronize()
         del src, dst
 
+    if args.profile_walk:
+        if args.alpha <= 0:
+            raise SystemExit("--profile-walk needs --alpha")
+        if args.profile_walk == "learned":
+            made = learned_step(args, g, ctx, n, r_s, eps0, tp, ws, pos, mass, out, stream, state)
+            if made is None:
+                raise SystemExit("no learned-seed weights for this particle count")
+            wp1, fstep = made[0](args.alpha), made[1]
+        else:
+            wp1, fstep = params(args.rcut, args.alpha), step
+        for _ in range(args.warmup):
+            fstep(wp1)
+        torch.cuda.synchronize()
+        evs = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(args.steps)]
+        for k in range(args.steps):
+            fstep(wp1, evs[k])
+        torch.cuda.synchronize()
+        walk_ms = float(np.mean([e[1].elapsed_time(e[2]) for e in evs]))
+        print(json.dumps({"profile_walk": args.profile_walk, "alpha": args.alpha, "steps": args.steps,
+                          "walk_ms": walk_ms, "walk_source_sha256": walk_source_sha()}))
+        return
+
     # reference forces: FP64 direct summation on the GPU for a random sample
     step(params(args.rcut, 0.001))
     tg_np = workloads.sample_indices(n, args.err_sample, seed=99)
@@ -174,15 +233,21 @@ def main():
     st_plain = g.g4_treepm_shortrange(ctx, tree, wps[1], out=out, want_stats=True)["stats"]
     learned = learned_variant(args, g, ctx, n, r_s, eps0, tp, ws, pos, mass, out, outs, stream, state, tg, ref,
                               ms_per_step)
-    st = st_plain
+    plain_value = n / (ms_per_step * 1e-3)
+    best_learned = learned is not None and "forces_per_s" in learned and learned["forces_per_s"] > plain_value
+    # roofline of the dominant kernel (the relative walk) of the variant that gives `value`
+    st = learned.pop("stats") if best_learned else st_plain
+    if learned is not None:
+        learned.pop("stats", None)
+    rwalk_ms = learned["walk_ms"] if best_learned else walk_ms
+    ralpha = learned["alpha"] if best_learned else alpha
     walk_flop = flops.walk_flops("treepm", "relative", st["n_visit"], st["n_p2m"], st["n_p2p"])
-    achieved = walk_flop / (walk_ms * 1e-3)
+    achieved = walk_flop / (rwalk_ms * 1e-3)
+    traffic = walk_traffic("learned" if best_learned else "plain", ralpha)
     util = {"pop": st["n_visit"] / max(1, 64 * st["w_pop"]), "p2m": st["n_p2m"] / max(1, 64 * st["w_p2m"]),
             "p2p": st["n_p2p"] / max(1, 64 * st["w_p2p"])}
     passes = {k: st[k] for k in ("w_pop", "w_p2m", "w_p2p", "w_entry", "w_leaf", "w_chunk", "max_stack")}
 
-    plain_value = n / (ms_per_step * 1e-3)
-    best_learned = learned is not None and "forces_per_s" in learned and learned["forces_per_s"] > plain_value
     result = {
         "metric": METRIC,
         "value": learned["forces_per_s"] if best_learned else plain_value,
@@ -209,7 +274,8 @@ def main():
                    "alpha_calibration": {str(k): v["p99"] for k, v in calib.items()}},
         "roofline": {"bound": "alu", "kernel": "k_walk<1,1,false> (relative TreePM walk)", "achieved": achieved / 1e12,
                      "peak": PEAK_FP32_VECTOR / 1e12, "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_VECTOR,
-                     "traffic": None, "avg_ms": walk_ms, "flop_per_launch": walk_flop},
+                     "traffic": traffic, "avg_ms": rwalk_ms, "flop_per_launch": walk_flop,
+                     "variant": "learned" if best_learned else "plain", "alpha": ralpha},
         "breakdown_ms": {"prewalk": seed_ms, "walk": walk_ms, "rest": ms_per_step - seed_ms - walk_ms},
         "interactions": {"per_particle_p2p": st["n_p2p"] / n, "per_particle_p2m": st["n_p2m"] / n,
                          "per_particle_visit": st["n_visit"] / n, "lane_utilisation": util, "walk_passes": passes,
@@ -306,11 +372,10 @@ def bench_forest(args, g, ctx):
             "autotuned": tuned, "R_cut": args.rcut, "alpha": 0.001}
 
 
-def learned_variant(args, g, ctx, n, r_s, eps0, tp, ws, pos, mass, out, outs, stream, state, tg, ref, plain_ms):
-    """The same step with the geometric pre-walk replaced by the trained network:
-    features -> MLP -> |a| seed -> relative walk; alpha calibrated like the plain walk."""
+def learned_step(args, g, ctx, n, r_s, eps0, tp, ws, pos, mass, out, stream, state):
+    """(lparams, lstep, wfile, meta) of the learned variant: features -> MLP ->
+    |a| seed -> relative walk; None if no weights for this particle count."""
     import torch
-    import workloads
     wfile = args.weights or os.path.join(ROOT, "paper_2010_03567_amd", "weights", f"seed_mlp_{n}.npz")
     if args.no_learned or not os.path.exists(wfile):
         return None
@@ -339,6 +404,19 @@ def learned_variant(args, g, ctx, n, r_s, eps0, tp, ws, pos, mass, out, outs, st
         if evs is not None:
             evs[2].record(stream)
         state["tree"] = tree
+
+    return lparams, lstep, wfile, meta
+
+
+def learned_variant(args, g, ctx, n, r_s, eps0, tp, ws, pos, mass, out, outs, stream, state, tg, ref, plain_ms):
+    """The same step with the geometric pre-walk replaced by the trained network:
+    features -> MLP -> |a| seed -> relative walk; alpha calibrated like the plain walk."""
+    import torch
+    import workloads
+    made = learned_step(args, g, ctx, n, r_s, eps0, tp, ws, pos, mass, out, stream, state)
+    if made is None:
+        return None
+    lparams, lstep, wfile, meta = made
 
     lcal, lalpha = {}, None
     for a in ALPHAS:
@@ -369,7 +447,7 @@ def learned_variant(args, g, ctx, n, r_s, eps0, tp, ws, pos, mass, out, outs, st
     return {"forces_per_s": n / (ms_l * 1e-3), "ms_per_step": ms_l, "alpha": lalpha, "seed_ms": mlp_ms,
             "walk_ms": lwalk_ms, "errors_vs_direct": lcal[lalpha],
             "alpha_calibration": {str(k): v["p99"] for k, v in lcal.items()},
-            "per_particle_p2p": stl["n_p2p"] / n, "per_particle_p2m": stl["n_p2m"] / n,
+            "per_particle_p2p": stl["n_p2p"] / n, "per_particle_p2m": stl["n_p2m"] / n, "stats": stl,
             "speedup_vs_plain": plain_ms / ms_l, "weights": os.path.basename(wfile),
             "trained_on": {k: meta.get(k) for k in ("n", "seeds", "rcut", "alpha", "steps", "tau")},
             "train_residual_rms_dex": meta.get("residual_rms")}

@@ -138,7 +138,7 @@ class Context:
 
     def __del__(self):
         h = getattr(self, "h", None)
-        if h:
+        if h and _L is not None:  # module globals may already be gone at interpreter exit
             _L.g4_ctx_destroy(h)
             self.h = None
 
@@ -204,7 +204,7 @@ class Tree:
 
     def __del__(self):
         h = getattr(self, "h", None)
-        if h:
+        if h and _L is not None:
             _L.g4_tree_free(self.ctx.h, h)
             self.h = None
 
