@@ -299,7 +299,9 @@ def main():
 
 def bench_fmm(args, g, ctx, n):
     """Symmetric FMM (p = 3, theta = 0.5, leaf 16) on the clustered box drawn
-    with its own seed, short-range kernel at the same split, R_cut = 4.5 r_s."""
+    with its own seed, short-range kernel at the same split, R_cut = 4.5 r_s;
+    atomic-sum mode timed per step, the sorted-list (bitwise reproducible) mode
+    timed alongside."""
     import torch
     import workloads
     scale = (128 ** 3 / n) ** (1.0 / 3.0)
@@ -311,31 +313,37 @@ def bench_fmm(args, g, ctx, n):
     mass = torch.from_numpy(m32).to(dev)
     tp = g.tree_params(True, 1.0, leaf_max=16)
     ws = torch.empty(g.g4_workspace_bytes(tp, n) + 256, dtype=torch.uint8, device=dev)
-    fp = g.fmm_params(kernel=1, theta=0.5, r_s=r_s, r_cut=4.5 * r_s, eps0=eps0)
-    state = {"factor": 1.0, "fws": None}
 
-    def step(ev=None):
-        x, y, z = g.g4_quantize(ctx, pos, tp)
-        p = g.particles(x, y, z, mass)
-        t = g.g4_build_tree(ctx, p, tp, ws=ws)
-        g.g4_compute_multipoles(ctx, t, 3)
-        if ev is not None:
-            ev[0].record()
-        o = g.g4_fmm_force(ctx, t, fp, list_factor=state["factor"], ws=state["fws"])
-        if ev is not None:
-            ev[1].record()
-        state["factor"], state["fws"], state["out"], state["p"] = o["list_factor"], o["ws"], o, p
+    def run(det, steps):
+        fp = g.fmm_params(kernel=1, theta=0.5, r_s=r_s, r_cut=4.5 * r_s, eps0=eps0, deterministic=det)
+        state = {"factor": 1.0, "fws": None}
 
-    step()
-    steps = max(3, args.steps // 2)
-    evs = [[torch.cuda.Event(enable_timing=True) for _ in range(2)] for _ in range(steps)]
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for k in range(steps):
-        step(evs[k])
-    torch.cuda.synchronize()
-    ms = (time.perf_counter() - t0) * 1e3 / steps
-    fmm_ms = float(np.mean([e[0].elapsed_time(e[1]) for e in evs]))
+        def step(ev=None):
+            x, y, z = g.g4_quantize(ctx, pos, tp)
+            p = g.particles(x, y, z, mass)
+            t = g.g4_build_tree(ctx, p, tp, ws=ws)
+            g.g4_compute_multipoles(ctx, t, 3)
+            if ev is not None:
+                ev[0].record()
+            o = g.g4_fmm_force(ctx, t, fp, list_factor=state["factor"], ws=state["fws"], want_stats=ev is None)
+            if ev is not None:
+                ev[1].record()
+            state["factor"], state["fws"], state["out"], state["p"] = o["list_factor"], o["ws"], o, p
+            if o["stats"] is not None:
+                state["stats"] = o["stats"]
+
+        step()
+        evs = [[torch.cuda.Event(enable_timing=True) for _ in range(2)] for _ in range(steps)]
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for k in range(steps):
+            step(evs[k])
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) * 1e3 / steps
+        return ms, float(np.mean([e[0].elapsed_time(e[1]) for e in evs])), state
+
+    ms, fmm_ms, state = run(0, max(3, args.steps // 2))
+    ms_det, fmm_det_ms, _ = run(1, 2)
     o = state["out"]
     a = np.stack([o["ax"].cpu().numpy(), o["ay"].cpu().numpy(), o["az"].cpu().numpy()], 1)
     net = float(np.abs((m32[:, None].astype(np.float64) * a).sum(0)).max() / (m32[:, None] * np.abs(a)).sum())
@@ -343,9 +351,13 @@ def bench_fmm(args, g, ctx, n):
     ref = g.g4_direct_force(ctx, state["p"], tp, g.walk_params(kernel=1, r_s=r_s, eps0=eps0),
                             targets=torch.from_numpy(tg).to(dev), want_pot=False)
     ref = np.stack([ref["ax"].cpu().numpy(), ref["ay"].cpu().numpy(), ref["az"].cpu().numpy()], 1)
-    log(f"[bench] fmm: {ms:.3f} ms/step (fmm {fmm_ms:.3f} ms), net force {net:.2e}")
+    st = state["stats"]
+    log(f"[bench] fmm: {ms:.3f} ms/step (fmm {fmm_ms:.3f} ms; sorted-list mode {fmm_det_ms:.3f} ms), "
+        f"net force {net:.2e}")
     return {"workload": "fmm_clustered_box_128^3 (seed 3), p=3, theta=0.5, leaf 16, R_cut 4.5 r_s",
             "forces_per_s": n / (ms * 1e-3), "ms_per_step": ms, "fmm_ms": fmm_ms,
+            "deterministic_mode": {"ms_per_step": ms_det, "fmm_ms": fmm_det_ms},
+            "interactions_per_particle": {"pp": st["n_pp"] / n, "pn": st["n_pn"] / n, "nn": st["n_nn"] / n},
             "net_force_over_sum_abs": net, "list_factor": state["factor"],
             "errors_vs_direct": workloads.percentiles(workloads.relative_errors(a[tg], ref))}
 

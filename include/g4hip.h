@@ -92,10 +92,15 @@ typedef struct {
 /* FMM (Sec. "Fast multipole method", "The FMM-PM approach"), p = 3.
  * Node pairs interact when (l_A + l_B)/r < theta and the cubes do not touch
  * and r >= h; kernel 1 drops pairs whose nearest sides are farther apart than
- * r_cut. */
+ * r_cut.  deterministic = 1 sums every target's sources in a fixed order
+ * (bitwise reproducible, slower: per-interaction lists are sorted); 0 gives
+ * the same interactions with sums accumulated by atomics (round-off may
+ * differ from run to run; the section on deterministic outcomes allows giving
+ * up binary invariance for speed). */
 typedef struct {
     int kernel;
     double G, eps0, r_s, r_cut, theta;
+    int deterministic;
 } g4_fmm_params;
 
 /* Counters filled by the force calls (host struct). */
@@ -242,10 +247,13 @@ int g4_mlp_train_step(g4_ctx *ctx, void *w_bf16, float *w_master, float *adam_st
                       float *loss);
 
 /* ------------------------------------------------------------------ FMM */
-/* Workspace for g4_fmm_force on this tree: pair frontier and interaction
- * lists sized list_factor x (48, 96, 160) x n entries, field expansions (20
- * floats per node), sort scratch.  list_factor <= 0 means 1. */
-int g4_fmm_workspace_bytes(const g4_tree *tree, double list_factor, size_t *bytes);
+/* Workspace for g4_fmm_force on this tree with these parameters: field
+ * expansions (20 floats per node) and, for deterministic = 1, a pair frontier
+ * and interaction lists of list_factor x (48, 96, 160) x n entries plus sort
+ * scratch; for deterministic = 0, a frontier of node pairs and a task list of
+ * list_factor x 2n entries each and FP64 accumulators (32 bytes per
+ * particle).  list_factor <= 0 means 1. */
+int g4_fmm_workspace_bytes(const g4_tree *tree, const g4_fmm_params *fp, double list_factor, size_t *bytes);
 
 /* Symmetric FMM at p = 3 (Sec. "Fast multipole method"): dual walk from
  * (root, root), field expansions in both nodes of every accepted pair,
@@ -253,9 +261,10 @@ int g4_fmm_workspace_bytes(const g4_tree *tree, double list_factor, size_t *byte
  * evaluation at the particles.  Needs g4_compute_multipoles(order 3).
  * ax, ay, az (pot nullable): device n float64, caller order.  Synchronises
  * (list sizes are read back); returns G4_ENOMEM when the lists exceed the
- * workspace of list_factor (retry with a larger factor).  Each target sums
- * its sources in the order of their first particle and level, so results do
- * not depend on list construction or node numbering.  n < 2^27. */
+ * workspace of list_factor (retry with a larger factor).  With deterministic
+ * = 1 each target sums its sources in the order of their first particle and
+ * level, so results do not depend on list construction or node numbering.
+ * n < 2^27. */
 int g4_fmm_force(g4_ctx *ctx, g4_tree *tree, const g4_fmm_params *fp, double list_factor, void *ws, size_t ws_bytes,
                  double *ax, double *ay, double *az, double *pot, g4_stats *stats);
 

@@ -330,10 +330,10 @@ int g4_direct_force(g4_ctx *ctx, const g4_particles *p, const g4_tree_params *tp
     return g4_launch_direct(ctx, p, tp, wp, truncate, targets, ntargets, ax, ay, az, pot);
 }
 
-int g4_fmm_workspace_bytes(const g4_tree *tree, double list_factor, size_t *bytes)
+int g4_fmm_workspace_bytes(const g4_tree *tree, const g4_fmm_params *fp, double list_factor, size_t *bytes)
 {
-    if (!tree || !bytes) return G4_EINVAL;
-    return g4_fmm_layout_bytes(tree, list_factor, bytes);
+    if (!tree || !fp || !bytes) return G4_EINVAL;
+    return g4_fmm_layout_bytes(tree, fp, list_factor, bytes);
 }
 
 int g4_fmm_force(g4_ctx *ctx, g4_tree *tree, const g4_fmm_params *fp, double list_factor, void *ws, size_t ws_bytes,

@@ -649,6 +649,480 @@ __global__ __launch_bounds__(256) void k_fmm_particles(FmmArgs A, const uint32_t
     if (POT && pot) pot[o] = G * dp_;
 }
 
+
+// ==================================================================== fast path
+// The same interactions as the list-based walk above, organised for the GPU
+// without per-interaction lists (Sec. "Fast multipole method" fixes which pairs
+// interact and how; the order of the floating-point sums is free):
+//  1. node-level dual walk, breadth first: a frontier item is a pair of
+//     internal nodes to be opened (or an internal node's self pair); one
+//     wavefront takes an item and gives one lane to every pair of daughters.
+//     Accepted pairs add both field expansions, summed per daughter in LDS and
+//     then added to the node fields with one contiguous atomic per coefficient.
+//     Opened pairs of internal nodes form the next frontier; every opened pair
+//     that involves a leaf becomes a task.
+//  2. tasks, one wavefront each: all pairs inside a leaf, all pairs of two
+//     leaves, or the particles of a leaf against the daughters of an internal
+//     node, each particle walking that subtree with the particle-node rules
+//     (particle-node interactions deposit the particle's field on the node;
+//     opened leaves give particle pairs).  Particle sums go to FP64
+//     accumulators with atomics, once per particle and task.
+//  3. downward shift (the kernel above) and evaluation at the particles.
+// Summation order follows the scheduling of the atomics, so results agree
+// with the list-based path to round-off but are not bitwise reproducible.
+#define TASK_SELF 0u  // all pairs inside leaf a
+#define TASK_LL 1u    // leaf a x leaf b
+#define TASK_LN 2u    // particles of leaf a against the daughters of internal node b
+#define FT_STK 32     // traversal stack of a task: one sibling entry per level
+
+__constant__ uint8_t c_tri[36][2] = {{0, 0}, {0, 1}, {1, 1}, {0, 2}, {1, 2}, {2, 2}, {0, 3}, {1, 3}, {2, 3}, {3, 3}, {0, 4}, {1, 4}, {2, 4}, {3, 4}, {4, 4}, {0, 5}, {1, 5}, {2, 5}, {3, 5}, {4, 5}, {5, 5}, {0, 6}, {1, 6}, {2, 6}, {3, 6}, {4, 6}, {5, 6}, {6, 6}, {0, 7}, {1, 7}, {2, 7}, {3, 7}, {4, 7}, {5, 7}, {6, 7}, {7, 7}};  // daughter pairs (i <= j) of a self pair, j-major
+
+struct FastArgs {
+    const WNode *wn;
+    const uint4 *parts;
+    const float *q3;
+    int S;
+    float unit, box, theta2, h2, asplit, hinv, rcut2;
+    int kernel;
+    const uint2 *fin;
+    uint2 *fout;
+    uint32_t *cnt;  // [0] frontier in, [1] frontier out, [2] tasks, [3] task cursor, [4] overflow
+    uint32_t cap_pairs;
+    uint4 *tasks;   // (kind, a, b, 0)
+    uint32_t cap_tasks;
+    float *F;       // 20 field coefficients per node
+    double *acc;    // 4 per particle (sorted order): a_x, a_y, a_z, potential, before the factor G
+    unsigned long long *stat;  // pp, pn, nn
+};
+
+__device__ __forceinline__ uint32_t fm_uni(uint32_t x) { return (uint32_t)__builtin_amdgcn_readfirstlane((int)x); }
+__device__ __forceinline__ uint64_t fm_ballot(bool c) { return __builtin_amdgcn_ballot_w64(c); }
+__device__ __forceinline__ uint32_t fm_below(uint64_t m)
+{
+    return __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+}
+__device__ __forceinline__ void fm_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+}
+
+// Wavefront-aggregated append of one item per lane that wants it (call with
+// all lanes active): this lane's slot.
+__device__ __forceinline__ uint32_t fm_push(uint32_t *counter, bool want)
+{
+    const uint64_t m = fm_ballot(want);
+    uint32_t b = 0;
+    if (m && (threadIdx.x & 63) == 0) b = atomicAdd(counter, (uint32_t)__builtin_popcountll(m));
+    return fm_uni(b) + fm_below(m);
+}
+
+// Two nodes: 0 dropped (beyond r_cut), 1 interact, 2 open.  Same arithmetic
+// as classify() above; r = s_b - s_a.
+__device__ __forceinline__ int fm_classify(const FastArgs &A, const WNode &a, const WNode &b, float r[3], float &r2)
+{
+    const int la = (int)(a.meta & 0xffu), lb = (int)(b.meta & 0xffu);
+    const int64_t dc[3] = {(int32_t)(b.gx - a.gx), (int32_t)(b.gy - a.gy), (int32_t)(b.gz - a.gz)};
+    const int64_t hs = (int64_t)((1ull << (A.S - la - 1)) + (1ull << (A.S - lb - 1)));
+    if (A.kernel == 1) {
+        float g2 = 0.f;
+        for (int k = 0; k < 3; k++) {
+            const int64_t gap = (dc[k] < 0 ? -dc[k] : dc[k]) - hs;
+            if (gap > 0) {
+                const float gf = (float)gap * A.unit;
+                g2 += gf * gf;
+            }
+        }
+        if (g2 > A.rcut2) return 0;
+    }
+    bool touching = true;
+    for (int k = 0; k < 3; k++)
+        if ((dc[k] < 0 ? -dc[k] : dc[k]) > hs) touching = false;
+    r[0] = (float)(int32_t)(b.cx - a.cx) * A.unit;
+    r[1] = (float)(int32_t)(b.cy - a.cy) * A.unit;
+    r[2] = (float)(int32_t)(b.cz - a.cz) * A.unit;
+    r2 = r[0] * r[0] + r[1] * r[1] + r[2] * r[2];
+    const float ls = ldexpf(A.box, -la) + ldexpf(A.box, -lb);
+    return (!touching && ls * ls < A.theta2 * r2 && r2 >= A.h2) ? 1 : 2;
+}
+
+// the walk starts from every root: its self pair, or a self task for a root leaf
+__global__ void k_fast_init(FastArgs A, int nroot)
+{
+    const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= nroot) return;
+    if (A.wn[b].meta & WN_LEAF) {
+        const uint32_t o = atomicAdd(&A.cnt[2], 1u);
+        if (o < A.cap_tasks) A.tasks[o] = make_uint4(TASK_SELF, (uint32_t)b, 0u, 0u);
+        else atomicOr(&A.cnt[4], 1u);
+    } else {
+        const uint32_t o = atomicAdd(&A.cnt[0], 1u);
+        if (o < A.cap_pairs) A.fout[o] = make_uint2((uint32_t)b, (uint32_t)b);
+        else atomicOr(&A.cnt[4], 1u);
+    }
+}
+
+template <bool POT>
+__global__ __launch_bounds__(256) void k_fast_open(FastArgs A)
+{
+    __shared__ float Floc[4][16][20];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    float(*FL)[20] = Floc[wv];
+    for (int v = lane; v < 320; v += 64) FL[v / 20][v % 20] = 0.f;
+    if (A.cnt[4]) return;  // the lists overflowed: the host retries with more room
+    const uint32_t nin = min(A.cnt[0], A.cap_pairs);
+    uint32_t c_nn = 0;
+    fm_sync();
+    for (uint32_t it = blockIdx.x * 4 + wv; it < nin; it += gridDim.x * 4) {
+        const uint2 pr = A.fin[it];
+        const uint32_t pa = fm_uni(pr.x), pb = fm_uni(pr.y);
+        const bool self = pa == pb;
+        const uint32_t ca = fm_uni(A.wn[pa].next), na = fm_uni(A.wn[pa].num);
+        const uint32_t cb = fm_uni(A.wn[pb].next), nb = fm_uni(A.wn[pb].num);
+        uint32_t i = 0, j = 0;
+        bool valid;
+        if (self) {
+            valid = (uint32_t)lane < na * (na + 1) / 2;
+            if (valid) {
+                i = c_tri[lane][0];
+                j = c_tri[lane][1];
+            }
+        } else {
+            valid = (uint32_t)lane < na * nb;
+            if (valid) {
+                i = (uint32_t)lane / nb;
+                j = (uint32_t)lane - i * nb;
+            }
+        }
+        int act = 0;  // 1 interact, 2 open, 3 self pair of a daughter
+        WNode w1, w2;
+        float r[3] = {0.f, 0.f, 0.f}, r2 = 0.f;
+        if (valid) {
+            w1 = A.wn[ca + i];
+            w2 = A.wn[cb + j];
+            act = (self && i == j) ? 3 : fm_classify(A, w1, w2, r, r2);
+        }
+        const bool inter = act == 1;
+        const uint64_t im = fm_ballot(inter);
+        if (im) {
+            if (inter) {
+                float g0, g1, g2, g3;
+                gfun_f(A.kernel, r2, A.asplit, g0, g1, g2, g3);
+                float f[20], q2[6], q3[10];
+                const float mr[3] = {-r[0], -r[1], -r[2]};
+                // daughter i sees daughter j at +r ...
+#pragma unroll
+                for (int k = 0; k < 20; k++) f[k] = 0.f;
+#pragma unroll
+                for (int k = 0; k < 6; k++) q2[k] = w2.q[k];
+                if (POT) {
+#pragma unroll
+                    for (int k = 0; k < 10; k++) q3[k] = A.q3[(size_t)(cb + j) * 10 + k];
+                }
+                add_field_f(f, r, g0, g1, g2, g3, w2.mass, q2, POT ? q3 : nullptr);
+#pragma unroll
+                for (int k = 0; k < 20; k++) atomicAdd(&FL[i][k], f[k]);
+                // ... and j sees i at -r (the mirrored expansion)
+#pragma unroll
+                for (int k = 0; k < 20; k++) f[k] = 0.f;
+#pragma unroll
+                for (int k = 0; k < 6; k++) q2[k] = w1.q[k];
+                if (POT) {
+#pragma unroll
+                    for (int k = 0; k < 10; k++) q3[k] = A.q3[(size_t)(ca + i) * 10 + k];
+                }
+                add_field_f(f, mr, g0, g1, g2, g3, w1.mass, q2, POT ? q3 : nullptr);
+                const uint32_t sj = self ? j : 8 + j;
+#pragma unroll
+                for (int k = 0; k < 20; k++) atomicAdd(&FL[sj][k], f[k]);
+            }
+            c_nn += (uint32_t)__builtin_popcountll(im);
+            fm_sync();
+            for (int v = lane; v < 320; v += 64) {
+                const uint32_t s = (uint32_t)v / 20, k = (uint32_t)v - s * 20;
+                const bool have = s < 8 ? s < na : (!self && s - 8 < nb);
+                const float val = FL[s][k];
+                if (have && val != 0.f) atomicAdd(&A.F[(size_t)(s < 8 ? ca + s : cb + (s - 8)) * 20 + k], val);
+                FL[s][k] = 0.f;
+            }
+            fm_sync();
+        }
+        const bool l1 = valid && (w1.meta & WN_LEAF), l2 = valid && (w2.meta & WN_LEAF);
+        const bool to_fr = (act == 3 && !l1) || (act == 2 && !l1 && !l2);
+        const bool to_task = (act == 3 && l1) || (act == 2 && (l1 || l2));
+        const uint32_t fo = fm_push(&A.cnt[1], to_fr);
+        const uint32_t to = fm_push(&A.cnt[2], to_task);
+        if (to_fr) {
+            if (fo < A.cap_pairs) A.fout[fo] = make_uint2(ca + i, cb + j);
+            else atomicOr(&A.cnt[4], 1u);
+        }
+        if (to_task) {
+            uint4 tk;
+            if (act == 3) tk = make_uint4(TASK_SELF, ca + i, 0u, 0u);
+            else if (l1 && l2) tk = make_uint4(TASK_LL, ca + i, cb + j, 0u);
+            else if (l1) tk = make_uint4(TASK_LN, ca + i, cb + j, 0u);
+            else tk = make_uint4(TASK_LN, cb + j, ca + i, 0u);
+            if (to < A.cap_tasks) A.tasks[to] = tk;
+            else atomicOr(&A.cnt[4], 1u);
+        }
+    }
+    if (lane == 0 && c_nn) atomicAdd(&A.stat[2], (unsigned long long)c_nn);
+}
+
+// force (and potential factor) on a target from one source particle of mass m
+template <int KER, bool POT>
+__device__ __forceinline__ void fm_pair(const FastArgs &A, const uint4 &t, const uint4 &s, float m, float &fx,
+                                        float &fy, float &fz, float &fp)
+{
+    const float sx = (float)(int32_t)(s.x - t.x) * A.unit;
+    const float sy = (float)(int32_t)(s.y - t.y) * A.unit;
+    const float sz = (float)(int32_t)(s.z - t.z) * A.unit;
+    float K, W;
+    pair_kernel<KER, POT>(sx * sx + sy * sy + sz * sz, A.asplit, A.h2, A.hinv, K, W);
+    const float mk = m * K;
+    fx += mk * sx;
+    fy += mk * sy;
+    fz += mk * sz;
+    if (POT) fp -= m * W;
+}
+
+template <bool POT>
+__device__ __forceinline__ void fm_deposit(const FastArgs &A, uint32_t j, float fx, float fy, float fz, float fp)
+{
+    double *a = A.acc + (size_t)j * 4;
+    atomicAdd(a + 0, (double)fx);
+    atomicAdd(a + 1, (double)fy);
+    atomicAdd(a + 2, (double)fz);
+    if (POT) atomicAdd(a + 3, (double)fp);
+}
+
+// every lane's sum of v (xor butterfly)
+__device__ __forceinline__ float fm_wave_sum(float v)
+{
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+    return v;
+}
+
+template <int KER, bool POT>
+__global__ __launch_bounds__(256) void k_fast_tasks(FastArgs A)
+{
+    __shared__ uint4 stk[4][FT_STK];
+    __shared__ float red[4][20];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const uint32_t ntask = min(A.cnt[2], A.cap_tasks);
+    unsigned long long c_pp = 0, c_pn = 0;
+    for (;;) {
+        uint32_t it = 0;
+        if (lane == 0) it = atomicAdd(&A.cnt[3], 1u);
+        it = fm_uni(it);
+        if (it >= ntask) break;
+        const uint4 tk = A.tasks[it];
+        const uint32_t kind = fm_uni(tk.x), ta = fm_uni(tk.y), tb = fm_uni(tk.z);
+        const uint32_t ja = fm_uni(A.wn[ta].next), na = fm_uni(A.wn[ta].num);
+        if (kind == TASK_SELF || (kind == TASK_LL && na + fm_uni(A.wn[tb].num) > 64)) {
+            // lanes over targets of one side, sources of the same or the other leaf
+            const uint32_t jb = kind == TASK_SELF ? ja : fm_uni(A.wn[tb].next);
+            const uint32_t nb = kind == TASK_SELF ? na : fm_uni(A.wn[tb].num);
+            for (int side = 0; side < (kind == TASK_SELF ? 1 : 2); side++) {
+                const uint32_t t0 = side ? jb : ja, nt = side ? nb : na;
+                const uint32_t s0 = kind == TASK_SELF ? ja : (side ? ja : jb), ns = kind == TASK_SELF ? na : (side ? na : nb);
+                for (uint32_t c0 = 0; c0 < nt; c0 += 64) {
+                    const uint32_t t = t0 + c0 + lane;
+                    const bool act = c0 + lane < nt;
+                    const uint4 me = A.parts[act ? t : t0];
+                    float fx = 0.f, fy = 0.f, fz = 0.f, fp = 0.f;
+                    for (uint32_t s = 0; s < ns; s++) {
+                        const uint4 src = A.parts[s0 + s];
+                        fm_pair<KER, POT>(A, me, src, (s0 + s != t) ? __uint_as_float(src.w) : 0.f, fx, fy, fz, fp);
+                    }
+                    if (act) fm_deposit<POT>(A, t, fx, fy, fz, fp);
+                }
+            }
+            c_pp += kind == TASK_SELF ? (unsigned long long)na * (na - 1) / 2 : (unsigned long long)na * nb;
+        } else if (kind == TASK_LL) {
+            // both leaves in one pass: lanes [0, na) are a's particles, [na, na + nb) b's
+            const uint32_t jb = fm_uni(A.wn[tb].next), nb = fm_uni(A.wn[tb].num);
+            const bool sa = (uint32_t)lane < na, act = (uint32_t)lane < na + nb;
+            const uint32_t t = sa ? ja + lane : jb + (lane - na);
+            const uint32_t s0 = sa ? jb : ja, ns = sa ? nb : na;
+            const uint4 me = A.parts[act ? t : ja];
+            float fx = 0.f, fy = 0.f, fz = 0.f, fp = 0.f;
+            const uint32_t smax = max(na, nb);
+            for (uint32_t s = 0; s < smax; s++) {
+                const bool ok = act && s < ns;
+                const uint4 src = A.parts[ok ? s0 + s : ja];
+                fm_pair<KER, POT>(A, me, src, ok ? __uint_as_float(src.w) : 0.f, fx, fy, fz, fp);
+            }
+            if (act) fm_deposit<POT>(A, t, fx, fy, fz, fp);
+            c_pp += (unsigned long long)na * nb;
+        } else {
+            // particles of leaf ta against the daughters of internal node tb
+            const uint32_t bn = fm_uni(A.wn[tb].next), bc = fm_uni(A.wn[tb].num);
+            for (uint32_t c0 = 0; c0 < na; c0 += 64) {
+                const uint32_t t = ja + c0 + lane;
+                const bool act = c0 + lane < na;
+                const uint4 me = A.parts[act ? t : ja];
+                const float mt = act ? __uint_as_float(me.w) : 0.f;
+                float fx = 0.f, fy = 0.f, fz = 0.f, fp = 0.f;
+                const uint64_t amask = fm_ballot(act);
+                int sp = 1;
+                if (lane == 0) stk[wv][0] = make_uint4(bn, bc, (uint32_t)amask, (uint32_t)(amask >> 32));
+                fm_sync();
+                while (sp > 0) {
+                    const uint4 e = stk[wv][sp - 1];
+                    const uint32_t node = fm_uni(e.x), cnt = fm_uni(e.y);
+                    const uint64_t mask = ((uint64_t)fm_uni(e.w) << 32) | (uint64_t)fm_uni(e.z);
+                    if (cnt > 1) {
+                        if (lane == 0) stk[wv][sp - 1] = make_uint4(node + 1, cnt - 1, e.z, e.w);
+                    } else {
+                        sp--;
+                    }
+                    const WNode w = A.wn[node];
+                    const bool mine = (mask >> lane) & 1ull;
+                    const int lev = (int)(w.meta & 0xffu);
+                    // particle (l = 0) against the node: the rules of fm_classify
+                    const int64_t dc[3] = {(int32_t)(w.gx - me.x), (int32_t)(w.gy - me.y), (int32_t)(w.gz - me.z)};
+                    const int64_t hs = (int64_t)(1ull << (A.S - lev - 1));
+                    bool drop = false;
+                    if (A.kernel == 1) {
+                        float g2 = 0.f;
+                        for (int k = 0; k < 3; k++) {
+                            const int64_t gap = (dc[k] < 0 ? -dc[k] : dc[k]) - hs;
+                            if (gap > 0) {
+                                const float gf = (float)gap * A.unit;
+                                g2 += gf * gf;
+                            }
+                        }
+                        drop = g2 > A.rcut2;
+                    }
+                    bool touching = true;
+                    for (int k = 0; k < 3; k++)
+                        if ((dc[k] < 0 ? -dc[k] : dc[k]) > hs) touching = false;
+                    const float r[3] = {(float)(int32_t)(w.cx - me.x) * A.unit, (float)(int32_t)(w.cy - me.y) * A.unit,
+                                        (float)(int32_t)(w.cz - me.z) * A.unit};
+                    const float r2 = r[0] * r[0] + r[1] * r[1] + r[2] * r[2];
+                    const float l = ldexpf(A.box, -lev);
+                    const bool inter = mine && !drop && !touching && l * l < A.theta2 * r2 && r2 >= A.h2;
+                    const bool open = mine && !drop && !inter;
+                    const uint64_t im = fm_ballot(inter);
+                    if (im) {
+                        float pf[20];
+#pragma unroll
+                        for (int k = 0; k < 20; k++) pf[k] = 0.f;
+                        if (inter) {
+                            float g0, g1, g2, g3;
+                            gfun_f(KER, r2, A.asplit, g0, g1, g2, g3);
+                            // the node's field at the particle: a = -F1, phi = -F0
+                            float f[20], q2[6], q3[10];
+#pragma unroll
+                            for (int k = 0; k < 20; k++) f[k] = 0.f;
+#pragma unroll
+                            for (int k = 0; k < 6; k++) q2[k] = w.q[k];
+                            if (POT) {
+#pragma unroll
+                                for (int k = 0; k < 10; k++) q3[k] = A.q3[(size_t)node * 10 + k];
+                            }
+                            add_field_f(f, r, g0, g1, g2, g3, w.mass, q2, POT ? q3 : nullptr);
+                            fx -= f[1];
+                            fy -= f[2];
+                            fz -= f[3];
+                            if (POT) fp -= f[0];
+                            // the particle's field at the node (source at -r)
+                            const float mr[3] = {-r[0], -r[1], -r[2]};
+                            add_field_f(pf, mr, g0, g1, g2, g3, mt, nullptr, nullptr);
+                        }
+#pragma unroll
+                        for (int k = 0; k < 20; k++) pf[k] = fm_wave_sum(pf[k]);
+                        if (lane == 0) {
+#pragma unroll
+                            for (int k = 0; k < 20; k++) red[wv][k] = pf[k];
+                        }
+                        fm_sync();
+                        if (lane < 20) atomicAdd(&A.F[(size_t)node * 20 + lane], red[wv][lane]);
+                        fm_sync();
+                        c_pn += (unsigned long long)__builtin_popcountll(im);
+                    }
+                    const uint64_t om = fm_ballot(open);
+                    if (om) {
+                        if (w.meta & WN_LEAF) {
+                            // particle pairs: the target side in registers, the source side summed over lanes
+                            for (uint32_t s = 0; s < w.num; s++) {
+                                const uint4 src = A.parts[w.next + s];
+                                const float ms = open ? __uint_as_float(src.w) : 0.f;
+                                const float sx = (float)(int32_t)(src.x - me.x) * A.unit;
+                                const float sy = (float)(int32_t)(src.y - me.y) * A.unit;
+                                const float sz = (float)(int32_t)(src.z - me.z) * A.unit;
+                                float K, W;
+                                pair_kernel<KER, POT>(sx * sx + sy * sy + sz * sz, A.asplit, A.h2, A.hinv, K, W);
+                                fx += ms * K * sx;
+                                fy += ms * K * sy;
+                                fz += ms * K * sz;
+                                if (POT) fp -= ms * W;
+                                const float mo = open ? mt : 0.f;
+                                const float gx = fm_wave_sum(-mo * K * sx), gy = fm_wave_sum(-mo * K * sy),
+                                            gz = fm_wave_sum(-mo * K * sz);
+                                const float gp = POT ? fm_wave_sum(-mo * W) : 0.f;
+                                if (lane == 0) fm_deposit<POT>(A, w.next + s, gx, gy, gz, gp);
+                            }
+                            c_pp += (unsigned long long)__builtin_popcountll(om) * w.num;
+                        } else if (sp < FT_STK) {
+                            if (lane == 0) stk[wv][sp] = make_uint4(w.next, w.num, (uint32_t)om, (uint32_t)(om >> 32));
+                            sp++;
+                        }
+                    }
+                    fm_sync();
+                }
+                if (act) fm_deposit<POT>(A, t, fx, fy, fz, fp);
+            }
+        }
+    }
+    if (lane == 0) {
+        if (c_pp) atomicAdd(&A.stat[0], c_pp);
+        if (c_pn) atomicAdd(&A.stat[1], c_pn);
+    }
+}
+
+// L2P at each particle plus its accumulated particle sums, written in caller order
+template <bool POT>
+__global__ void k_fast_finish(const FastArgs A, const uint32_t *__restrict__ leafid, const uint32_t *__restrict__ perm,
+                              int64_t n, double G, double *ax, double *ay, double *az, double *pot)
+{
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const uint4 me = A.parts[i];
+    const uint32_t L = leafid[i];
+    const WNode wl = A.wn[L];
+    const float a[3] = {(float)(int32_t)(me.x - wl.cx) * A.unit, (float)(int32_t)(me.y - wl.cy) * A.unit,
+                        (float)(int32_t)(me.z - wl.cz) * A.unit};
+    float P[20];
+#pragma unroll
+    for (int k = 0; k < 20; k++) P[k] = A.F[(size_t)L * 20 + k];
+    const float *F1 = P + 1, *F2 = P + 4, *F3 = P + 10;
+    float g[3], ph = P[0];
+#pragma unroll
+    for (int ii = 0; ii < 3; ii++) {
+        float s = -F1[ii];
+        ph -= F1[ii] * a[ii];
+#pragma unroll
+        for (int k = 0; k < 3; k++) {
+            s += F2[i2(ii, k)] * a[k];
+            ph += 0.5f * F2[i2(ii, k)] * a[ii] * a[k];
+#pragma unroll
+            for (int m = 0; m < 3; m++) {
+                s -= 0.5f * F3[i3(ii, k, m)] * a[k] * a[m];
+                ph -= F3[i3(ii, k, m)] * a[ii] * a[k] * a[m] * (1.0f / 6.0f);
+            }
+        }
+        g[ii] = s;
+    }
+    const double *q = A.acc + (size_t)i * 4;
+    const uint32_t o = perm[i];
+    ax[o] = G * (q[0] + (double)g[0]);
+    ay[o] = G * (q[1] + (double)g[1]);
+    az[o] = G * (q[2] + (double)g[2]);
+    if (POT && pot) pot[o] = G * (q[3] - (double)ph);
+}
+
 // ------------------------------------------------------------------ host side
 struct FmmLayout {
     size_t cnt, f0, f1, nkey, nkey2, nval, nval2, pkey, pkey2, pval, pval2, nstart, nend, pstart, pend, F, leafid,
@@ -698,12 +1172,154 @@ static int fmm_layout(int64_t n, int64_t cap_nodes, double factor, FmmLayout *L)
     return G4_OK;
 }
 
-int g4_fmm_layout_bytes(const g4_tree *t, double factor, size_t *bytes)
+struct FastLayout {
+    size_t cnt, f0, f1, tasks, F, acc, leafid, total;
+    uint32_t cap_pairs, cap_tasks;
+};
+
+static void fast_layout(int64_t n, int64_t cap_nodes, double factor, FastLayout *L)
 {
+    const double f = factor > 0 ? factor : 1.0;
+    L->cap_pairs = (uint32_t)std::min<double>(4.0e9, f * 2.0 * n + 4096);
+    L->cap_tasks = (uint32_t)std::min<double>(4.0e9, f * 2.0 * n + 4096);
+    size_t off = 0;
+    auto take = [&](size_t b) {
+        size_t o = off;
+        off += (b + 255) & ~(size_t)255;
+        return o;
+    };
+    L->cnt = take(64);
+    L->f0 = take((size_t)L->cap_pairs * 8);
+    L->f1 = take((size_t)L->cap_pairs * 8);
+    L->tasks = take((size_t)L->cap_tasks * 16);
+    L->F = take((size_t)cap_nodes * 20 * 4);
+    L->acc = take((size_t)n * 4 * 8);
+    L->leafid = take((size_t)n * 4);
+    L->total = off;
+}
+
+int g4_fmm_layout_bytes(const g4_tree *t, const g4_fmm_params *fp, double factor, size_t *bytes)
+{
+    if (!fp->deterministic) {
+        FastLayout F;
+        fast_layout(t->n, t->cap, factor, &F);
+        *bytes = F.total;
+        return G4_OK;
+    }
     FmmLayout L;
     int st = fmm_layout(t->n, t->cap, factor, &L);
     if (st) return st;
     *bytes = L.total;
+    return G4_OK;
+}
+
+template <int KER, bool POT>
+static void launch_fast_tasks(const FastArgs &A, unsigned blocks, hipStream_t s)
+{
+    k_fast_tasks<KER, POT><<<blocks, 256, 0, s>>>(A);
+}
+
+static int fmm_fast(g4_ctx *ctx, g4_tree *t, const g4_fmm_params *fp, double factor, void *ws, size_t ws_bytes,
+                    double *ax, double *ay, double *az, double *pot, g4_stats *stats)
+{
+    FastLayout L;
+    fast_layout(t->n, t->cap, factor, &L);
+    if (ws_bytes < L.total) return g4_set_err(ctx, G4_ENOMEM, "fmm workspace too small");
+    char *b = (char *)ws;
+    hipStream_t s = ctx->stream;
+    FastArgs A;
+    A.wn = t->wn;
+    A.parts = t->parts;
+    A.q3 = t->q3;
+    A.S = t->S;
+    A.unit = (float)t->unit;
+    A.box = (float)t->tp.box;
+    const float th = (float)fp->theta;
+    A.theta2 = th * th;
+    const double h = 2.8 * fp->eps0;
+    A.h2 = (float)(h * h);
+    A.hinv = h > 0 ? (float)(1.0 / h) : 0.f;
+    A.asplit = fp->kernel == 1 ? (float)(0.5 / fp->r_s) : 0.f;
+    A.rcut2 = (float)(fp->r_cut * fp->r_cut);
+    A.kernel = fp->kernel;
+    A.cnt = (uint32_t *)(b + L.cnt);
+    A.cap_pairs = L.cap_pairs;
+    A.tasks = (uint4 *)(b + L.tasks);
+    A.cap_tasks = L.cap_tasks;
+    A.F = (float *)(b + L.F);
+    A.acc = (double *)(b + L.acc);
+    A.stat = t->ctr->stat + 6;
+    uint2 *fr[2] = {(uint2 *)(b + L.f0), (uint2 *)(b + L.f1)};
+    if ((uint64_t)t->nbox > L.cap_pairs || (uint64_t)t->nbox > L.cap_tasks)
+        return g4_set_err(ctx, G4_ENOMEM, "fmm lists smaller than the root count");
+    G4_HIP(ctx, hipMemsetAsync(A.cnt, 0, 64, s));
+    G4_HIP(ctx, hipMemsetAsync(A.stat, 0, 3 * sizeof(unsigned long long), s));
+    G4_HIP(ctx, hipMemsetAsync(A.F, 0, (size_t)t->cap * 20 * 4, s));
+    G4_HIP(ctx, hipMemsetAsync(A.acc, 0, (size_t)t->n * 4 * 8, s));
+    A.fin = fr[1];
+    A.fout = fr[0];
+    k_fast_init<<<(t->nbox + 255) / 256, 256, 0, s>>>(A, t->nbox);
+    G4_HIP(ctx, hipGetLastError());
+    // node-level dual walk: one pass per level until the frontier is empty
+    const bool P = pot != nullptr;
+    int cur = 0;
+    uint32_t h4[8];
+    for (int pass = 0; pass < 64; pass++) {
+        A.fin = fr[cur];
+        A.fout = fr[cur ^ 1];
+        if (P) k_fast_open<true><<<2048, 256, 0, s>>>(A);
+        else k_fast_open<false><<<2048, 256, 0, s>>>(A);
+        k_fmm_rotate<<<1, 64, 0, s>>>(A.cnt);
+        cur ^= 1;
+        if ((pass & 3) == 3) {
+            G4_HIP(ctx, hipMemcpyAsync(h4, A.cnt, sizeof(h4), hipMemcpyDeviceToHost, s));
+            G4_HIP(ctx, hipStreamSynchronize(s));
+            if (h4[4]) return g4_set_err(ctx, G4_ENOMEM, "fmm lists exceed the workspace");
+            if (h4[0] == 0) break;
+        }
+    }
+    G4_HIP(ctx, hipGetLastError());
+    G4_HIP(ctx, hipMemcpyAsync(h4, A.cnt, sizeof(h4), hipMemcpyDeviceToHost, s));
+    G4_HIP(ctx, hipStreamSynchronize(s));
+    if (h4[4]) return g4_set_err(ctx, G4_ENOMEM, "fmm lists exceed the workspace");
+    if (h4[0] != 0) return g4_set_err(ctx, G4_EHIP, "fmm dual walk did not terminate");
+    const uint32_t ntask = h4[2];
+    if (ntask) {
+        const unsigned blocks = (unsigned)std::min<uint64_t>(2048, ((uint64_t)ntask + 3) / 4);
+        if (fp->kernel == 1) {
+            if (P) launch_fast_tasks<1, true>(A, blocks, s);
+            else launch_fast_tasks<1, false>(A, blocks, s);
+        } else {
+            if (P) launch_fast_tasks<0, true>(A, blocks, s);
+            else launch_fast_tasks<0, false>(A, blocks, s);
+        }
+    }
+    // downward pass and evaluation at the particles
+    FmmArgs D;
+    D.wn = t->wn;
+    D.ctr = t->ctr;
+    D.parent = t->parent;
+    D.unit = A.unit;
+    const int maxd = t->tp.max_depth;
+    for (int l = 1; l <= maxd; l++) k_fmm_l2l<<<1024, 256, 0, s>>>(D, l, A.F);
+    uint32_t *leafid = (uint32_t *)(b + L.leafid);
+    const int64_t nn_cap = t->cap;
+    k_fmm_leafmap<<<(unsigned)std::min<int64_t>(65535, (nn_cap + 255) / 256), 256, 0, s>>>(t->ctr, t->wn, leafid);
+    const unsigned pb = (unsigned)((t->n + 255) / 256);
+    if (P) k_fast_finish<true><<<pb, 256, 0, s>>>(A, leafid, t->perm1, t->n, fp->G, ax, ay, az, pot);
+    else k_fast_finish<false><<<pb, 256, 0, s>>>(A, leafid, t->perm1, t->n, fp->G, ax, ay, az, pot);
+    G4_HIP(ctx, hipGetLastError());
+    if (stats) {
+        DevCounters hc;
+        G4_HIP(ctx, hipMemcpyAsync(&hc, t->ctr, sizeof(hc), hipMemcpyDeviceToHost, s));
+        G4_HIP(ctx, hipStreamSynchronize(s));
+        std::memset(stats, 0, sizeof(*stats));
+        stats->n_pp = hc.stat[6];
+        stats->n_pn = hc.stat[7];
+        stats->n_nn = hc.stat[8];
+        stats->n_nodes = hc.node_count;
+        stats->flags = hc.flags;
+    }
     return G4_OK;
 }
 
@@ -717,6 +1333,7 @@ static int bits_for(uint64_t v)
 int g4_launch_fmm(g4_ctx *ctx, g4_tree *t, const g4_fmm_params *fp, double factor, void *ws, size_t ws_bytes,
                   double *ax, double *ay, double *az, double *pot, g4_stats *stats)
 {
+    if (!fp->deterministic) return fmm_fast(ctx, t, fp, factor, ws, ws_bytes, ax, ay, az, pot, stats);
     FmmLayout L;
     int st = fmm_layout(t->n, t->cap, factor, &L);
     if (st) return g4_set_err(ctx, st, "fmm workspace layout failed");

@@ -137,7 +137,7 @@ int g4_launch_mlp_forward(g4_ctx *ctx, const uint16_t *w, const float *feat, int
                           int mode);
 int g4_launch_mlp_grad(g4_ctx *ctx, const uint16_t *w, const float *feat, const float *target, int64_t n,
                        float tau, float *grad, float *loss);
-int g4_fmm_layout_bytes(const g4_tree *t, double factor, size_t *bytes);
+int g4_fmm_layout_bytes(const g4_tree *t, const g4_fmm_params *fp, double factor, size_t *bytes);
 int g4_launch_fmm(g4_ctx *ctx, g4_tree *t, const g4_fmm_params *fp, double factor, void *ws, size_t ws_bytes,
                   double *ax, double *ay, double *az, double *pot, g4_stats *stats);
 int g4_launch_mlp_adam(g4_ctx *ctx, uint16_t *w, float *master, float *m, float *v, const float *grad, float lr,

@@ -44,7 +44,7 @@ class g4_walk_params(C.Structure):
 
 class g4_fmm_params(C.Structure):
     _fields_ = [("kernel", C.c_int), ("G", C.c_double), ("eps0", C.c_double), ("r_s", C.c_double),
-                ("r_cut", C.c_double), ("theta", C.c_double)]
+                ("r_cut", C.c_double), ("theta", C.c_double), ("deterministic", C.c_int)]
 
 
 class g4_stats(C.Structure):
@@ -75,7 +75,7 @@ _SIGS = {
     "g4_direct_force": [_p, C.POINTER(g4_particles), C.POINTER(g4_tree_params), C.POINTER(g4_walk_params), _i32,
                         _p, _i64, _p, _p, _p, _p],
     "g4_mlp_features": [_p, _p, C.POINTER(g4_walk_params), _p, _p],
-    "g4_fmm_workspace_bytes": [_p, C.c_double, C.POINTER(_sz)],
+    "g4_fmm_workspace_bytes": [_p, C.POINTER(g4_fmm_params), C.c_double, C.POINTER(_sz)],
     "g4_forest_workspace_bytes": [C.POINTER(g4_tree_params), _i32, _i64, C.POINTER(_sz)],
     "g4_build_forest": [_p, _i32, _p, C.POINTER(g4_particles), C.POINTER(g4_tree_params), _p, _sz,
                         C.POINTER(C.c_void_p)],
@@ -319,15 +319,16 @@ def g4_mlp_train_step(ctx, w_bf16, master, adam_state, grad, feat, target, lr, s
 
 
 # ------------------------------------------------------------------ FMM
-def fmm_params(kernel=0, G=1.0, eps0=0.0, r_s=1.0, r_cut=1e30, theta=0.5):
+def fmm_params(kernel=0, G=1.0, eps0=0.0, r_s=1.0, r_cut=1e30, theta=0.5, deterministic=0):
     fp = g4_fmm_params()
     fp.kernel, fp.G, fp.eps0, fp.r_s, fp.r_cut, fp.theta = int(kernel), float(G), float(eps0), float(r_s), float(r_cut), float(theta)
+    fp.deterministic = int(deterministic)
     return fp
 
 
-def g4_fmm_workspace_bytes(tree, list_factor=1.0):
+def g4_fmm_workspace_bytes(tree, fp, list_factor=1.0):
     b = C.c_size_t()
-    code = _L.g4_fmm_workspace_bytes(tree.h, float(list_factor), C.byref(b))
+    code = _L.g4_fmm_workspace_bytes(tree.h, C.byref(fp), float(list_factor), C.byref(b))
     if code != G4_OK:
         raise G4Error(code, "fmm workspace size query failed")
     return int(b.value)
@@ -339,7 +340,7 @@ def g4_fmm_force(ctx, tree, fp, list_factor=1.0, ws=None, want_pot=False, want_s
     ax, ay, az, pot, _, _ = out if out is not None else _force_outputs(tree.n, ctx.device, want_pot, False, False)
     st = g4_stats() if want_stats else None
     for attempt in range(retries + 1):
-        nbytes = g4_fmm_workspace_bytes(tree, list_factor)
+        nbytes = g4_fmm_workspace_bytes(tree, fp, list_factor)
         if ws is None or ws.numel() < nbytes + 256:
             ws = torch.empty(nbytes + 256, dtype=torch.uint8, device=ctx.device)
         off = (-ws.data_ptr()) % 256

@@ -56,8 +56,11 @@ def check(a, ref, label, med=1e-5, p999=1e-3):
     assert np.median(e) <= med and np.percentile(e, 99.9) <= p999, msg
 
 
+@pytest.mark.parametrize("det", [0, 1])
 @pytest.mark.parametrize("kind,n", [("plummer", 3000), ("box", 30001), ("box", 131072)])
-def test_fmm_parity(g, ctx, kind, n):
+def test_fmm_parity(g, ctx, kind, n, det):
+    """Both summation modes against the oracle: the same interactions (counts
+    agree), forces and potentials at FP32 round-off of the oracle's FP64."""
     if kind == "plummer":
         ps = workloads.plummer(n, seed=51)
         kw = dict(kernel=0, eps0=0.01)
@@ -65,9 +68,9 @@ def test_fmm_parity(g, ctx, kind, n):
         ps = workloads.clustered_box(n, seed=52, nhalo=max(10, n // 500))
         kw = dict(kernel=1, **sr(n))
     tree, ot, p, tp, m32 = build(g, ctx, ps, kind == "box")
-    out = g.g4_fmm_force(ctx, tree, g.fmm_params(theta=0.5, **kw), want_pot=True, want_stats=True)
+    out = g.g4_fmm_force(ctx, tree, g.fmm_params(theta=0.5, deterministic=det, **kw), want_pot=True, want_stats=True)
     acc, pot, stt = ot.fmm(theta=0.5, **kw)
-    check(st3(out), acc, f"fmm {kind} {n}")
+    check(st3(out), acc, f"fmm {kind} {n} det={det}")
     perr = np.abs(out["pot"].cpu().numpy() - pot) / np.abs(pot)
     assert np.median(perr) < 1e-5
     s = out["stats"]
@@ -75,8 +78,9 @@ def test_fmm_parity(g, ctx, kind, n):
         assert abs(s[k] - int(v)) <= 1e-3 * max(1, int(v)), (k, s[k], int(v))
 
 
+@pytest.mark.parametrize("det", [0, 1])
 @pytest.mark.parametrize("kind", ["plummer", "box"])
-def test_fmm_momentum_conservation(g, ctx, kind):
+def test_fmm_momentum_conservation(g, ctx, kind, det):
     """Sec. "Fast multipole method": the symmetric expansion conserves momentum;
     on the GPU the net force is FP32 round-off of the total force magnitude."""
     if kind == "plummer":
@@ -86,7 +90,7 @@ def test_fmm_momentum_conservation(g, ctx, kind):
         ps = workloads.clustered_box(100000, seed=54, nhalo=200)
         kw = dict(kernel=1, **sr(100000))
     tree, ot, p, tp, m32 = build(g, ctx, ps, kind == "box")
-    a = st3(g.g4_fmm_force(ctx, tree, g.fmm_params(theta=0.5, **kw)))
+    a = st3(g.g4_fmm_force(ctx, tree, g.fmm_params(theta=0.5, deterministic=det, **kw)))
     net = np.abs((m32[:, None].astype(np.float64) * a).sum(0)).max()
     tot = (m32[:, None] * np.abs(a)).sum()
     assert net <= 1e-6 * tot, (net, tot)
@@ -97,16 +101,32 @@ def test_fmm_momentum_conservation(g, ctx, kind):
     assert np.abs((m32[:, None] * aw).sum(0)).max() > 10 * net
 
 
-def test_fmm_theta_to_zero_is_direct_sum(g, ctx):
+@pytest.mark.parametrize("det", [0, 1])
+def test_fmm_theta_to_zero_is_direct_sum(g, ctx, det):
     ps = workloads.clustered_box(4000, seed=55, nhalo=10)
     kw = sr(4000)
     kw["r_cut"] = 1e30
     tree, ot, p, tp, m32 = build(g, ctx, ps, True)
-    out = g.g4_fmm_force(ctx, tree, g.fmm_params(kernel=1, theta=1e-6, **kw), want_stats=True)
+    out = g.g4_fmm_force(ctx, tree, g.fmm_params(kernel=1, theta=1e-6, deterministic=det, **kw), want_stats=True)
     assert out["stats"]["n_pn"] == 0 and out["stats"]["n_nn"] == 0
     assert out["stats"]["n_pp"] == 4000 * 3999 // 2
     ref = g.g4_direct_force(ctx, p, tp, g.walk_params(kernel=1, **kw))
     check(st3(out), st3(ref), "fmm theta->0")
+
+
+def test_fmm_modes_agree(g, ctx):
+    """The atomic-sum mode and the sorted-list mode find the same interactions
+    and agree to FP32 round-off; the sorted-list mode repeats bitwise."""
+    ps = workloads.clustered_box(60000, seed=56, nhalo=120)
+    kw = dict(kernel=1, **sr(60000))
+    tree, ot, p, tp, m32 = build(g, ctx, ps, True)
+    fast = g.g4_fmm_force(ctx, tree, g.fmm_params(theta=0.5, deterministic=0, **kw), want_pot=True, want_stats=True)
+    det = g.g4_fmm_force(ctx, tree, g.fmm_params(theta=0.5, deterministic=1, **kw), want_pot=True, want_stats=True)
+    det2 = g.g4_fmm_force(ctx, tree, g.fmm_params(theta=0.5, deterministic=1, **kw), want_pot=True)
+    for k in ("n_pp", "n_pn", "n_nn"):
+        assert fast["stats"][k] == det["stats"][k], k
+    check(st3(fast), st3(det), "fast vs sorted", med=1e-6, p999=1e-4)
+    assert np.array_equal(st3(det), st3(det2))
 
 
 @pytest.mark.slow

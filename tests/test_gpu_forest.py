@@ -90,11 +90,18 @@ def test_forest_node_sets_and_oracle_parity(g, ctx, forest):
 
 
 def test_forest_fmm_equals_separate(g, ctx, forest):
+    """Sorted-list mode: bitwise equal to the boxes done one by one; atomic-sum
+    mode: equal to round-off."""
     boxes, off, f, m32, x, y, z, tp = forest
     kw = sr(20000)
-    fp = g.fmm_params(kernel=1, theta=0.5, **kw)
-    out = st3(g.g4_fmm_force(ctx, f, fp))
-    for b in (1, 2):
-        t = single(g, ctx, x, y, z, m32, off[b], off[b + 1], tp)
-        ref = st3(g.g4_fmm_force(ctx, t, fp))
-        assert np.array_equal(out[off[b]:off[b + 1]], ref), f"box {b}"
+    for det in (1, 0):
+        fp = g.fmm_params(kernel=1, theta=0.5, deterministic=det, **kw)
+        out = st3(g.g4_fmm_force(ctx, f, fp))
+        for b in (1, 2):
+            t = single(g, ctx, x, y, z, m32, off[b], off[b + 1], tp)
+            ref = st3(g.g4_fmm_force(ctx, t, fp))
+            if det:
+                assert np.array_equal(out[off[b]:off[b + 1]], ref), f"box {b}"
+            else:
+                e = workloads.relative_errors(out[off[b]:off[b + 1]], ref)
+                assert np.median(e) <= 1e-6 and e.max() <= 1e-3, (b, np.median(e), e.max())
