@@ -659,21 +659,21 @@ __global__ __launch_bounds__(256) void k_fmm_particles(FmmArgs A, const uint32_t
 //     wavefront takes an item and gives one lane to every pair of daughters.
 //     Accepted pairs add both field expansions, summed per daughter in LDS and
 //     then added to the node fields with one contiguous atomic per coefficient.
-//     Opened pairs of internal nodes form the next frontier; every opened pair
-//     that involves a leaf becomes a task.
-//  2. tasks, one wavefront each: all pairs inside a leaf, all pairs of two
-//     leaves, or the particles of a leaf against the daughters of an internal
-//     node, each particle walking that subtree with the particle-node rules
-//     (particle-node interactions deposit the particle's field on the node;
-//     opened leaves give particle pairs).  Particle sums go to FP64
-//     accumulators with atomics, once per particle and task.
-//  3. downward shift (the kernel above) and evaluation at the particles.
+//     Opened pairs of internal nodes form the next frontier; an opened pair of
+//     two leaves goes to the leaf-pair list, a leaf against an internal node
+//     to the leaf-node list.
+//  2. particle pairs, one wavefront per leaf: the pairs inside the leaf and
+//     with every partner leaf of the leaf-pair list (grouped per leaf by a
+//     counting sort), each pair evaluated from both of its leaves; sums go
+//     straight to the leaf's particles, no atomics.
+//  3. leaf-node pairs, one wavefront each: every particle of the leaf walks
+//     the internal node's subtree with the particle-node rules; particle-node
+//     interactions also put the particle's field on the node, opened leaves
+//     give particle pairs (both sides); sums go out with atomics.
+//  4. downward shift (the kernel above) and evaluation at the particles.
 // Summation order follows the scheduling of the atomics, so results agree
 // with the list-based path to round-off but are not bitwise reproducible.
-#define TASK_SELF 0u  // all pairs inside leaf a
-#define TASK_LL 1u    // leaf a x leaf b
-#define TASK_LN 2u    // particles of leaf a against the daughters of internal node b
-#define FT_STK 32     // traversal stack of a task: one sibling entry per level
+#define FT_STK 32  // traversal stack of a leaf-node pair: one sibling entry per level
 
 __constant__ uint8_t c_tri[36][2] = {{0, 0}, {0, 1}, {1, 1}, {0, 2}, {1, 2}, {2, 2}, {0, 3}, {1, 3}, {2, 3}, {3, 3}, {0, 4}, {1, 4}, {2, 4}, {3, 4}, {4, 4}, {0, 5}, {1, 5}, {2, 5}, {3, 5}, {4, 5}, {5, 5}, {0, 6}, {1, 6}, {2, 6}, {3, 6}, {4, 6}, {5, 6}, {6, 6}, {0, 7}, {1, 7}, {2, 7}, {3, 7}, {4, 7}, {5, 7}, {6, 7}, {7, 7}};  // daughter pairs (i <= j) of a self pair, j-major
 
@@ -686,10 +686,13 @@ struct FastArgs {
     int kernel;
     const uint2 *fin;
     uint2 *fout;
-    uint32_t *cnt;  // [0] frontier in, [1] frontier out, [2] tasks, [3] task cursor, [4] overflow
+    uint32_t *cnt;  // [0] frontier in, [1] frontier out, [2] leaf pairs, [3] leaf-node pairs, [4] overflow
     uint32_t cap_pairs;
-    uint4 *tasks;   // (kind, a, b, 0)
-    uint32_t cap_tasks;
+    uint2 *ll;      // opened (leaf, leaf) pairs
+    uint2 *ln;      // opened (leaf, internal node) pairs
+    uint32_t cap_ll, cap_ln;
+    uint32_t *pstart;  // CSR of partner leaves per node (node_count + 1)
+    uint32_t *plist;   // partner leaf of each entry (2 per leaf pair)
     float *F;       // 20 field coefficients per node
     double *acc;    // 4 per particle (sorted order): a_x, a_y, a_z, potential, before the factor G
     unsigned long long *stat;  // pp, pn, nn
@@ -746,20 +749,15 @@ __device__ __forceinline__ int fm_classify(const FastArgs &A, const WNode &a, co
     return (!touching && ls * ls < A.theta2 * r2 && r2 >= A.h2) ? 1 : 2;
 }
 
-// the walk starts from every root: its self pair, or a self task for a root leaf
+// the walk starts from the self pair of every internal root (a root leaf only
+// has its own particle pairs, which phase 2 does for every leaf)
 __global__ void k_fast_init(FastArgs A, int nroot)
 {
     const int b = blockIdx.x * blockDim.x + threadIdx.x;
-    if (b >= nroot) return;
-    if (A.wn[b].meta & WN_LEAF) {
-        const uint32_t o = atomicAdd(&A.cnt[2], 1u);
-        if (o < A.cap_tasks) A.tasks[o] = make_uint4(TASK_SELF, (uint32_t)b, 0u, 0u);
-        else atomicOr(&A.cnt[4], 1u);
-    } else {
-        const uint32_t o = atomicAdd(&A.cnt[0], 1u);
-        if (o < A.cap_pairs) A.fout[o] = make_uint2((uint32_t)b, (uint32_t)b);
-        else atomicOr(&A.cnt[4], 1u);
-    }
+    if (b >= nroot || (A.wn[b].meta & WN_LEAF)) return;
+    const uint32_t o = atomicAdd(&A.cnt[0], 1u);
+    if (o < A.cap_pairs) A.fout[o] = make_uint2((uint32_t)b, (uint32_t)b);
+    else atomicOr(&A.cnt[4], 1u);
 }
 
 template <bool POT>
@@ -769,7 +767,7 @@ __global__ __launch_bounds__(256) void k_fast_open(FastArgs A)
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     float(*FL)[20] = Floc[wv];
     for (int v = lane; v < 320; v += 64) FL[v / 20][v % 20] = 0.f;
-    if (A.cnt[4]) return;  // the lists overflowed: the host retries with more room
+    if (A.cnt[4]) return;  // a list overflowed: the host retries with more room
     const uint32_t nin = min(A.cnt[0], A.cap_pairs);
     uint32_t c_nn = 0;
     fm_sync();
@@ -849,24 +847,105 @@ __global__ __launch_bounds__(256) void k_fast_open(FastArgs A)
         }
         const bool l1 = valid && (w1.meta & WN_LEAF), l2 = valid && (w2.meta & WN_LEAF);
         const bool to_fr = (act == 3 && !l1) || (act == 2 && !l1 && !l2);
-        const bool to_task = (act == 3 && l1) || (act == 2 && (l1 || l2));
+        const bool to_ll = act == 2 && l1 && l2;
+        const bool to_ln = act == 2 && (l1 != l2);
         const uint32_t fo = fm_push(&A.cnt[1], to_fr);
-        const uint32_t to = fm_push(&A.cnt[2], to_task);
+        const uint32_t lo = fm_push(&A.cnt[2], to_ll);
+        const uint32_t no = fm_push(&A.cnt[3], to_ln);
         if (to_fr) {
             if (fo < A.cap_pairs) A.fout[fo] = make_uint2(ca + i, cb + j);
             else atomicOr(&A.cnt[4], 1u);
         }
-        if (to_task) {
-            uint4 tk;
-            if (act == 3) tk = make_uint4(TASK_SELF, ca + i, 0u, 0u);
-            else if (l1 && l2) tk = make_uint4(TASK_LL, ca + i, cb + j, 0u);
-            else if (l1) tk = make_uint4(TASK_LN, ca + i, cb + j, 0u);
-            else tk = make_uint4(TASK_LN, cb + j, ca + i, 0u);
-            if (to < A.cap_tasks) A.tasks[to] = tk;
+        if (to_ll) {
+            if (lo < A.cap_ll) A.ll[lo] = make_uint2(ca + i, cb + j);
+            else atomicOr(&A.cnt[4], 1u);
+        }
+        if (to_ln) {
+            if (no < A.cap_ln) A.ln[no] = l1 ? make_uint2(ca + i, cb + j) : make_uint2(cb + j, ca + i);
             else atomicOr(&A.cnt[4], 1u);
         }
     }
     if (lane == 0 && c_nn) atomicAdd(&A.stat[2], (unsigned long long)c_nn);
+}
+
+// ---- partner lists of the leaf pairs: count, exclusive scan, scatter
+__global__ void k_ll_count(const uint2 *__restrict__ ll, uint32_t n, uint32_t *__restrict__ cnt)
+{
+    for (uint32_t k = blockIdx.x * blockDim.x + threadIdx.x; k < n; k += gridDim.x * blockDim.x) {
+        const uint2 p = ll[k];
+        atomicAdd(&cnt[p.x], 1u);
+        atomicAdd(&cnt[p.y], 1u);
+    }
+}
+
+// exclusive scan of v[0..m) in place, 1024 values per block; block totals to bsum
+__global__ __launch_bounds__(256) void k_scan_blocks(uint32_t *__restrict__ v, uint32_t m, uint32_t *__restrict__ bsum)
+{
+    __shared__ uint32_t s[256];
+    const uint32_t base = blockIdx.x * 1024 + threadIdx.x * 4;
+    uint32_t x[4], t = 0;
+    for (int k = 0; k < 4; k++) {
+        x[k] = base + k < m ? v[base + k] : 0u;
+        t += x[k];
+    }
+    s[threadIdx.x] = t;
+    __syncthreads();
+    for (int off = 1; off < 256; off <<= 1) {
+        const uint32_t add = threadIdx.x >= (uint32_t)off ? s[threadIdx.x - off] : 0u;
+        __syncthreads();
+        s[threadIdx.x] += add;
+        __syncthreads();
+    }
+    uint32_t run = s[threadIdx.x] - t;  // exclusive prefix of this thread's four values
+    for (int k = 0; k < 4; k++) {
+        if (base + k < m) v[base + k] = run;
+        run += x[k];
+    }
+    if (threadIdx.x == 255) bsum[blockIdx.x] = s[255];
+}
+
+// exclusive scan of the block totals (one block), then the total at v[m]
+__global__ __launch_bounds__(1024) void k_scan_sums(uint32_t *__restrict__ bsum, uint32_t nb, uint32_t *__restrict__ total)
+{
+    __shared__ uint32_t s[1024];
+    uint32_t carry = 0;
+    for (uint32_t c0 = 0; c0 < nb; c0 += 1024) {
+        const uint32_t k = c0 + threadIdx.x;
+        const uint32_t x = k < nb ? bsum[k] : 0u;
+        s[threadIdx.x] = x;
+        __syncthreads();
+        for (int off = 1; off < 1024; off <<= 1) {
+            const uint32_t add = threadIdx.x >= (uint32_t)off ? s[threadIdx.x - off] : 0u;
+            __syncthreads();
+            s[threadIdx.x] += add;
+            __syncthreads();
+        }
+        if (k < nb) bsum[k] = carry + s[threadIdx.x] - x;
+        const uint32_t sum = s[1023];
+        __syncthreads();
+        carry += sum;
+    }
+    if (threadIdx.x == 0) *total = carry;
+}
+
+__global__ void k_scan_add(uint32_t *__restrict__ v, uint32_t m, const uint32_t *__restrict__ bsum,
+                           uint32_t *__restrict__ cursor)
+{
+    for (uint32_t k = blockIdx.x * blockDim.x + threadIdx.x; k < m; k += gridDim.x * blockDim.x) {
+        const uint32_t o = v[k] + bsum[k / 1024];
+        v[k] = o;
+        cursor[k] = o;
+    }
+}
+
+__global__ void k_ll_scatter(const uint2 *__restrict__ ll, uint32_t n, uint32_t *__restrict__ cursor,
+                             uint32_t *__restrict__ plist)
+{
+    for (uint32_t k = blockIdx.x * blockDim.x + threadIdx.x; k < n; k += gridDim.x * blockDim.x) {
+        const uint2 p = ll[k];
+        plist[atomicAdd(&cursor[p.x], 1u)] = p.y;
+        plist[atomicAdd(&cursor[p.y], 1u)] = p.x;
+    }
 }
 
 // force (and potential factor) on a target from one source particle of mass m
@@ -886,6 +965,82 @@ __device__ __forceinline__ void fm_pair(const FastArgs &A, const uint4 &t, const
     if (POT) fp -= m * W;
 }
 
+// Phase 2: all particle pairs of one leaf per wavefront.  Lane = (particle a,
+// stride slot k): slot k takes every S-th particle of each source leaf; the S
+// partial sums of a particle are added in LDS.  Writes acc (the first sum a
+// particle receives; phase 3 adds to it).
+template <int KER, bool POT>
+__global__ __launch_bounds__(256) void k_fast_pp(FastArgs A, uint32_t nnodes)
+{
+    __shared__ float part[4][64][4];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    unsigned long long c_pp = 0;
+    for (uint32_t q = blockIdx.x * 4 + wv; q < nnodes; q += gridDim.x * 4) {
+        const uint32_t meta = fm_uni(A.wn[q].meta);
+        if (!(meta & WN_LEAF)) continue;
+        const uint32_t ja = fm_uni(A.wn[q].next), na = fm_uni(A.wn[q].num);
+        const uint32_t p0 = fm_uni(A.pstart[q]), p1 = fm_uni(A.pstart[q + 1]);
+        for (uint32_t c0 = 0; c0 < na; c0 += 64) {
+            const uint32_t nc = min(na - c0, 64u);               // targets in this chunk
+            const uint32_t S = 64u / nc;                          // stride slots per target
+            const uint32_t a = (uint32_t)lane % nc, k = (uint32_t)lane / nc;
+            const bool act = k < S;
+            const uint32_t t = ja + c0 + a;
+            const uint4 me = A.parts[t];
+            float fx = 0.f, fy = 0.f, fz = 0.f, fp = 0.f;
+            // the leaf's own particles, then each partner leaf's
+            for (uint32_t e = p0; e <= p1; e++) {
+                uint32_t jb = ja, nb = na;
+                if (e < p1) {
+                    const uint32_t b = fm_uni(A.plist[e]);
+                    jb = fm_uni(A.wn[b].next);
+                    nb = fm_uni(A.wn[b].num);
+                }
+                for (uint32_t s = (act ? k : nb); s < nb; s += S) {
+                    const uint4 src = A.parts[jb + s];
+                    fm_pair<KER, POT>(A, me, src, (jb + s != t) ? __uint_as_float(src.w) : 0.f, fx, fy, fz, fp);
+                }
+            }
+            part[wv][lane][0] = fx;
+            part[wv][lane][1] = fy;
+            part[wv][lane][2] = fz;
+            part[wv][lane][3] = fp;
+            fm_sync();
+            if ((uint32_t)lane < nc) {
+                double sx = 0.0, sy = 0.0, sz = 0.0, sp = 0.0;
+                for (uint32_t kk = 0; kk < S; kk++) {
+                    const uint32_t l = kk * nc + a;
+                    sx += part[wv][l][0];
+                    sy += part[wv][l][1];
+                    sz += part[wv][l][2];
+                    sp += part[wv][l][3];
+                }
+                double *o = A.acc + (size_t)t * 4;
+                o[0] = sx;
+                o[1] = sy;
+                o[2] = sz;
+                o[3] = POT ? sp : 0.0;
+            }
+            fm_sync();
+        }
+        // pairs inside the leaf once, and each leaf pair once (it is listed at both leaves)
+        unsigned long long pairs = (unsigned long long)na * (na - 1) / 2;
+        for (uint32_t e = p0; e < p1; e++) {
+            const uint32_t b = fm_uni(A.plist[e]);
+            if (b > q) pairs += (unsigned long long)na * fm_uni(A.wn[b].num);
+        }
+        c_pp += pairs;
+    }
+    if (lane == 0 && c_pp) atomicAdd(&A.stat[0], c_pp);
+}
+
+// sum of v over lanes [0, width) of the wavefront (width a power of two), in every lane of that range
+__device__ __forceinline__ float fm_sum(float v, uint32_t width)
+{
+    for (uint32_t off = 1; off < width; off <<= 1) v += __shfl_xor(v, (int)off);
+    return v;
+}
+
 template <bool POT>
 __device__ __forceinline__ void fm_deposit(const FastArgs &A, uint32_t j, float fx, float fy, float fz, float fp)
 {
@@ -896,184 +1051,138 @@ __device__ __forceinline__ void fm_deposit(const FastArgs &A, uint32_t j, float 
     if (POT) atomicAdd(a + 3, (double)fp);
 }
 
-// every lane's sum of v (xor butterfly)
-__device__ __forceinline__ float fm_wave_sum(float v)
-{
-    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
-    return v;
-}
-
+// Phase 3: leaf-node pairs, one wavefront each: the leaf's particles (64 per
+// chunk) walk the daughters of the internal node with the particle-node rules.
 template <int KER, bool POT>
-__global__ __launch_bounds__(256) void k_fast_tasks(FastArgs A)
+__global__ __launch_bounds__(256) void k_fast_ln(FastArgs A, uint32_t npairs)
 {
     __shared__ uint4 stk[4][FT_STK];
     __shared__ float red[4][20];
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    const uint32_t ntask = min(A.cnt[2], A.cap_tasks);
     unsigned long long c_pp = 0, c_pn = 0;
-    for (;;) {
-        uint32_t it = 0;
-        if (lane == 0) it = atomicAdd(&A.cnt[3], 1u);
-        it = fm_uni(it);
-        if (it >= ntask) break;
-        const uint4 tk = A.tasks[it];
-        const uint32_t kind = fm_uni(tk.x), ta = fm_uni(tk.y), tb = fm_uni(tk.z);
+    for (uint32_t it = blockIdx.x * 4 + wv; it < npairs; it += gridDim.x * 4) {
+        const uint2 pr = A.ln[it];
+        const uint32_t ta = fm_uni(pr.x), tb = fm_uni(pr.y);
         const uint32_t ja = fm_uni(A.wn[ta].next), na = fm_uni(A.wn[ta].num);
-        if (kind == TASK_SELF || (kind == TASK_LL && na + fm_uni(A.wn[tb].num) > 64)) {
-            // lanes over targets of one side, sources of the same or the other leaf
-            const uint32_t jb = kind == TASK_SELF ? ja : fm_uni(A.wn[tb].next);
-            const uint32_t nb = kind == TASK_SELF ? na : fm_uni(A.wn[tb].num);
-            for (int side = 0; side < (kind == TASK_SELF ? 1 : 2); side++) {
-                const uint32_t t0 = side ? jb : ja, nt = side ? nb : na;
-                const uint32_t s0 = kind == TASK_SELF ? ja : (side ? ja : jb), ns = kind == TASK_SELF ? na : (side ? na : nb);
-                for (uint32_t c0 = 0; c0 < nt; c0 += 64) {
-                    const uint32_t t = t0 + c0 + lane;
-                    const bool act = c0 + lane < nt;
-                    const uint4 me = A.parts[act ? t : t0];
-                    float fx = 0.f, fy = 0.f, fz = 0.f, fp = 0.f;
-                    for (uint32_t s = 0; s < ns; s++) {
-                        const uint4 src = A.parts[s0 + s];
-                        fm_pair<KER, POT>(A, me, src, (s0 + s != t) ? __uint_as_float(src.w) : 0.f, fx, fy, fz, fp);
-                    }
-                    if (act) fm_deposit<POT>(A, t, fx, fy, fz, fp);
-                }
-            }
-            c_pp += kind == TASK_SELF ? (unsigned long long)na * (na - 1) / 2 : (unsigned long long)na * nb;
-        } else if (kind == TASK_LL) {
-            // both leaves in one pass: lanes [0, na) are a's particles, [na, na + nb) b's
-            const uint32_t jb = fm_uni(A.wn[tb].next), nb = fm_uni(A.wn[tb].num);
-            const bool sa = (uint32_t)lane < na, act = (uint32_t)lane < na + nb;
-            const uint32_t t = sa ? ja + lane : jb + (lane - na);
-            const uint32_t s0 = sa ? jb : ja, ns = sa ? nb : na;
+        const uint32_t bn = fm_uni(A.wn[tb].next), bc = fm_uni(A.wn[tb].num);
+        for (uint32_t c0 = 0; c0 < na; c0 += 64) {
+            const uint32_t nc = min(na - c0, 64u);
+            uint32_t width = 1;
+            while (width < nc) width <<= 1;
+            const uint32_t t = ja + c0 + lane;
+            const bool act = (uint32_t)lane < nc;
             const uint4 me = A.parts[act ? t : ja];
+            const float mt = act ? __uint_as_float(me.w) : 0.f;
             float fx = 0.f, fy = 0.f, fz = 0.f, fp = 0.f;
-            const uint32_t smax = max(na, nb);
-            for (uint32_t s = 0; s < smax; s++) {
-                const bool ok = act && s < ns;
-                const uint4 src = A.parts[ok ? s0 + s : ja];
-                fm_pair<KER, POT>(A, me, src, ok ? __uint_as_float(src.w) : 0.f, fx, fy, fz, fp);
-            }
-            if (act) fm_deposit<POT>(A, t, fx, fy, fz, fp);
-            c_pp += (unsigned long long)na * nb;
-        } else {
-            // particles of leaf ta against the daughters of internal node tb
-            const uint32_t bn = fm_uni(A.wn[tb].next), bc = fm_uni(A.wn[tb].num);
-            for (uint32_t c0 = 0; c0 < na; c0 += 64) {
-                const uint32_t t = ja + c0 + lane;
-                const bool act = c0 + lane < na;
-                const uint4 me = A.parts[act ? t : ja];
-                const float mt = act ? __uint_as_float(me.w) : 0.f;
-                float fx = 0.f, fy = 0.f, fz = 0.f, fp = 0.f;
-                const uint64_t amask = fm_ballot(act);
-                int sp = 1;
-                if (lane == 0) stk[wv][0] = make_uint4(bn, bc, (uint32_t)amask, (uint32_t)(amask >> 32));
-                fm_sync();
-                while (sp > 0) {
-                    const uint4 e = stk[wv][sp - 1];
-                    const uint32_t node = fm_uni(e.x), cnt = fm_uni(e.y);
-                    const uint64_t mask = ((uint64_t)fm_uni(e.w) << 32) | (uint64_t)fm_uni(e.z);
-                    if (cnt > 1) {
-                        if (lane == 0) stk[wv][sp - 1] = make_uint4(node + 1, cnt - 1, e.z, e.w);
-                    } else {
-                        sp--;
+            const uint64_t amask = fm_ballot(act);
+            int sp = 1;
+            if (lane == 0) stk[wv][0] = make_uint4(bn, bc, (uint32_t)amask, (uint32_t)(amask >> 32));
+            fm_sync();
+            while (sp > 0) {
+                const uint4 e = stk[wv][sp - 1];
+                const uint32_t node = fm_uni(e.x), cnt = fm_uni(e.y);
+                const uint64_t mask = ((uint64_t)fm_uni(e.w) << 32) | (uint64_t)fm_uni(e.z);
+                if (cnt > 1) {
+                    if (lane == 0) stk[wv][sp - 1] = make_uint4(node + 1, cnt - 1, e.z, e.w);
+                } else {
+                    sp--;
+                }
+                const WNode w = A.wn[node];
+                const bool mine = (mask >> lane) & 1ull;
+                const int lev = (int)(w.meta & 0xffu);
+                // particle (l = 0) against the node: the rules of fm_classify
+                const int64_t dc[3] = {(int32_t)(w.gx - me.x), (int32_t)(w.gy - me.y), (int32_t)(w.gz - me.z)};
+                const int64_t hs = (int64_t)(1ull << (A.S - lev - 1));
+                bool drop = false;
+                if (A.kernel == 1) {
+                    float g2 = 0.f;
+                    for (int k = 0; k < 3; k++) {
+                        const int64_t gap = (dc[k] < 0 ? -dc[k] : dc[k]) - hs;
+                        if (gap > 0) {
+                            const float gf = (float)gap * A.unit;
+                            g2 += gf * gf;
+                        }
                     }
-                    const WNode w = A.wn[node];
-                    const bool mine = (mask >> lane) & 1ull;
-                    const int lev = (int)(w.meta & 0xffu);
-                    // particle (l = 0) against the node: the rules of fm_classify
-                    const int64_t dc[3] = {(int32_t)(w.gx - me.x), (int32_t)(w.gy - me.y), (int32_t)(w.gz - me.z)};
-                    const int64_t hs = (int64_t)(1ull << (A.S - lev - 1));
-                    bool drop = false;
-                    if (A.kernel == 1) {
-                        float g2 = 0.f;
-                        for (int k = 0; k < 3; k++) {
-                            const int64_t gap = (dc[k] < 0 ? -dc[k] : dc[k]) - hs;
-                            if (gap > 0) {
-                                const float gf = (float)gap * A.unit;
-                                g2 += gf * gf;
-                            }
+                    drop = g2 > A.rcut2;
+                }
+                bool touching = true;
+                for (int k = 0; k < 3; k++)
+                    if ((dc[k] < 0 ? -dc[k] : dc[k]) > hs) touching = false;
+                const float r[3] = {(float)(int32_t)(w.cx - me.x) * A.unit, (float)(int32_t)(w.cy - me.y) * A.unit,
+                                    (float)(int32_t)(w.cz - me.z) * A.unit};
+                const float r2 = r[0] * r[0] + r[1] * r[1] + r[2] * r[2];
+                const float l = ldexpf(A.box, -lev);
+                const bool inter = mine && !drop && !touching && l * l < A.theta2 * r2 && r2 >= A.h2;
+                const bool open = mine && !drop && !inter;
+                const uint64_t im = fm_ballot(inter);
+                if (im) {
+                    float pf[20];
+#pragma unroll
+                    for (int k = 0; k < 20; k++) pf[k] = 0.f;
+                    if (inter) {
+                        float g0, g1, g2, g3;
+                        gfun_f(KER, r2, A.asplit, g0, g1, g2, g3);
+                        // the node's field at the particle: a = -F1, phi = -F0
+                        float f[20], q2[6], q3[10];
+#pragma unroll
+                        for (int k = 0; k < 20; k++) f[k] = 0.f;
+#pragma unroll
+                        for (int k = 0; k < 6; k++) q2[k] = w.q[k];
+                        if (POT) {
+#pragma unroll
+                            for (int k = 0; k < 10; k++) q3[k] = A.q3[(size_t)node * 10 + k];
                         }
-                        drop = g2 > A.rcut2;
+                        add_field_f(f, r, g0, g1, g2, g3, w.mass, q2, POT ? q3 : nullptr);
+                        fx -= f[1];
+                        fy -= f[2];
+                        fz -= f[3];
+                        if (POT) fp -= f[0];
+                        // the particle's field at the node (source at -r)
+                        const float mr[3] = {-r[0], -r[1], -r[2]};
+                        add_field_f(pf, mr, g0, g1, g2, g3, mt, nullptr, nullptr);
                     }
-                    bool touching = true;
-                    for (int k = 0; k < 3; k++)
-                        if ((dc[k] < 0 ? -dc[k] : dc[k]) > hs) touching = false;
-                    const float r[3] = {(float)(int32_t)(w.cx - me.x) * A.unit, (float)(int32_t)(w.cy - me.y) * A.unit,
-                                        (float)(int32_t)(w.cz - me.z) * A.unit};
-                    const float r2 = r[0] * r[0] + r[1] * r[1] + r[2] * r[2];
-                    const float l = ldexpf(A.box, -lev);
-                    const bool inter = mine && !drop && !touching && l * l < A.theta2 * r2 && r2 >= A.h2;
-                    const bool open = mine && !drop && !inter;
-                    const uint64_t im = fm_ballot(inter);
-                    if (im) {
-                        float pf[20];
 #pragma unroll
-                        for (int k = 0; k < 20; k++) pf[k] = 0.f;
-                        if (inter) {
-                            float g0, g1, g2, g3;
-                            gfun_f(KER, r2, A.asplit, g0, g1, g2, g3);
-                            // the node's field at the particle: a = -F1, phi = -F0
-                            float f[20], q2[6], q3[10];
+                    for (int k = 0; k < 20; k++) pf[k] = fm_sum(pf[k], width);
+                    if (lane == 0) {
 #pragma unroll
-                            for (int k = 0; k < 20; k++) f[k] = 0.f;
-#pragma unroll
-                            for (int k = 0; k < 6; k++) q2[k] = w.q[k];
-                            if (POT) {
-#pragma unroll
-                                for (int k = 0; k < 10; k++) q3[k] = A.q3[(size_t)node * 10 + k];
-                            }
-                            add_field_f(f, r, g0, g1, g2, g3, w.mass, q2, POT ? q3 : nullptr);
-                            fx -= f[1];
-                            fy -= f[2];
-                            fz -= f[3];
-                            if (POT) fp -= f[0];
-                            // the particle's field at the node (source at -r)
-                            const float mr[3] = {-r[0], -r[1], -r[2]};
-                            add_field_f(pf, mr, g0, g1, g2, g3, mt, nullptr, nullptr);
-                        }
-#pragma unroll
-                        for (int k = 0; k < 20; k++) pf[k] = fm_wave_sum(pf[k]);
-                        if (lane == 0) {
-#pragma unroll
-                            for (int k = 0; k < 20; k++) red[wv][k] = pf[k];
-                        }
-                        fm_sync();
-                        if (lane < 20) atomicAdd(&A.F[(size_t)node * 20 + lane], red[wv][lane]);
-                        fm_sync();
-                        c_pn += (unsigned long long)__builtin_popcountll(im);
-                    }
-                    const uint64_t om = fm_ballot(open);
-                    if (om) {
-                        if (w.meta & WN_LEAF) {
-                            // particle pairs: the target side in registers, the source side summed over lanes
-                            for (uint32_t s = 0; s < w.num; s++) {
-                                const uint4 src = A.parts[w.next + s];
-                                const float ms = open ? __uint_as_float(src.w) : 0.f;
-                                const float sx = (float)(int32_t)(src.x - me.x) * A.unit;
-                                const float sy = (float)(int32_t)(src.y - me.y) * A.unit;
-                                const float sz = (float)(int32_t)(src.z - me.z) * A.unit;
-                                float K, W;
-                                pair_kernel<KER, POT>(sx * sx + sy * sy + sz * sz, A.asplit, A.h2, A.hinv, K, W);
-                                fx += ms * K * sx;
-                                fy += ms * K * sy;
-                                fz += ms * K * sz;
-                                if (POT) fp -= ms * W;
-                                const float mo = open ? mt : 0.f;
-                                const float gx = fm_wave_sum(-mo * K * sx), gy = fm_wave_sum(-mo * K * sy),
-                                            gz = fm_wave_sum(-mo * K * sz);
-                                const float gp = POT ? fm_wave_sum(-mo * W) : 0.f;
-                                if (lane == 0) fm_deposit<POT>(A, w.next + s, gx, gy, gz, gp);
-                            }
-                            c_pp += (unsigned long long)__builtin_popcountll(om) * w.num;
-                        } else if (sp < FT_STK) {
-                            if (lane == 0) stk[wv][sp] = make_uint4(w.next, w.num, (uint32_t)om, (uint32_t)(om >> 32));
-                            sp++;
-                        }
+                        for (int k = 0; k < 20; k++) red[wv][k] = pf[k];
                     }
                     fm_sync();
+                    if (lane < 20) atomicAdd(&A.F[(size_t)node * 20 + lane], red[wv][lane]);
+                    fm_sync();
+                    c_pn += (unsigned long long)__builtin_popcountll(im);
                 }
-                if (act) fm_deposit<POT>(A, t, fx, fy, fz, fp);
+                const uint64_t om = fm_ballot(open);
+                if (om) {
+                    if (w.meta & WN_LEAF) {
+                        // particle pairs: the target side in registers, the source side summed over lanes
+                        for (uint32_t s = 0; s < w.num; s++) {
+                            const uint4 src = A.parts[w.next + s];
+                            const float ms = open ? __uint_as_float(src.w) : 0.f;
+                            const float sx = (float)(int32_t)(src.x - me.x) * A.unit;
+                            const float sy = (float)(int32_t)(src.y - me.y) * A.unit;
+                            const float sz = (float)(int32_t)(src.z - me.z) * A.unit;
+                            float K, W;
+                            pair_kernel<KER, POT>(sx * sx + sy * sy + sz * sz, A.asplit, A.h2, A.hinv, K, W);
+                            fx += ms * K * sx;
+                            fy += ms * K * sy;
+                            fz += ms * K * sz;
+                            if (POT) fp -= ms * W;
+                            const float mo = open ? mt : 0.f;
+                            const float gx = fm_sum(-mo * K * sx, width), gy = fm_sum(-mo * K * sy, width),
+                                        gz = fm_sum(-mo * K * sz, width);
+                            const float gp = POT ? fm_sum(-mo * W, width) : 0.f;
+                            if (lane == 0) fm_deposit<POT>(A, w.next + s, gx, gy, gz, gp);
+                        }
+                        c_pp += (unsigned long long)__builtin_popcountll(om) * w.num;
+                    } else if (sp < FT_STK) {
+                        if (lane == 0) stk[wv][sp] = make_uint4(w.next, w.num, (uint32_t)om, (uint32_t)(om >> 32));
+                        sp++;
+                    }
+                }
+                fm_sync();
             }
+            if (act) fm_deposit<POT>(A, t, fx, fy, fz, fp);
         }
     }
     if (lane == 0) {
@@ -1173,15 +1282,16 @@ static int fmm_layout(int64_t n, int64_t cap_nodes, double factor, FmmLayout *L)
 }
 
 struct FastLayout {
-    size_t cnt, f0, f1, tasks, F, acc, leafid, total;
-    uint32_t cap_pairs, cap_tasks;
+    size_t cnt, f0, f1, ll, ln, pstart, cursor, bsum, plist, F, acc, leafid, total;
+    uint32_t cap_pairs, cap_ll, cap_ln;
 };
 
 static void fast_layout(int64_t n, int64_t cap_nodes, double factor, FastLayout *L)
 {
     const double f = factor > 0 ? factor : 1.0;
-    L->cap_pairs = (uint32_t)std::min<double>(4.0e9, f * 2.0 * n + 4096);
-    L->cap_tasks = (uint32_t)std::min<double>(4.0e9, f * 2.0 * n + 4096);
+    L->cap_pairs = (uint32_t)std::min<double>(2.0e9, f * 3.0 * n + 4096);
+    L->cap_ll = (uint32_t)std::min<double>(2.0e9, f * 12.0 * n + 4096);
+    L->cap_ln = (uint32_t)std::min<double>(2.0e9, f * 3.0 * n + 4096);
     size_t off = 0;
     auto take = [&](size_t b) {
         size_t o = off;
@@ -1191,7 +1301,12 @@ static void fast_layout(int64_t n, int64_t cap_nodes, double factor, FastLayout 
     L->cnt = take(64);
     L->f0 = take((size_t)L->cap_pairs * 8);
     L->f1 = take((size_t)L->cap_pairs * 8);
-    L->tasks = take((size_t)L->cap_tasks * 16);
+    L->ll = take((size_t)L->cap_ll * 8);
+    L->ln = take((size_t)L->cap_ln * 8);
+    L->pstart = take((size_t)(cap_nodes + 1) * 4);
+    L->cursor = take((size_t)cap_nodes * 4);
+    L->bsum = take((size_t)(cap_nodes / 1024 + 2) * 4);
+    L->plist = take((size_t)L->cap_ll * 2 * 4);
     L->F = take((size_t)cap_nodes * 20 * 4);
     L->acc = take((size_t)n * 4 * 8);
     L->leafid = take((size_t)n * 4);
@@ -1214,9 +1329,10 @@ int g4_fmm_layout_bytes(const g4_tree *t, const g4_fmm_params *fp, double factor
 }
 
 template <int KER, bool POT>
-static void launch_fast_tasks(const FastArgs &A, unsigned blocks, hipStream_t s)
+static void launch_fast_particles(const FastArgs &A, uint32_t nnodes, uint32_t nln, hipStream_t s)
 {
-    k_fast_tasks<KER, POT><<<blocks, 256, 0, s>>>(A);
+    k_fast_pp<KER, POT><<<(unsigned)std::min<uint64_t>(2048, ((uint64_t)nnodes + 3) / 4), 256, 0, s>>>(A, nnodes);
+    if (nln) k_fast_ln<KER, POT><<<(unsigned)std::min<uint64_t>(2048, ((uint64_t)nln + 3) / 4), 256, 0, s>>>(A, nln);
 }
 
 static int fmm_fast(g4_ctx *ctx, g4_tree *t, const g4_fmm_params *fp, double factor, void *ws, size_t ws_bytes,
@@ -1244,23 +1360,25 @@ static int fmm_fast(g4_ctx *ctx, g4_tree *t, const g4_fmm_params *fp, double fac
     A.kernel = fp->kernel;
     A.cnt = (uint32_t *)(b + L.cnt);
     A.cap_pairs = L.cap_pairs;
-    A.tasks = (uint4 *)(b + L.tasks);
-    A.cap_tasks = L.cap_tasks;
+    A.ll = (uint2 *)(b + L.ll);
+    A.ln = (uint2 *)(b + L.ln);
+    A.cap_ll = L.cap_ll;
+    A.cap_ln = L.cap_ln;
+    A.pstart = (uint32_t *)(b + L.pstart);
+    A.plist = (uint32_t *)(b + L.plist);
     A.F = (float *)(b + L.F);
     A.acc = (double *)(b + L.acc);
     A.stat = t->ctr->stat + 6;
     uint2 *fr[2] = {(uint2 *)(b + L.f0), (uint2 *)(b + L.f1)};
-    if ((uint64_t)t->nbox > L.cap_pairs || (uint64_t)t->nbox > L.cap_tasks)
-        return g4_set_err(ctx, G4_ENOMEM, "fmm lists smaller than the root count");
+    if ((uint64_t)t->nbox > L.cap_pairs) return g4_set_err(ctx, G4_ENOMEM, "fmm frontier smaller than the root count");
     G4_HIP(ctx, hipMemsetAsync(A.cnt, 0, 64, s));
     G4_HIP(ctx, hipMemsetAsync(A.stat, 0, 3 * sizeof(unsigned long long), s));
     G4_HIP(ctx, hipMemsetAsync(A.F, 0, (size_t)t->cap * 20 * 4, s));
-    G4_HIP(ctx, hipMemsetAsync(A.acc, 0, (size_t)t->n * 4 * 8, s));
     A.fin = fr[1];
     A.fout = fr[0];
     k_fast_init<<<(t->nbox + 255) / 256, 256, 0, s>>>(A, t->nbox);
     G4_HIP(ctx, hipGetLastError());
-    // node-level dual walk: one pass per level until the frontier is empty
+    // 1. node-level dual walk: one pass per level until the frontier is empty
     const bool P = pot != nullptr;
     int cur = 0;
     uint32_t h4[8];
@@ -1279,22 +1397,32 @@ static int fmm_fast(g4_ctx *ctx, g4_tree *t, const g4_fmm_params *fp, double fac
         }
     }
     G4_HIP(ctx, hipGetLastError());
+    uint32_t nnodes = 0;
     G4_HIP(ctx, hipMemcpyAsync(h4, A.cnt, sizeof(h4), hipMemcpyDeviceToHost, s));
+    G4_HIP(ctx, hipMemcpyAsync(&nnodes, &t->ctr->node_count, 4, hipMemcpyDeviceToHost, s));
     G4_HIP(ctx, hipStreamSynchronize(s));
     if (h4[4]) return g4_set_err(ctx, G4_ENOMEM, "fmm lists exceed the workspace");
     if (h4[0] != 0) return g4_set_err(ctx, G4_EHIP, "fmm dual walk did not terminate");
-    const uint32_t ntask = h4[2];
-    if (ntask) {
-        const unsigned blocks = (unsigned)std::min<uint64_t>(2048, ((uint64_t)ntask + 3) / 4);
-        if (fp->kernel == 1) {
-            if (P) launch_fast_tasks<1, true>(A, blocks, s);
-            else launch_fast_tasks<1, false>(A, blocks, s);
-        } else {
-            if (P) launch_fast_tasks<0, true>(A, blocks, s);
-            else launch_fast_tasks<0, false>(A, blocks, s);
-        }
+    if (nnodes < 1 || (int64_t)nnodes > t->cap) return g4_set_err(ctx, G4_EHIP, "bad node count");
+    const uint32_t nll = h4[2], nln = h4[3];
+    // 2. partner lists of the leaf pairs (counting sort by leaf), then all particle pairs per leaf
+    uint32_t *cursor = (uint32_t *)(b + L.cursor), *bsum = (uint32_t *)(b + L.bsum);
+    G4_HIP(ctx, hipMemsetAsync(A.pstart, 0, (size_t)(nnodes + 1) * 4, s));
+    if (nll) k_ll_count<<<2048, 256, 0, s>>>(A.ll, nll, A.pstart);
+    const uint32_t nb = (nnodes + 1023) / 1024;
+    k_scan_blocks<<<nb, 256, 0, s>>>(A.pstart, nnodes, bsum);
+    k_scan_sums<<<1, 1024, 0, s>>>(bsum, nb, A.pstart + nnodes);
+    k_scan_add<<<(unsigned)std::min<uint32_t>(4096, (nnodes + 255) / 256), 256, 0, s>>>(A.pstart, nnodes, bsum, cursor);
+    if (nll) k_ll_scatter<<<2048, 256, 0, s>>>(A.ll, nll, cursor, A.plist);
+    // 2 and 3: particle pairs per leaf (writes every particle's sums), then the leaf-node pairs (adds)
+    if (fp->kernel == 1) {
+        if (P) launch_fast_particles<1, true>(A, nnodes, nln, s);
+        else launch_fast_particles<1, false>(A, nnodes, nln, s);
+    } else {
+        if (P) launch_fast_particles<0, true>(A, nnodes, nln, s);
+        else launch_fast_particles<0, false>(A, nnodes, nln, s);
     }
-    // downward pass and evaluation at the particles
+    // 4. downward pass and evaluation at the particles
     FmmArgs D;
     D.wn = t->wn;
     D.ctr = t->ctr;
@@ -1303,8 +1431,7 @@ static int fmm_fast(g4_ctx *ctx, g4_tree *t, const g4_fmm_params *fp, double fac
     const int maxd = t->tp.max_depth;
     for (int l = 1; l <= maxd; l++) k_fmm_l2l<<<1024, 256, 0, s>>>(D, l, A.F);
     uint32_t *leafid = (uint32_t *)(b + L.leafid);
-    const int64_t nn_cap = t->cap;
-    k_fmm_leafmap<<<(unsigned)std::min<int64_t>(65535, (nn_cap + 255) / 256), 256, 0, s>>>(t->ctr, t->wn, leafid);
+    k_fmm_leafmap<<<(unsigned)std::min<uint32_t>(65535, (nnodes + 255) / 256), 256, 0, s>>>(t->ctr, t->wn, leafid);
     const unsigned pb = (unsigned)((t->n + 255) / 256);
     if (P) k_fast_finish<true><<<pb, 256, 0, s>>>(A, leafid, t->perm1, t->n, fp->G, ax, ay, az, pot);
     else k_fast_finish<false><<<pb, 256, 0, s>>>(A, leafid, t->perm1, t->n, fp->G, ax, ay, az, pot);
