@@ -1034,13 +1034,6 @@ __global__ __launch_bounds__(256) void k_fast_pp(FastArgs A, uint32_t nnodes)
     if (lane == 0 && c_pp) atomicAdd(&A.stat[0], c_pp);
 }
 
-// sum of v over lanes [0, width) of the wavefront (width a power of two), in every lane of that range
-__device__ __forceinline__ float fm_sum(float v, uint32_t width)
-{
-    for (uint32_t off = 1; off < width; off <<= 1) v += __shfl_xor(v, (int)off);
-    return v;
-}
-
 template <bool POT>
 __device__ __forceinline__ void fm_deposit(const FastArgs &A, uint32_t j, float fx, float fy, float fz, float fp)
 {
@@ -1051,139 +1044,204 @@ __device__ __forceinline__ void fm_deposit(const FastArgs &A, uint32_t j, float 
     if (POT) atomicAdd(a + 3, (double)fp);
 }
 
-// Phase 3: leaf-node pairs, one wavefront each: the leaf's particles (64 per
-// chunk) walk the daughters of the internal node with the particle-node rules.
+// sum of v over each aligned 16-lane group, in every lane of the group
+__device__ __forceinline__ float fm_gsum(float v)
+{
+    for (int off = 8; off > 0; off >>= 1) v += __shfl_xor(v, off);
+    return v;
+}
+// this lane's group's 16 bits of a wavefront mask
+__device__ __forceinline__ uint32_t fm_gbits(uint64_t m, uint32_t g) { return (uint32_t)(m >> (16 * g)) & 0xffffu; }
+
+// Phase 3: leaf-node pairs, four per wavefront.  Each 16-lane group takes one
+// pair at a time (16 of the leaf's particles per chunk) and walks the
+// daughters of the internal node with the particle-node rules, with its own
+// stack of (first sibling, count, group lane mask) entries; a group whose walk
+// ends deposits its particles' sums and takes the wavefront's next pair.
 template <int KER, bool POT>
 __global__ __launch_bounds__(256) void k_fast_ln(FastArgs A, uint32_t npairs)
 {
-    __shared__ uint4 stk[4][FT_STK];
-    __shared__ float red[4][20];
+    __shared__ uint4 stk[4][4][FT_STK];
+    __shared__ float red[4][4][20];
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    unsigned long long c_pp = 0, c_pn = 0;
-    for (uint32_t it = blockIdx.x * 4 + wv; it < npairs; it += gridDim.x * 4) {
-        const uint2 pr = A.ln[it];
-        const uint32_t ta = fm_uni(pr.x), tb = fm_uni(pr.y);
-        const uint32_t ja = fm_uni(A.wn[ta].next), na = fm_uni(A.wn[ta].num);
-        const uint32_t bn = fm_uni(A.wn[tb].next), bc = fm_uni(A.wn[tb].num);
-        for (uint32_t c0 = 0; c0 < na; c0 += 64) {
-            const uint32_t nc = min(na - c0, 64u);
-            uint32_t width = 1;
-            while (width < nc) width <<= 1;
-            const uint32_t t = ja + c0 + lane;
-            const bool act = (uint32_t)lane < nc;
-            const uint4 me = A.parts[act ? t : ja];
-            const float mt = act ? __uint_as_float(me.w) : 0.f;
-            float fx = 0.f, fy = 0.f, fz = 0.f, fp = 0.f;
-            const uint64_t amask = fm_ballot(act);
-            int sp = 1;
-            if (lane == 0) stk[wv][0] = make_uint4(bn, bc, (uint32_t)amask, (uint32_t)(amask >> 32));
-            fm_sync();
-            while (sp > 0) {
-                const uint4 e = stk[wv][sp - 1];
-                const uint32_t node = fm_uni(e.x), cnt = fm_uni(e.y);
-                const uint64_t mask = ((uint64_t)fm_uni(e.w) << 32) | (uint64_t)fm_uni(e.z);
-                if (cnt > 1) {
-                    if (lane == 0) stk[wv][sp - 1] = make_uint4(node + 1, cnt - 1, e.z, e.w);
-                } else {
-                    sp--;
-                }
-                const WNode w = A.wn[node];
-                const bool mine = (mask >> lane) & 1ull;
-                const int lev = (int)(w.meta & 0xffu);
-                // particle (l = 0) against the node: the rules of fm_classify
-                const int64_t dc[3] = {(int32_t)(w.gx - me.x), (int32_t)(w.gy - me.y), (int32_t)(w.gz - me.z)};
-                const int64_t hs = (int64_t)(1ull << (A.S - lev - 1));
-                bool drop = false;
-                if (A.kernel == 1) {
-                    float g2 = 0.f;
-                    for (int k = 0; k < 3; k++) {
-                        const int64_t gap = (dc[k] < 0 ? -dc[k] : dc[k]) - hs;
-                        if (gap > 0) {
-                            const float gf = (float)gap * A.unit;
-                            g2 += gf * gf;
-                        }
-                    }
-                    drop = g2 > A.rcut2;
-                }
-                bool touching = true;
-                for (int k = 0; k < 3; k++)
-                    if ((dc[k] < 0 ? -dc[k] : dc[k]) > hs) touching = false;
-                const float r[3] = {(float)(int32_t)(w.cx - me.x) * A.unit, (float)(int32_t)(w.cy - me.y) * A.unit,
-                                    (float)(int32_t)(w.cz - me.z) * A.unit};
-                const float r2 = r[0] * r[0] + r[1] * r[1] + r[2] * r[2];
-                const float l = ldexpf(A.box, -lev);
-                const bool inter = mine && !drop && !touching && l * l < A.theta2 * r2 && r2 >= A.h2;
-                const bool open = mine && !drop && !inter;
-                const uint64_t im = fm_ballot(inter);
-                if (im) {
-                    float pf[20];
-#pragma unroll
-                    for (int k = 0; k < 20; k++) pf[k] = 0.f;
-                    if (inter) {
-                        float g0, g1, g2, g3;
-                        gfun_f(KER, r2, A.asplit, g0, g1, g2, g3);
-                        // the node's field at the particle: a = -F1, phi = -F0
-                        float f[20], q2[6], q3[10];
-#pragma unroll
-                        for (int k = 0; k < 20; k++) f[k] = 0.f;
-#pragma unroll
-                        for (int k = 0; k < 6; k++) q2[k] = w.q[k];
-                        if (POT) {
-#pragma unroll
-                            for (int k = 0; k < 10; k++) q3[k] = A.q3[(size_t)node * 10 + k];
-                        }
-                        add_field_f(f, r, g0, g1, g2, g3, w.mass, q2, POT ? q3 : nullptr);
-                        fx -= f[1];
-                        fy -= f[2];
-                        fz -= f[3];
-                        if (POT) fp -= f[0];
-                        // the particle's field at the node (source at -r)
-                        const float mr[3] = {-r[0], -r[1], -r[2]};
-                        add_field_f(pf, mr, g0, g1, g2, g3, mt, nullptr, nullptr);
-                    }
-#pragma unroll
-                    for (int k = 0; k < 20; k++) pf[k] = fm_sum(pf[k], width);
-                    if (lane == 0) {
-#pragma unroll
-                        for (int k = 0; k < 20; k++) red[wv][k] = pf[k];
-                    }
-                    fm_sync();
-                    if (lane < 20) atomicAdd(&A.F[(size_t)node * 20 + lane], red[wv][lane]);
-                    fm_sync();
-                    c_pn += (unsigned long long)__builtin_popcountll(im);
-                }
-                const uint64_t om = fm_ballot(open);
-                if (om) {
-                    if (w.meta & WN_LEAF) {
-                        // particle pairs: the target side in registers, the source side summed over lanes
-                        for (uint32_t s = 0; s < w.num; s++) {
-                            const uint4 src = A.parts[w.next + s];
-                            const float ms = open ? __uint_as_float(src.w) : 0.f;
-                            const float sx = (float)(int32_t)(src.x - me.x) * A.unit;
-                            const float sy = (float)(int32_t)(src.y - me.y) * A.unit;
-                            const float sz = (float)(int32_t)(src.z - me.z) * A.unit;
-                            float K, W;
-                            pair_kernel<KER, POT>(sx * sx + sy * sy + sz * sz, A.asplit, A.h2, A.hinv, K, W);
-                            fx += ms * K * sx;
-                            fy += ms * K * sy;
-                            fz += ms * K * sz;
-                            if (POT) fp -= ms * W;
-                            const float mo = open ? mt : 0.f;
-                            const float gx = fm_sum(-mo * K * sx, width), gy = fm_sum(-mo * K * sy, width),
-                                        gz = fm_sum(-mo * K * sz, width);
-                            const float gp = POT ? fm_sum(-mo * W, width) : 0.f;
-                            if (lane == 0) fm_deposit<POT>(A, w.next + s, gx, gy, gz, gp);
-                        }
-                        c_pp += (unsigned long long)__builtin_popcountll(om) * w.num;
-                    } else if (sp < FT_STK) {
-                        if (lane == 0) stk[wv][sp] = make_uint4(w.next, w.num, (uint32_t)om, (uint32_t)(om >> 32));
-                        sp++;
-                    }
-                }
-                fm_sync();
+    const uint32_t g = (uint32_t)lane >> 4, gl = (uint32_t)lane & 15u;
+    // this wavefront's contiguous share of the pairs
+    const uint32_t nw = gridDim.x * 4, wid = blockIdx.x * 4 + wv;
+    const uint32_t per = (npairs + nw - 1) / nw;
+    uint32_t next = min(npairs, wid * per);  // wavefront-uniform
+    const uint32_t end = min(npairs, next + per);
+    // group state (uniform within a group)
+    int sp = 0;
+    uint32_t ja = 0, na = 0, c0 = 0, tb = 0;
+    // lane state: one target particle
+    uint32_t t = 0;
+    bool act = false;
+    uint4 me = make_uint4(0u, 0u, 0u, 0u);
+    float mt = 0.f, fx = 0.f, fy = 0.f, fz = 0.f, fp = 0.f;
+    uint32_t n_pp = 0, n_pn = 0;
+    for (;;) {
+        // ---- groups whose walk ended: deposit, then the next chunk of the pair or the next pair
+        const bool done = sp == 0;
+        if (done && act) fm_deposit<POT>(A, t, fx, fy, fz, fp);
+        if (done) fx = fy = fz = fp = 0.f;
+        const bool more = done && c0 + 16 < na;
+        if (more) c0 += 16;
+        const bool want = done && !more;
+        const uint64_t wm = fm_ballot(want && gl == 0);  // one bit per group that needs a pair
+        const uint32_t k = next + (uint32_t)__builtin_popcountll(wm & ((1ull << (16 * g)) - 1ull));
+        next = min(end, next + (uint32_t)__builtin_popcountll(wm));
+        bool start = more;
+        if (want) {
+            if (k < end) {
+                const uint2 pr = A.ln[k];
+                ja = A.wn[pr.x].next;
+                na = A.wn[pr.x].num;
+                tb = pr.y;
+                c0 = 0;
+                start = true;
+            } else {
+                na = 0;
+                c0 = 0;
             }
-            if (act) fm_deposit<POT>(A, t, fx, fy, fz, fp);
         }
+        if (start) {
+            t = ja + c0 + gl;
+            act = c0 + gl < na;
+            me = A.parts[act ? t : ja];
+            mt = act ? __uint_as_float(me.w) : 0.f;
+        } else if (done) {
+            act = false;
+        }
+        const uint32_t am = fm_gbits(fm_ballot(act), g);
+        if (start) {
+            if (gl == 0) stk[wv][g][0] = make_uint4(A.wn[tb].next, A.wn[tb].num, am, 0u);
+            sp = 1;
+        }
+        if (!fm_ballot(sp > 0)) break;
+        fm_sync();
+        // ---- one step of every live group's walk
+        const bool live = sp > 0;
+        uint4 e = make_uint4(0u, 0u, 0u, 0u);
+        if (live) e = stk[wv][g][sp - 1];
+        const uint32_t node = e.x, cnt = e.y, gm = e.z;
+        if (live) {
+            if (cnt > 1) {
+                if (gl == 0) stk[wv][g][sp - 1] = make_uint4(node + 1, cnt - 1, gm, 0u);
+            } else {
+                sp--;
+            }
+        }
+        const WNode w = A.wn[live ? node : 0u];
+        const bool mine = live && ((gm >> gl) & 1u);
+        const int lev = (int)(w.meta & 0xffu);
+        // particle (l = 0) against the node: the rules of fm_classify
+        const int64_t dc[3] = {(int32_t)(w.gx - me.x), (int32_t)(w.gy - me.y), (int32_t)(w.gz - me.z)};
+        const int64_t hs = (int64_t)(1ull << (A.S - lev - 1));
+        bool drop = false;
+        if (A.kernel == 1) {
+            float g2 = 0.f;
+            for (int q = 0; q < 3; q++) {
+                const int64_t gap = (dc[q] < 0 ? -dc[q] : dc[q]) - hs;
+                if (gap > 0) {
+                    const float gf = (float)gap * A.unit;
+                    g2 += gf * gf;
+                }
+            }
+            drop = g2 > A.rcut2;
+        }
+        bool touching = true;
+        for (int q = 0; q < 3; q++)
+            if ((dc[q] < 0 ? -dc[q] : dc[q]) > hs) touching = false;
+        const float r[3] = {(float)(int32_t)(w.cx - me.x) * A.unit, (float)(int32_t)(w.cy - me.y) * A.unit,
+                            (float)(int32_t)(w.cz - me.z) * A.unit};
+        const float r2 = r[0] * r[0] + r[1] * r[1] + r[2] * r[2];
+        const float l = ldexpf(A.box, -lev);
+        const bool inter = mine && !drop && !touching && l * l < A.theta2 * r2 && r2 >= A.h2;
+        const bool open = mine && !drop && !inter;
+        const uint64_t im = fm_ballot(inter);
+        if (im) {
+            float pf[20];
+#pragma unroll
+            for (int q = 0; q < 20; q++) pf[q] = 0.f;
+            if (inter) {
+                float g0, g1, g2, g3;
+                gfun_f(KER, r2, A.asplit, g0, g1, g2, g3);
+                // the node's field at the particle: a = -F1, phi = -F0
+                float f[20], q2[6], q3[10];
+#pragma unroll
+                for (int q = 0; q < 20; q++) f[q] = 0.f;
+#pragma unroll
+                for (int q = 0; q < 6; q++) q2[q] = w.q[q];
+                if (POT) {
+#pragma unroll
+                    for (int q = 0; q < 10; q++) q3[q] = A.q3[(size_t)node * 10 + q];
+                }
+                add_field_f(f, r, g0, g1, g2, g3, w.mass, q2, POT ? q3 : nullptr);
+                fx -= f[1];
+                fy -= f[2];
+                fz -= f[3];
+                if (POT) fp -= f[0];
+                // the particle's field at the node (source at -r)
+                const float mr[3] = {-r[0], -r[1], -r[2]};
+                add_field_f(pf, mr, g0, g1, g2, g3, mt, nullptr, nullptr);
+                n_pn++;
+            }
+#pragma unroll
+            for (int q = 0; q < 20; q++) pf[q] = fm_gsum(pf[q]);
+            const bool gi = fm_gbits(im, g) != 0;
+            if (gi && gl == 0) {
+#pragma unroll
+                for (int q = 0; q < 20; q++) red[wv][g][q] = pf[q];
+            }
+            fm_sync();
+            if (gi) {
+                atomicAdd(&A.F[(size_t)node * 20 + gl], red[wv][g][gl]);
+                if (gl < 4) atomicAdd(&A.F[(size_t)node * 20 + 16 + gl], red[wv][g][16 + gl]);
+            }
+            fm_sync();
+        }
+        const uint64_t om = fm_ballot(open);
+        if (om) {
+            const uint32_t go = fm_gbits(om, g);
+            const bool gleaf = go && (w.meta & WN_LEAF);
+            const uint64_t lm = fm_ballot(gleaf);
+            if (lm) {
+                // particle pairs with the opened leaf: the target side in registers, the source
+                // side summed over the group; the loop runs to the largest such leaf
+                uint32_t nmax = gleaf ? w.num : 0u;
+                for (int off = 32; off > 0; off >>= 1) nmax = max(nmax, (uint32_t)__shfl_xor((int)nmax, off));
+                for (uint32_t s = 0; s < nmax; s++) {
+                    const bool ok = gleaf && s < w.num;
+                    const uint4 src = A.parts[ok ? w.next + s : 0u];
+                    const bool o = open && ok;
+                    const float ms = o ? __uint_as_float(src.w) : 0.f, mo = o ? mt : 0.f;
+                    const float sx = (float)(int32_t)(src.x - me.x) * A.unit;
+                    const float sy = (float)(int32_t)(src.y - me.y) * A.unit;
+                    const float sz = (float)(int32_t)(src.z - me.z) * A.unit;
+                    float K, W;
+                    pair_kernel<KER, POT>(sx * sx + sy * sy + sz * sz, A.asplit, A.h2, A.hinv, K, W);
+                    fx += ms * K * sx;
+                    fy += ms * K * sy;
+                    fz += ms * K * sz;
+                    if (POT) fp -= ms * W;
+                    const float gx = fm_gsum(-mo * K * sx), gy = fm_gsum(-mo * K * sy), gz = fm_gsum(-mo * K * sz);
+                    const float gp = POT ? fm_gsum(-mo * W) : 0.f;
+                    if (ok && gl == 0) fm_deposit<POT>(A, w.next + s, gx, gy, gz, gp);
+                }
+                if (open && gleaf) n_pp += w.num;
+            }
+            if (go && !gleaf && sp < FT_STK) {
+                if (gl == 0) stk[wv][g][sp] = make_uint4(w.next, w.num, go, 0u);
+                sp++;
+            }
+        }
+        fm_sync();
+    }
+    // counters: one atomic per wavefront
+    unsigned long long c_pp = n_pp, c_pn = n_pn;
+    for (int off = 32; off > 0; off >>= 1) {
+        c_pp += __shfl_xor(c_pp, off);
+        c_pn += __shfl_xor(c_pn, off);
     }
     if (lane == 0) {
         if (c_pp) atomicAdd(&A.stat[0], c_pp);
