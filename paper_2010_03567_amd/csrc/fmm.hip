@@ -760,20 +760,65 @@ __global__ void k_fast_init(FastArgs A, int nroot)
     else atomicOr(&A.cnt[4], 1u);
 }
 
+// Wavefront-local staging of appended pairs: up to 127 pending entries in LDS,
+// written out 64 at a time with one atomic on the global counter.
+struct Stage {
+    uint2 *buf;        // LDS, 128 entries
+    uint32_t n;        // pending (wavefront-uniform)
+};
+
+// append one pair per lane that wants it (all lanes active)
+__device__ __forceinline__ void st_push(Stage &S, bool want, uint2 v)
+{
+    const uint64_t m = fm_ballot(want);
+    if (want) S.buf[S.n + fm_below(m)] = v;
+    S.n += (uint32_t)__builtin_popcountll(m);
+}
+
+// write out 64 pending pairs (or all, if final) to out[] behind counter
+__device__ __forceinline__ void st_flush(Stage &S, bool final, uint2 *out, uint32_t *counter, uint32_t cap,
+                                         uint32_t *overflow)
+{
+    const int lane = threadIdx.x & 63;
+    while (S.n >= 64 || (final && S.n > 0)) {
+        const uint32_t k = min(S.n, 64u);
+        fm_sync();
+        uint32_t base = 0;
+        if (lane == 0) base = atomicAdd(counter, k);
+        base = fm_uni(base);
+        if ((uint32_t)lane < k) {
+            if (base + lane < cap) out[base + lane] = S.buf[lane];
+            else atomicOr(overflow, 1u);
+        }
+        // move the rest (< 64) to the front
+        const uint2 rest = (uint32_t)lane + k < S.n ? S.buf[lane + k] : make_uint2(0u, 0u);
+        fm_sync();
+        if ((uint32_t)lane + k < S.n) S.buf[lane] = rest;
+        S.n -= k;
+        fm_sync();
+    }
+}
+
 template <bool POT>
 __global__ __launch_bounds__(256) void k_fast_open(FastArgs A)
 {
     __shared__ float Floc[4][16][20];
+    __shared__ uint2 sbuf[4][3][128];
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     float(*FL)[20] = Floc[wv];
     for (int v = lane; v < 320; v += 64) FL[v / 20][v % 20] = 0.f;
     if (A.cnt[4]) return;  // a list overflowed: the host retries with more room
     const uint32_t nin = min(A.cnt[0], A.cap_pairs);
     uint32_t c_nn = 0;
+    Stage sf{sbuf[wv][0], 0u}, sl{sbuf[wv][1], 0u}, sn{sbuf[wv][2], 0u};
+    const uint32_t stride = gridDim.x * 4;
+    uint32_t it = blockIdx.x * 4 + wv;
+    uint2 pr = it < nin ? A.fin[it] : make_uint2(0u, 0u);
     fm_sync();
-    for (uint32_t it = blockIdx.x * 4 + wv; it < nin; it += gridDim.x * 4) {
-        const uint2 pr = A.fin[it];
+    for (; it < nin; it += stride) {
         const uint32_t pa = fm_uni(pr.x), pb = fm_uni(pr.y);
+        // the next item's pair, loaded while this one is worked on
+        if (it + stride < nin) pr = A.fin[it + stride];
         const bool self = pa == pb;
         const uint32_t ca = fm_uni(A.wn[pa].next), na = fm_uni(A.wn[pa].num);
         const uint32_t cb = fm_uni(A.wn[pb].next), nb = fm_uni(A.wn[pb].num);
@@ -846,25 +891,17 @@ __global__ __launch_bounds__(256) void k_fast_open(FastArgs A)
             fm_sync();
         }
         const bool l1 = valid && (w1.meta & WN_LEAF), l2 = valid && (w2.meta & WN_LEAF);
-        const bool to_fr = (act == 3 && !l1) || (act == 2 && !l1 && !l2);
-        const bool to_ll = act == 2 && l1 && l2;
-        const bool to_ln = act == 2 && (l1 != l2);
-        const uint32_t fo = fm_push(&A.cnt[1], to_fr);
-        const uint32_t lo = fm_push(&A.cnt[2], to_ll);
-        const uint32_t no = fm_push(&A.cnt[3], to_ln);
-        if (to_fr) {
-            if (fo < A.cap_pairs) A.fout[fo] = make_uint2(ca + i, cb + j);
-            else atomicOr(&A.cnt[4], 1u);
-        }
-        if (to_ll) {
-            if (lo < A.cap_ll) A.ll[lo] = make_uint2(ca + i, cb + j);
-            else atomicOr(&A.cnt[4], 1u);
-        }
-        if (to_ln) {
-            if (no < A.cap_ln) A.ln[no] = l1 ? make_uint2(ca + i, cb + j) : make_uint2(cb + j, ca + i);
-            else atomicOr(&A.cnt[4], 1u);
-        }
+        const uint2 pij = make_uint2(ca + i, cb + j);
+        st_push(sf, (act == 3 && !l1) || (act == 2 && !l1 && !l2), pij);
+        st_push(sl, act == 2 && l1 && l2, pij);
+        st_push(sn, act == 2 && (l1 != l2), l1 ? pij : make_uint2(cb + j, ca + i));
+        st_flush(sf, false, A.fout, &A.cnt[1], A.cap_pairs, &A.cnt[4]);
+        st_flush(sl, false, A.ll, &A.cnt[2], A.cap_ll, &A.cnt[4]);
+        st_flush(sn, false, A.ln, &A.cnt[3], A.cap_ln, &A.cnt[4]);
     }
+    st_flush(sf, true, A.fout, &A.cnt[1], A.cap_pairs, &A.cnt[4]);
+    st_flush(sl, true, A.ll, &A.cnt[2], A.cap_ll, &A.cnt[4]);
+    st_flush(sn, true, A.ln, &A.cnt[3], A.cap_ln, &A.cnt[4]);
     if (lane == 0 && c_nn) atomicAdd(&A.stat[2], (unsigned long long)c_nn);
 }
 
@@ -974,12 +1011,13 @@ __global__ __launch_bounds__(256) void k_fast_pp(FastArgs A, uint32_t nnodes)
 {
     __shared__ float part[4][64][4];
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    unsigned long long c_pp = 0;
+    unsigned long long n_pairs = 0;  // this lane's share of the pair count
     for (uint32_t q = blockIdx.x * 4 + wv; q < nnodes; q += gridDim.x * 4) {
         const uint32_t meta = fm_uni(A.wn[q].meta);
         if (!(meta & WN_LEAF)) continue;
         const uint32_t ja = fm_uni(A.wn[q].next), na = fm_uni(A.wn[q].num);
         const uint32_t p0 = fm_uni(A.pstart[q]), p1 = fm_uni(A.pstart[q + 1]);
+        if (lane == 0) n_pairs += (unsigned long long)na * (na - 1) / 2;  // pairs inside the leaf
         for (uint32_t c0 = 0; c0 < na; c0 += 64) {
             const uint32_t nc = min(na - c0, 64u);               // targets in this chunk
             const uint32_t S = 64u / nc;                          // stride slots per target
@@ -988,17 +1026,29 @@ __global__ __launch_bounds__(256) void k_fast_pp(FastArgs A, uint32_t nnodes)
             const uint32_t t = ja + c0 + a;
             const uint4 me = A.parts[t];
             float fx = 0.f, fy = 0.f, fz = 0.f, fp = 0.f;
-            // the leaf's own particles, then each partner leaf's
-            for (uint32_t e = p0; e <= p1; e++) {
-                uint32_t jb = ja, nb = na;
-                if (e < p1) {
-                    const uint32_t b = fm_uni(A.plist[e]);
-                    jb = fm_uni(A.wn[b].next);
-                    nb = fm_uni(A.wn[b].num);
+            // the leaf's own particles
+            for (uint32_t s = (act ? k : na); s < na; s += S) {
+                const uint4 src = A.parts[ja + s];
+                fm_pair<KER, POT>(A, me, src, (ja + s != t) ? __uint_as_float(src.w) : 0.f, fx, fy, fz, fp);
+            }
+            // partner leaves, their records fetched 64 at a time
+            for (uint32_t e0 = p0; e0 < p1; e0 += 64) {
+                const uint32_t ne = min(64u, p1 - e0);
+                uint32_t pj = 0, pn = 0;
+                if ((uint32_t)lane < ne) {
+                    const uint32_t b = A.plist[e0 + lane];
+                    pj = A.wn[b].next;
+                    pn = A.wn[b].num;
+                    // each leaf pair is listed at both leaves: count it at the lower node index
+                    if (c0 == 0 && b > q) n_pairs += (unsigned long long)na * pn;
                 }
-                for (uint32_t s = (act ? k : nb); s < nb; s += S) {
-                    const uint4 src = A.parts[jb + s];
-                    fm_pair<KER, POT>(A, me, src, (jb + s != t) ? __uint_as_float(src.w) : 0.f, fx, fy, fz, fp);
+                for (uint32_t e = 0; e < ne; e++) {
+                    const uint32_t jb = (uint32_t)__builtin_amdgcn_readlane((int)pj, (int)e);
+                    const uint32_t nb = (uint32_t)__builtin_amdgcn_readlane((int)pn, (int)e);
+                    for (uint32_t s = (act ? k : nb); s < nb; s += S) {
+                        const uint4 src = A.parts[jb + s];
+                        fm_pair<KER, POT>(A, me, src, __uint_as_float(src.w), fx, fy, fz, fp);
+                    }
                 }
             }
             part[wv][lane][0] = fx;
@@ -1023,15 +1073,9 @@ __global__ __launch_bounds__(256) void k_fast_pp(FastArgs A, uint32_t nnodes)
             }
             fm_sync();
         }
-        // pairs inside the leaf once, and each leaf pair once (it is listed at both leaves)
-        unsigned long long pairs = (unsigned long long)na * (na - 1) / 2;
-        for (uint32_t e = p0; e < p1; e++) {
-            const uint32_t b = fm_uni(A.plist[e]);
-            if (b > q) pairs += (unsigned long long)na * fm_uni(A.wn[b].num);
-        }
-        c_pp += pairs;
     }
-    if (lane == 0 && c_pp) atomicAdd(&A.stat[0], c_pp);
+    for (int off = 32; off > 0; off >>= 1) n_pairs += __shfl_xor(n_pairs, off);
+    if (lane == 0 && n_pairs) atomicAdd(&A.stat[0], n_pairs);
 }
 
 template <bool POT>
