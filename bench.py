@@ -54,6 +54,7 @@ def parse():
     ap.add_argument("--cpu-sample", type=int, default=20000)
     ap.add_argument("--err-sample", type=int, default=10000)
     ap.add_argument("--group", type=int, default=64)
+    ap.add_argument("--leaf", type=int, default=24, help="leaf size B of the headline tree")
     ap.add_argument("--copy-calibration-mb", type=int, default=0,
                     help="also run a plain device copy of this size (HBM counter calibration)")
     ap.add_argument("--profile-walk", choices=("plain", "learned"), default=None,
@@ -115,7 +116,7 @@ def main():
     scale = (128 ** 3 / n) ** (1.0 / 3.0)
     r_s = 1.25 / 256 * scale
     eps0 = scale / (40 * 128)
-    B = 8
+    B = args.leaf
     log(f"[bench] generating clustered box n={n}")
     ps = workloads.clustered_box(n, seed=2)
     dev = torch.device("cuda", 0)
@@ -388,11 +389,15 @@ def learned_step(args, g, ctx, n, r_s, eps0, tp, ws, pos, mass, out, stream, sta
     """(lparams, lstep, wfile, meta) of the learned variant: features -> MLP ->
     |a| seed -> relative walk; None if no weights for this particle count."""
     import torch
-    wfile = args.weights or os.path.join(ROOT, "paper_2010_03567_amd", "weights", f"seed_mlp_{n}.npz")
+    wdir = os.path.join(ROOT, "paper_2010_03567_amd", "weights")
+    wfile = args.weights or os.path.join(wdir, f"seed_mlp_{n}.npz" if args.leaf == 8 else f"seed_mlp_{n}_leaf{args.leaf}.npz")
     if args.no_learned or not os.path.exists(wfile):
         return None
     from paper_2010_03567_amd import train_seed
     wl, norm, meta = train_seed.load(wfile, ctx.device)
+    if int(meta.get("leaf", 8)) != args.leaf:
+        log(f"[bench] {os.path.basename(wfile)} was trained on leaf size {meta.get('leaf', 8)}, not {args.leaf}")
+        return None
     aseed = torch.empty(n, dtype=torch.float32, device=ctx.device)
     featbuf = torch.empty((n, 8), dtype=torch.float32, device=ctx.device)
     fwp = g.walk_params(kernel=1, r_s=r_s, eps0=eps0)
@@ -461,7 +466,7 @@ def learned_variant(args, g, ctx, n, r_s, eps0, tp, ws, pos, mass, out, outs, st
             "alpha_calibration": {str(k): v["p99"] for k, v in lcal.items()},
             "per_particle_p2p": stl["n_p2p"] / n, "per_particle_p2m": stl["n_p2m"] / n, "stats": stl,
             "speedup_vs_plain": plain_ms / ms_l, "weights": os.path.basename(wfile),
-            "trained_on": {k: meta.get(k) for k in ("n", "seeds", "rcut", "alpha", "steps", "tau")},
+            "trained_on": {k: meta.get(k) for k in ("n", "leaf", "seeds", "rcut", "alpha", "steps", "tau")},
             "train_residual_rms_dex": meta.get("residual_rms")}
 
 

@@ -8,7 +8,7 @@ with the library's own gradient and Adam kernels (BF16 weights, FP32 master
 copy).  The result is saved as an .npz (bf16 bits, feature standardisation,
 seed shift, metadata).
 
-    python -m paper_2010_03567_amd.train_seed --n 2097152 --out paper_2010_03567_amd/weights/seed_mlp_2097152.npz
+    python -m paper_2010_03567_amd.train_seed --n 2097152 --leaf 8 --out paper_2010_03567_amd/weights/seed_mlp_2097152.npz
 """
 from __future__ import annotations
 
@@ -55,12 +55,12 @@ def snapshot(ctx, n, seed, rcut_f, alpha, B=8):
     return feat, target
 
 
-def train(n, seeds, rcut_f, alpha, steps, lr, tau=0.0, log=print):
+def train(n, seeds, rcut_f, alpha, steps, lr, tau=0.0, log=print, B=8):
     ctx = g.Context()
     t0 = time.time()
     feats, targets = [], []
     for s in seeds:
-        f, t = snapshot(ctx, n, s, rcut_f, alpha)
+        f, t = snapshot(ctx, n, s, rcut_f, alpha, B)
         feats.append(f)
         targets.append(t)
         log(f"[train] snapshot seed {s} ready ({time.time() - t0:.1f} s)")
@@ -113,13 +113,14 @@ def main():
     ap.add_argument("--steps", type=int, default=1000)
     ap.add_argument("--lr", type=float, default=3e-3)
     ap.add_argument("--tau", type=float, default=0.0, help="pinball-loss quantile (0: mean squared error)")
+    ap.add_argument("--leaf", type=int, default=8, help="leaf size B of the trees the features come from")
     ap.add_argument("--out", type=str, required=True)
     a = ap.parse_args()
     lo, hi = (int(v) for v in a.seeds.split("-"))
     r = train(a.n, list(range(lo, hi + 1)), a.rcut, a.alpha, a.steps, a.lr, a.tau,
-              log=lambda m: print(m, file=sys.stderr, flush=True))
+              log=lambda m: print(m, file=sys.stderr, flush=True), B=a.leaf)
     os.makedirs(os.path.dirname(os.path.abspath(a.out)), exist_ok=True)
-    meta = dict(n=a.n, seeds=a.seeds, rcut=a.rcut, alpha=a.alpha, steps=a.steps, lr=a.lr, tau=a.tau,
+    meta = dict(n=a.n, leaf=a.leaf, seeds=a.seeds, rcut=a.rcut, alpha=a.alpha, steps=a.steps, lr=a.lr, tau=a.tau,
                 residual_quantiles=r["residual_quantiles"], residual_rms=r["residual_rms"], history=r["history"])
     np.savez(a.out, w_bf16=r["w"].view(torch.int16).cpu().numpy().view(np.uint16), norm=r["norm"].cpu().numpy(),
              meta=np.frombuffer(json.dumps(meta).encode(), dtype=np.uint8))
