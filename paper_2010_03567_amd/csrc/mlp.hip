@@ -44,81 +44,125 @@ __device__ __forceinline__ float sigm(float z) { return __builtin_amdgcn_rcpf(1.
 //      the walk), about 20 interactions per particle.
 // A missing ancestor is replaced by the node itself.  Optionally
 // standardised: (f - norm[k]) * norm[8 + k].
+// One wavefront per leaf.  Lane = (particle a of the leaf, slot k): the
+// near-field sum of particle a is split over S = 64 / (particles in the chunk)
+// slots, each taking every S-th source, and the partial sums are added in LDS;
+// lanes with k = 0 then form and write the particle's eight features.
 template <int KER>
-__global__ void k_mlp_features(const DevCounters *__restrict__ C, const WNode *__restrict__ wn,
-                               const double *__restrict__ mom, const uint32_t *__restrict__ parent,
-                               const uint4 *__restrict__ parts, const uint32_t *__restrict__ perm, double box,
-                               double unit, float asplit, float h2, float hinv, const float *__restrict__ norm,
-                               float *__restrict__ feat)
+__global__ __launch_bounds__(256) void k_mlp_features(const DevCounters *__restrict__ C, const WNode *__restrict__ wn,
+                                                      const double *__restrict__ mom,
+                                                      const uint32_t *__restrict__ parent,
+                                                      const uint4 *__restrict__ parts, const uint32_t *__restrict__ perm,
+                                                      double boxd, double unit_d, float asplit, float h2,
+                                                      float hinv, const float *__restrict__ norm,
+                                                      float *__restrict__ feat)
 {
+    __shared__ float part[4][64][3];
     const uint32_t nn = C->node_count;
-    const float unitf = (float)unit;
-    for (uint32_t q = blockIdx.x * blockDim.x + threadIdx.x; q < nn; q += gridDim.x * blockDim.x) {
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const float unit = (float)unit_d;
+    for (uint32_t q = blockIdx.x * 4 + wv; q < nn; q += gridDim.x * 4) {
         const WNode w = wn[q];
         if (!(w.meta & WN_LEAF)) continue;
-        const int level = (int)(w.meta & 0xffu);
-        const double l = ldexp(box, -level);
-        const double M = mom[(size_t)q * MOM_STRIDE];
         const uint32_t p = parent[q];
-        const uint32_t pp = p != 0xffffffffu ? p : q;
         const uint32_t gp = p != 0xffffffffu ? parent[p] : 0xffffffffu;
-        const double Mp = mom[(size_t)pp * MOM_STRIDE];
-        const double Mg = gp != 0xffffffffu ? mom[(size_t)gp * MOM_STRIDE] : Mp;
-        const WNode wp = wn[pp];
-        const double lp = ldexp(box, -(int)(wp.meta & 0xffu));
-        const double *dl = mom + (size_t)q * MOM_STRIDE + 1;
-        const double *dp = mom + (size_t)pp * MOM_STRIDE + 1;
-        float f[8];
-        f[0] = (float)log10(M);
-        f[1] = (float)log10(l);
-        f[2] = (float)level;
-        f[5] = (float)log10(Mp);
-        f[6] = (float)log10(Mg);
-        for (uint32_t j = w.next; j < w.next + w.num; j++) {
-            const uint4 pj = parts[j];
-            double a0 = (double)(int32_t)(pj.x - w.gx) * unit - dl[0], a1 = (double)(int32_t)(pj.y - w.gy) * unit - dl[1],
-                   a2 = (double)(int32_t)(pj.z - w.gz) * unit - dl[2];
-            f[3] = (float)log10(sqrt(a0 * a0 + a1 * a1 + a2 * a2) / l + 1e-3);
-            a0 = (double)(int32_t)(pj.x - wp.gx) * unit - dp[0];
-            a1 = (double)(int32_t)(pj.y - wp.gy) * unit - dp[1];
-            a2 = (double)(int32_t)(pj.z - wp.gz) * unit - dp[2];
-            f[4] = (float)log10(sqrt(a0 * a0 + a1 * a1 + a2 * a2) / lp + 1e-3);
-            float ax = 0.f, ay = 0.f, az = 0.f, K, W;
-            for (uint32_t k = w.next; k < w.next + w.num; k++) {
-                if (k == j) continue;
-                const uint4 pk = parts[k];
-                const float dx = (float)(int32_t)(pk.x - pj.x) * unitf, dy = (float)(int32_t)(pk.y - pj.y) * unitf,
-                            dz = (float)(int32_t)(pk.z - pj.z) * unitf;
-                pair_kernel<KER, false>(dx * dx + dy * dy + dz * dz, asplit, h2, hinv, K, W);
-                const float mk = __uint_as_float(pk.w) * K;
-                ax += mk * dx; ay += mk * dy; az += mk * dz;
-            }
-            // monopoles of the siblings of the leaf, then of the siblings of its parent
-            for (int lev = 0; lev < 2; lev++) {
-                const uint32_t self = lev == 0 ? q : p;
-                const uint32_t up = lev == 0 ? p : gp;
-                if (self == 0xffffffffu || up == 0xffffffffu) break;
-                const WNode wu = wn[up];
-                for (uint32_t c = wu.next; c < wu.next + wu.num; c++) {
-                    if (c == self) continue;
+        // monopoles of the siblings of the leaf (slots 0-7) and of its parent (slots 8-15), one per lane
+        uint32_t sx = 0, sy = 0, sz = 0;
+        float sm = 0.f;
+        if (lane < 16) {
+            const uint32_t self = lane < 8 ? q : p, up = lane < 8 ? p : gp;
+            if (self != 0xffffffffu && up != 0xffffffffu) {
+                const uint32_t nc = wn[up].num, c = wn[up].next + (lane & 7);
+                if ((uint32_t)(lane & 7) < nc && c != self) {
                     const WNode wc = wn[c];
-                    const float dx = (float)(int32_t)(wc.cx - pj.x) * unitf, dy = (float)(int32_t)(wc.cy - pj.y) * unitf,
-                                dz = (float)(int32_t)(wc.cz - pj.z) * unitf;
-                    pair_kernel<KER, false>(dx * dx + dy * dy + dz * dz, asplit, h2, hinv, K, W);
-                    const float mk = wc.mass * K;
-                    ax += mk * dx; ay += mk * dy; az += mk * dz;
+                    sx = wc.cx;
+                    sy = wc.cy;
+                    sz = wc.cz;
+                    sm = wc.mass;
                 }
             }
-            f[7] = log10f(fmaxf(sqrtf(ax * ax + ay * ay + az * az), 1e-30f));
-            float *o = feat + (size_t)perm[j] * 8;
-            for (int k = 0; k < 8; k++) o[k] = norm ? (f[k] - norm[k]) * norm[8 + k] : f[k];
+        }
+        for (uint32_t c0 = 0; c0 < w.num; c0 += 64) {
+            const uint32_t nc = min(w.num - c0, 64u);
+            const uint32_t S = 64u / nc;
+            const uint32_t a = (uint32_t)lane % nc, k = (uint32_t)lane / nc;
+            const bool act = k < S;
+            const uint32_t j = w.next + c0 + a;
+            const uint4 pj = parts[j];
+            float ax = 0.f, ay = 0.f, az = 0.f, K, W;
+            for (uint32_t s = (act ? k : w.num); s < w.num; s += S) {
+                const uint4 pk = parts[w.next + s];
+                const float dx = (float)(int32_t)(pk.x - pj.x) * unit, dy = (float)(int32_t)(pk.y - pj.y) * unit,
+                            dz = (float)(int32_t)(pk.z - pj.z) * unit;
+                pair_kernel<KER, false>(dx * dx + dy * dy + dz * dz, asplit, h2, hinv, K, W);
+                const float mk = w.next + s != j ? __uint_as_float(pk.w) * K : 0.f;
+                ax += mk * dx;
+                ay += mk * dy;
+                az += mk * dz;
+            }
+            for (uint32_t e = 0; e < 16; e += S) {
+                // sibling slot e + k, fetched from its lane
+                const int from = (int)min(e + k, 15u);
+                const uint32_t kx = (uint32_t)__shfl((int)sx, from), ky = (uint32_t)__shfl((int)sy, from),
+                               kz = (uint32_t)__shfl((int)sz, from);
+                const float km = __uint_as_float((uint32_t)__shfl((int)__float_as_uint(sm), from));
+                if (act && e + k < 16 && km != 0.f) {
+                    const float dx = (float)(int32_t)(kx - pj.x) * unit, dy = (float)(int32_t)(ky - pj.y) * unit,
+                                dz = (float)(int32_t)(kz - pj.z) * unit;
+                    pair_kernel<KER, false>(dx * dx + dy * dy + dz * dz, asplit, h2, hinv, K, W);
+                    const float mk = km * K;
+                    ax += mk * dx;
+                    ay += mk * dy;
+                    az += mk * dz;
+                }
+            }
+            part[wv][lane][0] = ax;
+            part[wv][lane][1] = ay;
+            part[wv][lane][2] = az;
+            __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            if ((uint32_t)lane < nc) {
+                // slot sums in slot order: leaf particles first, then siblings, as one sequence per slot
+                float tx = 0.f, ty = 0.f, tz = 0.f;
+                for (uint32_t kk = 0; kk < S; kk++) {
+                    tx += part[wv][kk * nc + a][0];
+                    ty += part[wv][kk * nc + a][1];
+                    tz += part[wv][kk * nc + a][2];
+                }
+                const int level = (int)(w.meta & 0xffu);
+                const uint32_t pp = p != 0xffffffffu ? p : q;
+                const WNode wp = wn[pp];
+                const double *dl = mom + (size_t)q * MOM_STRIDE + 1, *dp = mom + (size_t)pp * MOM_STRIDE + 1;
+                const double il = 1.0 / ldexp(boxd, -level), ilp = 1.0 / ldexp(boxd, -(int)(wp.meta & 0xffu));
+                float f[8];
+                f[0] = log10f((float)mom[(size_t)q * MOM_STRIDE]);
+                f[1] = log10f((float)ldexp(boxd, -level));
+                f[2] = (float)level;
+                // offsets from the centres of mass in FP64 (they may nearly cancel), logarithms in FP32
+                double a0 = (double)(int32_t)(pj.x - w.gx) * unit_d - dl[0],
+                       a1 = (double)(int32_t)(pj.y - w.gy) * unit_d - dl[1],
+                       a2 = (double)(int32_t)(pj.z - w.gz) * unit_d - dl[2];
+                f[3] = log10f((float)(sqrt(a0 * a0 + a1 * a1 + a2 * a2) * il + 1e-3));
+                a0 = (double)(int32_t)(pj.x - wp.gx) * unit_d - dp[0];
+                a1 = (double)(int32_t)(pj.y - wp.gy) * unit_d - dp[1];
+                a2 = (double)(int32_t)(pj.z - wp.gz) * unit_d - dp[2];
+                f[4] = log10f((float)(sqrt(a0 * a0 + a1 * a1 + a2 * a2) * ilp + 1e-3));
+                const float Mp = (float)mom[(size_t)pp * MOM_STRIDE];
+                f[5] = log10f(Mp);
+                f[6] = gp != 0xffffffffu ? log10f((float)mom[(size_t)gp * MOM_STRIDE]) : log10f(Mp);
+                f[7] = log10f(fmaxf(sqrtf(tx * tx + ty * ty + tz * tz), 1e-30f));
+                float *o = feat + (size_t)perm[j] * 8;
+                for (int kk = 0; kk < 8; kk++) o[kk] = norm ? (f[kk] - norm[kk]) * norm[8 + kk] : f[kk];
+            }
+            __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+            __builtin_amdgcn_wave_barrier();
         }
     }
 }
 
 int g4_launch_mlp_features(g4_ctx *ctx, const g4_tree *t, const g4_walk_params *wp, const float *norm, float *feat)
 {
-    int blocks = (int)((t->cap + 255) / 256);
+    int blocks = (int)((t->cap + 3) / 4);
     if (blocks > 4096) blocks = 4096;
     const double h = 2.8 * wp->eps0;
     const float asplit = wp->kernel == 1 ? (float)(0.5 / wp->r_s) : 0.f;
