@@ -123,6 +123,7 @@ static int g4_build_tree_views(g4_ctx *ctx, const g4_particles *p, const g4_tree
     t->q3 = (float *)(b + L.q3);
     t->mom = (double *)(b + L.mom);
     t->aseed = (float *)(b + L.aseed);
+    t->leafof = (uint32_t *)(b + L.leafof);
     t->walk_spill = (uint4 *)(b + L.spill);
     t->walk_spill_waves = L.spill_waves;
     t->sort_tmp = b + L.sort_tmp;
@@ -150,9 +151,11 @@ int g4_tree_info(g4_ctx *ctx, const g4_tree *tree, int64_t *nnodes, int64_t *lev
     G4_HIP(ctx, hipStreamSynchronize(ctx->stream));
     if (nnodes) *nnodes = h.node_count;
     if (level_start) {
+        // levels are stored one after another, so the starts are the running
+        // sums of the level sizes (the device keeps starts only for non-empty levels)
         const int maxd = tree->tp.max_depth;
-        for (int l = 0; l <= maxd; l++) level_start[l] = h.lvl_start[l];
-        level_start[maxd + 1] = h.lvl_start[maxd] + h.lvl_count[maxd];
+        level_start[0] = 0;
+        for (int l = 0; l <= maxd; l++) level_start[l + 1] = level_start[l] + h.lvl_count[l];
     }
     if (h.flags & 2u) return g4_set_err(ctx, G4_ENOMEM, "node capacity exceeded");
     return G4_OK;

@@ -45,7 +45,7 @@ static_assert(sizeof(WNode) == 64, "WNode must be 64 bytes");
 
 // Device counters at the head of the tree workspace.
 struct DevCounters {
-    uint32_t node_count;      // total nodes (written by the last split pass)
+    uint32_t node_count;      // total nodes (the level sizes summed after the split passes)
     uint32_t item_ctr;        // work-item counter of the persistent walk
     uint32_t flags;           // bit 0: depth-capped leaf above leaf_max; bit 1: node overflow
     uint32_t pad;
@@ -75,6 +75,7 @@ struct g4_tree {
     float *q3;                // 10 floats per node (potential only)
     double *mom;              // MOM_STRIDE doubles per node
     float *aseed;             // n floats, sorted order
+    uint32_t *leafof;         // n: the leaf holding each particle (sorted order), set with the moments
     uint4 *walk_spill;        // G4_WALK_SPILL stack entries per wavefront of the walk
     int64_t walk_spill_waves; // wavefronts with a spill area (multiple of 4)
     // forest of independent boxes: one root per box (nodes 0..nbox-1)
@@ -91,8 +92,8 @@ struct g4_tree {
 
 // Layout of a tree workspace (byte offsets).
 struct WsLayout {
-    size_t ctr, keys0, keys1, perm0, perm1, parts, bfirst, bcount, parent, wn, q3, mom, aseed, spill, sort_tmp,
-        sort_bytes, total;
+    size_t ctr, keys0, keys1, perm0, perm1, parts, bfirst, bcount, parent, wn, q3, mom, aseed, leafof, spill,
+        sort_tmp, sort_bytes, total;
     int64_t cap;
     int64_t spill_waves;
 };

@@ -4,7 +4,8 @@
 // first force with a geometric walk (footnote to that equation).  This module
 // replaces that pre-walk by a small network that predicts log10 |a| of each
 // particle from cheap tree features: an 8 -> 64 -> 64 -> 1 perceptron with
-// SiLU activations, BF16 weights and FP32 arithmetic.  Parameter layout (4801
+// SiLU activations, BF16 weights and FP32 arithmetic (the forward pass puts
+// the hidden 64 x 64 layer on the matrix cores).  Parameter layout (4801
 // values): W1[64][8], b1[64], W2[64][64], b2[64], w3[64], b3.
 //
 // Kernels: per-particle features from the particle's leaf, forward pass,
@@ -44,190 +45,228 @@ __device__ __forceinline__ float sigm(float z) { return __builtin_amdgcn_rcpf(1.
 //      the walk), about 20 interactions per particle.
 // A missing ancestor is replaced by the node itself.  Optionally
 // standardised: (f - norm[k]) * norm[8 + k].
-// One wavefront per leaf.  Lane = (particle a of the leaf, slot k): the
-// near-field sum of particle a is split over S = 64 / (particles in the chunk)
-// slots, each taking every S-th source, and the partial sums are added in LDS;
-// lanes with k = 0 then form and write the particle's eight features.
+// One lane per particle j (sorted order). Its leaf comes from the moments
+// pass (leafof), and the lanes of one leaf read the same records, so a
+// wavefront's loads touch few distinct lines. The near-field sum runs over
+// the leaf's particles in order, then over the sibling monopoles (children
+// of the parent other than the leaf, then children of the grandparent other
+// than the parent); the source loads go out four at a time (clamped
+// indices), so the loop is not a chain of single trips to memory.
 template <int KER>
-__global__ __launch_bounds__(256) void k_mlp_features(const DevCounters *__restrict__ C, const WNode *__restrict__ wn,
-                                                      const double *__restrict__ mom,
+__global__ __launch_bounds__(256) void k_mlp_features(const WNode *__restrict__ wn, const double *__restrict__ mom,
                                                       const uint32_t *__restrict__ parent,
+                                                      const uint32_t *__restrict__ leafof,
                                                       const uint4 *__restrict__ parts, const uint32_t *__restrict__ perm,
-                                                      double boxd, double unit_d, float asplit, float h2,
+                                                      int64_t n, double boxd, double unit_d, float asplit, float h2,
                                                       float hinv, const float *__restrict__ norm,
                                                       float *__restrict__ feat)
 {
-    __shared__ float part[4][64][3];
-    const uint32_t nn = C->node_count;
-    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const float unit = (float)unit_d;
-    for (uint32_t q = blockIdx.x * 4 + wv; q < nn; q += gridDim.x * 4) {
+    const uint32_t NONE = 0xffffffffu;
+    for (int64_t jj = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; jj < n; jj += (int64_t)gridDim.x * blockDim.x) {
+        const uint32_t j = (uint32_t)jj;
+        const uint32_t q = leafof[j];
+        const uint4 pj = parts[j];
+        const uint32_t row = perm[j];
         const WNode w = wn[q];
-        if (!(w.meta & WN_LEAF)) continue;
         const uint32_t p = parent[q];
-        const uint32_t gp = p != 0xffffffffu ? parent[p] : 0xffffffffu;
-        // monopoles of the siblings of the leaf (slots 0-7) and of its parent (slots 8-15), one per lane
-        uint32_t sx = 0, sy = 0, sz = 0;
-        float sm = 0.f;
-        if (lane < 16) {
-            const uint32_t self = lane < 8 ? q : p, up = lane < 8 ? p : gp;
-            if (self != 0xffffffffu && up != 0xffffffffu) {
-                const uint32_t nc = wn[up].num, c = wn[up].next + (lane & 7);
-                if ((uint32_t)(lane & 7) < nc && c != self) {
-                    const WNode wc = wn[c];
-                    sx = wc.cx;
-                    sy = wc.cy;
-                    sz = wc.cz;
-                    sm = wc.mass;
-                }
-            }
-        }
-        for (uint32_t c0 = 0; c0 < w.num; c0 += 64) {
-            const uint32_t nc = min(w.num - c0, 64u);
-            const uint32_t S = 64u / nc;
-            const uint32_t a = (uint32_t)lane % nc, k = (uint32_t)lane / nc;
-            const bool act = k < S;
-            const uint32_t j = w.next + c0 + a;
-            const uint4 pj = parts[j];
-            float ax = 0.f, ay = 0.f, az = 0.f, K, W;
-            for (uint32_t s = (act ? k : w.num); s < w.num; s += S) {
-                const uint4 pk = parts[w.next + s];
-                const float dx = (float)(int32_t)(pk.x - pj.x) * unit, dy = (float)(int32_t)(pk.y - pj.y) * unit,
-                            dz = (float)(int32_t)(pk.z - pj.z) * unit;
+        const uint32_t gp = p != NONE ? parent[p] : NONE;
+        const uint32_t pp = p != NONE ? p : q;
+        const WNode wp = wn[pp];
+        const double *ml = mom + (size_t)q * MOM_STRIDE, *mpp = mom + (size_t)pp * MOM_STRIDE;
+        const double mq = ml[0], mp = mpp[0];
+        const double mg = gp != NONE ? mom[(size_t)gp * MOM_STRIDE] : mp;
+        float ax = 0.f, ay = 0.f, az = 0.f, K, W;
+        const uint32_t stop = w.next + w.num;
+        for (uint32_t s0 = w.next; s0 < stop; s0 += 4) {
+            uint4 pk[4];
+#pragma unroll
+            for (uint32_t u = 0; u < 4; u++) pk[u] = parts[s0 + u < stop ? s0 + u : stop - 1];
+#pragma unroll
+            for (uint32_t u = 0; u < 4; u++) {
+                const float dx = (float)(int32_t)(pk[u].x - pj.x) * unit, dy = (float)(int32_t)(pk[u].y - pj.y) * unit,
+                            dz = (float)(int32_t)(pk[u].z - pj.z) * unit;
                 pair_kernel<KER, false>(dx * dx + dy * dy + dz * dz, asplit, h2, hinv, K, W);
-                const float mk = w.next + s != j ? __uint_as_float(pk.w) * K : 0.f;
+                const float mk = s0 + u < stop && s0 + u != j ? __uint_as_float(pk[u].w) * K : 0.f;
                 ax += mk * dx;
                 ay += mk * dy;
                 az += mk * dz;
             }
-            for (uint32_t e = 0; e < 16; e += S) {
-                // sibling slot e + k, fetched from its lane
-                const int from = (int)min(e + k, 15u);
-                const uint32_t kx = (uint32_t)__shfl((int)sx, from), ky = (uint32_t)__shfl((int)sy, from),
-                               kz = (uint32_t)__shfl((int)sz, from);
-                const float km = __uint_as_float((uint32_t)__shfl((int)__float_as_uint(sm), from));
-                if (act && e + k < 16 && km != 0.f) {
-                    const float dx = (float)(int32_t)(kx - pj.x) * unit, dy = (float)(int32_t)(ky - pj.y) * unit,
-                                dz = (float)(int32_t)(kz - pj.z) * unit;
-                    pair_kernel<KER, false>(dx * dx + dy * dy + dz * dz, asplit, h2, hinv, K, W);
-                    const float mk = km * K;
-                    ax += mk * dx;
-                    ay += mk * dy;
-                    az += mk * dz;
-                }
-            }
-            part[wv][lane][0] = ax;
-            part[wv][lane][1] = ay;
-            part[wv][lane][2] = az;
-            __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-            __builtin_amdgcn_wave_barrier();
-            if ((uint32_t)lane < nc) {
-                // slot sums in slot order: leaf particles first, then siblings, as one sequence per slot
-                float tx = 0.f, ty = 0.f, tz = 0.f;
-                for (uint32_t kk = 0; kk < S; kk++) {
-                    tx += part[wv][kk * nc + a][0];
-                    ty += part[wv][kk * nc + a][1];
-                    tz += part[wv][kk * nc + a][2];
-                }
-                const int level = (int)(w.meta & 0xffu);
-                const uint32_t pp = p != 0xffffffffu ? p : q;
-                const WNode wp = wn[pp];
-                const double *dl = mom + (size_t)q * MOM_STRIDE + 1, *dp = mom + (size_t)pp * MOM_STRIDE + 1;
-                const double il = 1.0 / ldexp(boxd, -level), ilp = 1.0 / ldexp(boxd, -(int)(wp.meta & 0xffu));
-                float f[8];
-                f[0] = log10f((float)mom[(size_t)q * MOM_STRIDE]);
-                f[1] = log10f((float)ldexp(boxd, -level));
-                f[2] = (float)level;
-                // offsets from the centres of mass in FP64 (they may nearly cancel), logarithms in FP32
-                double a0 = (double)(int32_t)(pj.x - w.gx) * unit_d - dl[0],
-                       a1 = (double)(int32_t)(pj.y - w.gy) * unit_d - dl[1],
-                       a2 = (double)(int32_t)(pj.z - w.gz) * unit_d - dl[2];
-                f[3] = log10f((float)(sqrt(a0 * a0 + a1 * a1 + a2 * a2) * il + 1e-3));
-                a0 = (double)(int32_t)(pj.x - wp.gx) * unit_d - dp[0];
-                a1 = (double)(int32_t)(pj.y - wp.gy) * unit_d - dp[1];
-                a2 = (double)(int32_t)(pj.z - wp.gz) * unit_d - dp[2];
-                f[4] = log10f((float)(sqrt(a0 * a0 + a1 * a1 + a2 * a2) * ilp + 1e-3));
-                const float Mp = (float)mom[(size_t)pp * MOM_STRIDE];
-                f[5] = log10f(Mp);
-                f[6] = gp != 0xffffffffu ? log10f((float)mom[(size_t)gp * MOM_STRIDE]) : log10f(Mp);
-                f[7] = log10f(fmaxf(sqrtf(tx * tx + ty * ty + tz * tz), 1e-30f));
-                float *o = feat + (size_t)perm[j] * 8;
-                for (int kk = 0; kk < 8; kk++) o[kk] = norm ? (f[kk] - norm[kk]) * norm[8 + kk] : f[kk];
-            }
-            __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-            __builtin_amdgcn_wave_barrier();
         }
+        for (int side = 0; side < 2; side++) {
+            const uint32_t self = side ? p : q, up = side ? gp : p;
+            if (self == NONE || up == NONE) continue;
+            const WNode wu = side ? wn[up] : wp;
+            // centre of mass and mass of each child (the first 16 bytes of its record)
+            uint4 ch[8];
+#pragma unroll
+            for (uint32_t c = 0; c < 8; c++)
+                ch[c] = reinterpret_cast<const uint4 *>(wn + wu.next + (c < wu.num ? c : 0))[0];
+#pragma unroll
+            for (uint32_t c = 0; c < 8; c++) {
+                if (c >= wu.num || wu.next + c == self) continue;
+                const float km = __uint_as_float(ch[c].w);
+                if (km == 0.f) continue;
+                const float dx = (float)(int32_t)(ch[c].x - pj.x) * unit, dy = (float)(int32_t)(ch[c].y - pj.y) * unit,
+                            dz = (float)(int32_t)(ch[c].z - pj.z) * unit;
+                pair_kernel<KER, false>(dx * dx + dy * dy + dz * dz, asplit, h2, hinv, K, W);
+                const float mk = km * K;
+                ax += mk * dx;
+                ay += mk * dy;
+                az += mk * dz;
+            }
+        }
+        const int level = (int)(w.meta & 0xffu);
+        const double il = 1.0 / ldexp(boxd, -level), ilp = 1.0 / ldexp(boxd, -(int)(wp.meta & 0xffu));
+        float f[8];
+        f[0] = log10f((float)mq);
+        f[1] = log10f((float)ldexp(boxd, -level));
+        f[2] = (float)level;
+        // offsets from the centres of mass in FP64 (they may nearly cancel), logarithms in FP32
+        double a0 = (double)(int32_t)(pj.x - w.gx) * unit_d - ml[1], a1 = (double)(int32_t)(pj.y - w.gy) * unit_d - ml[2],
+               a2 = (double)(int32_t)(pj.z - w.gz) * unit_d - ml[3];
+        f[3] = log10f((float)(sqrt(a0 * a0 + a1 * a1 + a2 * a2) * il + 1e-3));
+        a0 = (double)(int32_t)(pj.x - wp.gx) * unit_d - mpp[1];
+        a1 = (double)(int32_t)(pj.y - wp.gy) * unit_d - mpp[2];
+        a2 = (double)(int32_t)(pj.z - wp.gz) * unit_d - mpp[3];
+        f[4] = log10f((float)(sqrt(a0 * a0 + a1 * a1 + a2 * a2) * ilp + 1e-3));
+        f[5] = log10f((float)mp);
+        f[6] = log10f((float)mg);
+        f[7] = log10f(fmaxf(sqrtf(ax * ax + ay * ay + az * az), 1e-30f));
+        float *o = feat + (size_t)row * 8;
+        for (int kk = 0; kk < 8; kk++) o[kk] = norm ? (f[kk] - norm[kk]) * norm[8 + kk] : f[kk];
     }
 }
 
 int g4_launch_mlp_features(g4_ctx *ctx, const g4_tree *t, const g4_walk_params *wp, const float *norm, float *feat)
 {
-    int blocks = (int)((t->cap + 3) / 4);
-    if (blocks > 4096) blocks = 4096;
+    int64_t blocks = (t->n + 255) / 256;
+    if (blocks > 16384) blocks = 16384;
     const double h = 2.8 * wp->eps0;
     const float asplit = wp->kernel == 1 ? (float)(0.5 / wp->r_s) : 0.f;
     const float h2 = (float)(h * h), hinv = h > 0 ? (float)(1.0 / h) : 0.f;
     if (wp->kernel == 1)
-        k_mlp_features<1><<<blocks, 256, 0, ctx->stream>>>(t->ctr, t->wn, t->mom, t->parent, t->parts, t->perm1,
-                                                           t->tp.box, t->unit, asplit, h2, hinv, norm, feat);
+        k_mlp_features<1><<<(unsigned)blocks, 256, 0, ctx->stream>>>(t->wn, t->mom, t->parent, t->leafof, t->parts,
+                                                                     t->perm1, t->n, t->tp.box, t->unit, asplit, h2,
+                                                                     hinv, norm, feat);
     else
-        k_mlp_features<0><<<blocks, 256, 0, ctx->stream>>>(t->ctr, t->wn, t->mom, t->parent, t->parts, t->perm1,
-                                                           t->tp.box, t->unit, asplit, h2, hinv, norm, feat);
+        k_mlp_features<0><<<(unsigned)blocks, 256, 0, ctx->stream>>>(t->wn, t->mom, t->parent, t->leafof, t->parts,
+                                                                     t->perm1, t->n, t->tp.box, t->unit, asplit, h2,
+                                                                     hinv, norm, feat);
     G4_HIP(ctx, hipGetLastError());
     return G4_OK;
 }
 
 // ------------------------------------------------------------------ forward
-// One thread per particle; weights converted to FP32 once per block into LDS
-// and read at wave-uniform addresses (broadcast).  mode 0 writes y = log10|a|,
+// One wavefront per tile of 32 particles. Lane (c, h), c = lane % 32, takes
+// particle c of the tile and hidden units 8h + 16s + j (s < 4, j < 8) of the
+// first layer in FP32. The 64 x 64 second layer runs on the matrix cores
+// (32x32x16 BF16 products, FP32 accumulation): W2 is exact in BF16, and each
+// first-layer output is split as hi + lo with hi = bf16(h), lo = bf16(h - hi),
+// so the two products per step carry h to about 2^-17 relative, close to
+// FP32. A lane's 16 + 16 accumulator values are rows 8 (r / 4) + 4 h + r % 4
+// of the two 32-row output tiles for its particle; the last layer sums them
+// and the two halves of the wave are added. mode 0 writes y = log10|a|,
 // mode 1 writes 10^(y + shift).
-__global__ __launch_bounds__(256, 2) void k_mlp_forward(const uint16_t *__restrict__ w, const float *__restrict__ feat,
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef unsigned short u16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+
+#define FWD_TILE 32
+
+__global__ __launch_bounds__(256) void k_mlp_forward(const uint16_t *__restrict__ w, const float *__restrict__ feat,
                                                      int64_t n, float *__restrict__ out, float shift, int mode)
 {
-    __shared__ float W[MLP_NP + 3];
-    for (int k = threadIdx.x; k < MLP_NP; k += blockDim.x) W[k] = bf16_to_f32(w[k]);
+    // W1 rows (8 weights + bias, padded to 12 for 16-byte reads), then b2 and w3
+    __shared__ __attribute__((aligned(16))) float L1[64][12];
+    __shared__ float E[2][64];
+    for (int k = threadIdx.x; k < 64 * 9; k += blockDim.x) {
+        const int u = k / 9, i = k % 9;
+        L1[u][i] = bf16_to_f32(w[i < 8 ? u * 8 + i : OFF_B1 + u]);
+    }
+    for (int k = threadIdx.x; k < 64; k += blockDim.x) {
+        E[0][k] = bf16_to_f32(w[OFF_B2 + k]);
+        E[1][k] = bf16_to_f32(w[OFF_W3 + k]);
+    }
+    const float b3 = bf16_to_f32(w[OFF_B3]);
     __syncthreads();
-    // one particle per thread: no particle loop, so the weight reads from LDS
-    // are not hoisted into registers across particles
-    const int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (p < n) {
-        const float4 xa = reinterpret_cast<const float4 *>(feat)[2 * p];
-        const float4 xb = reinterpret_cast<const float4 *>(feat)[2 * p + 1];
-        const float x[8] = {xa.x, xa.y, xa.z, xa.w, xb.x, xb.y, xb.z, xb.w};
-        float h1[64];
+    const int lane = threadIdx.x & 63, c = lane & 31, h = lane >> 5;
+    // second-layer weights as matrix-core A operands: row 32 t + c, columns 16 s + 8 h + j
+    bf16x8 A[2][4];
 #pragma unroll
-        for (int o = 0; o < 64; o++) {
-            float z = W[OFF_B1 + o];
+    for (int t = 0; t < 2; t++)
 #pragma unroll
-            for (int i = 0; i < 8; i++) z = fmaf(W[o * 8 + i], x[i], z);
-            h1[o] = z * sigm(z);
+        for (int s = 0; s < 4; s++) {
+            u16x8 v;
+            const uint16_t *r = w + OFF_W2 + (32 * t + c) * 64 + 16 * s + 8 * h;
+#pragma unroll
+            for (int j = 0; j < 8; j++) v[j] = r[j];
+            A[t][s] = __builtin_bit_cast(bf16x8, v);
         }
-        float y = W[OFF_B3];
-#pragma unroll 1
-        for (int o = 0; o < 64; o += 4) {
-            // four independent dot products per pass for instruction-level parallelism
-            float z0 = W[OFF_B2 + o], z1 = W[OFF_B2 + o + 1], z2 = W[OFF_B2 + o + 2], z3 = W[OFF_B2 + o + 3];
-            const float *r = W + OFF_W2 + o * 64;
+    const int64_t tiles = (n + FWD_TILE - 1) / FWD_TILE;
+    const int64_t wave = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) >> 6;
+    const int64_t nwave = ((int64_t)gridDim.x * blockDim.x) >> 6;
+    for (int64_t tile = wave; tile < tiles; tile += nwave) {
+        const int64_t p = tile * FWD_TILE + c;
+        const bool valid = p < n;
+        float x[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+        if (valid) {
+            const float4 xa = reinterpret_cast<const float4 *>(feat)[2 * p];
+            const float4 xb = reinterpret_cast<const float4 *>(feat)[2 * p + 1];
+            x[0] = xa.x; x[1] = xa.y; x[2] = xa.z; x[3] = xa.w;
+            x[4] = xb.x; x[5] = xb.y; x[6] = xb.z; x[7] = xb.w;
+        }
+        // an offset the compiler cannot see through, so the first-layer
+        // weights are read from LDS per tile instead of held in registers
+        int row0 = 8 * h;
+        asm volatile("" : "+v"(row0));
+        bf16x8 Bh[4], Bl[4];
 #pragma unroll
-            for (int i = 0; i < 64; i++) {
-                z0 = fmaf(r[i], h1[i], z0);
-                z1 = fmaf(r[64 + i], h1[i], z1);
-                z2 = fmaf(r[128 + i], h1[i], z2);
-                z3 = fmaf(r[192 + i], h1[i], z3);
+        for (int s = 0; s < 4; s++)
+#pragma unroll
+            for (int j = 0; j < 8; j++) {
+                const float *r = L1[row0 + 16 * s + j];
+                const float4 ra = *reinterpret_cast<const float4 *>(r);
+                const float4 rb = *reinterpret_cast<const float4 *>(r + 4);
+                float z = r[8];
+                z = fmaf(ra.x, x[0], z); z = fmaf(ra.y, x[1], z); z = fmaf(ra.z, x[2], z); z = fmaf(ra.w, x[3], z);
+                z = fmaf(rb.x, x[4], z); z = fmaf(rb.y, x[5], z); z = fmaf(rb.z, x[6], z); z = fmaf(rb.w, x[7], z);
+                const float a = z * sigm(z);
+                const __bf16 hi = (__bf16)a;
+                Bh[s][j] = hi;
+                Bl[s][j] = (__bf16)(a - (float)hi);
             }
-            y = fmaf(W[OFF_W3 + o], z0 * sigm(z0), y);
-            y = fmaf(W[OFF_W3 + o + 1], z1 * sigm(z1), y);
-            y = fmaf(W[OFF_W3 + o + 2], z2 * sigm(z2), y);
-            y = fmaf(W[OFF_W3 + o + 3], z3 * sigm(z3), y);
+        f32x16 acc0 = {}, acc1 = {};
+#pragma unroll
+        for (int s = 0; s < 4; s++) {
+            acc0 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(A[0][s], Bh[s], acc0, 0, 0, 0);
+            acc1 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(A[1][s], Bh[s], acc1, 0, 0, 0);
+            acc0 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(A[0][s], Bl[s], acc0, 0, 0, 0);
+            acc1 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(A[1][s], Bl[s], acc1, 0, 0, 0);
         }
-        out[p] = mode ? exp10f(y + shift) : y;
+        float y = 0.f;
+#pragma unroll
+        for (int r = 0; r < 16; r++) {
+            const int o = 8 * (r >> 2) + 4 * h + (r & 3);
+            const float z0 = acc0[r] + E[0][o], z1 = acc1[r] + E[0][32 + o];
+            y = fmaf(E[1][o], z0 * sigm(z0), y);
+            y = fmaf(E[1][32 + o], z1 * sigm(z1), y);
+        }
+        y += __shfl_xor(y, 32);
+        if (h == 0 && valid) {
+            y += b3;
+            out[p] = mode ? exp10f(y + shift) : y;
+        }
     }
 }
 
 int g4_launch_mlp_forward(g4_ctx *ctx, const uint16_t *w, const float *feat, int64_t n, float *out, float shift,
                           int mode)
 {
-    const int64_t blocks = (n + 255) / 256;
+    // about eight tiles per wavefront, so the A operands load once per eight tiles
+    const int64_t tiles = (n + FWD_TILE - 1) / FWD_TILE;
+    int64_t blocks = (tiles + 31) / 32;
+    if (blocks > 4096) blocks = 4096;
     if (n > 0) k_mlp_forward<<<(unsigned)blocks, 256, 0, ctx->stream>>>(w, feat, n, out, shift, mode);
     G4_HIP(ctx, hipGetLastError());
     return G4_OK;
