@@ -511,9 +511,10 @@ __global__ void k_moments(const DevCounters *__restrict__ C, const uint4 *__rest
         const uint32_t g[3] = {w.gx, w.gy, w.gz};
         T M = 0, c1[3] = {0, 0, 0}, s[3];
         T Q2[6] = {0, 0, 0, 0, 0, 0}, Q3[10] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
-        if ((w.meta & WN_LEAF) && w.num <= 32) {
+        if (sizeof(T) == 4 && (w.meta & WN_LEAF) && w.num <= 32) {
             // up to four particles per lane, loaded together (clamped
-            // indices) and kept in registers for both passes
+            // indices) and kept in registers for both passes (measured
+            // faster for the single-precision levels only)
             const uint32_t stop = w.next + w.num;
             uint4 pv[4];
 #pragma unroll
