@@ -80,10 +80,10 @@ def walk_source_sha():
     return h.hexdigest()
 
 
-def walk_traffic(variant, alpha):
+def walk_traffic(variant, alpha, leaf):
     """HBM bytes per launch of the relative walk from the committed counter
-    summary, if it was taken on the current walk sources for this variant and
-    alpha; None otherwise."""
+    summary, if it was taken on the current walk sources for this variant,
+    alpha and leaf size; None otherwise."""
     if not os.path.exists(TRAFFIC_FILE):
         return None
     kv = {}
@@ -94,7 +94,7 @@ def walk_traffic(variant, alpha):
                 kv[k.strip()] = v.strip()
     try:
         if kv.get("source_sha256") != walk_source_sha() or kv.get("variant") != variant or \
-                abs(float(kv.get("alpha", "nan")) - alpha) > 1e-12:
+                abs(float(kv.get("alpha", "nan")) - alpha) > 1e-12 or kv.get("leaf_max") != str(leaf):
             return None
         return float(kv["traffic_bytes_per_launch"])
     except (KeyError, ValueError):
@@ -244,7 +244,7 @@ def main():
     ralpha = learned["alpha"] if best_learned else alpha
     walk_flop = flops.walk_flops("treepm", "relative", st["n_visit"], st["n_p2m"], st["n_p2p"])
     achieved = walk_flop / (rwalk_ms * 1e-3)
-    traffic = walk_traffic("learned" if best_learned else "plain", ralpha)
+    traffic = walk_traffic("learned" if best_learned else "plain", ralpha, args.leaf)
     util = {"pop": st["n_visit"] / max(1, 64 * st["w_pop"]), "p2m": st["n_p2m"] / max(1, 64 * st["w_p2m"]),
             "p2p": st["n_p2p"] / max(1, 64 * st["w_p2p"])}
     passes = {k: st[k] for k in ("w_pop", "w_p2m", "w_p2p", "w_entry", "w_leaf", "w_chunk", "max_stack")}
