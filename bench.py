@@ -57,6 +57,8 @@ def parse():
     ap.add_argument("--leaf", type=int, default=24, help="leaf size B of the headline tree")
     ap.add_argument("--copy-calibration-mb", type=int, default=0,
                     help="also run a plain device copy of this size (HBM counter calibration)")
+    ap.add_argument("--sr-table", type=int, default=0,
+                    help="intervals of the short-range factor table of the walks (0: erfc/exp per interaction)")
     ap.add_argument("--profile-walk", choices=("plain", "learned"), default=None,
                     help="only time `steps` steps of this variant at --alpha (no reference sums, no calibration), "
                          "for counter runs of the walk")
@@ -132,9 +134,10 @@ def main():
 
     def params(rcut_f, alpha):
         r_cut = rcut_f * r_s
-        seed = g.walk_params(kernel=1, criterion=0, theta=0.7, r_s=r_s, r_cut=r_cut, eps0=eps0, group_size=args.group)
+        seed = g.walk_params(kernel=1, criterion=0, theta=0.7, r_s=r_s, r_cut=r_cut, eps0=eps0, group_size=args.group,
+                             sr_table=args.sr_table)
         rel = g.walk_params(kernel=1, criterion=1, alpha=alpha, r_s=r_s, r_cut=r_cut, eps0=eps0, seed_from_tree=1,
-                            group_size=args.group)
+                            group_size=args.group, sr_table=args.sr_table)
         return seed, rel
 
     def step(wps, evs=None):
@@ -265,7 +268,7 @@ def main():
         "config": {"workload": "treepm_shortrange_clustered_box_128^3", "n": n, "box": 1.0, "r_s": r_s,
                    "r_cut": args.rcut * r_s, "R_cut": args.rcut, "eps0": eps0, "leaf_max": B, "order": 3,
                    "alpha": learned["alpha"] if best_learned else alpha, "theta_seed": 0.7,
-                   "group_size": args.group,
+                   "group_size": args.group, "sr_table": args.sr_table,
                    "variant": "learned (MLP |a| seed + relative walk)" if best_learned
                    else "plain (geometric pre-walk + relative walk)"},
         "plain": {"forces_per_s": plain_value, "ms_per_step": ms_per_step, "alpha": alpha,
@@ -404,7 +407,7 @@ def learned_step(args, g, ctx, n, r_s, eps0, tp, ws, pos, mass, out, stream, sta
 
     def lparams(alpha):
         return g.walk_params(kernel=1, criterion=1, alpha=alpha, r_s=r_s, r_cut=args.rcut * r_s, eps0=eps0,
-                             a_seed=aseed, group_size=args.group)
+                             a_seed=aseed, group_size=args.group, sr_table=args.sr_table)
 
     def lstep(wp, evs=None):
         x, y, z = g.g4_quantize(ctx, pos, tp)

@@ -77,7 +77,18 @@ typedef struct {
  * a_seed:    device, caller order, |a| per particle (nullable).
  * seed_from_tree: with a_seed NULL, 1 = use the |a| that the previous
  *            geometric (criterion 0) call left in this tree instead of
- *            running a pre-walk (lets a caller time the two walks apart). */
+ *            running a pre-walk (lets a caller time the two walks apart).
+ * sr_table:  kernel 1 only.  0 = evaluate the short-range factors with erfc
+ *            and exp per interaction; 8..512 = interpolate them from a
+ *            one-dimensional look-up table of that many intervals over
+ *            alpha_split r in [0, 6] (Sec. "TreePM approach": the paper
+ *            interpolates linearly in a table of 48 to 256 entries; here
+ *            each interval holds a cubic Hermite piece, max. error about
+ *            4e-6 of the Newtonian factor at 64 intervals).  Pairs beyond
+ *            alpha_split r = 6 (factor < 2e-15) get the value at 6.  The
+ *            table lives in the tree workspace and is rebuilt when its
+ *            length changes.  Node decisions and interaction counts do not
+ *            depend on it. */
 typedef struct {
     int kernel;
     int criterion;
@@ -87,6 +98,7 @@ typedef struct {
     const float *a_seed;
     int group_size;
     int seed_from_tree;
+    int sr_table;
 } g4_walk_params;
 
 /* FMM (Sec. "Fast multipole method", "The FMM-PM approach"), p = 3.

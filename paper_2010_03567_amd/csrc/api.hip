@@ -125,6 +125,8 @@ static int g4_build_tree_views(g4_ctx *ctx, const g4_particles *p, const g4_tree
     t->aseed = (float *)(b + L.aseed);
     t->leafof = (uint32_t *)(b + L.leafof);
     t->walk_spill = (uint4 *)(b + L.spill);
+    t->srtab = (float4 *)(b + L.srtab);
+    t->tab_n = 0;
     t->walk_spill_waves = L.spill_waves;
     t->sort_tmp = b + L.sort_tmp;
     t->sort_tmp_bytes = L.sort_bytes;
@@ -257,6 +259,8 @@ static int tree_force_impl(g4_ctx *ctx, g4_tree *tree, const g4_walk_params *wp,
     if (kernel == 1 && !(wp->r_cut > 0)) return g4_set_err(ctx, G4_EINVAL, "r_cut must be positive");
     if (wp->eps0 < 0) return g4_set_err(ctx, G4_EINVAL, "eps0 must be >= 0");
     if (wp->group_size < 0 || wp->group_size > 64) return g4_set_err(ctx, G4_EINVAL, "group_size must be 0..64");
+    if (wp->sr_table != 0 && (wp->sr_table < 8 || wp->sr_table > G4_SRTAB_MAX))
+        return g4_set_err(ctx, G4_EINVAL, "sr_table must be 0 or 8..512");
     if (!tree->tp.periodic && kernel == 1) return g4_set_err(ctx, G4_EINVAL, "short-range kernel needs a periodic box");
     if (stats) G4_HIP(ctx, hipMemsetAsync(tree->ctr->stat, 0, sizeof(tree->ctr->stat), ctx->stream));
     int st;

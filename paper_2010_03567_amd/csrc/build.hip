@@ -68,6 +68,7 @@ int g4_layout(const g4_tree_params *tp, int64_t n, WsLayout *L)
     if (waves > G4_WALK_MAX_WAVES) waves = G4_WALK_MAX_WAVES;
     L->spill_waves = waves;
     L->spill = take((size_t)waves * G4_WALK_SPILL * 16);
+    L->srtab = take((size_t)G4_SRTAB_FUNCS * G4_SRTAB_MAX * 16);
     size_t sb = 0;
     if (rocprim::radix_sort_pairs((void *)nullptr, sb, (uint64_t *)nullptr, (uint64_t *)nullptr,
                                   (uint32_t *)nullptr, (uint32_t *)nullptr, (size_t)(n > 0 ? n : 1), 0, 63) !=

@@ -96,3 +96,44 @@ __device__ __forceinline__ void pair_kernel(float r2, float asplit, float h2, fl
     }
 }
 
+// Short-range factors by table (Sec. "TreePM approach": one-dimensional
+// look-up table instead of erfc per interaction).  With x = alpha_split r,
+//   S_0 = erfc x,  S_n = erfc x + (2x/sqrt(pi)) e^{-x^2} P_n(x^2),
+//   P_1 = 1, P_2 = 1 + 2x^2/3, P_3 = 1 + 2x^2/3 + 4x^4/15,
+// so that the short-range g_0..g_3 are the Newtonian ones (1/r, -1/r^3,
+// 3/r^5, -15/r^7) times S_0..S_3.  tab[f * n + k] holds the cubic Hermite
+// piece of S_f on interval k, in u in [0, 1]; t = r * tscale = x n / x_max.
+__device__ __forceinline__ void sr_locate(float r, float tscale, uint32_t n, uint32_t &k, float &u)
+{
+    const float t = fminf(r * tscale, (float)n);
+    k = min((uint32_t)t, n - 1u);
+    u = t - (float)k;
+}
+__device__ __forceinline__ float sr_eval(const float4 &c, float u)
+{
+    return fmaf(u, fmaf(u, fmaf(u, c.w, c.z), c.y), c.x);
+}
+
+// pair_kernel<1, POT> with the short-range factors from the table
+template <bool POT>
+__device__ __forceinline__ void pair_kernel_tab(float r2, const float4 *__restrict__ tab, uint32_t n, float tscale,
+                                                float asplit, float h2, float hinv, float &K, float &W)
+{
+    float rinv = r2 > 0.f ? rsq(r2) : 0.f;
+    float rinv2 = rinv * rinv;
+    float r = r2 * rinv;
+    uint32_t k;
+    float u;
+    sr_locate(r, tscale, n, k, u);
+    K = sr_eval(tab[n + k], u) * rinv * rinv2;
+    if (POT) W = sr_eval(tab[k], u) * rinv;
+    if (r2 < h2) {
+        float uh = r * hinv;
+        K = soft_force(uh, hinv);
+        if (POT) W = soft_pot(uh, hinv);
+        float x = asplit * r;
+        float a3 = asplit * asplit * asplit;
+        K -= a3 * lr_force_x3(x);
+        if (POT) W -= asplit * erf_over_x(x);
+    }
+}

@@ -43,6 +43,12 @@ static_assert(sizeof(WNode) == 64, "WNode must be 64 bytes");
 // [4..9] Q2 packed, [10..19] Q3 packed (xxx xxy xxz xyy xyz xzz yyy yyz yzz zzz).
 #define MOM_STRIDE 20
 
+// Short-range factor table: S_0..S_3 (erfc-type factors of g_0..g_3), up to
+// G4_SRTAB_MAX intervals over x = alpha_split r in [0, G4_SRTAB_XMAX].
+#define G4_SRTAB_FUNCS 4
+#define G4_SRTAB_MAX 512
+#define G4_SRTAB_XMAX 6.0
+
 // Device counters at the head of the tree workspace.
 struct DevCounters {
     uint32_t node_count;      // total nodes (the level sizes summed after the split passes)
@@ -77,6 +83,8 @@ struct g4_tree {
     float *aseed;             // n floats, sorted order
     uint32_t *leafof;         // n: the leaf holding each particle (sorted order), set with the moments
     uint4 *walk_spill;        // G4_WALK_SPILL stack entries per wavefront of the walk
+    float4 *srtab;            // short-range factor table: G4_SRTAB_FUNCS x tab_n cubic pieces
+    int tab_n;                // intervals it holds (0: not built); it is in units of alpha_split r
     int64_t walk_spill_waves; // wavefronts with a spill area (multiple of 4)
     // forest of independent boxes: one root per box (nodes 0..nbox-1)
     int nbox;
@@ -93,7 +101,7 @@ struct g4_tree {
 // Layout of a tree workspace (byte offsets).
 struct WsLayout {
     size_t ctr, keys0, keys1, perm0, perm1, parts, bfirst, bcount, parent, wn, q3, mom, aseed, leafof, spill,
-        sort_tmp, sort_bytes, total;
+        srtab, sort_tmp, sort_bytes, total;
     int64_t cap;
     int64_t spill_waves;
 };

@@ -37,6 +37,9 @@ struct WalkArgs {
     float box;        // physical root side
     float h, h2, hinv;
     float asplit;     // 1/(2 r_s)
+    const float4 *tab;  // short-range factor table (kernel 2), tn intervals, t = r * tscale
+    uint32_t tn;
+    float tscale;
     float rcut2;
     float theta2;
     float alpha;      // relative-criterion accuracy parameter
@@ -65,6 +68,18 @@ __device__ __forceinline__ void gfun(float r2, float rinv, const WalkArgs &A, fl
         g1 = -rinv * ri2;
         g2 = -3.0f * g1 * ri2;
         g3 = -5.0f * g2 * ri2;
+    } else if (KER == 2) {
+        // the short-range factors from the table: g_n = (Newtonian g_n) S_n
+        uint32_t k;
+        float u;
+        sr_locate(r2 * rinv, A.tscale, A.tn, k, u);
+        const float s1 = sr_eval(A.tab[A.tn + k], u), s2 = sr_eval(A.tab[2 * A.tn + k], u),
+                    s3 = sr_eval(A.tab[3 * A.tn + k], u);
+        const float ri3 = rinv * ri2;
+        g0 = sr_eval(A.tab[k], u) * rinv;
+        g1 = -s1 * ri3;
+        g2 = 3.0f * s2 * ri3 * ri2;
+        g3 = -15.0f * s3 * ri3 * ri2 * ri2;
     } else {
         float r = r2 * rinv;
         float x = A.asplit * r;
@@ -313,7 +328,8 @@ __global__ __launch_bounds__(256) void k_walk(const WalkArgs A)
                 const float sz = (float)(int32_t)(src.z - q_z) * A.unit;
                 const float s2 = fmaf(sx, sx, fmaf(sy, sy, sz * sz));
                 float K, Wp;
-                pair_kernel<KER, POT>(s2, A.asplit, A.h2, A.hinv, K, Wp);
+                if constexpr (KER == 2) pair_kernel_tab<POT>(s2, A.tab, A.tn, A.tscale, A.asplit, A.h2, A.hinv, K, Wp);
+                else pair_kernel<KER, POT>(s2, A.asplit, A.h2, A.hinv, K, Wp);
                 const float mk = mj * K;
                 q_fx = fmaf(mk, sx, q_fx);
                 q_fy = fmaf(mk, sy, q_fy);
@@ -395,7 +411,7 @@ __global__ __launch_bounds__(256) void k_walk(const WalkArgs A)
             // exclusion zone; the nearest-edge distance is max(|d| unit - l/2, 0) per axis
             const int32_t gx = (int32_t)(R.gx - T.x), gy = (int32_t)(R.gy - T.y), gz = (int32_t)(R.gz - T.z);
             bool ok = valid;
-            if (KER == 1) {
+            if (KER >= 1) {
                 // nearest edge of the node's cube farther than r_cut: drop it
                 const float qx = fmaxf(fabsf((float)gx) * A.unit - R.hl, 0.f);
                 const float qy = fmaxf(fabsf((float)gy) * A.unit - R.hl, 0.f);
@@ -497,7 +513,9 @@ __global__ __launch_bounds__(256) void k_walk(const WalkArgs A)
         A.ax[o] = gx;
         A.ay[o] = gy;
         A.az[o] = gz;
-        if (POT && A.pot) A.pot[o] = A.G * W.acc[3][lane];
+        if constexpr (POT) {
+            if (A.pot) A.pot[o] = A.G * W.acc[3][lane];
+        }
         const float amag = (float)sqrt(gx * gx + gy * gy + gz * gz);
         if (A.aout_sorted) A.aout_sorted[i] = amag;
         if (A.aout_caller) A.aout_caller[o] = amag;
@@ -541,6 +559,34 @@ static void launch_walk(const WalkArgs &A, hipStream_t s)
     k_walk<KER, CRIT, POT><<<(unsigned)blocks, 256, 0, s>>>(A);
 }
 
+// Cubic Hermite pieces of S_0..S_3 (see pair_kernel_tab) on n intervals of
+// x in [0, G4_SRTAB_XMAX], from FP64 values and derivatives at the interval
+// ends; dS_f/dx = -2^(f+1) x^(2f) e^{-x^2} / ((2f-1)!! sqrt(pi)).
+__device__ inline void sr_value(int f, double x, double &v, double &d)
+{
+    const double e = exp(-x * x), c = 1.1283791670955126;  // 2/sqrt(pi)
+    const double x2 = x * x;
+    const double P = f == 0 ? 0.0 : (f == 1 ? 1.0 : (f == 2 ? 1.0 + x2 * (2.0 / 3) : 1.0 + x2 * (2.0 / 3 + x2 * (4.0 / 15))));
+    v = erfc(x) + c * x * e * P;
+    const double dfac = f == 0 ? 1.0 : (f == 1 ? 2.0 * x2 : (f == 2 ? 4.0 / 3 * x2 * x2 : 8.0 / 15 * x2 * x2 * x2));
+    d = -c * e * dfac;
+}
+
+__global__ void k_srtab(float4 *__restrict__ tab, int n)
+{
+    const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= G4_SRTAB_FUNCS * n) return;
+    const int f = idx / n, k = idx % n;
+    const double dx = G4_SRTAB_XMAX / n;
+    double f0, d0, f1, d1;
+    sr_value(f, k * dx, f0, d0);
+    sr_value(f, (k + 1) * dx, f1, d1);
+    d0 *= dx;
+    d1 *= dx;
+    tab[idx] = make_float4((float)f0, (float)d0, (float)(3.0 * (f1 - f0) - 2.0 * d0 - d1),
+                           (float)(2.0 * (f0 - f1) + d0 + d1));
+}
+
 int g4_launch_walk(g4_ctx *ctx, g4_tree *t, const g4_walk_params *wp, int kernel, int criterion, double *ax,
                    double *ay, double *az, double *pot, uint32_t *counts, float *aout_caller, float *aout_sorted,
                    int stat_slot)
@@ -563,6 +609,16 @@ int g4_launch_walk(g4_ctx *ctx, g4_tree *t, const g4_walk_params *wp, int kernel
     A.h2 = (float)(h * h);
     A.hinv = h > 0 ? (float)(1.0 / h) : 0.f;
     A.asplit = kernel == 1 ? (float)(0.5 / wp->r_s) : 0.f;
+    const bool tabulated = kernel == 1 && wp->sr_table > 0;
+    A.tab = t->srtab;
+    A.tn = tabulated ? (uint32_t)wp->sr_table : 0u;
+    A.tscale = tabulated ? (float)(0.5 / wp->r_s * wp->sr_table / G4_SRTAB_XMAX) : 0.f;
+    if (tabulated && t->tab_n != wp->sr_table) {
+        // the table is in units of x = alpha_split r, so it depends on its length only
+        k_srtab<<<(G4_SRTAB_FUNCS * wp->sr_table + 63) / 64, 64, 0, ctx->stream>>>(t->srtab, wp->sr_table);
+        G4_HIP(ctx, hipGetLastError());
+        t->tab_n = wp->sr_table;
+    }
     A.rcut2 = (float)(wp->r_cut * wp->r_cut);
     A.theta2 = (float)(criterion == 0 ? (wp->criterion == 0 ? wp->theta * wp->theta : wp->theta_seed * wp->theta_seed)
                                       : 0.0);
@@ -624,6 +680,9 @@ int g4_launch_walk(g4_ctx *ctx, g4_tree *t, const g4_walk_params *wp, int kernel
     if (kernel == 0) {
         if (criterion == 0) { if (P) launch_walk<0, 0, true>(A, s); else launch_walk<0, 0, false>(A, s); }
         else { if (P) launch_walk<0, 1, true>(A, s); else launch_walk<0, 1, false>(A, s); }
+    } else if (tabulated) {
+        if (criterion == 0) { if (P) launch_walk<2, 0, true>(A, s); else launch_walk<2, 0, false>(A, s); }
+        else { if (P) launch_walk<2, 1, true>(A, s); else launch_walk<2, 1, false>(A, s); }
     } else {
         if (criterion == 0) { if (P) launch_walk<1, 0, true>(A, s); else launch_walk<1, 0, false>(A, s); }
         else { if (P) launch_walk<1, 1, true>(A, s); else launch_walk<1, 1, false>(A, s); }

@@ -39,7 +39,8 @@ class g4_walk_params(C.Structure):
     _fields_ = [("kernel", C.c_int), ("criterion", C.c_int), ("order", C.c_int), ("exclusion", C.c_int),
                 ("G", C.c_double), ("eps0", C.c_double), ("r_s", C.c_double), ("r_cut", C.c_double),
                 ("theta", C.c_double), ("alpha", C.c_double), ("theta_seed", C.c_double),
-                ("a_seed", C.c_void_p), ("group_size", C.c_int), ("seed_from_tree", C.c_int)]
+                ("a_seed", C.c_void_p), ("group_size", C.c_int), ("seed_from_tree", C.c_int),
+                ("sr_table", C.c_int)]
 
 
 class g4_fmm_params(C.Structure):
@@ -155,7 +156,7 @@ def tree_params(periodic, box, origin=(0.0, 0.0, 0.0), leaf_max=8, max_depth=21)
 
 
 def walk_params(kernel=0, criterion=0, order=3, exclusion=1, G=1.0, eps0=0.0, r_s=1.0, r_cut=1e30, theta=0.7,
-                alpha=0.005, theta_seed=0.7, a_seed=None, group_size=64, seed_from_tree=0):
+                alpha=0.005, theta_seed=0.7, a_seed=None, group_size=64, seed_from_tree=0, sr_table=0):
     wp = g4_walk_params()
     wp.kernel, wp.criterion, wp.order, wp.exclusion = int(kernel), int(criterion), int(order), int(exclusion)
     wp.G, wp.eps0, wp.r_s, wp.r_cut = float(G), float(eps0), float(r_s), float(r_cut)
@@ -163,6 +164,7 @@ def walk_params(kernel=0, criterion=0, order=3, exclusion=1, G=1.0, eps0=0.0, r_
     wp.a_seed = None if a_seed is None else a_seed.data_ptr()
     wp.group_size = int(group_size)
     wp.seed_from_tree = int(seed_from_tree)
+    wp.sr_table = int(sr_table)
     wp._keep = a_seed
     return wp
 

@@ -231,26 +231,67 @@ def box_case(g, ctx):
     return make_case(g, ctx, workloads.clustered_box(30001, seed=7, nhalo=60), True, 8)
 
 
-def test_treepm_geometric_parity(g, ctx, box_case):
+# sr_table 0 evaluates erfc/exp per interaction; 64 interpolates the short-range
+# factors from the table (cubic pieces, max. error 2.9e-6 of the Newtonian
+# factor), well inside the parity bar
+@pytest.mark.parametrize("sr_table", [0, 64])
+def test_treepm_geometric_parity(g, ctx, box_case, sr_table):
     c = box_case
     kw = sr_params(c.n)
-    wp = g.walk_params(kernel=1, criterion=0, theta=0.7, **kw)
+    wp = g.walk_params(kernel=1, criterion=0, theta=0.7, sr_table=sr_table, **kw)
     out = g.g4_treepm_shortrange(ctx, c.tree, wp, want_pot=True, want_counts=True)
     acc, pot, cnt = c.ot.walk(kernel=1, criterion=0, theta=0.7, nthreads=16, **kw)
-    assert_parity(stack3(out), acc, out["counts"].cpu().numpy(), cnt, "treepm geometric")
+    assert_parity(stack3(out), acc, out["counts"].cpu().numpy(), cnt, f"treepm geometric, table {sr_table}")
     perr = np.abs(out["pot"].cpu().numpy() - pot) / np.abs(pot)
     assert np.median(perr) < 1e-5
 
 
-def test_treepm_relative_parity(g, ctx, box_case):
+@pytest.mark.parametrize("sr_table", [0, 64])
+def test_treepm_relative_parity(g, ctx, box_case, sr_table):
     c = box_case
     kw = sr_params(c.n)
     a0, _, _ = c.ot.walk(kernel=1, criterion=0, theta=0.7, nthreads=16, **kw)
     seed = np.linalg.norm(a0, axis=1).astype(np.float32)
-    wp = g.walk_params(kernel=1, criterion=1, alpha=0.005, a_seed=torch.from_numpy(seed).cuda(), **kw)
+    wp = g.walk_params(kernel=1, criterion=1, alpha=0.005, a_seed=torch.from_numpy(seed).cuda(), sr_table=sr_table,
+                       **kw)
     out = g.g4_treepm_shortrange(ctx, c.tree, wp, want_counts=True)
     acc, _, cnt = c.ot.walk(kernel=1, criterion=1, alpha=0.005, aseed=seed, nthreads=16, **kw)
-    assert_parity(stack3(out), acc, out["counts"].cpu().numpy(), cnt, "treepm relative")
+    assert_parity(stack3(out), acc, out["counts"].cpu().numpy(), cnt, f"treepm relative, table {sr_table}")
+
+
+# largest error of the tabulated factors S_0..S_3 (cubic Hermite pieces on
+# [0, 6] in alpha_split r, FP32 coefficients), by table length: the Hermite
+# bound dx^4 max|d^4 S / dx^4| / 384, and the FP32 floor
+SR_TABLE_ERR = {16: 8e-4, 64: 3e-6, 128: 2.5e-7}
+
+
+@pytest.mark.parametrize("n_tab", sorted(SR_TABLE_ERR))
+def test_sr_table_matches_direct_evaluation(g, ctx, box_case, n_tab):
+    """The table changes no decision (the same seeds give identical interaction
+    counts) and moves forces and potentials by no more than the table error:
+    per particle the relative change has median below the largest factor error
+    and 99.9th percentile below ten times it (sums with cancellation), or 1e-4
+    where FP32 round-off dominates."""
+    c = box_case
+    kw = sr_params(c.n)
+    geo = g.g4_treepm_shortrange(ctx, c.tree, g.walk_params(kernel=1, criterion=0, theta=0.7, **kw))
+    seed = torch.sqrt(geo["ax"] ** 2 + geo["ay"] ** 2 + geo["az"] ** 2).float()
+    outs = []
+    for tab in (0, n_tab):
+        wp = g.walk_params(kernel=1, criterion=1, alpha=0.003, a_seed=seed, sr_table=tab, **kw)
+        outs.append(g.g4_treepm_shortrange(ctx, c.tree, wp, want_pot=True, want_counts=True, want_stats=True))
+    d, t = outs
+    assert torch.equal(d["counts"], t["counts"])
+    for k in ("n_p2p", "n_p2m", "n_visit"):
+        assert d["stats"][k] == t["stats"][k], k
+    err = workloads.relative_errors(stack3(t), stack3(d))
+    perr = np.abs(t["pot"].cpu().numpy() - d["pot"].cpu().numpy()) / np.abs(d["pot"].cpu().numpy())
+    msg = (f"table {n_tab}: force median {np.median(err):.2e} p99.9 {np.percentile(err, 99.9):.2e}, "
+           f"potential median {np.median(perr):.2e}")
+    print(msg)
+    bound = max(SR_TABLE_ERR[n_tab], 1e-6)
+    assert np.median(err) <= bound and np.percentile(err, 99.9) <= max(10 * bound, 1e-4), msg
+    assert np.median(perr) <= bound, msg
 
 
 @pytest.mark.parametrize("group", [1, 17, 64])
