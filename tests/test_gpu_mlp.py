@@ -29,9 +29,12 @@ def random_weights(seed, scale=0.3):
     return w.cuda(), w.double().numpy()
 
 
-def test_features_parity(g, ctx):
+# leaf size 40: sources in more than one batch of the per-particle loop, and leaves
+# beyond the register-staged moments path
+@pytest.mark.parametrize("B", [8, 40])
+def test_features_parity(g, ctx, B):
     ps = workloads.clustered_box(20001, seed=31, nhalo=40)
-    tp = g.tree_params(True, 1.0, leaf_max=8)
+    tp = g.tree_params(True, 1.0, leaf_max=B)
     x, y, z = g.g4_quantize(ctx, torch.from_numpy(ps.pos).cuda(), tp)
     m32 = ps.mass.astype(np.float32)
     p = g.particles(x, y, z, torch.from_numpy(m32).cuda())
@@ -41,7 +44,7 @@ def test_features_parity(g, ctx):
     wp = g.walk_params(kernel=1, **kw)
     f = g.g4_mlp_features(ctx, tree, wp).cpu().numpy()
     st, X, Y, Z = oracle.quantize(ps.pos, True, 1.0)
-    ot = oracle.Tree(X, Y, Z, m32.astype(np.float64), True, 1.0, 8)
+    ot = oracle.Tree(X, Y, Z, m32.astype(np.float64), True, 1.0, B)
     ref = ot.features(kernel=1, **kw)
     np.testing.assert_allclose(f[:, :7], ref[:, :7], rtol=0, atol=2e-5)
     # near-field force feature: FP32 pair sums with the node centre of mass on the integer grid

@@ -117,10 +117,11 @@ def test_tree_depth_cap_coincident(g, ctx):
 
 
 # ---------------------------------------------------------------- moments
-@pytest.mark.parametrize("kind", ["plummer", "box"])
-def test_moments_parity(g, ctx, kind):
+# leaf size 48: leaves of 33..48 particles take the general (not register-staged) leaf path
+@pytest.mark.parametrize("kind,B", [("plummer", 8), ("box", 8), ("box", 48)])
+def test_moments_parity(g, ctx, kind, B):
     ps = workloads.plummer(8192, seed=5) if kind == "plummer" else workloads.clustered_box(30001, seed=6, nhalo=60)
-    c = make_case(g, ctx, ps, kind == "box", 8)
+    c = make_case(g, ctx, ps, kind == "box", B)
     ex = g.g4_tree_export(ctx, c.tree, moments=True)
     key = lambda l, cc: (int(l), int(cc[0]), int(cc[1]), int(cc[2]))
     lv, ce = ex["level"].cpu().numpy(), ex["cell"].cpu().numpy().view(np.uint32)
