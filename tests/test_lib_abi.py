@@ -49,3 +49,37 @@ def test_binding_refuses_to_run_without_library(tmp_path, monkeypatch):
     mod = importlib.util.module_from_spec(spec)
     with pytest.raises(ImportError):
         spec.loader.exec_module(mod)
+
+
+def test_binding_structs_match_header(tmp_path):
+    """The ctypes mirrors of the parameter and counter structs have the C header's
+    size and field offsets (a silent mismatch would corrupt every call)."""
+    import shutil
+    import subprocess
+    if shutil.which("gcc") is None:
+        pytest.skip("no host C compiler")
+    import importlib.util
+    src = os.path.join(ROOT, "paper_2010_03567_amd", "g4hip.py")
+    spec = importlib.util.spec_from_file_location("g4hip_structs", src)
+    mod = importlib.util.module_from_spec(spec)
+    try:
+        spec.loader.exec_module(mod)
+    except ImportError:
+        pytest.skip("libg4hip.so not built")
+    structs = ("g4_tree_params", "g4_particles", "g4_walk_params", "g4_fmm_params", "g4_stats")
+    lines = ['#include <stdio.h>', '#include <stddef.h>', f'#include "{HEADER}"', 'int main(void) {']
+    for s in structs:
+        lines.append(f'printf("{s} size %zu\\n", sizeof({s}));')
+        for name, _ in getattr(mod, s)._fields_:
+            lines.append(f'printf("{s} {name} %zu\\n", offsetof({s}, {name}));')
+    lines.append("return 0; }")
+    c = tmp_path / "layout.c"
+    c.write_text("\n".join(lines))
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-std=c11", "-o", str(exe), str(c)], check=True)
+    out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split("\n")
+    for line in filter(None, out):
+        s, field, value = line.split()
+        cls = getattr(mod, s)
+        got = ctypes.sizeof(cls) if field == "size" else getattr(cls, field).offset
+        assert got == int(value), (s, field, got, value)
