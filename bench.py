@@ -51,6 +51,7 @@ def parse():
     ap.add_argument("--weights", type=str, default="", help="learned-seed weights (.npz); default by particle count")
     ap.add_argument("--no-fmm", action="store_true")
     ap.add_argument("--no-forest", action="store_true")
+    ap.add_argument("--no-large", action="store_true", help="skip the learned-vs-plain comparison at 256^3")
     ap.add_argument("--cpu-sample", type=int, default=20000)
     ap.add_argument("--err-sample", type=int, default=10000)
     ap.add_argument("--group", type=int, default=64)
@@ -292,6 +293,8 @@ def main():
         result["as_stated_rcut4.5_alpha0.005"] = {"forces_per_s": n / (ms45 * 1e-3), "ms_per_step": ms45,
                                                   "prewalk_ms": s45, "walk_ms": w45, "errors_vs_direct": e45}
         log(f"[bench] as stated: {ms45:.3f} ms/step, errors {e45}")
+    if not args.no_large:
+        result["learned_vs_plain_256^3"] = bench_learned_large(args, g, ctx)
     if not args.no_fmm:
         result["fmm"] = bench_fmm(args, g, ctx, n)
     if not args.no_forest:
@@ -299,6 +302,95 @@ def main():
     if not args.no_cpu_baseline:
         result["cpu_baseline"] = cpu_baseline(ps, n, B, r_s, args.rcut * r_s, eps0, alpha, args)
     print(json.dumps(result), flush=True)
+
+
+def bench_learned_large(args, g, ctx):
+    """Learned against plain seeding on the clustered box at N = 256^3 (held-out
+    evaluation seed 2001; the network was trained on seeds 1001-1020 at the same
+    size and leaf size): for each variant the largest alpha of the grid whose
+    p99 error against FP64 direct summation (untruncated, 10^4 random targets)
+    is <= 1e-3, then interactions per particle, time per step and percentiles."""
+    import torch
+    import workloads
+    from paper_2010_03567_amd import train_seed
+    n = 256 ** 3
+    wfile = os.path.join(ROOT, "paper_2010_03567_amd", "weights", f"seed_mlp_{n}_leaf{args.leaf}.npz")
+    if not os.path.exists(wfile):
+        return None
+    scale = (128 ** 3 / n) ** (1.0 / 3.0)
+    r_s, eps0 = 1.25 / 256 * scale, scale / (40 * 128)
+    r_cut = args.rcut * r_s
+    log(f"[bench] generating clustered box n={n} (evaluation seed 2001)")
+    ps = workloads.clustered_box(n, seed=2001)
+    dev = ctx.device
+    pos = torch.from_numpy(ps.pos).to(dev)
+    mass = torch.from_numpy(ps.mass.astype(np.float32)).to(dev)
+    del ps
+    tp = g.tree_params(True, 1.0, leaf_max=args.leaf)
+    ws = torch.empty(g.g4_workspace_bytes(tp, n) + 256, dtype=torch.uint8, device=dev)
+    outs = [torch.empty(n, dtype=torch.float64, device=dev) for _ in range(3)]
+    out = (*outs, None, None, None)
+    wl, norm, meta = train_seed.load(wfile, dev)
+    aseed = torch.empty(n, dtype=torch.float32, device=dev)
+    featbuf = torch.empty((n, 8), dtype=torch.float32, device=dev)
+    fwp = g.walk_params(kernel=1, r_s=r_s, eps0=eps0)
+    st = {}
+
+    def wparams(alpha, seed):
+        return g.walk_params(kernel=1, criterion=1, alpha=alpha, theta_seed=0.7, r_s=r_s, r_cut=r_cut, eps0=eps0,
+                             a_seed=seed, group_size=args.group)
+
+    def step(variant, alpha, want_stats=False):
+        x, y, z = g.g4_quantize(ctx, pos, tp)
+        p = g.particles(x, y, z, mass)
+        tree = g.g4_build_tree(ctx, p, tp, ws=ws)
+        g.g4_compute_multipoles(ctx, tree, 3)
+        if variant == "learned":
+            feat = g.g4_mlp_features(ctx, tree, fwp, norm, out=featbuf)
+            g.g4_mlp_forward(ctx, wl, feat, shift=0.0, mode=1, out=aseed)
+        # plain: the library runs the geometric pre-walk (theta_seed) before the relative walk
+        r = g.g4_treepm_shortrange(ctx, tree, wparams(alpha, aseed if variant == "learned" else None), out=out,
+                                   want_stats=want_stats)
+        st["p"] = p
+        return r
+
+    step("plain", 0.001)
+    tg = torch.from_numpy(workloads.sample_indices(n, args.err_sample, seed=99)).to(dev)
+    ref = g.g4_direct_force(ctx, st["p"], tp, g.walk_params(kernel=1, r_s=r_s, r_cut=1e30, eps0=eps0), targets=tg,
+                            want_pot=False)
+    ref = np.stack([ref["ax"].cpu().numpy(), ref["ay"].cpu().numpy(), ref["az"].cpu().numpy()], 1)
+    res = {"workload": f"clustered box 256^3 (evaluation seed 2001), R_cut {args.rcut} r_s, leaf {args.leaf}",
+           "n": n, "weights": os.path.basename(wfile), "train_residual_rms_dex": meta.get("residual_rms")}
+    for variant in ("plain", "learned"):
+        cal, chosen = {}, None
+        for a in ALPHAS:
+            step(variant, a)
+            cal[a] = workloads.percentiles(workloads.relative_errors(torch.stack(outs, 1)[tg].cpu().numpy(), ref))
+            if cal[a]["p99"] <= ERR_BOUND:
+                chosen = a
+                break
+        if chosen is None:
+            res[variant] = {"error": "no alpha in the grid met the error bound"}
+            continue
+        for _ in range(2):
+            step(variant, chosen)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(5):
+            step(variant, chosen)
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) * 1e3 / 5
+        s = step(variant, chosen, want_stats=True)["stats"]
+        res[variant] = {"alpha": chosen, "ms_per_step": ms, "forces_per_s": n / (ms * 1e-3),
+                        "errors_vs_direct": cal[chosen], "alpha_calibration": {str(k): v["p99"] for k, v in cal.items()},
+                        "per_particle": {"p2p": s["n_p2p"] / n, "p2m": s["n_p2m"] / n, "visit": s["n_visit"] / n,
+                                         "prewalk_p2p": s["n_seed_p2p"] / n, "prewalk_p2m": s["n_seed_p2m"] / n}}
+        log(f"[bench] 256^3 {variant}: {ms:.2f} ms/step at alpha {chosen}, errors {cal[chosen]}")
+    if "ms_per_step" in res.get("plain", {}) and "ms_per_step" in res.get("learned", {}):
+        res["speedup_learned_vs_plain"] = res["plain"]["ms_per_step"] / res["learned"]["ms_per_step"]
+    del ws, outs, featbuf, aseed
+    torch.cuda.empty_cache()
+    return res
 
 
 def bench_fmm(args, g, ctx, n):
