@@ -185,18 +185,6 @@ __global__ void k_init(DevCounters *C, uint32_t *bfirst, uint32_t *bcount, uint3
     }
 }
 
-// first index in keys[lo, hi) with key >= target
-__device__ __forceinline__ uint32_t lower_bound_u64(const uint64_t *__restrict__ keys, uint32_t lo, uint32_t hi,
-                                                    uint64_t target)
-{
-    while (lo < hi) {
-        uint32_t mid = lo + ((hi - lo) >> 1);
-        if (keys[mid] < target) lo = mid + 1;
-        else hi = mid;
-    }
-    return lo;
-}
-
 // sum over the eight lanes of a group; every lane ends with the same bits
 template <typename T>
 __device__ __forceinline__ T grp8_sum(T v)
@@ -208,7 +196,7 @@ __device__ __forceinline__ T grp8_sum(T v)
 }
 
 // nodes up to this many particles find their octant boundaries by one
-// strided pass over their keys instead of binary searches
+// strided pass over their keys instead of a search
 static constexpr uint32_t kScanMax = 256;
 // blocks of the split passes: one per compute unit keeps the number of
 // same-address atomics per level at most this
@@ -235,6 +223,7 @@ static constexpr int kSplitBlocks = 256;
 // An empty level returns at once and writes nothing; the node count is
 // summed from the level sizes after the last level.
 
+// nodes a block takes per pass (LDS lists and octant starts are sized for it)
 #define SPLIT_CHUNK 1024
 
 __device__ __forceinline__ void node_record(DevCounters *C, const uint4 *__restrict__ parts, WNode *__restrict__ wn,
