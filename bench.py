@@ -34,6 +34,7 @@ sys.path.insert(0, ROOT)
 METRIC = "particle forces/s at 99th-pct rel. force err ≤1e-3 vs direct sum; learned vs plain"
 PEAK_FP32_VECTOR = 157.3e12  # MI355X FP32 vector peak, FLOP/s
 ERR_BOUND = 1e-3
+KEY_KINDS = {"morton": 0, "ph": 1}
 ALPHAS = (0.004, 0.0028, 0.002, 0.0014, 0.001, 0.0007, 0.0005, 0.00035, 0.00025)
 
 
@@ -58,6 +59,8 @@ def parse():
     ap.add_argument("--leaf", type=int, default=24, help="leaf size B of the headline tree")
     ap.add_argument("--copy-calibration-mb", type=int, default=0,
                     help="also run a plain device copy of this size (HBM counter calibration)")
+    ap.add_argument("--keys", choices=("morton", "ph"), default="morton",
+                    help="curve order of the particles: Morton or Peano-Hilbert (same nodes)")
     ap.add_argument("--sr-table", type=int, default=0,
                     help="intervals of the short-range factor table of the walks (0: erfc/exp per interaction)")
     ap.add_argument("--profile-walk", choices=("plain", "learned"), default=None,
@@ -126,7 +129,7 @@ def main():
     ctx = g.Context()
     pos = torch.from_numpy(ps.pos).to(dev)
     mass = torch.from_numpy(ps.mass.astype(np.float32)).to(dev)
-    tp = g.tree_params(True, ps.box, leaf_max=B)
+    tp = g.tree_params(True, ps.box, leaf_max=B, key_kind=KEY_KINDS[args.keys])
     ws = torch.empty(g.g4_workspace_bytes(tp, n) + 256, dtype=torch.uint8, device=dev)
     outs = [torch.empty(n, dtype=torch.float64, device=dev) for _ in range(3)]
     out = (*outs, None, None, None)
@@ -269,7 +272,7 @@ def main():
         "config": {"workload": "treepm_shortrange_clustered_box_128^3", "n": n, "box": 1.0, "r_s": r_s,
                    "r_cut": args.rcut * r_s, "R_cut": args.rcut, "eps0": eps0, "leaf_max": B, "order": 3,
                    "alpha": learned["alpha"] if best_learned else alpha, "theta_seed": 0.7,
-                   "group_size": args.group, "sr_table": args.sr_table,
+                   "group_size": args.group, "sr_table": args.sr_table, "keys": args.keys,
                    "variant": "learned (MLP |a| seed + relative walk)" if best_learned
                    else "plain (geometric pre-walk + relative walk)"},
         "plain": {"forces_per_s": plain_value, "ms_per_step": ms_per_step, "alpha": alpha,
@@ -326,7 +329,7 @@ def bench_learned_large(args, g, ctx):
     pos = torch.from_numpy(ps.pos).to(dev)
     mass = torch.from_numpy(ps.mass.astype(np.float32)).to(dev)
     del ps
-    tp = g.tree_params(True, 1.0, leaf_max=args.leaf)
+    tp = g.tree_params(True, 1.0, leaf_max=args.leaf, key_kind=KEY_KINDS[args.keys])
     ws = torch.empty(g.g4_workspace_bytes(tp, n) + 256, dtype=torch.uint8, device=dev)
     outs = [torch.empty(n, dtype=torch.float64, device=dev) for _ in range(3)]
     out = (*outs, None, None, None)

@@ -45,13 +45,19 @@ typedef enum {
  *               [2^30, 3*2^30) so coordinate differences never wrap
  *               (Sec. "Non-periodic potentials"); one step = box/2^31.
  * leaf_max  = B: a node is split only while it holds more than B particles.
- * max_depth: deepest level (<= 21); leaves there may hold more than B. */
+ * max_depth: deepest level (<= 21); leaves there may hold more than B.
+ * key_kind:  order of the particles along a space-filling curve through the
+ *            top 21 bits of each coordinate: 0 Morton (bit interleaving),
+ *            1 Peano-Hilbert (the paper's curve).  Both cut into the same
+ *            nested cubes, so the node set, the decisions and the forces are
+ *            the same; only the particle and node order change. */
 typedef struct {
     int periodic;
     double box;
     double origin[3];
     int leaf_max;
     int max_depth;
+    int key_kind;
 } g4_tree_params;
 
 /* Particle set in the caller's order: integer coordinates and masses. */
@@ -187,11 +193,12 @@ int g4_tree_info(g4_ctx *ctx, const g4_tree *tree, int64_t *nnodes, int64_t *lev
 
 /* Copy node data to caller device buffers (any pointer may be NULL):
  * level (int32), cell (3 x uint32 per node: integer cube index at its level),
- * count (int64 particles), leaf (int32), mass (f64), com (3 x f64 physical,
+ * count (int64 particles), first (int64: the node's first particle in curve
+ * order; its particles are the next count), leaf (int32), mass (f64), com (3 x f64 physical,
  * relative to the root's lower corner), q2 (6 x f64: xx xy xz yy yz zz), q3 (10 x f64:
  * xxx xxy xxz xyy xyz xzz yyy yyz yzz zzz).  Moments need g4_compute_multipoles. */
 int g4_tree_export(g4_ctx *ctx, const g4_tree *tree, int32_t *level, uint32_t *cell, int64_t *count,
-                   int32_t *leaf, double *mass, double *com, double *q2, double *q3);
+                   int64_t *first, int32_t *leaf, double *mass, double *com, double *q2, double *q3);
 
 int g4_tree_free(g4_ctx *ctx, g4_tree *tree);
 

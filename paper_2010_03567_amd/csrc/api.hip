@@ -12,6 +12,7 @@ static int check_tp(g4_ctx *ctx, const g4_tree_params *tp)
     if (tp->leaf_max < 1) return g4_set_err(ctx, G4_EINVAL, "leaf_max must be >= 1");
     if (tp->max_depth < 1 || tp->max_depth > G4_MAXLEV)
         return g4_set_err(ctx, G4_EINVAL, "max_depth must be in [1, 21]");
+    if (tp->key_kind != 0 && tp->key_kind != 1) return g4_set_err(ctx, G4_EINVAL, "key_kind must be 0 or 1");
     return G4_OK;
 }
 
@@ -163,13 +164,13 @@ int g4_tree_info(g4_ctx *ctx, const g4_tree *tree, int64_t *nnodes, int64_t *lev
     return G4_OK;
 }
 
-int g4_tree_export(g4_ctx *ctx, const g4_tree *tree, int32_t *level, uint32_t *cell, int64_t *count, int32_t *leaf,
-                   double *mass, double *com, double *q2, double *q3)
+int g4_tree_export(g4_ctx *ctx, const g4_tree *tree, int32_t *level, uint32_t *cell, int64_t *count,
+                   int64_t *first, int32_t *leaf, double *mass, double *com, double *q2, double *q3)
 {
     if (!ctx || !tree) return G4_EINVAL;
     if ((mass || com || q2 || q3) && !tree->moments_order)
         return g4_set_err(ctx, G4_ESTATE, "moments not computed");
-    return g4_launch_export(ctx, tree, level, cell, count, leaf, mass, com, q2, q3);
+    return g4_launch_export(ctx, tree, level, cell, count, first, leaf, mass, com, q2, q3);
 }
 
 int g4_tree_free(g4_ctx *ctx, g4_tree *tree)

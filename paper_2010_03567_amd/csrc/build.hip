@@ -148,20 +148,57 @@ __device__ __forceinline__ uint64_t spread3(uint32_t v)
     return x;
 }
 
-// Morton key from the top 21 bits of each root-relative coordinate; the
-// level-l octant digit (x<<2 | y<<1 | z) sits at bit 3 (21 - l).
-// Morton keys, the identity permutation, and the particles packed as one
+// Peano-Hilbert index of a cell of the 2^21 grid, from its 21-bit
+// coordinates, by Skilling's method ("Programming the Hilbert curve", AIP
+// Conf. Proc. 707, 2004): from the top bit down, the coordinates are reflected
+// and exchanged so that each level's sub-cube is entered in the curve's own
+// orientation, then Gray-decoded; the result interleaved x, y, z from the top
+// bit is the index.  Its level-l digit (bits 3 (21 - l) .. +2) labels one
+// octant of the level-(l - 1) cube, as the Morton digit does, so both keys
+// cut the same nested cubes.
+__device__ __forceinline__ uint64_t ph_key21(uint32_t x, uint32_t y, uint32_t z)
+{
+    uint32_t c[3] = {x, y, z};
+    for (uint32_t q = 1u << 20; q > 1u; q >>= 1) {
+        const uint32_t p = q - 1u;
+        for (int i = 0; i < 3; i++) {
+            if (c[i] & q) {
+                c[0] ^= p;  // reflect the low bits of the first coordinate
+            } else {
+                const uint32_t t = (c[0] ^ c[i]) & p;  // exchange the low bits with coordinate i
+                c[0] ^= t;
+                c[i] ^= t;
+            }
+        }
+    }
+    c[1] ^= c[0];
+    c[2] ^= c[1];
+    uint32_t t = 0;
+    for (uint32_t q = 1u << 20; q > 1u; q >>= 1)
+        if (c[2] & q) t ^= q - 1u;
+    return (spread3(c[0] ^ t) << 2) | (spread3(c[1] ^ t) << 1) | spread3(c[2] ^ t);
+}
+
+// Curve key from the top 21 bits of each root-relative coordinate: Morton
+// (bit interleaving; the level-l octant digit (x<<2 | y<<1 | z) sits at bit
+// 3 (21 - l)) or Peano-Hilbert.
+__device__ __forceinline__ uint64_t curve_key(uint32_t x, uint32_t y, uint32_t z, int drop, uint32_t corner, int kind)
+{
+    const uint32_t rx = (x - corner) >> drop, ry = (y - corner) >> drop, rz = (z - corner) >> drop;
+    return kind == 1 ? ph_key21(rx, ry, rz) : (spread3(rx) << 2) | (spread3(ry) << 1) | spread3(rz);
+}
+
+// Curve keys, the identity permutation, and the particles packed as one
 // 16-byte record each in caller order (pk), so that the gather into key
 // order reads one record per particle instead of four separate words.
 __global__ void k_keys(const uint32_t *__restrict__ X, const uint32_t *__restrict__ Y,
                        const uint32_t *__restrict__ Z, const float *__restrict__ m, int64_t n, int drop,
-                       uint32_t corner, uint64_t *__restrict__ keys, uint32_t *__restrict__ perm,
+                       uint32_t corner, int kind, uint64_t *__restrict__ keys, uint32_t *__restrict__ perm,
                        uint4 *__restrict__ pk)
 {
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
         const uint32_t x = X[i], y = Y[i], z = Z[i];
-        uint32_t rx = (x - corner) >> drop, ry = (y - corner) >> drop, rz = (z - corner) >> drop;
-        keys[i] = (spread3(rx) << 2) | (spread3(ry) << 1) | spread3(rz);
+        keys[i] = curve_key(x, y, z, drop, corner, kind);
         perm[i] = (uint32_t)i;
         pk[i] = make_uint4(x, y, z, __float_as_uint(m[i]));
     }
@@ -460,8 +497,8 @@ int g4_launch_build(g4_ctx *ctx, g4_tree *t, const g4_particles *p)
     hipStream_t s = ctx->stream;
     const int64_t n = t->n;
     const int maxd = t->tp.max_depth < 1 ? 1 : (t->tp.max_depth > G4_MAXLEV ? G4_MAXLEV : t->tp.max_depth);
-    k_keys<<<grid_for(n), kBlock, 0, s>>>(p->x, p->y, p->z, p->mass, n, t->S - G4_MAXLEV, t->corner, t->keys0,
-                                          t->perm0, packed_staging(t));
+    k_keys<<<grid_for(n), kBlock, 0, s>>>(p->x, p->y, p->z, p->mass, n, t->S - G4_MAXLEV, t->corner,
+                                          t->tp.key_kind, t->keys0, t->perm0, packed_staging(t));
     G4_HIP(ctx, hipGetLastError());
     size_t sb = t->sort_tmp_bytes;
     G4_HIP(ctx, rocprim::radix_sort_pairs<KeySortConfig>(t->sort_tmp, sb, t->keys0, t->keys1, t->perm0, t->perm1,
@@ -634,9 +671,10 @@ int g4_launch_moments(g4_ctx *ctx, g4_tree *t)
 
 // ------------------------------------------------------------------ export
 __global__ void k_export(const DevCounters *__restrict__ C, const WNode *__restrict__ wn,
-                         const uint32_t *__restrict__ bcount, const double *__restrict__ mom, int S, uint32_t corner,
-                         double unit, int32_t *level, uint32_t *cell, int64_t *count, int32_t *leaf, double *mass,
-                         double *com, double *q2, double *q3)
+                         const uint32_t *__restrict__ bfirst, const uint32_t *__restrict__ bcount,
+                         const double *__restrict__ mom, int S, uint32_t corner, double unit, int32_t *level,
+                         uint32_t *cell, int64_t *count, int64_t *first, int32_t *leaf, double *mass, double *com,
+                         double *q2, double *q3)
 {
     const uint32_t nn = C->node_count;
     for (uint32_t q = blockIdx.x * blockDim.x + threadIdx.x; q < nn; q += gridDim.x * blockDim.x) {
@@ -646,6 +684,7 @@ __global__ void k_export(const DevCounters *__restrict__ C, const WNode *__restr
         if (level) level[q] = l;
         if (leaf) leaf[q] = (w.meta & WN_LEAF) ? 1 : 0;
         if (count) count[q] = bcount[q];
+        if (first) first[q] = bfirst[q];
         for (int k = 0; k < 3; k++) {
             uint64_t rel = (uint64_t)(uint32_t)(g[k] - corner) - (1ull << (S - l - 1));
             if (cell) cell[3 * (size_t)q + k] = (uint32_t)(rel >> (S - l));
@@ -659,11 +698,12 @@ __global__ void k_export(const DevCounters *__restrict__ C, const WNode *__restr
     }
 }
 
-int g4_launch_export(g4_ctx *ctx, const g4_tree *t, int32_t *level, uint32_t *cell, int64_t *count, int32_t *leaf,
-                     double *mass, double *com, double *q2, double *q3)
+int g4_launch_export(g4_ctx *ctx, const g4_tree *t, int32_t *level, uint32_t *cell, int64_t *count,
+                     int64_t *first, int32_t *leaf, double *mass, double *com, double *q2, double *q3)
 {
-    k_export<<<grid_for(t->cap), kBlock, 0, ctx->stream>>>(t->ctr, t->wn, t->bcount, t->mom, t->S, t->corner,
-                                                           t->unit, level, cell, count, leaf, mass, com, q2, q3);
+    k_export<<<grid_for(t->cap), kBlock, 0, ctx->stream>>>(t->ctr, t->wn, t->bfirst, t->bcount, t->mom, t->S,
+                                                           t->corner, t->unit, level, cell, count, first, leaf, mass,
+                                                           com, q2, q3);
     G4_HIP(ctx, hipGetLastError());
     return G4_OK;
 }
@@ -704,15 +744,14 @@ __global__ void k_boxkey(const uint32_t *__restrict__ perm, int64_t n, const int
     }
 }
 
-// the particles and their Morton keys in the final (box, key) order
+// the particles and their curve keys in the final (box, key) order
 __global__ void k_gather_keys(const uint4 *__restrict__ pk, const uint32_t *__restrict__ perm, int64_t n, int drop,
-                              uint32_t corner, uint4 *__restrict__ parts, uint64_t *__restrict__ keys)
+                              uint32_t corner, int kind, uint4 *__restrict__ parts, uint64_t *__restrict__ keys)
 {
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
         const uint4 q = pk[perm[i]];
         parts[i] = q;
-        const uint32_t rx = (q.x - corner) >> drop, ry = (q.y - corner) >> drop, rz = (q.z - corner) >> drop;
-        keys[i] = (spread3(rx) << 2) | (spread3(ry) << 1) | spread3(rz);
+        keys[i] = curve_key(q.x, q.y, q.z, drop, corner, kind);
     }
 }
 
@@ -743,8 +782,8 @@ int g4_launch_build_forest(g4_ctx *ctx, g4_tree *t, const g4_particles *p, const
     hipStream_t s = ctx->stream;
     const int64_t n = t->n;
     const int maxd = t->tp.max_depth < 1 ? 1 : (t->tp.max_depth > G4_MAXLEV ? G4_MAXLEV : t->tp.max_depth);
-    k_keys<<<grid_for(n), kBlock, 0, s>>>(p->x, p->y, p->z, p->mass, n, t->S - G4_MAXLEV, t->corner, t->keys0,
-                                          t->perm0, packed_staging(t));
+    k_keys<<<grid_for(n), kBlock, 0, s>>>(p->x, p->y, p->z, p->mass, n, t->S - G4_MAXLEV, t->corner,
+                                          t->tp.key_kind, t->keys0, t->perm0, packed_staging(t));
     G4_HIP(ctx, hipGetLastError());
     size_t sb = t->sort_tmp_bytes;
     G4_HIP(ctx, rocprim::radix_sort_pairs<KeySortConfig>(t->sort_tmp, sb, t->keys0, t->keys1, t->perm0, t->perm1,
@@ -759,7 +798,7 @@ int g4_launch_build_forest(g4_ctx *ctx, g4_tree *t, const g4_particles *p, const
     t->perm0 = t->perm1;
     t->perm1 = tmp;
     k_gather_keys<<<grid_for(n), kBlock, 0, s>>>(packed_staging(t), t->perm1, n, t->S - G4_MAXLEV, t->corner,
-                                                  t->parts, t->keys1);
+                                                  t->tp.key_kind, t->parts, t->keys1);
     k_init_forest<<<(t->nbox + 255) / 256, 256, 0, s>>>(t->ctr, t->bfirst, t->bcount, t->parent, off_dev, t->nbox);
     G4_HIP(ctx, hipGetLastError());
     for (int l = 0; l <= maxd; l++)

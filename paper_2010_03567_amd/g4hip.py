@@ -27,7 +27,7 @@ G4_OK, G4_EINVAL, G4_ENOMEM, G4_EHIP, G4_ESTATE, G4_EROOT = 0, -1, -2, -3, -4, -
 
 class g4_tree_params(C.Structure):
     _fields_ = [("periodic", C.c_int), ("box", C.c_double), ("origin", C.c_double * 3),
-                ("leaf_max", C.c_int), ("max_depth", C.c_int)]
+                ("leaf_max", C.c_int), ("max_depth", C.c_int), ("key_kind", C.c_int)]
 
 
 class g4_particles(C.Structure):
@@ -69,7 +69,7 @@ _SIGS = {
     "g4_build_tree": [_p, C.POINTER(g4_particles), C.POINTER(g4_tree_params), _p, _sz, C.POINTER(C.c_void_p)],
     "g4_compute_multipoles": [_p, _p, _i32],
     "g4_tree_info": [_p, _p, C.POINTER(_i64), _p],
-    "g4_tree_export": [_p, _p, _p, _p, _p, _p, _p, _p, _p, _p],
+    "g4_tree_export": [_p, _p, _p, _p, _p, _p, _p, _p, _p, _p, _p],
     "g4_tree_free": [_p, _p],
     "g4_tree_force": [_p, _p, C.POINTER(g4_walk_params), _p, _p, _p, _p, _p, _p, C.POINTER(g4_stats)],
     "g4_treepm_shortrange": [_p, _p, C.POINTER(g4_walk_params), _p, _p, _p, _p, _p, _p, C.POINTER(g4_stats)],
@@ -144,7 +144,7 @@ class Context:
             self.h = None
 
 
-def tree_params(periodic, box, origin=(0.0, 0.0, 0.0), leaf_max=8, max_depth=21):
+def tree_params(periodic, box, origin=(0.0, 0.0, 0.0), leaf_max=8, max_depth=21, key_kind=0):
     tp = g4_tree_params()
     tp.periodic = int(periodic)
     tp.box = float(box)
@@ -152,6 +152,7 @@ def tree_params(periodic, box, origin=(0.0, 0.0, 0.0), leaf_max=8, max_depth=21)
         tp.origin[k] = float(origin[k])
     tp.leaf_max = int(leaf_max)
     tp.max_depth = int(max_depth)
+    tp.key_kind = int(key_kind)
     return tp
 
 
@@ -239,6 +240,7 @@ def g4_tree_export(ctx, tree, moments=True):
     out = dict(level=torch.empty(nn, dtype=torch.int32, device=dev),
                cell=torch.empty((nn, 3), dtype=torch.int32, device=dev),
                count=torch.empty(nn, dtype=torch.int64, device=dev),
+               first=torch.empty(nn, dtype=torch.int64, device=dev),
                leaf=torch.empty(nn, dtype=torch.int32, device=dev))
     if moments:
         out.update(mass=torch.empty(nn, dtype=torch.float64, device=dev),
@@ -246,8 +248,8 @@ def g4_tree_export(ctx, tree, moments=True):
                    q2=torch.empty((nn, 6), dtype=torch.float64, device=dev),
                    q3=torch.empty((nn, 10), dtype=torch.float64, device=dev))
     g = lambda k: _ptr(out[k]) if k in out else None
-    ctx.check(_L.g4_tree_export(ctx.h, tree.h, g("level"), g("cell"), g("count"), g("leaf"), g("mass"), g("com"),
-                                g("q2"), g("q3")))
+    ctx.check(_L.g4_tree_export(ctx.h, tree.h, g("level"), g("cell"), g("count"), g("first"), g("leaf"), g("mass"),
+                                g("com"), g("q2"), g("q3")))
     return out
 
 

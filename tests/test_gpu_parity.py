@@ -38,13 +38,13 @@ class Case:
     pass
 
 
-def make_case(g, ctx, ps, periodic, B, max_depth=21):
+def make_case(g, ctx, ps, periodic, B, max_depth=21, key_kind=0):
     c = Case()
     if periodic:
         org, box = (0.0, 0.0, 0.0), ps.box
     else:
         org, box = workloads.isolated_root(ps.pos)
-    c.tp = g.tree_params(periodic, box, org, leaf_max=B, max_depth=max_depth)
+    c.tp = g.tree_params(periodic, box, org, leaf_max=B, max_depth=max_depth, key_kind=key_kind)
     x, y, z = g.g4_quantize(ctx, torch.from_numpy(ps.pos).cuda(), c.tp)
     st, X, Y, Z = oracle.quantize(ps.pos, periodic, box, org)
     assert st == 0
@@ -92,16 +92,49 @@ def node_set(level, cell, count, leaf):
     return {(int(l), int(c[0]), int(c[1]), int(c[2]), int(k), int(f)) for l, c, k, f in zip(level, cell, count, leaf)}
 
 
-@pytest.mark.parametrize("kind,n,B", [("plummer", 8192, 8), ("box", 30001, 8), ("box", 65, 4), ("plummer", 1, 8),
-                                      ("box", 4096, 16)])
-def test_tree_node_set_bit_exact(g, ctx, kind, n, B):
+@pytest.mark.parametrize("kind,n,B,keys", [("plummer", 8192, 8, 0), ("box", 30001, 8, 0), ("box", 65, 4, 0),
+                                           ("plummer", 1, 8, 0), ("box", 4096, 16, 0), ("plummer", 8192, 8, 1),
+                                           ("box", 30001, 8, 1)])
+def test_tree_node_set_bit_exact(g, ctx, kind, n, B, keys):
+    """The node set (level, cube, count, leaf) equals the oracle's recursive
+    partition, with Morton (keys 0) and Peano-Hilbert (keys 1) order alike."""
     ps = workloads.plummer(n, seed=3) if kind == "plummer" else workloads.clustered_box(n, seed=4, nhalo=max(2, n // 500))
-    c = make_case(g, ctx, ps, kind == "box", B)
+    c = make_case(g, ctx, ps, kind == "box", B, key_kind=keys)
     ex = g.g4_tree_export(ctx, c.tree, moments=False)
     mine = node_set(ex["level"].cpu().numpy(), ex["cell"].cpu().numpy().view(np.uint32), ex["count"].cpu().numpy(),
                     ex["leaf"].cpu().numpy())
     ref = node_set(*c.ot.nodes())
     assert mine == ref
+
+
+@pytest.mark.parametrize("keys", [0, 1])
+def test_curve_order_on_a_grid(g, ctx, keys):
+    """One particle at the centre of each cell of an 8^3 grid, leaf size 1: the
+    leaves in particle order visit the cells in Morton order (keys 0: the bits
+    of x, y, z interleaved) or along the Peano-Hilbert curve (keys 1: a
+    permutation of the cells in which consecutive cells share a face)."""
+    ax = (np.arange(8) + 0.5) / 8
+    pos = np.stack(np.meshgrid(ax, ax, ax, indexing="ij"), -1).reshape(-1, 3)
+    rng = np.random.default_rng(11)
+    pos = pos[rng.permutation(len(pos))]
+    tp = g.tree_params(True, 1.0, leaf_max=1, key_kind=keys)
+    x, y, z = g.g4_quantize(ctx, torch.from_numpy(pos).cuda(), tp)
+    m = torch.full((len(pos),), 1.0 / len(pos), dtype=torch.float32, device="cuda")
+    tree = g.g4_build_tree(ctx, g.particles(x, y, z, m), tp)
+    ex = g.g4_tree_export(ctx, tree, moments=False)
+    leaf = ex["leaf"].cpu().numpy() == 1
+    assert np.all(ex["level"].cpu().numpy()[leaf] == 3) and leaf.sum() == 512
+    cells = ex["cell"].cpu().numpy().view(np.uint32)[leaf].astype(np.int64)
+    order = np.argsort(ex["first"].cpu().numpy()[leaf])
+    seq = cells[order]
+    assert len({tuple(c) for c in seq}) == 512
+    if keys == 0:
+        code = [sum(((int(cx) >> b & 1) << (3 * b + 2)) | ((int(cy) >> b & 1) << (3 * b + 1)) |
+                    ((int(cz) >> b & 1) << (3 * b)) for b in range(3)) for cx, cy, cz in seq]
+        assert code == sorted(code)
+    else:
+        steps = np.abs(np.diff(seq, axis=0)).sum(1)
+        assert np.all(steps == 1), steps
 
 
 def test_tree_depth_cap_coincident(g, ctx):
@@ -293,6 +326,25 @@ def test_sr_table_matches_direct_evaluation(g, ctx, box_case, n_tab):
     bound = max(SR_TABLE_ERR[n_tab], 1e-6)
     assert np.median(err) <= bound and np.percentile(err, 99.9) <= max(10 * bound, 1e-4), msg
     assert np.median(perr) <= bound, msg
+
+
+def test_curve_order_changes_no_interaction(g, ctx, box_case):
+    """Morton and Peano-Hilbert trees of the same particles hold the same nodes,
+    so the same seeds give every particle the same interactions; forces differ
+    only by the order of the FP32 terms within each FP64 sum."""
+    c = box_case
+    kw = sr_params(c.n)
+    a0, _, _ = c.ot.walk(kernel=1, criterion=0, theta=0.7, nthreads=16, **kw)
+    seed = torch.from_numpy(np.linalg.norm(a0, axis=1).astype(np.float32)).cuda()
+    wp = g.walk_params(kernel=1, criterion=1, alpha=0.003, a_seed=seed, **kw)
+    morton = g.g4_treepm_shortrange(ctx, c.tree, wp, want_counts=True)
+    tp = g.tree_params(True, c.box, leaf_max=8, key_kind=1)
+    tree = g.g4_build_tree(ctx, c.p, tp)
+    g.g4_compute_multipoles(ctx, tree, 3)
+    ph = g.g4_treepm_shortrange(ctx, tree, wp, want_counts=True)
+    assert torch.equal(morton["counts"], ph["counts"])
+    err = workloads.relative_errors(stack3(ph), stack3(morton))
+    assert np.median(err) <= 1e-6 and err.max() <= 1e-4, (np.median(err), err.max())
 
 
 @pytest.mark.parametrize("group", [1, 17, 64])
