@@ -24,7 +24,7 @@ if ROOT not in sys.path:
 import workloads  # noqa: E402
 import paper_2010_03567_amd.g4hip as g  # noqa: E402
 
-LEAVES = (4, 8, 16, 32)
+LEAVES = (4, 8, 16, 24, 32)
 GROUPS = (16, 32, 48, 64)
 
 
