@@ -263,7 +263,10 @@ static int tree_force_impl(g4_ctx *ctx, g4_tree *tree, const g4_walk_params *wp,
     if (wp->sr_table != 0 && (wp->sr_table < 8 || wp->sr_table > G4_SRTAB_MAX))
         return g4_set_err(ctx, G4_EINVAL, "sr_table must be 0 or 8..512");
     if (!tree->tp.periodic && kernel == 1) return g4_set_err(ctx, G4_EINVAL, "short-range kernel needs a periodic box");
-    if (stats) G4_HIP(ctx, hipMemsetAsync(tree->ctr->stat, 0, sizeof(tree->ctr->stat), ctx->stream));
+    if (stats) {
+        const int zs = g4_launch_zero(ctx, tree->ctr->stat, sizeof(tree->ctr->stat));
+        if (zs) return zs;
+    }
     int st;
     if (wp->criterion == 1) {
         if (wp->a_seed) {

@@ -124,7 +124,7 @@ int g4_launch_quantize(g4_ctx *ctx, const double *pos, int64_t n, const g4_tree_
                        uint32_t *y, uint32_t *z, int32_t *flag)
 {
     double inv = tp->periodic ? TWO32 / tp->box : TWO31 / tp->box;
-    G4_HIP(ctx, hipMemsetAsync(flag, 0, 4, ctx->stream));
+    if (int st = g4_launch_zero(ctx, flag, 4)) return st;
     if (n > 0)
         k_quantize<<<grid_for(n), kBlock, 0, ctx->stream>>>(pos, n, tp->periodic, inv, tp->origin[0], tp->origin[1],
                                                            tp->origin[2], x, y, z, flag);
@@ -704,6 +704,22 @@ int g4_launch_export(g4_ctx *ctx, const g4_tree *t, int32_t *level, uint32_t *ce
     k_export<<<grid_for(t->cap), kBlock, 0, ctx->stream>>>(t->ctr, t->wn, t->bfirst, t->bcount, t->mom, t->S,
                                                            t->corner, t->unit, level, cell, count, first, leaf, mass,
                                                            com, q2, q3);
+    G4_HIP(ctx, hipGetLastError());
+    return G4_OK;
+}
+
+// ------------------------------------------------------------------ zeroing
+__global__ void k_zero_words(uint32_t *__restrict__ p, size_t nwords)
+{
+    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < nwords; i += (size_t)gridDim.x * blockDim.x)
+        p[i] = 0u;
+}
+
+int g4_launch_zero(g4_ctx *ctx, void *p, size_t bytes)
+{
+    const size_t nw = bytes / 4;
+    if (nw == 0) return G4_OK;
+    k_zero_words<<<grid_for((int64_t)nw), kBlock, 0, ctx->stream>>>(static_cast<uint32_t *>(p), nw);
     G4_HIP(ctx, hipGetLastError());
     return G4_OK;
 }

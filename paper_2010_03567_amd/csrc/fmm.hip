@@ -1473,9 +1473,9 @@ static int fmm_fast(g4_ctx *ctx, g4_tree *t, const g4_fmm_params *fp, double fac
     A.stat = t->ctr->stat + 6;
     uint2 *fr[2] = {(uint2 *)(b + L.f0), (uint2 *)(b + L.f1)};
     if ((uint64_t)t->nbox > L.cap_pairs) return g4_set_err(ctx, G4_ENOMEM, "fmm frontier smaller than the root count");
-    G4_HIP(ctx, hipMemsetAsync(A.cnt, 0, 64, s));
-    G4_HIP(ctx, hipMemsetAsync(A.stat, 0, 3 * sizeof(unsigned long long), s));
-    G4_HIP(ctx, hipMemsetAsync(A.F, 0, (size_t)t->cap * 20 * 4, s));
+    if (int zst = g4_launch_zero(ctx, A.cnt, 64)) return zst;
+    if (int zst = g4_launch_zero(ctx, A.stat, 3 * sizeof(unsigned long long))) return zst;
+    if (int zst = g4_launch_zero(ctx, A.F, (size_t)t->cap * 20 * 4)) return zst;
     A.fin = fr[1];
     A.fout = fr[0];
     k_fast_init<<<(t->nbox + 255) / 256, 256, 0, s>>>(A, t->nbox);
@@ -1509,7 +1509,7 @@ static int fmm_fast(g4_ctx *ctx, g4_tree *t, const g4_fmm_params *fp, double fac
     const uint32_t nll = h4[2], nln = h4[3];
     // 2. partner lists of the leaf pairs (counting sort by leaf), then all particle pairs per leaf
     uint32_t *cursor = (uint32_t *)(b + L.cursor), *bsum = (uint32_t *)(b + L.bsum);
-    G4_HIP(ctx, hipMemsetAsync(A.pstart, 0, (size_t)(nnodes + 1) * 4, s));
+    if (int zst = g4_launch_zero(ctx, A.pstart, (size_t)(nnodes + 1) * 4)) return zst;
     if (nll) k_ll_count<<<2048, 256, 0, s>>>(A.ll, nll, A.pstart);
     const uint32_t nb = (nnodes + 1023) / 1024;
     k_scan_blocks<<<nb, 256, 0, s>>>(A.pstart, nnodes, bsum);
@@ -1643,10 +1643,10 @@ int g4_launch_fmm(g4_ctx *ctx, g4_tree *t, const g4_fmm_params *fp, double facto
                                               0, 32 + bits_for((uint64_t)t->n), s));
     uint32_t *nstart = (uint32_t *)(b + L.nstart), *nend = (uint32_t *)(b + L.nend);
     uint32_t *pstart = (uint32_t *)(b + L.pstart), *pend = (uint32_t *)(b + L.pend);
-    G4_HIP(ctx, hipMemsetAsync(nstart, 0, (size_t)t->cap * 4, s));
-    G4_HIP(ctx, hipMemsetAsync(nend, 0, (size_t)t->cap * 4, s));
-    G4_HIP(ctx, hipMemsetAsync(pstart, 0, (size_t)t->n * 4, s));
-    G4_HIP(ctx, hipMemsetAsync(pend, 0, (size_t)t->n * 4, s));
+    if (int zst = g4_launch_zero(ctx, nstart, (size_t)t->cap * 4)) return zst;
+    if (int zst = g4_launch_zero(ctx, nend, (size_t)t->cap * 4)) return zst;
+    if (int zst = g4_launch_zero(ctx, pstart, (size_t)t->n * 4)) return zst;
+    if (int zst = g4_launch_zero(ctx, pend, (size_t)t->n * 4)) return zst;
     if (n_node) k_fmm_csr<<<2048, 256, 0, s>>>(nk2, n_node, nstart, nend);
     if (n_part) k_fmm_csr<<<2048, 256, 0, s>>>(pk2, n_part, pstart, pend);
     A.nval = nv2;

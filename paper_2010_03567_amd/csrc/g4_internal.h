@@ -140,6 +140,9 @@ int g4_launch_direct(g4_ctx *ctx, const g4_particles *p, const g4_tree_params *t
 int g4_launch_quantize(g4_ctx *ctx, const double *pos, int64_t n, const g4_tree_params *tp, uint32_t *x,
                        uint32_t *y, uint32_t *z, int32_t *flag);
 int g4_launch_gather_seed(g4_ctx *ctx, g4_tree *t, const float *a_seed_caller);
+// zero `bytes` (a multiple of 4) of device memory with a kernel, so that the
+// calls stay valid under stream capture (no memset nodes in a graph)
+int g4_launch_zero(g4_ctx *ctx, void *p, size_t bytes);
 int g4_launch_mlp_features(g4_ctx *ctx, const g4_tree *t, const g4_walk_params *wp, const float *norm,
                            float *feat);
 int g4_launch_mlp_forward(g4_ctx *ctx, const uint16_t *w, const float *feat, int64_t n, float *out, float shift,

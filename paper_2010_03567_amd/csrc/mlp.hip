@@ -392,8 +392,8 @@ __global__ __launch_bounds__(TB) void k_mlp_grad(const uint16_t *__restrict__ w,
 int g4_launch_mlp_grad(g4_ctx *ctx, const uint16_t *w, const float *feat, const float *target, int64_t n, float tau,
                        float *grad, float *loss)
 {
-    G4_HIP(ctx, hipMemsetAsync(grad, 0, MLP_NP * sizeof(float), ctx->stream));
-    G4_HIP(ctx, hipMemsetAsync(loss, 0, sizeof(float), ctx->stream));
+    if (int st = g4_launch_zero(ctx, grad, MLP_NP * sizeof(float))) return st;
+    if (int st = g4_launch_zero(ctx, loss, sizeof(float))) return st;
     if (n > 0)
         k_mlp_grad<<<(unsigned)((n + TB - 1) / TB), TB, 0, ctx->stream>>>(w, feat, target, n, 1.0f / (float)n, tau,
                                                                         grad, loss);

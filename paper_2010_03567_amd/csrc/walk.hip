@@ -673,7 +673,7 @@ int g4_launch_walk(g4_ctx *ctx, g4_tree *t, const g4_walk_params *wp, int kernel
         const int v = atoi(env);
         if (v >= 1 && v <= WK_LDS_STK) A.lds_stk = v;
     }
-    G4_HIP(ctx, hipMemsetAsync(A.item_ctr, 0, sizeof(uint32_t), ctx->stream));
+    if (int st = g4_launch_zero(ctx, A.item_ctr, sizeof(uint32_t))) return st;
     A.wstat = stat_slot == 0 ? t->ctr->stat + 9 : nullptr;
     hipStream_t s = ctx->stream;
     const bool P = pot != nullptr;
