@@ -296,6 +296,35 @@ __global__ __launch_bounds__(256) void k_walk(const WalkArgs A)
     // order; every step evaluates one pair per busy lane.  Without `drain` the
     // phase ends as soon as a lane cannot be refilled, so every step is full;
     // lanes keep their unfinished items for the next phase.
+    // One pair for every lane that holds an item.  The target itself is among
+    // the sources of its own leaf: its separation is zero, where the kernel
+    // is finite, so its force term is exactly zero and only the potential
+    // needs the mass masked.
+    auto pair_step = [&]() {
+        const uint4 src = A.parts[q_src];
+        const float mj = (POT && q_src == q_self) ? 0.f : __uint_as_float(src.w);
+        const float sx = (float)(int32_t)(src.x - q_x) * A.unit;
+        const float sy = (float)(int32_t)(src.y - q_y) * A.unit;
+        const float sz = (float)(int32_t)(src.z - q_z) * A.unit;
+        const float s2 = fmaf(sx, sx, fmaf(sy, sy, sz * sz));
+        float K, Wp;
+        if constexpr (KER == 2) pair_kernel_tab<POT>(s2, A.tab, A.tn, A.tscale, A.asplit, A.h2, A.hinv, K, Wp);
+        else pair_kernel<KER, POT>(s2, A.asplit, A.h2, A.hinv, K, Wp);
+        const float mk = mj * K;
+        q_fx = fmaf(mk, sx, q_fx);
+        q_fy = fmaf(mk, sy, q_fy);
+        q_fz = fmaf(mk, sz, q_fz);
+        if (POT) q_fp = fmaf(-mj, Wp, q_fp);
+        q_src++;
+        q_rem--;
+        if (q_rem == 0) {
+            lds_add(&W.acc[0][q_t], (double)q_fx);
+            lds_add(&W.acc[1][q_t], (double)q_fy);
+            lds_add(&W.acc[2][q_t], (double)q_fz);
+            if constexpr (POT) lds_add(&W.acc[3][q_t], (double)q_fp);
+            q_fx = q_fy = q_fz = q_fp = 0.f;
+        }
+    };
     auto run_pairs = [&](bool drain) {
         w_phase++;
         for (;;) {
@@ -318,32 +347,15 @@ __global__ __launch_bounds__(256) void k_walk(const WalkArgs A)
                 lt_h += min((uint32_t)__builtin_popcountll(idle), avail);
             }
             const uint64_t busy = ballot(q_rem != 0);
-            if (!busy || (!drain && busy != ~0ull)) break;
-            w_pp++;
-            if (q_rem != 0) {
-                const uint4 src = A.parts[q_src];
-                const float mj = q_src != q_self ? __uint_as_float(src.w) : 0.f;
-                const float sx = (float)(int32_t)(src.x - q_x) * A.unit;
-                const float sy = (float)(int32_t)(src.y - q_y) * A.unit;
-                const float sz = (float)(int32_t)(src.z - q_z) * A.unit;
-                const float s2 = fmaf(sx, sx, fmaf(sy, sy, sz * sz));
-                float K, Wp;
-                if constexpr (KER == 2) pair_kernel_tab<POT>(s2, A.tab, A.tn, A.tscale, A.asplit, A.h2, A.hinv, K, Wp);
-                else pair_kernel<KER, POT>(s2, A.asplit, A.h2, A.hinv, K, Wp);
-                const float mk = mj * K;
-                q_fx = fmaf(mk, sx, q_fx);
-                q_fy = fmaf(mk, sy, q_fy);
-                q_fz = fmaf(mk, sz, q_fz);
-                if (POT) q_fp = fmaf(-mj, Wp, q_fp);
-                q_src++;
-                q_rem--;
-                if (q_rem == 0) {
-                    lds_add(&W.acc[0][q_t], (double)q_fx);
-                    lds_add(&W.acc[1][q_t], (double)q_fy);
-                    lds_add(&W.acc[2][q_t], (double)q_fz);
-                    if constexpr (POT) lds_add(&W.acc[3][q_t], (double)q_fp);
-                    q_fx = q_fy = q_fz = q_fp = 0.f;
-                }
+            if (drain) {
+                if (!busy) break;
+                w_pp++;
+                if (q_rem != 0) pair_step();
+            } else {
+                // every lane holds an item (busy is all ones)
+                if (busy != ~0ull) break;
+                w_pp++;
+                pair_step();
             }
         }
     };
