@@ -51,6 +51,8 @@ def parse():
     ap.add_argument("--no-learned", action="store_true")
     ap.add_argument("--weights", type=str, default="", help="learned-seed weights (.npz); default by particle count")
     ap.add_argument("--no-fmm", action="store_true")
+    ap.add_argument("--fmm-leaf", type=int, default=48,
+                    help="leaf size of the FMM tree (48: fastest of 8-96 at theta 0.5 on this box)")
     ap.add_argument("--no-forest", action="store_true")
     ap.add_argument("--no-large", action="store_true", help="skip the learned-vs-plain comparison at 256^3")
     ap.add_argument("--cpu-sample", type=int, default=20000)
@@ -397,7 +399,7 @@ def bench_learned_large(args, g, ctx):
 
 
 def bench_fmm(args, g, ctx, n):
-    """Symmetric FMM (p = 3, theta = 0.5, leaf 16) on the clustered box drawn
+    """Symmetric FMM (p = 3, theta = 0.5, leaf --fmm-leaf) on the clustered box drawn
     with its own seed, short-range kernel at the same split, R_cut = 4.5 r_s;
     atomic-sum mode timed per step, the sorted-list (bitwise reproducible) mode
     timed alongside."""
@@ -410,7 +412,7 @@ def bench_fmm(args, g, ctx, n):
     pos = torch.from_numpy(ps.pos).to(dev)
     m32 = ps.mass.astype(np.float32)
     mass = torch.from_numpy(m32).to(dev)
-    tp = g.tree_params(True, 1.0, leaf_max=16)
+    tp = g.tree_params(True, 1.0, leaf_max=args.fmm_leaf)
     ws = torch.empty(g.g4_workspace_bytes(tp, n) + 256, dtype=torch.uint8, device=dev)
 
     def run(det, steps):
@@ -453,7 +455,7 @@ def bench_fmm(args, g, ctx, n):
     st = state["stats"]
     log(f"[bench] fmm: {ms:.3f} ms/step (fmm {fmm_ms:.3f} ms; sorted-list mode {fmm_det_ms:.3f} ms), "
         f"net force {net:.2e}")
-    return {"workload": "fmm_clustered_box_128^3 (seed 3), p=3, theta=0.5, leaf 16, R_cut 4.5 r_s",
+    return {"workload": f"fmm_clustered_box_128^3 (seed 3), p=3, theta=0.5, leaf {args.fmm_leaf}, R_cut 4.5 r_s",
             "forces_per_s": n / (ms * 1e-3), "ms_per_step": ms, "fmm_ms": fmm_ms,
             "deterministic_mode": {"ms_per_step": ms_det, "fmm_ms": fmm_det_ms},
             "interactions_per_particle": {"pp": st["n_pp"] / n, "pn": st["n_pn"] / n, "nn": st["n_nn"] / n},

@@ -674,6 +674,7 @@ __global__ __launch_bounds__(256) void k_fmm_particles(FmmArgs A, const uint32_t
 // Summation order follows the scheduling of the atomics, so results agree
 // with the list-based path to round-off but are not bitwise reproducible.
 #define FT_STK 32  // traversal stack of a leaf-node pair: one sibling entry per level
+#define FT_SB 16   // source block of the particle pairs with an opened leaf
 
 __constant__ uint8_t c_tri[36][2] = {{0, 0}, {0, 1}, {1, 1}, {0, 2}, {1, 2}, {2, 2}, {0, 3}, {1, 3}, {2, 3}, {3, 3}, {0, 4}, {1, 4}, {2, 4}, {3, 4}, {4, 4}, {0, 5}, {1, 5}, {2, 5}, {3, 5}, {4, 5}, {5, 5}, {0, 6}, {1, 6}, {2, 6}, {3, 6}, {4, 6}, {5, 6}, {6, 6}, {0, 7}, {1, 7}, {2, 7}, {3, 7}, {4, 7}, {5, 7}, {6, 7}, {7, 7}};  // daughter pairs (i <= j) of a self pair, j-major
 
@@ -1102,13 +1103,22 @@ __device__ __forceinline__ uint32_t fm_gbits(uint64_t m, uint32_t g) { return (u
 // daughters of the internal node with the particle-node rules, with its own
 // stack of (first sibling, count, group lane mask) entries; a group whose walk
 // ends deposits its particles' sums and takes the wavefront's next pair.
+// Leaves opened in a step give particle pairs for the targets that opened
+// them only; these are spread one pair per lane over the whole wavefront.
 template <int KER, bool POT>
 __global__ __launch_bounds__(256) void k_fast_ln(FastArgs A, uint32_t npairs)
 {
-    __shared__ uint4 stk[4][4][FT_STK];
+    __shared__ uint2 stk[4][4][FT_STK];     // (first sibling, count | group lane mask << 16)
     __shared__ float red[4][4][20];
+    __shared__ uint4 tpos[4][64];           // targets (grid position, mass bits) for the leaf pairs
+    __shared__ float tacc[4][64][4];        // their pair sums
+    __shared__ float sacc[4][4][FT_SB][4];  // pair sums of the current source block of each group
+    __shared__ uint2 gblk[4][4];            // each group's source block: first particle, count
+    __shared__ uint8_t trank[4][4][16];     // each group's open targets: rank -> lane in the group
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const uint32_t g = (uint32_t)lane >> 4, gl = (uint32_t)lane & 15u;
+    tacc[wv][lane][0] = tacc[wv][lane][1] = tacc[wv][lane][2] = tacc[wv][lane][3] = 0.f;
+    for (uint32_t v = (uint32_t)lane; v < 4u * FT_SB * 4u; v += 64u) (&sacc[wv][0][0][0])[v] = 0.f;
     // this wavefront's contiguous share of the pairs
     const uint32_t nw = gridDim.x * 4, wid = blockIdx.x * 4 + wv;
     const uint32_t per = (npairs + nw - 1) / nw;
@@ -1158,19 +1168,19 @@ __global__ __launch_bounds__(256) void k_fast_ln(FastArgs A, uint32_t npairs)
         }
         const uint32_t am = fm_gbits(fm_ballot(act), g);
         if (start) {
-            if (gl == 0) stk[wv][g][0] = make_uint4(A.wn[tb].next, A.wn[tb].num, am, 0u);
+            if (gl == 0) stk[wv][g][0] = make_uint2(A.wn[tb].next, A.wn[tb].num | (am << 16));
             sp = 1;
         }
         if (!fm_ballot(sp > 0)) break;
         fm_sync();
         // ---- one step of every live group's walk
         const bool live = sp > 0;
-        uint4 e = make_uint4(0u, 0u, 0u, 0u);
+        uint2 e = make_uint2(0u, 0u);
         if (live) e = stk[wv][g][sp - 1];
-        const uint32_t node = e.x, cnt = e.y, gm = e.z;
+        const uint32_t node = e.x, cnt = e.y & 0xffffu, gm = e.y >> 16;
         if (live) {
             if (cnt > 1) {
-                if (gl == 0) stk[wv][g][sp - 1] = make_uint4(node + 1, cnt - 1, gm, 0u);
+                if (gl == 0) stk[wv][g][sp - 1] = make_uint2(node + 1, (cnt - 1) | (gm << 16));
             } else {
                 sp--;
             }
@@ -1250,32 +1260,79 @@ __global__ __launch_bounds__(256) void k_fast_ln(FastArgs A, uint32_t npairs)
             const bool gleaf = go && (w.meta & WN_LEAF);
             const uint64_t lm = fm_ballot(gleaf);
             if (lm) {
-                // particle pairs with the opened leaf: the target side in registers, the source
-                // side summed over the group; the loop runs to the largest such leaf
+                // particle pairs with the opened leaves of the wavefront's groups, one pair per
+                // lane: group g pairs its open targets with the leaf's sources in blocks of
+                // FT_SB; both sides are summed in LDS and the sources' sums deposited per block
+                const uint32_t om16 = fm_gbits(om, g);
+                if (open && gleaf) {
+                    trank[wv][g][__builtin_popcount(om16 & ((1u << gl) - 1u))] = (uint8_t)gl;
+                    tpos[wv][lane] = make_uint4(me.x, me.y, me.z, __float_as_uint(mt));
+                }
+                // the longest opened leaf of the wavefront
                 uint32_t nmax = gleaf ? w.num : 0u;
                 for (int off = 32; off > 0; off >>= 1) nmax = max(nmax, (uint32_t)__shfl_xor((int)nmax, off));
-                for (uint32_t s = 0; s < nmax; s++) {
-                    const bool ok = gleaf && s < w.num;
-                    const uint4 src = A.parts[ok ? w.next + s : 0u];
-                    const bool o = open && ok;
-                    const float ms = o ? __uint_as_float(src.w) : 0.f, mo = o ? mt : 0.f;
-                    const float sx = (float)(int32_t)(src.x - me.x) * A.unit;
-                    const float sy = (float)(int32_t)(src.y - me.y) * A.unit;
-                    const float sz = (float)(int32_t)(src.z - me.z) * A.unit;
-                    float K, W;
-                    pair_kernel<KER, POT>(sx * sx + sy * sy + sz * sz, A.asplit, A.h2, A.hinv, K, W);
-                    fx += ms * K * sx;
-                    fy += ms * K * sy;
-                    fz += ms * K * sz;
-                    if (POT) fp -= ms * W;
-                    const float gx = fm_gsum(-mo * K * sx), gy = fm_gsum(-mo * K * sy), gz = fm_gsum(-mo * K * sz);
-                    const float gp = POT ? fm_gsum(-mo * W) : 0.f;
-                    if (ok && gl == 0) fm_deposit<POT>(A, w.next + s, gx, gy, gz, gp);
+                const uint32_t gk = gleaf ? (uint32_t)__builtin_popcount(om16) : 0u;
+                for (uint32_t b0 = 0; b0 < nmax; b0 += FT_SB) {
+                    const uint32_t nb = gleaf && b0 < w.num ? min(w.num - b0, (uint32_t)FT_SB) : 0u;
+                    // pair ranges of the four groups (uniform)
+                    const uint32_t P0 = __builtin_amdgcn_readlane((int)(gk * nb), 0),
+                                   P1 = __builtin_amdgcn_readlane((int)(gk * nb), 16),
+                                   P2 = __builtin_amdgcn_readlane((int)(gk * nb), 32),
+                                   P3 = __builtin_amdgcn_readlane((int)(gk * nb), 48);
+                    if (gl == 0) gblk[wv][g] = make_uint2(w.next + b0, nb);
+                    fm_sync();
+                    const uint32_t e1 = P0, e2 = e1 + P1, e3 = e2 + P2, ptot = e3 + P3;
+                    for (uint32_t base = 0; base < ptot; base += 64) {
+                        const uint32_t p = base + (uint32_t)lane;
+                        if (p < ptot) {
+                            const uint32_t gg = (p >= e1 ? 1u : 0u) + (p >= e2 ? 1u : 0u) + (p >= e3 ? 1u : 0u);
+                            const uint32_t pl = p - (gg == 0 ? 0u : gg == 1 ? e1 : gg == 2 ? e2 : e3);
+                            const uint2 gb = gblk[wv][gg];
+                            // pl = rank nb + k, k < nb <= FT_SB
+                            uint32_t rk = (uint32_t)((float)pl * __builtin_amdgcn_rcpf((float)gb.y));
+                            if (rk * gb.y > pl) rk--;
+                            else if ((rk + 1u) * gb.y <= pl) rk++;
+                            const uint32_t ks = pl - rk * gb.y;
+                            const uint32_t tl = 16u * gg + trank[wv][gg][rk];
+                            const uint4 T = tpos[wv][tl];
+                            const uint4 src = A.parts[gb.x + ks];
+                            const float sx = (float)(int32_t)(src.x - T.x) * A.unit;
+                            const float sy = (float)(int32_t)(src.y - T.y) * A.unit;
+                            const float sz = (float)(int32_t)(src.z - T.z) * A.unit;
+                            float K, W;
+                            pair_kernel<KER, POT>(sx * sx + sy * sy + sz * sz, A.asplit, A.h2, A.hinv, K, W);
+                            const float ms = __uint_as_float(src.w), mo = __uint_as_float(T.w);
+                            atomicAdd(&tacc[wv][tl][0], ms * K * sx);
+                            atomicAdd(&tacc[wv][tl][1], ms * K * sy);
+                            atomicAdd(&tacc[wv][tl][2], ms * K * sz);
+                            if (POT) atomicAdd(&tacc[wv][tl][3], -ms * W);
+                            atomicAdd(&sacc[wv][gg][ks][0], -mo * K * sx);
+                            atomicAdd(&sacc[wv][gg][ks][1], -mo * K * sy);
+                            atomicAdd(&sacc[wv][gg][ks][2], -mo * K * sz);
+                            if (POT) atomicAdd(&sacc[wv][gg][ks][3], -mo * W);
+                        }
+                    }
+                    fm_sync();
+                    // the sources' sums of this block, cleared for the next
+                    if (gk) {
+                        for (uint32_t kk = gl; kk < nb; kk += 16) {
+                            float *sa = sacc[wv][g][kk];
+                            fm_deposit<POT>(A, w.next + b0 + kk, sa[0], sa[1], sa[2], sa[3]);
+                            sa[0] = sa[1] = sa[2] = sa[3] = 0.f;
+                        }
+                    }
+                    fm_sync();
                 }
+                // the targets' sums into their registers
+                fx += tacc[wv][lane][0];
+                fy += tacc[wv][lane][1];
+                fz += tacc[wv][lane][2];
+                if (POT) fp += tacc[wv][lane][3];
+                tacc[wv][lane][0] = tacc[wv][lane][1] = tacc[wv][lane][2] = tacc[wv][lane][3] = 0.f;
                 if (open && gleaf) n_pp += w.num;
             }
             if (go && !gleaf && sp < FT_STK) {
-                if (gl == 0) stk[wv][g][sp] = make_uint4(w.next, w.num, go, 0u);
+                if (gl == 0) stk[wv][g][sp] = make_uint2(w.next, w.num | (go << 16));
                 sp++;
             }
         }

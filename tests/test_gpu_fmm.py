@@ -57,8 +57,9 @@ def check(a, ref, label, med=1e-5, p999=1e-3):
 
 
 @pytest.mark.parametrize("det", [0, 1])
-@pytest.mark.parametrize("kind,n", [("plummer", 3000), ("box", 30001), ("box", 131072)])
-def test_fmm_parity(g, ctx, kind, n, det):
+@pytest.mark.parametrize("kind,n,B", [("plummer", 3000, 16), ("box", 30001, 16), ("box", 131072, 16),
+                                      ("box", 131072, 48)])
+def test_fmm_parity(g, ctx, kind, n, B, det):
     """Both summation modes against the oracle: the same interactions (counts
     agree), forces and potentials at FP32 round-off of the oracle's FP64."""
     if kind == "plummer":
@@ -67,7 +68,7 @@ def test_fmm_parity(g, ctx, kind, n, det):
     else:
         ps = workloads.clustered_box(n, seed=52, nhalo=max(10, n // 500))
         kw = dict(kernel=1, **sr(n))
-    tree, ot, p, tp, m32 = build(g, ctx, ps, kind == "box")
+    tree, ot, p, tp, m32 = build(g, ctx, ps, kind == "box", B)
     out = g.g4_fmm_force(ctx, tree, g.fmm_params(theta=0.5, deterministic=det, **kw), want_pot=True, want_stats=True)
     acc, pot, stt = ot.fmm(theta=0.5, **kw)
     check(st3(out), acc, f"fmm {kind} {n} det={det}")
@@ -131,13 +132,13 @@ def test_fmm_modes_agree(g, ctx):
 
 @pytest.mark.slow
 def test_fmm_full_size(g, ctx):
-    """The clustered 128^3 box at full size: net force at round-off, and errors
-    against FP64 direct summation on a 10^4 sample at the level the oracle's FMM
-    shows at smaller N (dominated by the r_cut truncation)."""
+    """The clustered 128^3 box at full size, leaf 48 as timed: net force at
+    round-off, and errors against FP64 direct summation on a 10^4 sample at the
+    level the oracle's FMM shows at smaller N (dominated by the r_cut truncation)."""
     n = 128 ** 3
     ps = workloads.clustered_box(n, seed=3)
     kw = sr(n)
-    tree, ot, p, tp, m32 = build(g, ctx, ps, True)
+    tree, ot, p, tp, m32 = build(g, ctx, ps, True, 48)
     out = g.g4_fmm_force(ctx, tree, g.fmm_params(kernel=1, theta=0.5, **kw), want_stats=True)
     a = st3(out)
     net = np.abs((m32[:, None].astype(np.float64) * a).sum(0)).max()
