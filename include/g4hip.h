@@ -150,10 +150,11 @@ const char *g4_last_error(const g4_ctx *ctx);
 /* ---------------------------------------------------------- integer mapping */
 /* pos: device, n x 3 float64 row-major (physical).  Writes x, y, z (device,
  * n uint32 each) per the mapping of g4_tree_params (periodic: floor(x/L 2^32)
- * mod 2^32; isolated: 2^30 + floor((x-origin)/box 2^31)).  Synchronises and
- * returns G4_EROOT if an isolated particle lies outside the root cube
- * (coordinates are then clamped to the root).  `flag` is a device int32
- * scratch word supplied by the caller. */
+ * mod 2^32; isolated: 2^30 + floor((x-origin)/box 2^31)).  Isolated root:
+ * synchronises and returns G4_EROOT if a particle lies outside the root cube
+ * (coordinates are then clamped to the root).  Periodic: cannot fail, returns
+ * without synchronising.  `flag` is a device int32 scratch word supplied by
+ * the caller (written only for an isolated root). */
 int g4_quantize(g4_ctx *ctx, const double *pos, int64_t n, const g4_tree_params *tp,
                 uint32_t *x, uint32_t *y, uint32_t *z, int32_t *flag);
 

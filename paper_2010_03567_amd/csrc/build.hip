@@ -124,11 +124,14 @@ int g4_launch_quantize(g4_ctx *ctx, const double *pos, int64_t n, const g4_tree_
                        uint32_t *y, uint32_t *z, int32_t *flag)
 {
     double inv = tp->periodic ? TWO32 / tp->box : TWO31 / tp->box;
-    if (int st = g4_launch_zero(ctx, flag, 4)) return st;
+    if (!tp->periodic)
+        if (int st = g4_launch_zero(ctx, flag, 4)) return st;
     if (n > 0)
         k_quantize<<<grid_for(n), kBlock, 0, ctx->stream>>>(pos, n, tp->periodic, inv, tp->origin[0], tp->origin[1],
                                                            tp->origin[2], x, y, z, flag);
     G4_HIP(ctx, hipGetLastError());
+    // the periodic map cannot fail: no read-back, so the host does not wait here
+    if (tp->periodic) return G4_OK;
     int32_t h = 0;
     G4_HIP(ctx, hipMemcpyAsync(&h, flag, 4, hipMemcpyDeviceToHost, ctx->stream));
     G4_HIP(ctx, hipStreamSynchronize(ctx->stream));

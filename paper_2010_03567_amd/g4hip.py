@@ -186,7 +186,7 @@ def g4_quantize(ctx, pos, tp):
     x = torch.empty(n, dtype=torch.int32, device=dev)
     y = torch.empty_like(x)
     z = torch.empty_like(x)
-    flag = torch.zeros(1, dtype=torch.int32, device=dev)
+    flag = torch.empty(1, dtype=torch.int32, device=dev)  # cleared by the library when it is used
     ctx.check(_L.g4_quantize(ctx.h, _ptr(pos), n, C.byref(tp), _ptr(x), _ptr(y), _ptr(z), _ptr(flag)))
     return x, y, z
 
