@@ -52,7 +52,8 @@ def parse():
     ap.add_argument("--weights", type=str, default="", help="learned-seed weights (.npz); default by particle count")
     ap.add_argument("--no-fmm", action="store_true")
     ap.add_argument("--fmm-leaf", type=int, default=48,
-                    help="leaf size of the FMM tree (48: fastest of 8-96 at theta 0.5 on this box)")
+                    help="leaf size of the second, tuned FMM line (48: fastest of 8-96 at theta 0.5 on this box; "
+                         "the first line keeps the configuration's leaf 16)")
     ap.add_argument("--no-forest", action="store_true")
     ap.add_argument("--no-large", action="store_true", help="skip the learned-vs-plain comparison at 256^3")
     ap.add_argument("--cpu-sample", type=int, default=20000)
@@ -399,10 +400,11 @@ def bench_learned_large(args, g, ctx):
 
 
 def bench_fmm(args, g, ctx, n):
-    """Symmetric FMM (p = 3, theta = 0.5, leaf --fmm-leaf) on the clustered box drawn
-    with its own seed, short-range kernel at the same split, R_cut = 4.5 r_s;
-    atomic-sum mode timed per step, the sorted-list (bitwise reproducible) mode
-    timed alongside."""
+    """Symmetric FMM (p = 3, theta = 0.5) on the clustered box drawn with its own
+    seed, short-range kernel at the same split, R_cut = 4.5 r_s: leaf 16 as the
+    configuration states (atomic-sum mode timed per step, the sorted-list,
+    bitwise reproducible mode timed alongside), and the atomic-sum mode again at
+    the leaf size that measured fastest (--fmm-leaf)."""
     import torch
     import workloads
     scale = (128 ** 3 / n) ** (1.0 / 3.0)
@@ -412,55 +414,67 @@ def bench_fmm(args, g, ctx, n):
     pos = torch.from_numpy(ps.pos).to(dev)
     m32 = ps.mass.astype(np.float32)
     mass = torch.from_numpy(m32).to(dev)
-    tp = g.tree_params(True, 1.0, leaf_max=args.fmm_leaf)
-    ws = torch.empty(g.g4_workspace_bytes(tp, n) + 256, dtype=torch.uint8, device=dev)
-
-    def run(det, steps):
-        fp = g.fmm_params(kernel=1, theta=0.5, r_s=r_s, r_cut=4.5 * r_s, eps0=eps0, deterministic=det)
-        state = {"factor": 1.0, "fws": None}
-
-        def step(ev=None):
-            x, y, z = g.g4_quantize(ctx, pos, tp)
-            p = g.particles(x, y, z, mass)
-            t = g.g4_build_tree(ctx, p, tp, ws=ws)
-            g.g4_compute_multipoles(ctx, t, 3)
-            if ev is not None:
-                ev[0].record()
-            o = g.g4_fmm_force(ctx, t, fp, list_factor=state["factor"], ws=state["fws"], want_stats=ev is None)
-            if ev is not None:
-                ev[1].record()
-            state["factor"], state["fws"], state["out"], state["p"] = o["list_factor"], o["ws"], o, p
-            if o["stats"] is not None:
-                state["stats"] = o["stats"]
-
-        step()
-        evs = [[torch.cuda.Event(enable_timing=True) for _ in range(2)] for _ in range(steps)]
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        for k in range(steps):
-            step(evs[k])
-        torch.cuda.synchronize()
-        ms = (time.perf_counter() - t0) * 1e3 / steps
-        return ms, float(np.mean([e[0].elapsed_time(e[1]) for e in evs])), state
-
-    ms, fmm_ms, state = run(0, max(3, args.steps // 2))
-    ms_det, fmm_det_ms, _ = run(1, 2)
-    o = state["out"]
-    a = np.stack([o["ax"].cpu().numpy(), o["ay"].cpu().numpy(), o["az"].cpu().numpy()], 1)
-    net = float(np.abs((m32[:, None].astype(np.float64) * a).sum(0)).max() / (m32[:, None] * np.abs(a)).sum())
     tg = workloads.sample_indices(n, args.err_sample, seed=98)
-    ref = g.g4_direct_force(ctx, state["p"], tp, g.walk_params(kernel=1, r_s=r_s, eps0=eps0),
-                            targets=torch.from_numpy(tg).to(dev), want_pot=False)
-    ref = np.stack([ref["ax"].cpu().numpy(), ref["ay"].cpu().numpy(), ref["az"].cpu().numpy()], 1)
-    st = state["stats"]
-    log(f"[bench] fmm: {ms:.3f} ms/step (fmm {fmm_ms:.3f} ms; sorted-list mode {fmm_det_ms:.3f} ms), "
-        f"net force {net:.2e}")
-    return {"workload": f"fmm_clustered_box_128^3 (seed 3), p=3, theta=0.5, leaf {args.fmm_leaf}, R_cut 4.5 r_s",
-            "forces_per_s": n / (ms * 1e-3), "ms_per_step": ms, "fmm_ms": fmm_ms,
-            "deterministic_mode": {"ms_per_step": ms_det, "fmm_ms": fmm_det_ms},
-            "interactions_per_particle": {"pp": st["n_pp"] / n, "pn": st["n_pn"] / n, "nn": st["n_nn"] / n},
-            "net_force_over_sum_abs": net, "list_factor": state["factor"],
-            "errors_vs_direct": workloads.percentiles(workloads.relative_errors(a[tg], ref))}
+    ref = {}
+
+    def case(leaf, with_sorted):
+        tp = g.tree_params(True, 1.0, leaf_max=leaf)
+        ws = torch.empty(g.g4_workspace_bytes(tp, n) + 256, dtype=torch.uint8, device=dev)
+
+        def run(det, steps):
+            fp = g.fmm_params(kernel=1, theta=0.5, r_s=r_s, r_cut=4.5 * r_s, eps0=eps0, deterministic=det)
+            state = {"factor": 1.0, "fws": None}
+
+            def step(ev=None):
+                x, y, z = g.g4_quantize(ctx, pos, tp)
+                p = g.particles(x, y, z, mass)
+                t = g.g4_build_tree(ctx, p, tp, ws=ws)
+                g.g4_compute_multipoles(ctx, t, 3)
+                if ev is not None:
+                    ev[0].record()
+                o = g.g4_fmm_force(ctx, t, fp, list_factor=state["factor"], ws=state["fws"], want_stats=ev is None)
+                if ev is not None:
+                    ev[1].record()
+                state["factor"], state["fws"], state["out"], state["p"] = o["list_factor"], o["ws"], o, p
+                if o["stats"] is not None:
+                    state["stats"] = o["stats"]
+
+            step()
+            evs = [[torch.cuda.Event(enable_timing=True) for _ in range(2)] for _ in range(steps)]
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for k in range(steps):
+                step(evs[k])
+            torch.cuda.synchronize()
+            ms = (time.perf_counter() - t0) * 1e3 / steps
+            return ms, float(np.mean([e[0].elapsed_time(e[1]) for e in evs])), state
+
+        ms, fmm_ms, state = run(0, max(3, args.steps // 2))
+        o = state["out"]
+        a = np.stack([o["ax"].cpu().numpy(), o["ay"].cpu().numpy(), o["az"].cpu().numpy()], 1)
+        net = float(np.abs((m32[:, None].astype(np.float64) * a).sum(0)).max() / (m32[:, None] * np.abs(a)).sum())
+        if "a" not in ref:
+            r = g.g4_direct_force(ctx, state["p"], tp, g.walk_params(kernel=1, r_s=r_s, eps0=eps0),
+                                  targets=torch.from_numpy(tg).to(dev), want_pot=False)
+            ref["a"] = np.stack([r["ax"].cpu().numpy(), r["ay"].cpu().numpy(), r["az"].cpu().numpy()], 1)
+        st = state["stats"]
+        res = {"workload": f"fmm_clustered_box_128^3 (seed 3), p=3, theta=0.5, leaf {leaf}, R_cut 4.5 r_s",
+               "forces_per_s": n / (ms * 1e-3), "ms_per_step": ms, "fmm_ms": fmm_ms,
+               "interactions_per_particle": {"pp": st["n_pp"] / n, "pn": st["n_pn"] / n, "nn": st["n_nn"] / n},
+               "net_force_over_sum_abs": net, "list_factor": state["factor"],
+               "errors_vs_direct": workloads.percentiles(workloads.relative_errors(a[tg], ref["a"]))}
+        msg = f"[bench] fmm leaf {leaf}: {ms:.3f} ms/step (fmm {fmm_ms:.3f} ms"
+        if with_sorted:
+            ms_det, fmm_det_ms, _ = run(1, 2)
+            res["deterministic_mode"] = {"ms_per_step": ms_det, "fmm_ms": fmm_det_ms}
+            msg += f"; sorted-list mode {fmm_det_ms:.3f} ms"
+        log(msg + f"), net force {net:.2e}")
+        return res
+
+    out = case(16, True)
+    if args.fmm_leaf != 16:
+        out["tuned_leaf"] = case(args.fmm_leaf, False)
+    return out
 
 
 def bench_forest(args, g, ctx):

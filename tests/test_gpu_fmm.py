@@ -131,14 +131,16 @@ def test_fmm_modes_agree(g, ctx):
 
 
 @pytest.mark.slow
-def test_fmm_full_size(g, ctx):
-    """The clustered 128^3 box at full size, leaf 48 as timed: net force at
-    round-off, and errors against FP64 direct summation on a 10^4 sample at the
-    level the oracle's FMM shows at smaller N (dominated by the r_cut truncation)."""
+@pytest.mark.parametrize("B", [16, 48])
+def test_fmm_full_size(g, ctx, B):
+    """The clustered 128^3 box at full size, at the configuration's leaf 16 and the
+    timed leaf 48: net force at round-off, and errors against FP64 direct
+    summation on a 10^4 sample at the level the oracle's FMM shows at smaller N
+    (dominated by the r_cut truncation)."""
     n = 128 ** 3
     ps = workloads.clustered_box(n, seed=3)
     kw = sr(n)
-    tree, ot, p, tp, m32 = build(g, ctx, ps, True, 48)
+    tree, ot, p, tp, m32 = build(g, ctx, ps, True, B)
     out = g.g4_fmm_force(ctx, tree, g.fmm_params(kernel=1, theta=0.5, **kw), want_stats=True)
     a = st3(out)
     net = np.abs((m32[:, None].astype(np.float64) * a).sum(0)).max()
