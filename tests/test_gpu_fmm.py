@@ -115,6 +115,29 @@ def test_fmm_theta_to_zero_is_direct_sum(g, ctx, det):
     check(st3(out), st3(ref), "fmm theta->0")
 
 
+@pytest.mark.parametrize("det", [0, 1])
+def test_fmm_parity_coincident_clumps(g, ctx, det):
+    """Two clumps of 100 coincident particles 0.002 apart (inside each other's
+    softening edge) in a clustered box: depth-capped leaves of 100, larger than
+    the leaf size and than the blocks of the particle-pair kernels; forces,
+    potentials and interaction counts as the oracle's."""
+    ps0 = workloads.clustered_box(20000, seed=57, nhalo=40)
+    pos = ps0.pos.copy()
+    pos[:100] = (0.31, 0.52, 0.77)
+    pos[100:200] = (0.312, 0.52, 0.77)
+    ps = workloads.ParticleSet(pos, ps0.mass, ps0.box, {})
+    kw = dict(kernel=1, **sr(20000))
+    tree, ot, p, tp, m32 = build(g, ctx, ps, True, 16)
+    out = g.g4_fmm_force(ctx, tree, g.fmm_params(theta=0.5, deterministic=det, **kw), want_pot=True, want_stats=True)
+    acc, pot, stt = ot.fmm(theta=0.5, **kw)
+    check(st3(out), acc, f"fmm clumps det={det}")
+    perr = np.abs(out["pot"].cpu().numpy() - pot) / np.abs(pot)
+    assert np.median(perr) < 1e-5
+    s = out["stats"]
+    for k, v in zip(("n_pp", "n_pn", "n_nn"), stt):
+        assert abs(s[k] - int(v)) <= 1e-3 * max(1, int(v)), (k, s[k], int(v))
+
+
 def test_fmm_modes_agree(g, ctx):
     """The atomic-sum mode and the sorted-list mode find the same interactions
     and agree to FP32 round-off; the sorted-list mode repeats bitwise."""

@@ -293,6 +293,37 @@ def test_treepm_relative_parity(g, ctx, box_case, sr_table):
     assert_parity(stack3(out), acc, out["counts"].cpu().numpy(), cnt, f"treepm relative, table {sr_table}")
 
 
+def clumped_box(n, seed):
+    """A clustered box with two clumps of 100 coincident particles 0.002 apart
+    (inside the softening edge of each other): the depth cap leaves them in
+    leaves of 100, far above the leaf size."""
+    ps = workloads.clustered_box(n, seed=seed, nhalo=max(10, n // 500))
+    pos = ps.pos.copy()
+    pos[:100] = (0.31, 0.52, 0.77)
+    pos[100:200] = (0.312, 0.52, 0.77)
+    return workloads.ParticleSet(pos, ps.mass, ps.box, {})
+
+
+def test_treepm_parity_coincident_clumps(g, ctx):
+    """Leaves of 100 coincident particles: pairs at zero separation (finite
+    kernel, no force), softened pairs between the clumps, and the lane queue
+    running items longer than a wavefront; geometric and relative walks."""
+    ps = clumped_box(20000, 58)
+    c = make_case(g, ctx, ps, True, 8)
+    kw = sr_params(c.n)
+    out = g.g4_treepm_shortrange(ctx, c.tree, g.walk_params(kernel=1, criterion=0, theta=0.7, **kw),
+                                 want_pot=True, want_counts=True)
+    acc, pot, cnt = c.ot.walk(kernel=1, criterion=0, theta=0.7, nthreads=16, **kw)
+    assert_parity(stack3(out), acc, out["counts"].cpu().numpy(), cnt, "treepm geometric, clumps")
+    assert np.median(np.abs(out["pot"].cpu().numpy() - pot) / np.abs(pot)) < 1e-5
+    seed = np.linalg.norm(acc, axis=1).astype(np.float32)
+    out = g.g4_treepm_shortrange(ctx, c.tree, g.walk_params(kernel=1, criterion=1, alpha=0.005,
+                                                            a_seed=torch.from_numpy(seed).cuda(), **kw),
+                                 want_counts=True)
+    acc, _, cnt = c.ot.walk(kernel=1, criterion=1, alpha=0.005, aseed=seed, nthreads=16, **kw)
+    assert_parity(stack3(out), acc, out["counts"].cpu().numpy(), cnt, "treepm relative, clumps")
+
+
 # largest error of the tabulated factors S_0..S_3 (cubic Hermite pieces on
 # [0, 6] in alpha_split r, FP32 coefficients), by table length: the Hermite
 # bound dx^4 max|d^4 S / dx^4| / 384, and the FP32 floor
