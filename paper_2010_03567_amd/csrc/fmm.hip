@@ -763,33 +763,43 @@ __global__ void k_fast_init(FastArgs A, int nroot)
 
 // Wavefront-local staging of appended pairs: up to 127 pending entries in LDS,
 // written out 64 at a time with one atomic on the global counter.
+template <uint32_t CAP>
 struct Stage {
-    uint2 *buf;        // LDS, 128 entries
+    uint2 *buf;        // LDS, CAP entries; a push adds at most 64, writes go out CAP - 64 at a time
     uint32_t n;        // pending (wavefront-uniform)
 };
 
 // append one pair per lane that wants it (all lanes active)
-__device__ __forceinline__ void st_push(Stage &S, bool want, uint2 v)
+template <uint32_t CAP>
+__device__ __forceinline__ void st_push(Stage<CAP> &S, bool want, uint2 v)
 {
     const uint64_t m = fm_ballot(want);
     if (want) S.buf[S.n + fm_below(m)] = v;
     S.n += (uint32_t)__builtin_popcountll(m);
 }
 
-// write out 64 pending pairs (or all, if final) to out[] behind counter
-__device__ __forceinline__ void st_flush(Stage &S, bool final, uint2 *out, uint32_t *counter, uint32_t cap,
+// write out cap - 64 pending pairs (or all, if final) to out[] behind counter.
+// Every wavefront appends to the same counter, and same-address atomics are
+// serialised across the chip, so larger batches mean fewer of them.
+template <uint32_t CAP>
+__device__ __forceinline__ void st_flush(Stage<CAP> &S, bool final, uint2 *out, uint32_t *counter, uint32_t cap,
                                          uint32_t *overflow)
 {
     const int lane = threadIdx.x & 63;
-    while (S.n >= 64 || (final && S.n > 0)) {
-        const uint32_t k = min(S.n, 64u);
+    constexpr uint32_t chunk = CAP - 64u;
+    while (S.n >= chunk || (final && S.n > 0)) {
+        const uint32_t k = min(S.n, chunk);
         fm_sync();
         uint32_t base = 0;
         if (lane == 0) base = atomicAdd(counter, k);
         base = fm_uni(base);
-        if ((uint32_t)lane < k) {
-            if (base + lane < cap) out[base + lane] = S.buf[lane];
-            else atomicOr(overflow, 1u);
+#pragma unroll
+        for (uint32_t l0 = 0; l0 < chunk; l0 += 64u) {
+            const uint32_t l = l0 + (uint32_t)lane;
+            if (l < k) {
+                if (base + l < cap) out[base + l] = S.buf[l];
+                else atomicOr(overflow, 1u);
+            }
         }
         // move the rest (< 64) to the front
         const uint2 rest = (uint32_t)lane + k < S.n ? S.buf[lane + k] : make_uint2(0u, 0u);
@@ -804,14 +814,15 @@ template <bool POT>
 __global__ __launch_bounds__(256) void k_fast_open(FastArgs A)
 {
     __shared__ float Floc[4][16][20];
-    __shared__ uint2 sbuf[4][3][128];
+    __shared__ uint2 sbf[4][128], sbl[4][256], sbn[4][128];  // staging: frontier, leaf pairs, leaf-node pairs
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     float(*FL)[20] = Floc[wv];
     for (int v = lane; v < 320; v += 64) FL[v / 20][v % 20] = 0.f;
     if (A.cnt[4]) return;  // a list overflowed: the host retries with more room
     const uint32_t nin = min(A.cnt[0], A.cap_pairs);
     uint32_t c_nn = 0;
-    Stage sf{sbuf[wv][0], 0u}, sl{sbuf[wv][1], 0u}, sn{sbuf[wv][2], 0u};
+    Stage<128> sf{sbf[wv], 0u}, sn{sbn[wv], 0u};
+    Stage<256> sl{sbl[wv], 0u};
     const uint32_t stride = gridDim.x * 4;
     uint32_t it = blockIdx.x * 4 + wv;
     uint2 pr = it < nin ? A.fin[it] : make_uint2(0u, 0u);
