@@ -675,6 +675,7 @@ __global__ __launch_bounds__(256) void k_fmm_particles(FmmArgs A, const uint32_t
 // with the list-based path to round-off but are not bitwise reproducible.
 #define FT_STK 32  // traversal stack of a leaf-node pair: one sibling entry per level
 #define FT_SB 16   // source block of the particle pairs with an opened leaf
+#define FP_SRC 512 // partner particles listed in LDS at a time by the leaf-pair kernel
 
 __constant__ uint8_t c_tri[36][2] = {{0, 0}, {0, 1}, {1, 1}, {0, 2}, {1, 2}, {2, 2}, {0, 3}, {1, 3}, {2, 3}, {3, 3}, {0, 4}, {1, 4}, {2, 4}, {3, 4}, {4, 4}, {0, 5}, {1, 5}, {2, 5}, {3, 5}, {4, 5}, {5, 5}, {0, 6}, {1, 6}, {2, 6}, {3, 6}, {4, 6}, {5, 6}, {6, 6}, {0, 7}, {1, 7}, {2, 7}, {3, 7}, {4, 7}, {5, 7}, {6, 7}, {7, 7}};  // daughter pairs (i <= j) of a self pair, j-major
 
@@ -1022,6 +1023,7 @@ template <int KER, bool POT>
 __global__ __launch_bounds__(256) void k_fast_pp(FastArgs A, uint32_t nnodes)
 {
     __shared__ float part[4][64][4];
+    __shared__ uint32_t srcs[4][FP_SRC];  // partner particles of the current window
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     unsigned long long n_pairs = 0;  // this lane's share of the pair count
     for (uint32_t q = blockIdx.x * 4 + wv; q < nnodes; q += gridDim.x * 4) {
@@ -1043,7 +1045,9 @@ __global__ __launch_bounds__(256) void k_fast_pp(FastArgs A, uint32_t nnodes)
                 const uint4 src = A.parts[ja + s];
                 fm_pair<KER, POT>(A, me, src, (ja + s != t) ? __uint_as_float(src.w) : 0.f, fx, fy, fz, fp);
             }
-            // partner leaves, their records fetched 64 at a time
+            // partner leaves, their records fetched 64 at a time; their particles are listed
+            // one after another in LDS, so that the S slots of a target stride over all of
+            // them at once (small leaves would otherwise leave most slots idle)
             for (uint32_t e0 = p0; e0 < p1; e0 += 64) {
                 const uint32_t ne = min(64u, p1 - e0);
                 uint32_t pj = 0, pn = 0;
@@ -1054,13 +1058,24 @@ __global__ __launch_bounds__(256) void k_fast_pp(FastArgs A, uint32_t nnodes)
                     // each leaf pair is listed at both leaves: count it at the lower node index
                     if (c0 == 0 && b > q) n_pairs += (unsigned long long)na * pn;
                 }
-                for (uint32_t e = 0; e < ne; e++) {
-                    const uint32_t jb = (uint32_t)__builtin_amdgcn_readlane((int)pj, (int)e);
-                    const uint32_t nb = (uint32_t)__builtin_amdgcn_readlane((int)pn, (int)e);
-                    for (uint32_t s = (act ? k : nb); s < nb; s += S) {
-                        const uint4 src = A.parts[jb + s];
+                // exclusive prefix of the partners' particle counts
+                uint32_t incl = pn;
+                for (int d = 1; d < 64; d <<= 1) {
+                    const uint32_t v = (uint32_t)__shfl_up((int)incl, d);
+                    if (lane >= d) incl += v;
+                }
+                const uint32_t excl = incl - pn;
+                const uint32_t total = (uint32_t)__builtin_amdgcn_readlane((int)incl, 63);
+                for (uint32_t w0 = 0; w0 < total; w0 += FP_SRC) {
+                    const uint32_t wn = min((uint32_t)FP_SRC, total - w0);
+                    const uint32_t lo = max(excl, w0), hi = min(excl + pn, w0 + wn);
+                    for (uint32_t x = lo; x < hi; x++) srcs[wv][x - w0] = pj + (x - excl);
+                    fm_sync();
+                    for (uint32_t s = (act ? k : wn); s < wn; s += S) {
+                        const uint4 src = A.parts[srcs[wv][s]];
                         fm_pair<KER, POT>(A, me, src, __uint_as_float(src.w), fx, fy, fz, fp);
                     }
+                    fm_sync();
                 }
             }
             part[wv][lane][0] = fx;
