@@ -676,6 +676,7 @@ __global__ __launch_bounds__(256) void k_fmm_particles(FmmArgs A, const uint32_t
 #define FT_STK 32  // traversal stack of a leaf-node pair: one sibling entry per level
 #define FT_SB 16   // source block of the particle pairs with an opened leaf
 #define FP_SRC 512 // partner particles listed in LDS at a time by the leaf-pair kernel
+#define FT_NC 2     // copies of the daughters' field sums in the node-pair passes
 
 __constant__ uint8_t c_tri[36][2] = {{0, 0}, {0, 1}, {1, 1}, {0, 2}, {1, 2}, {2, 2}, {0, 3}, {1, 3}, {2, 3}, {3, 3}, {0, 4}, {1, 4}, {2, 4}, {3, 4}, {4, 4}, {0, 5}, {1, 5}, {2, 5}, {3, 5}, {4, 5}, {5, 5}, {0, 6}, {1, 6}, {2, 6}, {3, 6}, {4, 6}, {5, 6}, {6, 6}, {0, 7}, {1, 7}, {2, 7}, {3, 7}, {4, 7}, {5, 7}, {6, 7}, {7, 7}};  // daughter pairs (i <= j) of a self pair, j-major
 
@@ -814,11 +815,13 @@ __device__ __forceinline__ void st_flush(Stage<CAP> &S, bool final, uint2 *out, 
 template <bool POT>
 __global__ __launch_bounds__(256) void k_fast_open(FastArgs A)
 {
-    __shared__ float Floc[4][16][20];
+    // field sums of the daughters, FT_NC copies: the lanes of one daughter spread over the
+    // copies, since float atomics to one LDS address serialise
+    __shared__ float Floc[4][FT_NC][16][20];
     __shared__ uint2 sbf[4][128], sbl[4][256], sbn[4][128];  // staging: frontier, leaf pairs, leaf-node pairs
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    float(*FL)[20] = Floc[wv];
-    for (int v = lane; v < 320; v += 64) FL[v / 20][v % 20] = 0.f;
+    float(*FL)[16][20] = Floc[wv];
+    for (int v = lane; v < FT_NC * 320; v += 64) (&FL[0][0][0])[v] = 0.f;
     if (A.cnt[4]) return;  // a list overflowed: the host retries with more room
     const uint32_t nin = min(A.cnt[0], A.cap_pairs);
     uint32_t c_nn = 0;
@@ -877,7 +880,7 @@ __global__ __launch_bounds__(256) void k_fast_open(FastArgs A)
                 }
                 add_field_f(f, r, g0, g1, g2, g3, w2.mass, q2, POT ? q3 : nullptr);
 #pragma unroll
-                for (int k = 0; k < 20; k++) atomicAdd(&FL[i][k], f[k]);
+                for (int k = 0; k < 20; k++) atomicAdd(&FL[j % FT_NC][i][k], f[k]);
                 // ... and j sees i at -r (the mirrored expansion)
 #pragma unroll
                 for (int k = 0; k < 20; k++) f[k] = 0.f;
@@ -890,16 +893,20 @@ __global__ __launch_bounds__(256) void k_fast_open(FastArgs A)
                 add_field_f(f, mr, g0, g1, g2, g3, w1.mass, q2, POT ? q3 : nullptr);
                 const uint32_t sj = self ? j : 8 + j;
 #pragma unroll
-                for (int k = 0; k < 20; k++) atomicAdd(&FL[sj][k], f[k]);
+                for (int k = 0; k < 20; k++) atomicAdd(&FL[i % FT_NC][sj][k], f[k]);
             }
             c_nn += (uint32_t)__builtin_popcountll(im);
             fm_sync();
             for (int v = lane; v < 320; v += 64) {
                 const uint32_t s = (uint32_t)v / 20, k = (uint32_t)v - s * 20;
                 const bool have = s < 8 ? s < na : (!self && s - 8 < nb);
-                const float val = FL[s][k];
+                float val = 0.f;
+#pragma unroll
+                for (int c = 0; c < FT_NC; c++) {
+                    val += FL[c][s][k];
+                    FL[c][s][k] = 0.f;
+                }
                 if (have && val != 0.f) atomicAdd(&A.F[(size_t)(s < 8 ? ca + s : cb + (s - 8)) * 20 + k], val);
-                FL[s][k] = 0.f;
             }
             fm_sync();
         }
