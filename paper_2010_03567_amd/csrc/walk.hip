@@ -184,7 +184,7 @@ __device__ __forceinline__ void lds_add(double *p, double v)
 }
 
 // 64 particle-node interactions from the node ring, one per lane (lanes >= n idle).
-template <int KER, bool POT>
+template <int KER, bool POT, bool ORD3>
 __device__ __forceinline__ void eval_p2m(const WalkArgs &A, WaveLds<POT> &W, uint32_t head, uint32_t n, int lane)
 {
     if ((uint32_t)lane >= n) return;
@@ -211,7 +211,7 @@ __device__ __forceinline__ void eval_p2m(const WalkArgs &A, WaveLds<POT> &W, uin
     const float rqr = fmaf(dx, qx, fmaf(dy, qy, dz * qz));
     const float tr = qa.x + qa.w + qb.y;
     // the node's contribution is -(fx, fy, fz): the sign goes into the FP64 conversion below
-    if (A.order >= 3) {
+    if (ORD3) {
         const float fac = fmaf(mass, g1, 0.5f * fmaf(g2, tr, g3 * rqr));
         fx = fmaf(fac, dx, g2 * qx);
         fy = fmaf(fac, dy, g2 * qy);
@@ -240,7 +240,8 @@ __device__ __forceinline__ void eval_p2m(const WalkArgs &A, WaveLds<POT> &W, uin
     if constexpr (POT) lds_add(&W.acc[3][t], -(double)fp);
 }
 
-template <int KER, int CRIT, bool POT>
+// ORD3: p = 3, the force includes the quadrupole term (p = 2: monopole force)
+template <int KER, int CRIT, bool POT, bool ORD3>
 __global__ __launch_bounds__(256) void k_walk(const WalkArgs A)
 {
     __shared__ WaveLds<POT> lds[4];
@@ -390,7 +391,7 @@ __global__ __launch_bounds__(256) void k_walk(const WalkArgs A)
             r.cz = nd.cz;
             if (level == 0) r.crit = __builtin_huge_valf();
             else if (CRIT == 0) r.crit = l * l;
-            else r.crit = nd.mass * (A.order >= 3 ? l * l * l : l * l);
+            else r.crit = nd.mass * (ORD3 ? l * l * l : l * l);
             r.gx = nd.gx;
             r.gy = nd.gy;
             r.gz = nd.gz;
@@ -437,7 +438,7 @@ __global__ __launch_bounds__(256) void k_walk(const WalkArgs A)
                 accept = accept && (R.crit < A.theta2 * r2);
             } else {
                 // M (l/r)^p / r^2 < alpha |a|  <=>  M l^p < alpha |a| r^(p+2)
-                const float rp = A.order >= 3 ? r2 * r2 * r2 * rinv : r2 * r2;
+                const float rp = ORD3 ? r2 * r2 * r2 * rinv : r2 * r2;
                 accept = accept && (R.crit < __uint_as_float(T.w) * rp);
             }
             const bool use = ok && accept;
@@ -471,7 +472,7 @@ __global__ __launch_bounds__(256) void k_walk(const WalkArgs A)
             w_pass++;
             if (pm_t - pm_h >= 64) {
                 wave_sync_lds();
-                eval_p2m<KER, POT>(A, W, pm_h, 64u, lane);
+                eval_p2m<KER, POT, ORD3>(A, W, pm_h, 64u, lane);
                 pm_h += 64;
                 w_pm++;
             }
@@ -512,7 +513,7 @@ __global__ __launch_bounds__(256) void k_walk(const WalkArgs A)
     wave_sync_lds();
     while (pm_t != pm_h) {
         const uint32_t n = min(pm_t - pm_h, 64u);
-        eval_p2m<KER, POT>(A, W, pm_h, n, lane);
+        eval_p2m<KER, POT, ORD3>(A, W, pm_h, n, lane);
         pm_h += n;
         w_pm++;
     }
@@ -568,7 +569,8 @@ static void launch_walk(const WalkArgs &A, hipStream_t s)
     int64_t blocks = ((int64_t)A.nitems + 3) / 4;
     if (blocks > A.spill_waves / 4) blocks = A.spill_waves / 4;
     if (blocks < 1) blocks = 1;
-    k_walk<KER, CRIT, POT><<<(unsigned)blocks, 256, 0, s>>>(A);
+    if (A.order >= 3) k_walk<KER, CRIT, POT, true><<<(unsigned)blocks, 256, 0, s>>>(A);
+    else k_walk<KER, CRIT, POT, false><<<(unsigned)blocks, 256, 0, s>>>(A);
 }
 
 // Cubic Hermite pieces of S_0..S_3 (see pair_kernel_tab) on n intervals of
