@@ -1,5 +1,5 @@
 // direct.hip -- direct summation on the device, FP64 throughout: the exact
-// reference against which the paper judges every force algorithm (Sec.
+// reference against which the paper measures every force algorithm (Sec.
 // "Softened potential in periodic systems").  Kernel 0: spline-softened
 // Newtonian; kernel 1: the short-range force of eq. (eqnpo4) over the nearest
 // image only, optionally truncated at r_cut.  One thread per target; source
