@@ -283,7 +283,7 @@ def main():
         "learned": learned,
         "errors": {"vs_direct_untruncated": calib[alpha], "sample": int(len(tg_np)),
                    "alpha_calibration": {str(k): v["p99"] for k, v in calib.items()}},
-        "roofline": {"bound": "alu", "kernel": "k_walk<1,1,false> (relative TreePM walk)", "achieved": achieved / 1e12,
+        "roofline": {"bound": "alu", "kernel": "k_walk<1,1,false,true> (relative TreePM walk, p = 3)", "achieved": achieved / 1e12,
                      "peak": PEAK_FP32_VECTOR / 1e12, "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_VECTOR,
                      "traffic": traffic, "avg_ms": rwalk_ms, "flop_per_launch": walk_flop,
                      "variant": "learned" if best_learned else "plain", "alpha": ralpha},
