@@ -210,27 +210,62 @@ __device__ __forceinline__ void put(uint64_t *key, uint32_t *val, uint32_t at, c
     val[at] = src;
 }
 
-// wavefront-aggregated append: returns this lane's base index
-__device__ __forceinline__ uint32_t wave_append(uint32_t *counter, uint32_t n)
+
+// Block-aggregated append to three counters at once (all 256 threads call it):
+// one atomic per counter and block instead of per wavefront, since every
+// block appends to the same three counters and same-address atomics are
+// serialised across the chip.  Returns this thread's base index in each list.
+__device__ __forceinline__ uint3 block_append3(uint32_t *c0, uint32_t *c1, uint32_t *c2, uint32_t n0, uint32_t n1,
+                                               uint32_t n2)
 {
-    const int lane = threadIdx.x & 63;
-    uint32_t incl = n;
+    __shared__ uint32_t wsum[4][3], base[3];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    uint32_t i0 = n0, i1 = n1, i2 = n2;  // inclusive scans within the wavefront
     for (int off = 1; off < 64; off <<= 1) {
-        const uint32_t v = __shfl_up(incl, off);
-        if (lane >= off) incl += v;
+        const uint32_t v0 = __shfl_up(i0, off), v1 = __shfl_up(i1, off), v2 = __shfl_up(i2, off);
+        if (lane >= off) {
+            i0 += v0;
+            i1 += v1;
+            i2 += v2;
+        }
     }
-    const uint32_t total = __shfl(incl, 63);
-    uint32_t base = 0;
-    if (lane == 63 && total) base = atomicAdd(counter, total);
-    base = __shfl(base, 63);
-    return base + incl - n;
+    if (lane == 63) {
+        wsum[wv][0] = i0;
+        wsum[wv][1] = i1;
+        wsum[wv][2] = i2;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const uint32_t t0 = wsum[0][0] + wsum[1][0] + wsum[2][0] + wsum[3][0];
+        const uint32_t t1 = wsum[0][1] + wsum[1][1] + wsum[2][1] + wsum[3][1];
+        const uint32_t t2 = wsum[0][2] + wsum[1][2] + wsum[2][2] + wsum[3][2];
+        base[0] = t0 ? atomicAdd(c0, t0) : 0u;
+        base[1] = t1 ? atomicAdd(c1, t1) : 0u;
+        base[2] = t2 ? atomicAdd(c2, t2) : 0u;
+    }
+    __syncthreads();
+    uint32_t b0 = base[0], b1 = base[1], b2 = base[2];
+    for (int w = 0; w < wv; w++) {
+        b0 += wsum[w][0];
+        b1 += wsum[w][1];
+        b2 += wsum[w][2];
+    }
+    __syncthreads();  // wsum and base are reused by the next call
+    return make_uint3(b0 + i0 - n0, b1 + i1 - n1, b2 + i2 - n2);
 }
 
 __global__ __launch_bounds__(256) void k_fmm_traverse(FmmArgs A)
 {
-    // after an overflow the lists are incomplete: stop touching them
-    if (A.cnt[4]) return;
+    // after an overflow the lists are incomplete: stop touching them (decided once per
+    // block, since every thread of the block must reach the barriers of the appends)
+    __shared__ uint32_t s_over;
+    if (threadIdx.x == 0) s_over = A.cnt[4];
+    __syncthreads();
+    if (s_over) return;
     const uint32_t nin = min(A.cnt[0], A.cap_pairs);
+    // interaction counters: particle pairs, particle-node, node-node (summed over the loop,
+    // one atomic per wavefront at the end)
+    unsigned long long c_pp = 0, c_pn = 0, c_nn = 0;
     for (uint32_t base = blockIdx.x * blockDim.x; base < nin; base += gridDim.x * blockDim.x) {
         const uint32_t t = base + threadIdx.x;
         Act X;
@@ -240,26 +275,13 @@ __global__ __launch_bounds__(256) void k_fmm_traverse(FmmArgs A)
             const uint2 pr = A.fin[t];
             X = classify(A, pr.x, pr.y);
         }
-        const uint32_t op = wave_append(&A.cnt[1], X.n_pairs);
-        const uint32_t on = wave_append(&A.cnt[2], X.n_node);
-        const uint32_t ok = wave_append(&A.cnt[3], X.n_part);
-        // interaction counters: particle pairs, particle-node, node-node (one atomic per wavefront)
-        unsigned long long c_pp = 0, c_pn = 0, c_nn = 0;
-        if (X.kind == ACT_PP) c_pp = 1;
-        if (X.kind == ACT_OPEN_PP) c_pp = (unsigned long long)X.na * X.nb;
-        if (X.kind == ACT_SELF_LEAF) c_pp = (unsigned long long)X.a.num * (X.a.num - 1) / 2;
-        if (X.kind == ACT_PN) c_pn = 1;
-        if (X.kind == ACT_NN) c_nn = 1;
-        for (int off = 32; off > 0; off >>= 1) {
-            c_pp += __shfl_xor(c_pp, off);
-            c_pn += __shfl_xor(c_pn, off);
-            c_nn += __shfl_xor(c_nn, off);
-        }
-        if ((threadIdx.x & 63) == 0) {
-            if (c_pp) atomicAdd(&A.stat[0], c_pp);
-            if (c_pn) atomicAdd(&A.stat[1], c_pn);
-            if (c_nn) atomicAdd(&A.stat[2], c_nn);
-        }
+        const uint3 off3 = block_append3(&A.cnt[1], &A.cnt[2], &A.cnt[3], X.n_pairs, X.n_node, X.n_part);
+        const uint32_t op = off3.x, on = off3.y, ok = off3.z;
+        if (X.kind == ACT_PP) c_pp += 1;
+        if (X.kind == ACT_OPEN_PP) c_pp += (unsigned long long)X.na * X.nb;
+        if (X.kind == ACT_SELF_LEAF) c_pp += (unsigned long long)X.a.num * (X.a.num - 1) / 2;
+        if (X.kind == ACT_PN) c_pn += 1;
+        if (X.kind == ACT_NN) c_nn += 1;
         if (t >= nin) continue;
         if ((uint64_t)op + X.n_pairs > A.cap_pairs || (uint64_t)on + X.n_node > A.cap_node ||
             (uint64_t)ok + X.n_part > A.cap_part) {
@@ -309,6 +331,16 @@ __global__ __launch_bounds__(256) void k_fmm_traverse(FmmArgs A)
         default:
             break;
         }
+    }
+    for (int off = 32; off > 0; off >>= 1) {
+        c_pp += __shfl_xor(c_pp, off);
+        c_pn += __shfl_xor(c_pn, off);
+        c_nn += __shfl_xor(c_nn, off);
+    }
+    if ((threadIdx.x & 63) == 0) {
+        if (c_pp) atomicAdd(&A.stat[0], c_pp);
+        if (c_pn) atomicAdd(&A.stat[1], c_pn);
+        if (c_nn) atomicAdd(&A.stat[2], c_nn);
     }
 }
 
