@@ -745,16 +745,6 @@ __device__ __forceinline__ void fm_sync()
     __builtin_amdgcn_wave_barrier();
 }
 
-// Wavefront-aggregated append of one item per lane that wants it (call with
-// all lanes active): this lane's slot.
-__device__ __forceinline__ uint32_t fm_push(uint32_t *counter, bool want)
-{
-    const uint64_t m = fm_ballot(want);
-    uint32_t b = 0;
-    if (m && (threadIdx.x & 63) == 0) b = atomicAdd(counter, (uint32_t)__builtin_popcountll(m));
-    return fm_uni(b) + fm_below(m);
-}
-
 // Two nodes: 0 dropped (beyond r_cut), 1 interact, 2 open.  Same arithmetic
 // as classify() above; r = s_b - s_a.
 __device__ __forceinline__ int fm_classify(const FastArgs &A, const WNode &a, const WNode &b, float r[3], float &r2)
