@@ -886,14 +886,25 @@ __global__ __launch_bounds__(256) void k_fast_open(FastArgs A)
         const bool inter = act == 1;
         const uint64_t im = fm_ballot(inter);
         if (im) {
-            if (inter) {
-                float g0, g1, g2, g3;
-                gfun_f(A.kernel, r2, A.asplit, g0, g1, g2, g3);
-                float f[20], q2[6], q3[10];
-                const float mr[3] = {-r[0], -r[1], -r[2]};
-                // daughter i sees daughter j at +r ...
+            // The two expansions of each interacting pair are summed per daughter with LDS float
+            // atomics, which serialise on one address.  Neighbouring lanes that add to the same
+            // daughter first combine their expansions (one cross-lane move within a row of 16):
+            // (i, j) and (i, j + 1) for side i of a pair of distinct nodes, (i, j) and (i + 1, j)
+            // for side j of a node with itself.
+            const bool nb_inter = (im >> ((lane + 1) & 63)) & 1ull;
+            const bool row_next = (lane & 15) != 15, row_prev = (lane & 15) != 0;
+            const bool takeA = !self && valid && (j & 1u) == 0 && j + 1 < nb && row_next;
+            const bool giveA = !self && valid && (j & 1u) == 1 && row_prev;
+            const bool takeB = self && valid && (i & 1u) == 0 && i + 1 <= j && row_next;
+            const bool giveB = self && valid && (i & 1u) == 1 && row_prev;
+            float g0 = 0.f, g1 = 0.f, g2 = 0.f, g3 = 0.f;
+            if (inter) gfun_f(A.kernel, r2, A.asplit, g0, g1, g2, g3);
+            float f[20], q2[6], q3[10];
+            const float mr[3] = {-r[0], -r[1], -r[2]};
+            // daughter i sees daughter j at +r ...
 #pragma unroll
-                for (int k = 0; k < 20; k++) f[k] = 0.f;
+            for (int k = 0; k < 20; k++) f[k] = 0.f;
+            if (inter) {
 #pragma unroll
                 for (int k = 0; k < 6; k++) q2[k] = w2.q[k];
                 if (POT) {
@@ -901,11 +912,24 @@ __global__ __launch_bounds__(256) void k_fast_open(FastArgs A)
                     for (int k = 0; k < 10; k++) q3[k] = A.q3[(size_t)(cb + j) * 10 + k];
                 }
                 add_field_f(f, r, g0, g1, g2, g3, w2.mass, q2, POT ? q3 : nullptr);
+            }
+            if (!self) {
 #pragma unroll
-                for (int k = 0; k < 20; k++) atomicAdd(&FL[j % FT_NC][i][k], f[k]);
-                // ... and j sees i at -r (the mirrored expansion)
+                for (int k = 0; k < 20; k++) {
+                    const float o = __int_as_float(
+                        __builtin_amdgcn_update_dpp(0, __float_as_int(f[k]), 0x101, 0xf, 0xf, false));  // lane + 1
+                    if (takeA) f[k] += o;
+                }
+            }
+            if (self ? inter : ((inter || (takeA && nb_inter)) && !giveA)) {
+                const uint32_t cA = (self ? j : j >> 1) % FT_NC;
 #pragma unroll
-                for (int k = 0; k < 20; k++) f[k] = 0.f;
+                for (int k = 0; k < 20; k++) atomicAdd(&FL[cA][i][k], f[k]);
+            }
+            // ... and j sees i at -r (the mirrored expansion)
+#pragma unroll
+            for (int k = 0; k < 20; k++) f[k] = 0.f;
+            if (inter) {
 #pragma unroll
                 for (int k = 0; k < 6; k++) q2[k] = w1.q[k];
                 if (POT) {
@@ -913,9 +937,20 @@ __global__ __launch_bounds__(256) void k_fast_open(FastArgs A)
                     for (int k = 0; k < 10; k++) q3[k] = A.q3[(size_t)(ca + i) * 10 + k];
                 }
                 add_field_f(f, mr, g0, g1, g2, g3, w1.mass, q2, POT ? q3 : nullptr);
-                const uint32_t sj = self ? j : 8 + j;
+            }
+            if (self) {
 #pragma unroll
-                for (int k = 0; k < 20; k++) atomicAdd(&FL[i % FT_NC][sj][k], f[k]);
+                for (int k = 0; k < 20; k++) {
+                    const float o = __int_as_float(
+                        __builtin_amdgcn_update_dpp(0, __float_as_int(f[k]), 0x101, 0xf, 0xf, false));  // lane + 1
+                    if (takeB) f[k] += o;
+                }
+            }
+            if (self ? ((inter || (takeB && nb_inter)) && !giveB) : inter) {
+                const uint32_t sj = self ? j : 8 + j;
+                const uint32_t cB = (self ? i >> 1 : i) % FT_NC;
+#pragma unroll
+                for (int k = 0; k < 20; k++) atomicAdd(&FL[cB][sj][k], f[k]);
             }
             c_nn += (uint32_t)__builtin_popcountll(im);
             fm_sync();
