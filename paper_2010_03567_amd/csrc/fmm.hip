@@ -834,6 +834,23 @@ __device__ __forceinline__ void st_flush(Stage<CAP> &S, bool final, uint2 *out, 
     }
 }
 
+// value of lane + S within this lane's row of 16 (0 past the row's end): DPP row_shl
+template <int S>
+__device__ __forceinline__ uint32_t fm_from_next(uint32_t v)
+{
+    return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x100 + S, 0xf, 0xf, false);
+}
+// adds the expansions of lane + S to this lane's where it takes them (bit B of take)
+template <int S, int B>
+__device__ __forceinline__ void fm_combine(float f[20], uint32_t take)
+{
+#pragma unroll
+    for (int k = 0; k < 20; k++) {
+        const float o = __uint_as_float(fm_from_next<S>(__float_as_uint(f[k])));
+        if ((take >> B) & 1u) f[k] += o;
+    }
+}
+
 template <bool POT>
 __global__ __launch_bounds__(256) void k_fast_open(FastArgs A)
 {
@@ -887,16 +904,26 @@ __global__ __launch_bounds__(256) void k_fast_open(FastArgs A)
         const uint64_t im = fm_ballot(inter);
         if (im) {
             // The two expansions of each interacting pair are summed per daughter with LDS float
-            // atomics, which serialise on one address.  Neighbouring lanes that add to the same
-            // daughter first combine their expansions (one cross-lane move within a row of 16):
-            // (i, j) and (i, j + 1) for side i of a pair of distinct nodes, (i, j) and (i + 1, j)
-            // for side j of a node with itself.
-            const bool nb_inter = (im >> ((lane + 1) & 63)) & 1ull;
-            const bool row_next = (lane & 15) != 15, row_prev = (lane & 15) != 0;
-            const bool takeA = !self && valid && (j & 1u) == 0 && j + 1 < nb && row_next;
-            const bool giveA = !self && valid && (j & 1u) == 1 && row_prev;
-            const bool takeB = self && valid && (i & 1u) == 0 && i + 1 <= j && row_next;
-            const bool giveB = self && valid && (i & 1u) == 1 && row_prev;
+            // atomics, which serialise on one address.  Lanes that add to the same daughter and
+            // sit next to each other first combine their expansions by a tree of cross-lane
+            // moves within rows of 16 lanes: the pairs (i, j), (i, j + 1), ... for side i of a
+            // pair of distinct nodes, (i, j), (i + 1, j), ... for side j of a node with itself.
+            // m is the pair's position in that run, n the run's length.
+            const uint32_t cm = self ? i : j, cn = self ? j + 1 : nb;
+            const bool comb = valid;
+            uint32_t lvl_take = 0, anyi = inter ? 1u : 0u;  // bit s: took at distance 2^s
+            bool given = false;
+            auto level = [&](uint32_t st, uint32_t b, uint32_t nbr) {
+                const bool take = comb && !given && (cm % (2 * st)) == 0 && cm + st < cn && (lane & 15) + st <= 15;
+                if (comb && !given && (cm % (2 * st)) == st && (uint32_t)(lane & 15) >= st) given = true;
+                if (take) {
+                    lvl_take |= 1u << b;
+                    anyi |= nbr;
+                }
+            };
+            level(1, 0, fm_from_next<1>(anyi));
+            level(2, 1, fm_from_next<2>(anyi));
+            level(4, 2, fm_from_next<4>(anyi));
             float g0 = 0.f, g1 = 0.f, g2 = 0.f, g3 = 0.f;
             if (inter) gfun_f(A.kernel, r2, A.asplit, g0, g1, g2, g3);
             float f[20], q2[6], q3[10];
@@ -914,14 +941,11 @@ __global__ __launch_bounds__(256) void k_fast_open(FastArgs A)
                 add_field_f(f, r, g0, g1, g2, g3, w2.mass, q2, POT ? q3 : nullptr);
             }
             if (!self) {
-#pragma unroll
-                for (int k = 0; k < 20; k++) {
-                    const float o = __int_as_float(
-                        __builtin_amdgcn_update_dpp(0, __float_as_int(f[k]), 0x101, 0xf, 0xf, false));  // lane + 1
-                    if (takeA) f[k] += o;
-                }
+                fm_combine<1, 0>(f, lvl_take);
+                fm_combine<2, 1>(f, lvl_take);
+                fm_combine<4, 2>(f, lvl_take);
             }
-            if (self ? inter : ((inter || (takeA && nb_inter)) && !giveA)) {
+            if (self ? inter : (anyi && !given)) {
                 const uint32_t cA = (self ? j : j >> 1) % FT_NC;
 #pragma unroll
                 for (int k = 0; k < 20; k++) atomicAdd(&FL[cA][i][k], f[k]);
@@ -939,14 +963,11 @@ __global__ __launch_bounds__(256) void k_fast_open(FastArgs A)
                 add_field_f(f, mr, g0, g1, g2, g3, w1.mass, q2, POT ? q3 : nullptr);
             }
             if (self) {
-#pragma unroll
-                for (int k = 0; k < 20; k++) {
-                    const float o = __int_as_float(
-                        __builtin_amdgcn_update_dpp(0, __float_as_int(f[k]), 0x101, 0xf, 0xf, false));  // lane + 1
-                    if (takeB) f[k] += o;
-                }
+                fm_combine<1, 0>(f, lvl_take);
+                fm_combine<2, 1>(f, lvl_take);
+                fm_combine<4, 2>(f, lvl_take);
             }
-            if (self ? ((inter || (takeB && nb_inter)) && !giveB) : inter) {
+            if (self ? (anyi && !given) : inter) {
                 const uint32_t sj = self ? j : 8 + j;
                 const uint32_t cB = (self ? i >> 1 : i) % FT_NC;
 #pragma unroll
