@@ -924,14 +924,22 @@ __global__ __launch_bounds__(256) void k_fast_open(FastArgs A)
             level(1, 0, fm_from_next<1>(anyi));
             level(2, 1, fm_from_next<2>(anyi));
             level(4, 2, fm_from_next<4>(anyi));
-            // the other side's pairs of one daughter are not adjacent: one step of pairing,
-            // the pair at position m even taking position m + 1 (a lane-indexed move)
+            // the other side's pairs of one daughter are not adjacent: two steps of a tree of
+            // lane-indexed moves, the pair at position m taking position m + 1 (m even), then
+            // m + 2 (m a multiple of 4)
             const uint32_t sm = self ? j - i : i, sn = self ? na - i : na;
-            const uint32_t s_src = self ? (uint32_t)lane + j + 1 : (uint32_t)lane + nb;
-            const bool s_take = valid && (sm & 1u) == 0 && sm + 1 < sn;
-            const bool s_give = valid && (sm & 1u) == 1;
-            const int s_lane = (int)(s_take ? s_src : (uint32_t)lane);
-            const bool s_inter = __shfl((int)(inter ? 1 : 0), s_lane) != 0;
+            const uint32_t s_src1 = self ? (uint32_t)lane + j + 1 : (uint32_t)lane + nb;
+            const uint32_t s_src2 = self ? (uint32_t)lane + 2 * j + 3 : (uint32_t)lane + 2 * nb;
+            const bool s_take1 = valid && (sm & 1u) == 0 && sm + 1 < sn;
+            const bool s_take2 = valid && (sm & 3u) == 0 && sm + 2 < sn;
+            const bool s_give = valid && (sm & 3u) != 0;
+            const int s_lane1 = (int)(s_take1 ? s_src1 : (uint32_t)lane);
+            const int s_lane2 = (int)(s_take2 ? s_src2 : (uint32_t)lane);
+            int s_any = inter ? 1 : 0;
+            const int s_any1 = __shfl(s_any, s_lane1);  // every lane takes part in the moves
+            if (s_take1) s_any |= s_any1;
+            const int s_any2 = __shfl(s_any, s_lane2);
+            if (s_take2) s_any |= s_any2;
             float g0 = 0.f, g1 = 0.f, g2 = 0.f, g3 = 0.f;
             if (inter) gfun_f(A.kernel, r2, A.asplit, g0, g1, g2, g3);
             float f[20], q2[6], q3[10];
@@ -955,12 +963,17 @@ __global__ __launch_bounds__(256) void k_fast_open(FastArgs A)
             } else {
 #pragma unroll
                 for (int k = 0; k < 20; k++) {
-                    const float o = __shfl(f[k], s_lane);
-                    if (s_take) f[k] += o;
+                    const float o = __shfl(f[k], s_lane1);
+                    if (s_take1) f[k] += o;
+                }
+#pragma unroll
+                for (int k = 0; k < 20; k++) {
+                    const float o = __shfl(f[k], s_lane2);
+                    if (s_take2) f[k] += o;
                 }
             }
-            if (self ? ((inter || (s_take && s_inter)) && !s_give) : (anyi && !given)) {
-                const uint32_t cA = (self ? sm >> 1 : j >> 1) % FT_NC;
+            if (self ? (s_any && !s_give) : (anyi && !given)) {
+                const uint32_t cA = (self ? sm >> 2 : j >> 1) % FT_NC;
 #pragma unroll
                 for (int k = 0; k < 20; k++) atomicAdd(&FL[cA][i][k], f[k]);
             }
@@ -983,13 +996,18 @@ __global__ __launch_bounds__(256) void k_fast_open(FastArgs A)
             } else {
 #pragma unroll
                 for (int k = 0; k < 20; k++) {
-                    const float o = __shfl(f[k], s_lane);
-                    if (s_take) f[k] += o;
+                    const float o = __shfl(f[k], s_lane1);
+                    if (s_take1) f[k] += o;
+                }
+#pragma unroll
+                for (int k = 0; k < 20; k++) {
+                    const float o = __shfl(f[k], s_lane2);
+                    if (s_take2) f[k] += o;
                 }
             }
-            if (self ? (anyi && !given) : ((inter || (s_take && s_inter)) && !s_give)) {
+            if (self ? (anyi && !given) : (s_any && !s_give)) {
                 const uint32_t sj = self ? j : 8 + j;
-                const uint32_t cB = (self ? i >> 1 : i >> 1) % FT_NC;
+                const uint32_t cB = (self ? i >> 1 : i >> 2) % FT_NC;
 #pragma unroll
                 for (int k = 0; k < 20; k++) atomicAdd(&FL[cB][sj][k], f[k]);
             }
