@@ -51,8 +51,8 @@ def parse():
     ap.add_argument("--no-learned", action="store_true")
     ap.add_argument("--weights", type=str, default="", help="learned-seed weights (.npz); default by particle count")
     ap.add_argument("--no-fmm", action="store_true")
-    ap.add_argument("--fmm-leaf", type=int, default=48,
-                    help="leaf size of the second, tuned FMM line (48: fastest of 8-96 at theta 0.5 on this box; "
+    ap.add_argument("--fmm-leaf", type=int, default=32,
+                    help="leaf size of the second, tuned FMM line (32: fastest of 8-96 at theta 0.5 on this box; "
                          "the first line keeps the configuration's leaf 16)")
     ap.add_argument("--no-forest", action="store_true")
     ap.add_argument("--no-large", action="store_true", help="skip the learned-vs-plain comparison at 256^3")
