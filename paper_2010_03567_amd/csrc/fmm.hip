@@ -1238,10 +1238,15 @@ __device__ __forceinline__ void fm_deposit(const FastArgs &A, uint32_t j, float 
     if (POT) atomicAdd(a + 3, (double)fp);
 }
 
-// sum of v over each aligned 16-lane group, in every lane of the group
-__device__ __forceinline__ float fm_gsum(float v)
+// sum of v over each aligned 16-lane group (a DPP row), in the group's first lane; the
+// other lanes end with partial sums.  Four row shifts with the adds, no LDS traffic; every
+// lane of the wavefront must be active.
+__device__ __forceinline__ float fm_gsum0(float v)
 {
-    for (int off = 8; off > 0; off >>= 1) v += __shfl_xor(v, off);
+    v += __uint_as_float(fm_from_next<1>(__float_as_uint(v)));
+    v += __uint_as_float(fm_from_next<2>(__float_as_uint(v)));
+    v += __uint_as_float(fm_from_next<4>(__float_as_uint(v)));
+    v += __uint_as_float(fm_from_next<8>(__float_as_uint(v)));
     return v;
 }
 // this lane's group's 16 bits of a wavefront mask
@@ -1390,7 +1395,7 @@ __global__ __launch_bounds__(256) void k_fast_ln(FastArgs A, uint32_t npairs)
                 n_pn++;
             }
 #pragma unroll
-            for (int q = 0; q < 20; q++) pf[q] = fm_gsum(pf[q]);
+            for (int q = 0; q < 20; q++) pf[q] = fm_gsum0(pf[q]);  // read by lane 0 of the group
             const bool gi = fm_gbits(im, g) != 0;
             if (gi && gl == 0) {
 #pragma unroll
