@@ -1423,8 +1423,12 @@ __global__ __launch_bounds__(256) void k_fast_ln(FastArgs A, uint32_t npairs)
                     tpos[wv][lane] = make_uint4(me.x, me.y, me.z, __float_as_uint(mt));
                 }
                 // the longest opened leaf of the wavefront
-                uint32_t nmax = gleaf ? w.num : 0u;
-                for (int off = 32; off > 0; off >>= 1) nmax = max(nmax, (uint32_t)__shfl_xor((int)nmax, off));
+                // (the node and gleaf are uniform within a group: one lane of each group suffices)
+                const uint32_t nl = gleaf ? w.num : 0u;
+                const uint32_t nmax = max(max((uint32_t)__builtin_amdgcn_readlane((int)nl, 0),
+                                              (uint32_t)__builtin_amdgcn_readlane((int)nl, 16)),
+                                          max((uint32_t)__builtin_amdgcn_readlane((int)nl, 32),
+                                              (uint32_t)__builtin_amdgcn_readlane((int)nl, 48)));
                 const uint32_t gk = gleaf ? (uint32_t)__builtin_popcount(om16) : 0u;
                 for (uint32_t b0 = 0; b0 < nmax; b0 += FT_SB) {
                     const uint32_t nb = gleaf && b0 < w.num ? min(w.num - b0, (uint32_t)FT_SB) : 0u;
