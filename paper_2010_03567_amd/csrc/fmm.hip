@@ -1042,12 +1042,31 @@ __global__ __launch_bounds__(256) void k_fast_open(FastArgs A)
 }
 
 // ---- partner lists of the leaf pairs: count, exclusive scan, scatter
-__global__ void k_ll_count(const uint2 *__restrict__ ll, uint32_t n, uint32_t *__restrict__ cnt)
+// The dual walk emits the pairs of one leaf close together, so neighbouring lanes often
+// name the same leaf: each run of equal values in consecutive lanes makes one atomic.
+// ll_run gives the first and last lane of this lane's run; all 64 lanes must be active.
+__device__ __forceinline__ void ll_run(uint32_t v, int lane, int &first, int &last)
 {
-    for (uint32_t k = blockIdx.x * blockDim.x + threadIdx.x; k < n; k += gridDim.x * blockDim.x) {
-        const uint2 p = ll[k];
-        atomicAdd(&cnt[p.x], 1u);
-        atomicAdd(&cnt[p.y], 1u);
+    const uint32_t up = (uint32_t)__shfl_up((int)v, 1), dn = (uint32_t)__shfl_down((int)v, 1);
+    const uint64_t heads = __builtin_amdgcn_ballot_w64(lane == 0 || up != v);
+    const uint64_t tails = __builtin_amdgcn_ballot_w64(lane == 63 || dn != v);
+    first = 63 - __builtin_clzll(heads & ((2ull << lane) - 1ull));  // lane 0 is always a head
+    last = __builtin_ctzll(tails & ~((1ull << lane) - 1ull));       // lane 63 is always a tail
+}
+
+// loops run over whole blocks (uniform), so every lane takes part in the run detection;
+// lanes past the end hold ~0, which no leaf index equals
+__global__ __launch_bounds__(256) void k_ll_count(const uint2 *__restrict__ ll, uint32_t n, uint32_t *__restrict__ cnt)
+{
+    const int lane = threadIdx.x & 63;
+    for (uint32_t b = blockIdx.x * blockDim.x; b < n; b += gridDim.x * blockDim.x) {
+        const uint32_t k = b + threadIdx.x;
+        const uint2 p = k < n ? ll[k] : make_uint2(~0u, ~0u);
+        int f, l;
+        ll_run(p.x, lane, f, l);
+        if (k < n && lane == l) atomicAdd(&cnt[p.x], (uint32_t)(l - f + 1));
+        ll_run(p.y, lane, f, l);
+        if (k < n && lane == l) atomicAdd(&cnt[p.y], (uint32_t)(l - f + 1));
     }
 }
 
@@ -1111,13 +1130,25 @@ __global__ void k_scan_add(uint32_t *__restrict__ v, uint32_t m, const uint32_t 
     }
 }
 
-__global__ void k_ll_scatter(const uint2 *__restrict__ ll, uint32_t n, uint32_t *__restrict__ cursor,
-                             uint32_t *__restrict__ plist)
+// the last lane of a run reserves the run's slots; the run's lanes fill them in lane order
+__global__ __launch_bounds__(256) void k_ll_scatter(const uint2 *__restrict__ ll, uint32_t n,
+                                                    uint32_t *__restrict__ cursor, uint32_t *__restrict__ plist)
 {
-    for (uint32_t k = blockIdx.x * blockDim.x + threadIdx.x; k < n; k += gridDim.x * blockDim.x) {
-        const uint2 p = ll[k];
-        plist[atomicAdd(&cursor[p.x], 1u)] = p.y;
-        plist[atomicAdd(&cursor[p.y], 1u)] = p.x;
+    const int lane = threadIdx.x & 63;
+    for (uint32_t b = blockIdx.x * blockDim.x; b < n; b += gridDim.x * blockDim.x) {
+        const uint32_t k = b + threadIdx.x;
+        const uint2 p = k < n ? ll[k] : make_uint2(~0u, ~0u);
+        int f, l;
+        uint32_t o = 0;
+        ll_run(p.x, lane, f, l);
+        if (k < n && lane == l) o = atomicAdd(&cursor[p.x], (uint32_t)(l - f + 1));
+        o = (uint32_t)__shfl((int)o, l);
+        if (k < n) plist[o + (uint32_t)(lane - f)] = p.y;
+        o = 0;
+        ll_run(p.y, lane, f, l);
+        if (k < n && lane == l) o = atomicAdd(&cursor[p.y], (uint32_t)(l - f + 1));
+        o = (uint32_t)__shfl((int)o, l);
+        if (k < n) plist[o + (uint32_t)(lane - f)] = p.x;
     }
 }
 
