@@ -121,8 +121,14 @@ typedef struct {
     int deterministic;
 } g4_fmm_params;
 
-/* Counters filled by the force calls (host struct). */
+/* Counters and phase times filled by the force calls (host struct).
+ * t_build, t_moments: duration of the tree's last g4_build_tree /
+ * g4_build_forest and g4_compute_multipoles (HIP events on the context's
+ * stream); t_seed: the geometric pre-walk, or the gather of a caller's
+ * a_seed, of this call (0 for a geometric call); t_walk: this call's walk, or
+ * the whole FMM of g4_fmm_force.  Seconds. */
 typedef struct {
+    double t_build, t_moments, t_seed, t_walk;
     uint64_t n_p2p;      /* particle-particle interactions */
     uint64_t n_p2m;      /* particle-node (one-sided) interactions */
     uint64_t n_visit;    /* node visits by active lanes (criterion evaluations) */
@@ -132,7 +138,14 @@ typedef struct {
     /* 64-lane steps of the walk: node visits, particle-node interactions,
      * particle-particle interactions; lane utilisation = count / (64 x steps) */
     uint64_t w_pop, w_p2m, w_p2p;
-    uint32_t flags;      /* bit 0: a leaf at max_depth holds more than leaf_max particles */
+    /* bit 0: a leaf at max_depth holds more than leaf_max particles;
+     * bit 1: node capacity exceeded (cannot happen within the documented sizes);
+     * bit 2: a walk's traversal stack overflowed, forces incomplete;
+     * bit 3: an FMM leaf-node stack overflowed, forces incomplete.
+     * Bits 2 and 3 stay set until the tree is rebuilt and make the force call
+     * that reads them (any call with stats, every g4_fmm_force) and
+     * g4_tree_info return G4_ENOMEM. */
+    uint32_t flags;
     uint32_t max_stack;  /* deepest traversal stack of the walk (entries; the top 32 are kept in LDS) */
     /* walk bookkeeping: sibling sets popped, (opened leaf, target) items,
      * particle-pair phases of the lane queue */

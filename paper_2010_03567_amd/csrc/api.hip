@@ -19,6 +19,41 @@ static int check_tp(g4_ctx *ctx, const g4_tree_params *tp)
 static int g4_build_tree_views(g4_ctx *ctx, const g4_particles *p, const g4_tree_params *tp, void *ws,
                                const WsLayout *Lp, g4_tree **out);
 
+int g4_phase_begin(g4_ctx *ctx, g4_tree *t, int k)
+{
+    if (!t->ev_made) {
+        for (int e = 0; e < 8; e++) G4_HIP(ctx, hipEventCreate(&t->ev[e]));
+        t->ev_made = 1;
+    }
+    t->ev_rec &= ~(1 << k);
+    G4_HIP(ctx, hipEventRecord(t->ev[2 * k], ctx->stream));
+    return G4_OK;
+}
+
+int g4_phase_end(g4_ctx *ctx, g4_tree *t, int k)
+{
+    G4_HIP(ctx, hipEventRecord(t->ev[2 * k + 1], ctx->stream));
+    t->ev_rec |= 1 << k;
+    return G4_OK;
+}
+
+double g4_phase_seconds(const g4_tree *t, int k)
+{
+    if (!t->ev_made || !(t->ev_rec & (1 << k))) return 0.0;
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, t->ev[2 * k], t->ev[2 * k + 1]) != hipSuccess) return 0.0;
+    return 1e-3 * (double)ms;
+}
+
+// fill the phase times of stats (the stream has been synchronised)
+static void fill_times(const g4_tree *t, g4_stats *stats, bool seeded)
+{
+    stats->t_build = g4_phase_seconds(t, 0);
+    stats->t_moments = g4_phase_seconds(t, 1);
+    stats->t_seed = seeded ? g4_phase_seconds(t, 2) : 0.0;
+    stats->t_walk = g4_phase_seconds(t, 3);
+}
+
 extern "C" {
 
 int g4_ctx_create(int device, void *hip_stream, g4_ctx **out)
@@ -79,9 +114,11 @@ int g4_build_tree(g4_ctx *ctx, const g4_particles *p, const g4_tree_params *tp, 
     g4_tree *t = nullptr;
     st = g4_build_tree_views(ctx, p, tp, ws, &L, &t);
     if (st) return st;
-    st = g4_launch_build(ctx, t, p);
+    st = g4_phase_begin(ctx, t, 0);
+    if (!st) st = g4_launch_build(ctx, t, p);
+    if (!st) st = g4_phase_end(ctx, t, 0);
     if (st) {
-        delete t;
+        g4_tree_free(ctx, t);
         return st;
     }
     *out = t;
@@ -131,6 +168,8 @@ static int g4_build_tree_views(g4_ctx *ctx, const g4_particles *p, const g4_tree
     t->walk_spill_waves = L.spill_waves;
     t->sort_tmp = b + L.sort_tmp;
     t->sort_tmp_bytes = L.sort_bytes;
+    t->ev_made = 0;
+    t->ev_rec = 0;
     *out = t;
     return G4_OK;
 }
@@ -139,7 +178,9 @@ int g4_compute_multipoles(g4_ctx *ctx, g4_tree *tree, int order)
 {
     if (!ctx || !tree) return G4_EINVAL;
     if (order != 2 && order != 3) return g4_set_err(ctx, G4_EINVAL, "order must be 2 or 3");
-    int st = g4_launch_moments(ctx, tree);
+    int st = g4_phase_begin(ctx, tree, 1);
+    if (!st) st = g4_launch_moments(ctx, tree);
+    if (!st) st = g4_phase_end(ctx, tree, 1);
     if (st) return st;
     tree->moments_order = order;
     tree->seed_valid = 0;
@@ -161,6 +202,8 @@ int g4_tree_info(g4_ctx *ctx, const g4_tree *tree, int64_t *nnodes, int64_t *lev
         for (int l = 0; l <= maxd; l++) level_start[l + 1] = level_start[l] + h.lvl_count[l];
     }
     if (h.flags & 2u) return g4_set_err(ctx, G4_ENOMEM, "node capacity exceeded");
+    if (h.flags & G4_FLAG_WALK_STACK) return g4_set_err(ctx, G4_ENOMEM, "walk traversal stack overflowed");
+    if (h.flags & G4_FLAG_FMM_STACK) return g4_set_err(ctx, G4_ENOMEM, "FMM leaf-node stack overflowed");
     return G4_OK;
 }
 
@@ -178,6 +221,8 @@ int g4_tree_free(g4_ctx *ctx, g4_tree *tree)
     if (tree) {
         // the items may still be in flight to the device: wait before releasing their host copy
         if (ctx && tree->items_host) hipStreamSynchronize(ctx->stream);
+        if (tree->ev_made)
+            for (int e = 0; e < 8; e++) hipEventDestroy(tree->ev[e]);
         delete[] tree->box_off;
         delete[] tree->items_host;
     }
@@ -236,8 +281,14 @@ int g4_build_forest(g4_ctx *ctx, int nbox, const int64_t *box_offsets, const g4_
         return g4_set_err(ctx, G4_ENOMEM, "host allocation failed");
     }
     for (int b = 0; b <= nbox; b++) t->box_off[b] = box_offsets[b];
+    st = g4_phase_begin(ctx, t, 0);
+    if (st) {
+        g4_tree_free(ctx, t);
+        return st;
+    }
     G4_HIP(ctx, hipMemcpyAsync(off_dev, t->box_off, (size_t)(nbox + 1) * 8, hipMemcpyHostToDevice, ctx->stream));
     st = g4_launch_build_forest(ctx, t, p, off_dev, bkey0, bkey1);
+    if (!st) st = g4_phase_end(ctx, t, 0);
     if (st) {
         g4_tree_free(ctx, t);
         return st;
@@ -268,28 +319,40 @@ static int tree_force_impl(g4_ctx *ctx, g4_tree *tree, const g4_walk_params *wp,
         if (zs) return zs;
     }
     int st;
+    bool seeded = false;
     if (wp->criterion == 1) {
+        if (wp->seed_from_tree && !wp->a_seed && !tree->seed_valid)
+            return g4_set_err(ctx, G4_ESTATE, "no geometric walk has left |a| in this tree");
+        if (!wp->a_seed && !wp->seed_from_tree && !(wp->theta_seed > 0))
+            return g4_set_err(ctx, G4_EINVAL, "theta_seed must be positive");
+        if (wp->a_seed || !wp->seed_from_tree) {
+            seeded = true;
+            st = g4_phase_begin(ctx, tree, 2);
+            if (st) return st;
+        }
         if (wp->a_seed) {
             st = g4_launch_gather_seed(ctx, tree, wp->a_seed);
         } else if (wp->seed_from_tree) {
-            if (!tree->seed_valid) return g4_set_err(ctx, G4_ESTATE, "no geometric walk has left |a| in this tree");
             st = G4_OK;
         } else {
-            if (!(wp->theta_seed > 0)) return g4_set_err(ctx, G4_EINVAL, "theta_seed must be positive");
             // geometric pre-walk (first-force footnote of eq. eqnrelcriterion): |a| estimate
             // written into the tree's sorted seed buffer; its forces are scratch and go to ax..az
             st = g4_launch_walk(ctx, tree, wp, kernel, 0, ax, ay, az, nullptr, nullptr, nullptr, tree->aseed, 3);
         }
         if (st) return st;
+        if (seeded && (st = g4_phase_end(ctx, tree, 2))) return st;
     }
+    if ((st = g4_phase_begin(ctx, tree, 3))) return st;
     st = g4_launch_walk(ctx, tree, wp, kernel, wp->criterion, ax, ay, az, pot, counts, a_out,
                         wp->criterion == 0 ? tree->aseed : nullptr, 0);
     if (st) return st;
+    if ((st = g4_phase_end(ctx, tree, 3))) return st;
     if (wp->criterion == 0) tree->seed_valid = 1;
     if (stats) {
         DevCounters h;
         G4_HIP(ctx, hipMemcpyAsync(&h, tree->ctr, sizeof(h), hipMemcpyDeviceToHost, ctx->stream));
         G4_HIP(ctx, hipStreamSynchronize(ctx->stream));
+        fill_times(tree, stats, seeded);
         stats->n_p2p = h.stat[0];
         stats->n_p2m = h.stat[1];
         stats->n_visit = h.stat[2];
@@ -306,6 +369,7 @@ static int tree_force_impl(g4_ctx *ctx, g4_tree *tree, const g4_walk_params *wp,
         stats->w_entry = h.stat[13];
         stats->w_leaf = h.stat[14];
         stats->w_chunk = h.stat[15];
+        if (h.flags & G4_FLAG_WALK_STACK) return g4_set_err(ctx, G4_ENOMEM, "walk traversal stack overflowed");
     }
     return G4_OK;
 }
@@ -360,7 +424,21 @@ int g4_fmm_force(g4_ctx *ctx, g4_tree *tree, const g4_fmm_params *fp, double lis
     if (!(fp->theta > 0) || fp->eps0 < 0) return g4_set_err(ctx, G4_EINVAL, "bad theta or eps0");
     if (((uintptr_t)ws & 255) != 0) return g4_set_err(ctx, G4_EINVAL, "workspace must be 256-byte aligned");
     if (tree->n >= (1ll << 27)) return g4_set_err(ctx, G4_EINVAL, "FMM supports up to 2^27 particles per call");
-    return g4_launch_fmm(ctx, tree, fp, list_factor, ws, ws_bytes, ax, ay, az, pot, stats);
+    int st = g4_phase_begin(ctx, tree, 3);
+    if (st) return st;
+    st = g4_launch_fmm(ctx, tree, fp, list_factor, ws, ws_bytes, ax, ay, az, pot, stats);
+    if (st) return st;
+    if ((st = g4_phase_end(ctx, tree, 3))) return st;
+    // the FMM synchronises anyway (list sizes): its overflow flag is always checked
+    uint32_t flags = 0;
+    G4_HIP(ctx, hipMemcpyAsync(&flags, &tree->ctr->flags, 4, hipMemcpyDeviceToHost, ctx->stream));
+    G4_HIP(ctx, hipStreamSynchronize(ctx->stream));
+    if (stats) {
+        fill_times(tree, stats, false);
+        stats->flags = flags;
+    }
+    if (flags & G4_FLAG_FMM_STACK) return g4_set_err(ctx, G4_ENOMEM, "FMM leaf-node stack overflowed");
+    return G4_OK;
 }
 
 int g4_mlp_features(g4_ctx *ctx, const g4_tree *tree, const g4_walk_params *wp, const float *norm, float *feat)

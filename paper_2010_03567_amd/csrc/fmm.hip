@@ -731,6 +731,7 @@ struct FastArgs {
     float *F;       // 20 field coefficients per node
     double *acc;    // 4 per particle (sorted order): a_x, a_y, a_z, potential, before the factor G
     unsigned long long *stat;  // pp, pn, nn
+    uint32_t *flags;           // tree flags: G4_FLAG_FMM_STACK if a leaf-node stack overflows
 };
 
 __device__ __forceinline__ uint32_t fm_uni(uint32_t x) { return (uint32_t)__builtin_amdgcn_readfirstlane((int)x); }
@@ -1523,6 +1524,8 @@ __global__ __launch_bounds__(256) void k_fast_ln(FastArgs A, uint32_t npairs)
             if (go && !gleaf && sp < FT_STK) {
                 if (gl == 0) stk[wv][g][sp] = make_uint2(w.next, w.num | (go << 16));
                 sp++;
+            } else if (go && !gleaf && gl == 0) {
+                atomicOr(A.flags, G4_FLAG_FMM_STACK);  // one entry per level: never expected
             }
         }
         fm_sync();
@@ -1717,6 +1720,7 @@ static int fmm_fast(g4_ctx *ctx, g4_tree *t, const g4_fmm_params *fp, double fac
     A.F = (float *)(b + L.F);
     A.acc = (double *)(b + L.acc);
     A.stat = t->ctr->stat + 6;
+    A.flags = &t->ctr->flags;
     uint2 *fr[2] = {(uint2 *)(b + L.f0), (uint2 *)(b + L.f1)};
     if ((uint64_t)t->nbox > L.cap_pairs) return g4_set_err(ctx, G4_ENOMEM, "fmm frontier smaller than the root count");
     if (int zst = g4_launch_zero(ctx, A.cnt, 64)) return zst;

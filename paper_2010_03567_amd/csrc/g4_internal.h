@@ -53,7 +53,8 @@ static_assert(sizeof(WNode) == 64, "WNode must be 64 bytes");
 struct DevCounters {
     uint32_t node_count;      // total nodes (the level sizes summed after the split passes)
     uint32_t item_ctr;        // work-item counter of the persistent walk
-    uint32_t flags;           // bit 0: depth-capped leaf above leaf_max; bit 1: node overflow
+    uint32_t flags;           // bit 0: depth-capped leaf above leaf_max; bit 1: node overflow;
+                              // bit 2: walk stack overflow; bit 3: FMM leaf-node stack overflow
     uint32_t pad;
     uint32_t lvl_start[G4_MAXLEV + 4];  // first node of each level
     uint32_t lvl_count[G4_MAXLEV + 4];  // nodes of each level (children allocated by atomics)
@@ -96,7 +97,22 @@ struct g4_tree {
     int64_t items_cap;
     void *sort_tmp;
     size_t sort_tmp_bytes;
+    // phase timers on the context's stream: build, moments, seed, walk (start, end)
+    hipEvent_t ev[8];
+    int ev_made;              // events created
+    int ev_rec;               // bit k: pair k (build, moments, seed, walk) recorded
 };
+
+#define G4_FLAG_WALK_STACK 4u
+#define G4_FLAG_FMM_STACK 8u
+#define G4_FLAG_FATAL (2u | G4_FLAG_WALK_STACK | G4_FLAG_FMM_STACK)
+
+// phase k of the timers: 0 build, 1 moments, 2 seed, 3 walk
+int g4_phase_begin(g4_ctx *ctx, g4_tree *t, int k);
+int g4_phase_end(g4_ctx *ctx, g4_tree *t, int k);
+// seconds between the recorded events of phase k (0 if not recorded); the
+// events must be complete (the caller has synchronised the stream)
+double g4_phase_seconds(const g4_tree *t, int k);
 
 // Layout of a tree workspace (byte offsets).
 struct WsLayout {

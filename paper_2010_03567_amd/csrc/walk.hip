@@ -55,6 +55,7 @@ struct WalkArgs {
     uint4 *spill;               // per-wavefront spill area of the traversal stack
     int64_t spill_waves;        // wavefronts the spill area has room for (a multiple of 4)
     int lds_stk;                // stack entries kept in LDS (<= WK_LDS_STK)
+    uint32_t *flags;            // tree flags: G4_FLAG_WALK_STACK if the stack bound is ever broken
 };
 
 // g1, g2, g3 (and g0) of the interaction kernel at r (r2, rinv given), r >= h.
@@ -506,6 +507,9 @@ __global__ __launch_bounds__(256) void k_walk(const WalkArgs A)
                 }
                 sp++;
                 max_sp = max(max_sp, sp);
+            } else if (lane == 0) {
+                // beyond the depth bound above: never expected, but never silent
+                atomicOr(A.flags, G4_FLAG_WALK_STACK);
             }
         }
     }
@@ -682,6 +686,7 @@ int g4_launch_walk(g4_ctx *ctx, g4_tree *t, const g4_walk_params *wp, int kernel
     A.spill = t->walk_spill;
     A.spill_waves = t->walk_spill_waves;
     A.lds_stk = WK_LDS_STK;
+    A.flags = &t->ctr->flags;
     if (const char *env = getenv("G4_WALK_LDS_STACK")) {
         // diagnostic: keep fewer entries in LDS so that the spill path runs
         const int v = atoi(env);

@@ -49,7 +49,9 @@ class g4_fmm_params(C.Structure):
 
 
 class g4_stats(C.Structure):
-    _fields_ = [("n_p2p", C.c_uint64), ("n_p2m", C.c_uint64), ("n_visit", C.c_uint64),
+    _fields_ = [("t_build", C.c_double), ("t_moments", C.c_double), ("t_seed", C.c_double),
+                ("t_walk", C.c_double),
+                ("n_p2p", C.c_uint64), ("n_p2m", C.c_uint64), ("n_visit", C.c_uint64),
                 ("n_seed_p2p", C.c_uint64), ("n_seed_p2m", C.c_uint64), ("n_seed_visit", C.c_uint64),
                 ("n_pp", C.c_uint64), ("n_pn", C.c_uint64), ("n_nn", C.c_uint64),
                 ("n_nodes", C.c_uint64), ("w_pop", C.c_uint64), ("w_p2m", C.c_uint64), ("w_p2p", C.c_uint64),
@@ -57,7 +59,7 @@ class g4_stats(C.Structure):
                 ("w_entry", C.c_uint64), ("w_leaf", C.c_uint64), ("w_chunk", C.c_uint64)]
 
     def as_dict(self):
-        return {k: int(getattr(self, k)) for k, _ in self._fields_}
+        return {k: (float if k.startswith("t_") else int)(getattr(self, k)) for k, _ in self._fields_}
 
 
 _p, _i64, _i32, _sz = C.c_void_p, C.c_int64, C.c_int, C.c_size_t

@@ -125,3 +125,36 @@ def test_gpu_fmm_touching_cells_never_interact(g, ctx, cells, expect, det):
     out = g.g4_fmm_force(ctx, tree, fp, want_stats=True)
     s = out["stats"]
     assert (s["n_pp"], s["n_pn"], s["n_nn"]) == expect
+
+
+def test_gpu_stats_phase_times(g, ctx):
+    """g4_stats carries the hipEvent durations of the build, the moments, the
+    seed (pre-walk) and the walk; each is positive and together they fit in
+    the host's wall time around the same calls.  A geometric call has no seed
+    phase, and a FMM call reports its whole duration as t_walk."""
+    import time
+
+    import workloads
+    ps = workloads.clustered_box(200000, seed=5, nhalo=50)
+    pos = torch.from_numpy(ps.pos).to(ctx.device)
+    m = torch.from_numpy(ps.mass.astype(np.float32)).to(ctx.device)
+    tp = g.tree_params(True, 1.0, leaf_max=16)
+    n = ps.pos.shape[0]
+    kw = dict(kernel=1, r_s=1.25 / 256 * (128 ** 3 / n) ** (1 / 3), eps0=0.0)
+    kw["r_cut"] = 4.5 * kw["r_s"]
+    x, y, z = g.g4_quantize(ctx, pos, tp)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    tree = g.g4_build_tree(ctx, g.particles(x, y, z, m), tp)
+    g.g4_compute_multipoles(ctx, tree, 3)
+    out = g.g4_tree_force(ctx, tree, g.walk_params(criterion=1, alpha=0.005, **kw), want_stats=True)
+    wall = time.perf_counter() - t0
+    s = out["stats"]
+    ts = [s["t_build"], s["t_moments"], s["t_seed"], s["t_walk"]]
+    print("phase times", ts, "wall", wall)
+    assert all(t > 0 for t in ts) and sum(ts) <= wall
+    s = g.g4_tree_force(ctx, tree, g.walk_params(criterion=0, theta=0.7, **kw), want_stats=True)["stats"]
+    assert s["t_seed"] == 0.0 and s["t_walk"] > 0 and s["flags"] & 0xC == 0
+    s = g.g4_fmm_force(ctx, tree, g.fmm_params(kernel=1, theta=0.5, r_s=kw["r_s"], r_cut=kw["r_cut"]),
+                       want_stats=True)["stats"]
+    assert s["t_walk"] > 0 and s["t_build"] > 0 and s["flags"] & 0xC == 0
