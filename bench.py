@@ -1,22 +1,31 @@
 #!/usr/bin/env python3
 """Benchmark of the gravity hot path on one MI355X.
 
-Workload: the clustered periodic box of 128^3 equal-mass particles (60 % of the
+Headline workload (the one the metric names: learned against plain seeding of
+the relative criterion): the clustered periodic box of 256^3 = 16 777 216
+equal-mass particles drawn with the held-out evaluation seed 2001 (60 % of the
 mass in 2000 Hernquist haloes, 40 % uniform), TreePM split r_s = 1.25 L/256
-(mesh 256^3), softening L/(40*128), leaf size 8, p = 3.
+scaled to the mean spacing (mesh 512^3 at 256^3), softening L/(40 * 256), leaf
+size 24, p = 3, wavefront groups of 64.
 
 A step is one pass of the whole path: integer mapping -> Morton keys + radix
-sort -> octree -> multipoles -> |a| seed (geometric pre-walk, theta = 0.7) ->
-relative TreePM short-range walk -> forces in the caller's order.  Inputs are
-resident in HBM before the timed region.
+sort -> octree -> multipoles -> |a| seed -> relative TreePM short-range walk ->
+forces in the caller's order.  The seed is the geometric pre-walk (theta =
+0.7) for the plain variant and the trained network (features + MLP) for the
+learned one.  Inputs are resident in HBM before the timed region.
 
 The metric asks for forces/s at a 99th-percentile relative force error <= 1e-3
 against direct summation.  At R_cut = 4.5 r_s the cut-off alone leaves a
 99th-percentile error near 0.1 against the untruncated short-range direct
-sum, so the headline runs at R_cut = 7 r_s (where the paper quotes a 1e-5
-suppression) and picks the largest alpha whose measured 99th percentile meets
-the bound.  The as-stated R_cut = 4.5 r_s, alpha = 0.005 line is reported
-beside it.  Prints one JSON line.
+sum, so the walk runs at R_cut = 7 r_s (where the paper quotes a 1e-5
+suppression) and each variant takes the largest alpha of a sqrt(2) grid whose
+measured 99th percentile (10^4 random targets, FP64 direct summation on the
+device) meets the bound.  `value` is the faster variant that meets it.
+
+Extra keys: the same comparison on the 128^3 box (seed 2), the as-stated
+R_cut = 4.5 r_s, alpha = 0.005 line, the FMM at p = 3, theta = 0.5, the
+batched forest of 64 boxes, and the FP64 oracle on the host cores.  Prints one
+JSON line.
 """
 from __future__ import annotations
 
@@ -32,10 +41,15 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 METRIC = "particle forces/s at 99th-pct rel. force err ≤1e-3 vs direct sum; learned vs plain"
-PEAK_FP32_VECTOR = 157.3e12  # MI355X FP32 vector peak, FLOP/s
+PEAK_FP32_VECTOR = 157.3e12      # MI355X FP32 vector peak (assumes packed FP32 FMA), FLOP/s
+PEAK_FP32_NONPACKED = 78.6e12    # 256 CU x 4 SIMD x 16 lanes x 2 x 2.4 GHz: what non-packed FMA can issue
 ERR_BOUND = 1e-3
 KEY_KINDS = {"morton": 0, "ph": 1}
 ALPHAS = (0.004, 0.0028, 0.002, 0.0014, 0.001, 0.0007, 0.0005, 0.00035, 0.00025)
+HEADLINE_N = 256 ** 3
+HEADLINE_SEED = 2001
+SMALL_N = 128 ** 3
+SMALL_SEED = 2
 
 
 def parse():
@@ -43,23 +57,23 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--n", type=int, default=128 ** 3)
-    ap.add_argument("--rcut", type=float, default=7.0, help="R_cut in units of r_s for the headline")
-    ap.add_argument("--alpha", type=float, default=0.0, help="fix alpha instead of calibrating it")
+    ap.add_argument("--n", type=int, default=HEADLINE_N, help="particles of the headline box")
+    ap.add_argument("--seed", type=int, default=HEADLINE_SEED, help="generator seed of the headline box")
+    ap.add_argument("--rcut", type=float, default=7.0, help="R_cut in units of r_s")
+    ap.add_argument("--alpha", type=float, default=0.0, help="fix alpha for both variants instead of calibrating it")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=20.0, help="CPU work the oracle baseline aims at")
     ap.add_argument("--no-as-stated", action="store_true")
+    ap.add_argument("--no-small", action="store_true", help="skip the 128^3 comparison")
     ap.add_argument("--no-learned", action="store_true")
     ap.add_argument("--weights", type=str, default="", help="learned-seed weights (.npz); default by particle count")
     ap.add_argument("--no-fmm", action="store_true")
     ap.add_argument("--fmm-leaf", type=int, default=32,
-                    help="leaf size of the second, tuned FMM line (32: fastest of 8-96 at theta 0.5 on this box; "
-                         "the first line keeps the configuration's leaf 16)")
+                    help="leaf size of the second, tuned FMM line (the first keeps the configuration's leaf 16)")
     ap.add_argument("--no-forest", action="store_true")
-    ap.add_argument("--no-large", action="store_true", help="skip the learned-vs-plain comparison at 256^3")
-    ap.add_argument("--cpu-sample", type=int, default=20000)
     ap.add_argument("--err-sample", type=int, default=10000)
     ap.add_argument("--group", type=int, default=64)
-    ap.add_argument("--leaf", type=int, default=24, help="leaf size B of the headline tree")
+    ap.add_argument("--leaf", type=int, default=24, help="leaf size B of the tree")
     ap.add_argument("--copy-calibration-mb", type=int, default=0,
                     help="also run a plain device copy of this size (HBM counter calibration)")
     ap.add_argument("--keys", choices=("morton", "ph"), default="morton",
@@ -67,8 +81,8 @@ def parse():
     ap.add_argument("--sr-table", type=int, default=0,
                     help="intervals of the short-range factor table of the walks (0: erfc/exp per interaction)")
     ap.add_argument("--profile-walk", choices=("plain", "learned"), default=None,
-                    help="only time `steps` steps of this variant at --alpha (no reference sums, no calibration), "
-                         "for counter runs of the walk")
+                    help="only time `steps` steps of this variant at --alpha on the headline box (no reference "
+                         "sums, no calibration), for counter runs of the walk")
     return ap.parse_args()
 
 
@@ -77,7 +91,11 @@ def log(msg):
 
 
 WALK_SOURCES = ("walk.hip", "g4_device.h", "g4_internal.h")
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "walk_treepm_clustered128_traffic.txt")
+
+
+def traffic_file(n):
+    side = round(n ** (1 / 3))
+    return os.path.join(ROOT, "profiles", f"walk_treepm_clustered{side}_traffic.txt")
 
 
 def walk_source_sha():
@@ -89,14 +107,15 @@ def walk_source_sha():
     return h.hexdigest()
 
 
-def walk_traffic(variant, alpha, leaf):
+def walk_traffic(n, variant, alpha, leaf):
     """HBM bytes per launch of the relative walk from the committed counter
-    summary, if it was taken on the current walk sources for this variant,
-    alpha and leaf size; None otherwise."""
-    if not os.path.exists(TRAFFIC_FILE):
+    summary, if it was taken on the current walk sources for this box size,
+    variant, alpha and leaf size; None otherwise."""
+    path = traffic_file(n)
+    if not os.path.exists(path):
         return None
     kv = {}
-    with open(TRAFFIC_FILE) as fh:
+    with open(path) as fh:
         for line in fh:
             if ":" in line and not line.startswith("#"):
                 k, v = line.split(":", 1)
@@ -110,6 +129,200 @@ def walk_traffic(variant, alpha, leaf):
         return None
 
 
+def treepm_scales(n):
+    """Split scale and softening of the clustered-box workload at n particles
+    (fixed relative to the mean spacing: r_s = 1.25/256, eps0 = 1/(40*128) at 128^3)."""
+    scale = (128 ** 3 / n) ** (1.0 / 3.0)
+    return 1.25 / 256 * scale, scale / (40 * 128)
+
+
+class TreePMCase:
+    """One clustered periodic box resident on the device, with the plain
+    (geometric pre-walk) and learned (MLP) seeding of the relative walk."""
+
+    def __init__(self, g, ctx, args, n, seed, weights=""):
+        import torch
+        import workloads
+        self.g, self.ctx, self.args, self.n, self.seed = g, ctx, args, n, seed
+        self.r_s, self.eps0 = treepm_scales(n)
+        self.r_cut = args.rcut * self.r_s
+        log(f"[bench] generating clustered box n={n} seed={seed}")
+        ps = workloads.clustered_box(n, seed=seed)
+        self.ps = ps
+        dev = ctx.device
+        self.pos = torch.from_numpy(ps.pos).to(dev)
+        self.mass = torch.from_numpy(ps.mass.astype(np.float32)).to(dev)
+        self.tp = g.tree_params(True, ps.box, leaf_max=args.leaf, key_kind=KEY_KINDS[args.keys])
+        self.ws = torch.empty(g.g4_workspace_bytes(self.tp, n) + 256, dtype=torch.uint8, device=dev)
+        self.outs = [torch.empty(n, dtype=torch.float64, device=dev) for _ in range(3)]
+        self.out = (*self.outs, None, None, None)
+        self.stream = torch.cuda.current_stream(dev)
+        self.state = {}
+        self.learned = None
+        wdir = os.path.join(ROOT, "paper_2010_03567_amd", "weights")
+        wfile = weights or os.path.join(wdir, f"seed_mlp_{n}_leaf{args.leaf}.npz")
+        if not args.no_learned and os.path.exists(wfile):
+            from paper_2010_03567_amd import train_seed
+            wl, norm, meta = train_seed.load(wfile, dev)
+            if int(meta.get("leaf", 8)) == args.leaf:
+                self.learned = dict(w=wl, norm=norm, meta=meta, file=os.path.basename(wfile),
+                                    aseed=torch.empty(n, dtype=torch.float32, device=dev),
+                                    feat=torch.empty((n, 8), dtype=torch.float32, device=dev),
+                                    fwp=g.walk_params(kernel=1, r_s=self.r_s, eps0=self.eps0))
+            else:
+                log(f"[bench] {os.path.basename(wfile)} was trained on leaf {meta.get('leaf')}, not {args.leaf}")
+        self.ref = None
+        self.tg = None
+
+    def params(self, variant, alpha, r_cut=None):
+        g, a = self.g, self.args
+        kw = dict(kernel=1, r_s=self.r_s, r_cut=self.r_cut if r_cut is None else r_cut, eps0=self.eps0,
+                  group_size=a.group, sr_table=a.sr_table)
+        if variant == "plain":
+            return (g.walk_params(criterion=0, theta=0.7, **kw),
+                    g.walk_params(criterion=1, alpha=alpha, seed_from_tree=1, **kw))
+        return (None, g.walk_params(criterion=1, alpha=alpha, a_seed=self.learned["aseed"], **kw))
+
+    def step(self, variant, wps, evs=None, want_stats=False):
+        """One pass of the path; evs: 4 events (start, after moments, after seed, after walk)."""
+        g, ctx = self.g, self.ctx
+        if evs is not None:
+            evs[0].record(self.stream)
+        x, y, z = g.g4_quantize(ctx, self.pos, self.tp)
+        p = g.particles(x, y, z, self.mass)
+        tree = g.g4_build_tree(ctx, p, self.tp, ws=self.ws)
+        g.g4_compute_multipoles(ctx, tree, 3)
+        if evs is not None:
+            evs[1].record(self.stream)
+        seed_stats = None
+        if variant == "plain":
+            seed_stats = g.g4_treepm_shortrange(ctx, tree, wps[0], out=self.out, want_stats=want_stats)["stats"]
+        else:
+            L = self.learned
+            feat = g.g4_mlp_features(ctx, tree, L["fwp"], L["norm"], out=L["feat"])
+            g.g4_mlp_forward(ctx, L["w"], feat, shift=0.0, mode=1, out=L["aseed"])
+        if evs is not None:
+            evs[2].record(self.stream)
+        st = g.g4_treepm_shortrange(ctx, tree, wps[1], out=self.out, want_stats=want_stats)["stats"]
+        if evs is not None:
+            evs[3].record(self.stream)
+        self.state["tree"], self.state["p"] = tree, p
+        return seed_stats, st
+
+    def reference(self):
+        """FP64 direct summation (untruncated short-range q = 0 sum) on a random sample of targets."""
+        import torch
+        import workloads
+        if self.ref is None:
+            g = self.g
+            self.step("plain", self.params("plain", 0.001))
+            tg = workloads.sample_indices(self.n, self.args.err_sample, seed=99)
+            self.tg = torch.from_numpy(tg).to(self.ctx.device)
+            wpd = g.walk_params(kernel=1, r_s=self.r_s, r_cut=1e30, eps0=self.eps0)
+            r = g.g4_direct_force(self.ctx, self.state["p"], self.tp, wpd, targets=self.tg, want_pot=False)
+            self.ref = np.stack([r["ax"].cpu().numpy(), r["ay"].cpu().numpy(), r["az"].cpu().numpy()], 1)
+        return self.ref
+
+    def errors(self, variant, wps):
+        import torch
+        import workloads
+        ref = self.reference()
+        self.step(variant, wps)
+        a = torch.stack(self.outs, 1)[self.tg].cpu().numpy()
+        return workloads.percentiles(workloads.relative_errors(a, ref))
+
+    def calibrate(self, variant, fixed=0.0):
+        cal, chosen = {}, None
+        for a in ((fixed,) if fixed > 0 else ALPHAS):
+            cal[a] = self.errors(variant, self.params(variant, a))
+            log(f"[bench] n={self.n} {variant} alpha={a}: {cal[a]}")
+            if cal[a]["p99"] <= ERR_BOUND or fixed > 0:
+                chosen = a
+                break
+        return chosen, cal
+
+    def timed(self, variant, wps, steps, warmup):
+        """Wall time per step over exactly `steps` steps (synchronised on both
+        sides) and the per-step event times of the phases."""
+        import torch
+        for _ in range(warmup):
+            self.step(variant, wps)
+        torch.cuda.synchronize()
+        evs = [[torch.cuda.Event(enable_timing=True) for _ in range(4)] for _ in range(steps)]
+        t0 = time.perf_counter()
+        for k in range(steps):
+            self.step(variant, wps, evs[k])
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) * 1e3 / steps
+        ph = np.array([[e[0].elapsed_time(e[1]), e[1].elapsed_time(e[2]), e[2].elapsed_time(e[3]),
+                        e[0].elapsed_time(e[3])] for e in evs])
+        return ms, {"build_moments_ms": float(np.median(ph[:, 0])), "seed_ms": float(np.median(ph[:, 1])),
+                    "walk_ms": float(np.median(ph[:, 2])), "walk_ms_mean": float(np.mean(ph[:, 2])),
+                    "step_ms_median_events": float(np.median(ph[:, 3]))}
+
+    def variant(self, variant, steps, warmup, fixed=0.0):
+        alpha, cal = self.calibrate(variant, fixed)
+        if alpha is None:
+            return {"error": "no alpha in the grid met the error bound",
+                    "alpha_calibration": {str(k): v["p99"] for k, v in cal.items()}}
+        wps = self.params(variant, alpha)
+        ms, ph = self.timed(variant, wps, steps, warmup)
+        sst, st = self.step(variant, wps, want_stats=True)
+        n = self.n
+        res = {"alpha": alpha, "ms_per_step": ms, "forces_per_s": n / (ms * 1e-3), "phases": ph,
+               "errors_vs_direct": cal[alpha], "alpha_calibration": {str(k): v["p99"] for k, v in cal.items()},
+               "per_particle": {"p2p": st["n_p2p"] / n, "p2m": st["n_p2m"] / n, "visit": st["n_visit"] / n},
+               "stats": st}
+        if sst is not None:
+            res["per_particle"].update(prewalk_p2p=sst["n_p2p"] / n, prewalk_p2m=sst["n_p2m"] / n,
+                                       prewalk_visit=sst["n_visit"] / n)
+        log(f"[bench] n={n} {variant}: {ms:.3f} ms/step at alpha {alpha} (seed {ph['seed_ms']:.3f} ms, walk "
+            f"{ph['walk_ms']:.3f} ms), errors {cal[alpha]}")
+        return res
+
+    def compare(self, steps, warmup, fixed=0.0):
+        out = {"workload": f"clustered box {round(self.n ** (1 / 3))}^3 (seed {self.seed}), R_cut {self.args.rcut} r_s, "
+                           f"leaf {self.args.leaf}", "n": self.n, "seed": self.seed}
+        out["plain"] = self.variant("plain", steps, warmup, fixed)
+        if self.learned is not None:
+            out["learned"] = self.variant("learned", steps, warmup, fixed)
+            out["learned"]["weights"] = self.learned["file"]
+            meta = self.learned["meta"]
+            out["learned"]["trained_on"] = {k: meta.get(k) for k in ("n", "leaf", "seeds", "rcut", "alpha", "steps",
+                                                                      "tau")}
+            out["learned"]["train_residual_rms_dex"] = meta.get("residual_rms")
+        if "ms_per_step" in out["plain"] and "ms_per_step" in out.get("learned", {}):
+            out["speedup_learned_vs_plain"] = out["plain"]["ms_per_step"] / out["learned"]["ms_per_step"]
+            # what skipping the pre-walk entirely could give: the plain step without its seed phase
+            p = out["plain"]
+            out["learned_ceiling_speedup"] = p["ms_per_step"] / (p["ms_per_step"] - p["phases"]["seed_ms"])
+        return out
+
+    def free(self):
+        import torch
+        self.state.clear()
+        del self.ws, self.outs, self.out, self.pos, self.mass
+        if self.learned is not None:
+            self.learned.clear()
+        torch.cuda.empty_cache()
+
+
+def walk_roofline(flops, st, walk_ms, n, variant, alpha, leaf):
+    """Roofline entry of the relative walk: algorithmic FLOPs at the
+    per-interaction units of the measurement plan (particle-particle and
+    particle-node interactions only) over the mean HIP-event duration."""
+    alg = flops.walk_flops_algorithmic("treepm", st["n_p2m"], st["n_p2p"])
+    visit = flops.VISIT_BOOKKEEPING[("treepm", "relative")] * float(st["n_visit"])
+    achieved = alg / (walk_ms * 1e-3)
+    return {"bound": "alu", "kernel": "k_walk<1,1,false,true> (relative TreePM walk, p = 3)",
+            "achieved": achieved / 1e12, "peak": PEAK_FP32_VECTOR / 1e12, "unit": "TFLOP/s",
+            "frac": achieved / PEAK_FP32_VECTOR, "traffic": walk_traffic(n, variant, alpha, leaf),
+            "frac_of_nonpacked_issue_peak": achieved / PEAK_FP32_NONPACKED,
+            "avg_ms": walk_ms, "flop_per_launch": alg,
+            "flop_units": {"p2p": flops.P2P_ALG["treepm"], "p2m": flops.P2M_ALG["treepm"]},
+            "visit_flop_not_counted": visit, "variant": variant, "alpha": alpha}
+
+
 def main():
     args = parse()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
@@ -117,298 +330,105 @@ def main():
                           "n_gpus": args.gpus}))
         sys.exit(2)
     import torch
-    import workloads
     from paper_2010_03567_amd import flops
     import paper_2010_03567_amd.g4hip as g
 
-    n = args.n
-    scale = (128 ** 3 / n) ** (1.0 / 3.0)
-    r_s = 1.25 / 256 * scale
-    eps0 = scale / (40 * 128)
-    B = args.leaf
-    log(f"[bench] generating clustered box n={n}")
-    ps = workloads.clustered_box(n, seed=2)
-    dev = torch.device("cuda", 0)
     ctx = g.Context()
-    pos = torch.from_numpy(ps.pos).to(dev)
-    mass = torch.from_numpy(ps.mass.astype(np.float32)).to(dev)
-    tp = g.tree_params(True, ps.box, leaf_max=B, key_kind=KEY_KINDS[args.keys])
-    ws = torch.empty(g.g4_workspace_bytes(tp, n) + 256, dtype=torch.uint8, device=dev)
-    outs = [torch.empty(n, dtype=torch.float64, device=dev) for _ in range(3)]
-    out = (*outs, None, None, None)
-    stream = torch.cuda.current_stream(dev)
-    state = {}
-
-    def params(rcut_f, alpha):
-        r_cut = rcut_f * r_s
-        seed = g.walk_params(kernel=1, criterion=0, theta=0.7, r_s=r_s, r_cut=r_cut, eps0=eps0, group_size=args.group,
-                             sr_table=args.sr_table)
-        rel = g.walk_params(kernel=1, criterion=1, alpha=alpha, r_s=r_s, r_cut=r_cut, eps0=eps0, seed_from_tree=1,
-                            group_size=args.group, sr_table=args.sr_table)
-        return seed, rel
-
-    def step(wps, evs=None):
-        x, y, z = g.g4_quantize(ctx, pos, tp)
-        p = g.particles(x, y, z, mass)
-        tree = g.g4_build_tree(ctx, p, tp, ws=ws)
-        g.g4_compute_multipoles(ctx, tree, 3)
-        if evs is not None:
-            evs[0].record(stream)
-        g.g4_treepm_shortrange(ctx, tree, wps[0], out=out)
-        if evs is not None:
-            evs[1].record(stream)
-        g.g4_treepm_shortrange(ctx, tree, wps[1], out=out)
-        if evs is not None:
-            evs[2].record(stream)
-        state["tree"], state["p"] = tree, p
-
     if args.copy_calibration_mb:
-        src = torch.ones(args.copy_calibration_mb * 2 ** 18, dtype=torch.float32, device=dev)
+        src = torch.ones(args.copy_calibration_mb * 2 ** 18, dtype=torch.float32, device=ctx.device)
         dst = torch.empty_like(src)
         for _ in range(3):
             dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
 
+    head = TreePMCase(g, ctx, args, args.n, args.seed, args.weights)
     if args.profile_walk:
         if args.alpha <= 0:
             raise SystemExit("--profile-walk needs --alpha")
-        if args.profile_walk == "learned":
-            made = learned_step(args, g, ctx, n, r_s, eps0, tp, ws, pos, mass, out, stream, state)
-            if made is None:
-                raise SystemExit("no learned-seed weights for this particle count")
-            wp1, fstep = made[0](args.alpha), made[1]
-        else:
-            wp1, fstep = params(args.rcut, args.alpha), step
-        for _ in range(args.warmup):
-            fstep(wp1)
-        torch.cuda.synchronize()
-        evs = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(args.steps)]
-        for k in range(args.steps):
-            fstep(wp1, evs[k])
-        torch.cuda.synchronize()
-        walk_ms = float(np.mean([e[1].elapsed_time(e[2]) for e in evs]))
-        print(json.dumps({"profile_walk": args.profile_walk, "alpha": args.alpha, "steps": args.steps,
-                          "walk_ms": walk_ms, "walk_source_sha256": walk_source_sha()}))
+        if args.profile_walk == "learned" and head.learned is None:
+            raise SystemExit("no learned-seed weights for this particle count")
+        ms, ph = head.timed(args.profile_walk, head.params(args.profile_walk, args.alpha), args.steps, args.warmup)
+        print(json.dumps({"profile_walk": args.profile_walk, "n": args.n, "alpha": args.alpha, "steps": args.steps,
+                          "ms_per_step": ms, "walk_ms": ph["walk_ms_mean"], "walk_source_sha256": walk_source_sha()}))
         return
 
-    # reference forces: FP64 direct summation on the GPU for a random sample
-    step(params(args.rcut, 0.001))
-    tg_np = workloads.sample_indices(n, args.err_sample, seed=99)
-    tg = torch.from_numpy(tg_np).to(dev)
-    wpd = g.walk_params(kernel=1, r_s=r_s, r_cut=1e30, eps0=eps0)
-    ref = g.g4_direct_force(ctx, state["p"], tp, wpd, targets=tg, want_pot=False)
-    ref = np.stack([ref["ax"].cpu().numpy(), ref["ay"].cpu().numpy(), ref["az"].cpu().numpy()], 1)
-
-    def errors(wps):
-        step(wps)
-        a = torch.stack(outs, 1)[tg].cpu().numpy()
-        return workloads.percentiles(workloads.relative_errors(a, ref))
-
-    def timed(wps, steps, warmup):
-        for _ in range(warmup):
-            step(wps)
-        torch.cuda.synchronize()
-        events = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(steps)]
-        t0 = time.perf_counter()
-        for k in range(steps):
-            step(wps, events[k])
-        torch.cuda.synchronize()
-        t1 = time.perf_counter()
-        seed_ms = float(np.mean([e[0].elapsed_time(e[1]) for e in events]))
-        walk_ms = float(np.mean([e[1].elapsed_time(e[2]) for e in events]))
-        return (t1 - t0) * 1e3 / steps, seed_ms, walk_ms
-
-    # calibrate alpha against the error bound
-    calib = {}
-    if args.alpha > 0:
-        alpha = args.alpha
-        calib[alpha] = errors(params(args.rcut, alpha))
-    else:
-        alpha = None
-        for a in ALPHAS:
-            calib[a] = errors(params(args.rcut, a))
-            log(f"[bench] R_cut={args.rcut} alpha={a}: {calib[a]}")
-            if calib[a]["p99"] <= ERR_BOUND:
-                alpha = a
-                break
-        if alpha is None:
-            alpha = ALPHAS[-1]
-    wps = params(args.rcut, alpha)
-    log(f"[bench] timing {args.steps} steps at R_cut={args.rcut} r_s, alpha={alpha}")
-    ms_per_step, seed_ms, walk_ms = timed(wps, args.steps, args.warmup)
-    log(f"[bench] {ms_per_step:.3f} ms/step; pre-walk {seed_ms:.3f} ms, walk {walk_ms:.3f} ms")
-
-    tree = state["tree"]
-    st_seed = g.g4_treepm_shortrange(ctx, tree, wps[0], out=out, want_stats=True)["stats"]
-    st_plain = g.g4_treepm_shortrange(ctx, tree, wps[1], out=out, want_stats=True)["stats"]
-    learned = learned_variant(args, g, ctx, n, r_s, eps0, tp, ws, pos, mass, out, outs, stream, state, tg, ref,
-                              ms_per_step)
-    plain_value = n / (ms_per_step * 1e-3)
-    best_learned = learned is not None and "forces_per_s" in learned and learned["forces_per_s"] > plain_value
-    # roofline of the dominant kernel (the relative walk) of the variant that gives `value`
-    st = learned.pop("stats") if best_learned else st_plain
-    if learned is not None:
-        learned.pop("stats", None)
-    rwalk_ms = learned["walk_ms"] if best_learned else walk_ms
-    ralpha = learned["alpha"] if best_learned else alpha
-    walk_flop = flops.walk_flops("treepm", "relative", st["n_visit"], st["n_p2m"], st["n_p2p"])
-    achieved = walk_flop / (rwalk_ms * 1e-3)
-    traffic = walk_traffic("learned" if best_learned else "plain", ralpha, args.leaf)
+    cmp = head.compare(args.steps, args.warmup, args.alpha)
+    n = args.n
+    ok = {k: cmp[k] for k in ("plain", "learned") if "ms_per_step" in cmp.get(k, {})}
+    best = min(ok, key=lambda k: ok[k]["ms_per_step"])
+    chosen = ok[best]
+    st = chosen.pop("stats")
+    for k in ok:
+        ok[k].pop("stats", None)
+    roof = walk_roofline(flops, st, chosen["phases"]["walk_ms_mean"], n, best, chosen["alpha"], args.leaf)
     util = {"pop": st["n_visit"] / max(1, 64 * st["w_pop"]), "p2m": st["n_p2m"] / max(1, 64 * st["w_p2m"]),
             "p2p": st["n_p2p"] / max(1, 64 * st["w_p2p"])}
-    passes = {k: st[k] for k in ("w_pop", "w_p2m", "w_p2p", "w_entry", "w_leaf", "w_chunk", "max_stack")}
-
+    side = round(n ** (1 / 3))
     result = {
         "metric": METRIC,
-        "value": learned["forces_per_s"] if best_learned else plain_value,
+        "value": chosen["forces_per_s"],
         "unit": "forces/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": learned["ms_per_step"] if best_learned else ms_per_step,
+        "ms_per_step": chosen["ms_per_step"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": "treepm_shortrange_clustered_box_128^3", "n": n, "box": 1.0, "r_s": r_s,
-                   "r_cut": args.rcut * r_s, "R_cut": args.rcut, "eps0": eps0, "leaf_max": B, "order": 3,
-                   "alpha": learned["alpha"] if best_learned else alpha, "theta_seed": 0.7,
+        "config": {"workload": f"learned_vs_plain_treepm_clustered_box_{side}^3", "n": n, "seed": args.seed,
+                   "box": 1.0, "r_s": head.r_s, "r_cut": head.r_cut, "R_cut": args.rcut, "eps0": head.eps0,
+                   "leaf_max": args.leaf, "order": 3, "alpha": chosen["alpha"], "theta_seed": 0.7,
                    "group_size": args.group, "sr_table": args.sr_table, "keys": args.keys,
-                   "variant": "learned (MLP |a| seed + relative walk)" if best_learned
+                   "variant": "learned (MLP |a| seed + relative walk)" if best == "learned"
                    else "plain (geometric pre-walk + relative walk)"},
-        "plain": {"forces_per_s": plain_value, "ms_per_step": ms_per_step, "alpha": alpha,
-                  "errors_vs_direct": calib[alpha]},
-        "learned": learned,
-        "errors": {"vs_direct_untruncated": calib[alpha], "sample": int(len(tg_np)),
-                   "alpha_calibration": {str(k): v["p99"] for k, v in calib.items()}},
-        "roofline": {"bound": "alu", "kernel": "k_walk<1,1,false,true> (relative TreePM walk, p = 3)", "achieved": achieved / 1e12,
-                     "peak": PEAK_FP32_VECTOR / 1e12, "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_VECTOR,
-                     "traffic": traffic, "avg_ms": rwalk_ms, "flop_per_launch": walk_flop,
-                     "variant": "learned" if best_learned else "plain", "alpha": ralpha},
-        "breakdown_ms": {"prewalk": seed_ms, "walk": walk_ms, "rest": ms_per_step - seed_ms - walk_ms},
-        "interactions": {"per_particle_p2p": st["n_p2p"] / n, "per_particle_p2m": st["n_p2m"] / n,
-                         "per_particle_visit": st["n_visit"] / n, "lane_utilisation": util, "walk_passes": passes,
-                         "prewalk_per_particle": {"p2p": st_seed["n_p2p"] / n, "p2m": st_seed["n_p2m"] / n}},
+        "comparison": cmp,
+        "roofline": roof,
+        "walk_counters": {"lane_utilisation": util,
+                          "passes": {k: st[k] for k in ("w_pop", "w_p2m", "w_p2p", "w_entry", "w_leaf", "w_chunk",
+                                                        "max_stack")}},
     }
-    if not args.no_as_stated:
-        wps45 = params(4.5, 0.005)
-        e45 = errors(wps45)
-        ms45, s45, w45 = timed(wps45, max(3, args.steps // 2), 1)
-        result["as_stated_rcut4.5_alpha0.005"] = {"forces_per_s": n / (ms45 * 1e-3), "ms_per_step": ms45,
-                                                  "prewalk_ms": s45, "walk_ms": w45, "errors_vs_direct": e45}
-        log(f"[bench] as stated: {ms45:.3f} ms/step, errors {e45}")
-    if not args.no_large:
-        result["learned_vs_plain_256^3"] = bench_learned_large(args, g, ctx)
+    cpu_input = (head.ps, head.r_s, head.r_cut, head.eps0, chosen["alpha"])
+    head.free()
+    del head
+    if not args.no_small and args.n != SMALL_N:
+        small = TreePMCase(g, ctx, args, SMALL_N, SMALL_SEED)
+        sc = small.compare(max(5, args.steps), 2, args.alpha)
+        for k in ("plain", "learned"):
+            if k in sc:
+                sc[k].pop("stats", None)
+        result["treepm_128^3"] = sc
+        if not args.no_as_stated:
+            wps45 = small.params("plain", 0.005, r_cut=4.5 * small.r_s)
+            e45 = small.errors("plain", wps45)
+            ms45, ph45 = small.timed("plain", wps45, 5, 1)
+            result["as_stated_rcut4.5_alpha0.005_128^3"] = {"forces_per_s": SMALL_N / (ms45 * 1e-3),
+                                                          "ms_per_step": ms45, "phases": ph45,
+                                                          "errors_vs_direct": e45}
+            log(f"[bench] as stated (128^3, R_cut 4.5, alpha 0.005): {ms45:.3f} ms/step, errors {e45}")
+        small.free()
+        del small
     if not args.no_fmm:
-        result["fmm"] = bench_fmm(args, g, ctx, n)
+        result["fmm"] = bench_fmm(args, g, ctx, flops)
     if not args.no_forest:
         result["forest"] = bench_forest(args, g, ctx)
     if not args.no_cpu_baseline:
-        result["cpu_baseline"] = cpu_baseline(ps, n, B, r_s, args.rcut * r_s, eps0, alpha, args)
+        result["cpu_baseline"] = cpu_baseline(*cpu_input, args)
     print(json.dumps(result), flush=True)
 
 
-def bench_learned_large(args, g, ctx):
-    """Learned against plain seeding on the clustered box at N = 256^3 (held-out
-    evaluation seed 2001; the network was trained on seeds 1001-1020 at the same
-    size and leaf size): for each variant the largest alpha of the grid whose
-    p99 error against FP64 direct summation (untruncated, 10^4 random targets)
-    is <= 1e-3, then interactions per particle, time per step and percentiles."""
+def bench_fmm(args, g, ctx, flops):
+    """Symmetric FMM (p = 3, theta = 0.5) on the clustered 128^3 box drawn with
+    its own seed (3), short-range kernel at the same split, R_cut = 4.5 r_s:
+    leaf 16 as the configuration states (atomic-sum mode timed per step, the
+    sorted-list, bitwise reproducible mode timed alongside), and the
+    atomic-sum mode again at the leaf size that measured fastest (--fmm-leaf)."""
     import torch
     import workloads
-    from paper_2010_03567_amd import train_seed
-    n = 256 ** 3
-    wfile = os.path.join(ROOT, "paper_2010_03567_amd", "weights", f"seed_mlp_{n}_leaf{args.leaf}.npz")
-    if not os.path.exists(wfile):
-        return None
-    scale = (128 ** 3 / n) ** (1.0 / 3.0)
-    r_s, eps0 = 1.25 / 256 * scale, scale / (40 * 128)
-    r_cut = args.rcut * r_s
-    log(f"[bench] generating clustered box n={n} (evaluation seed 2001)")
-    ps = workloads.clustered_box(n, seed=2001)
-    dev = ctx.device
-    pos = torch.from_numpy(ps.pos).to(dev)
-    mass = torch.from_numpy(ps.mass.astype(np.float32)).to(dev)
-    del ps
-    tp = g.tree_params(True, 1.0, leaf_max=args.leaf, key_kind=KEY_KINDS[args.keys])
-    ws = torch.empty(g.g4_workspace_bytes(tp, n) + 256, dtype=torch.uint8, device=dev)
-    outs = [torch.empty(n, dtype=torch.float64, device=dev) for _ in range(3)]
-    out = (*outs, None, None, None)
-    wl, norm, meta = train_seed.load(wfile, dev)
-    aseed = torch.empty(n, dtype=torch.float32, device=dev)
-    featbuf = torch.empty((n, 8), dtype=torch.float32, device=dev)
-    fwp = g.walk_params(kernel=1, r_s=r_s, eps0=eps0)
-    st = {}
-
-    def wparams(alpha, seed):
-        return g.walk_params(kernel=1, criterion=1, alpha=alpha, theta_seed=0.7, r_s=r_s, r_cut=r_cut, eps0=eps0,
-                             a_seed=seed, group_size=args.group)
-
-    def step(variant, alpha, want_stats=False):
-        x, y, z = g.g4_quantize(ctx, pos, tp)
-        p = g.particles(x, y, z, mass)
-        tree = g.g4_build_tree(ctx, p, tp, ws=ws)
-        g.g4_compute_multipoles(ctx, tree, 3)
-        if variant == "learned":
-            feat = g.g4_mlp_features(ctx, tree, fwp, norm, out=featbuf)
-            g.g4_mlp_forward(ctx, wl, feat, shift=0.0, mode=1, out=aseed)
-        # plain: the library runs the geometric pre-walk (theta_seed) before the relative walk
-        r = g.g4_treepm_shortrange(ctx, tree, wparams(alpha, aseed if variant == "learned" else None), out=out,
-                                   want_stats=want_stats)
-        st["p"] = p
-        return r
-
-    step("plain", 0.001)
-    tg = torch.from_numpy(workloads.sample_indices(n, args.err_sample, seed=99)).to(dev)
-    ref = g.g4_direct_force(ctx, st["p"], tp, g.walk_params(kernel=1, r_s=r_s, r_cut=1e30, eps0=eps0), targets=tg,
-                            want_pot=False)
-    ref = np.stack([ref["ax"].cpu().numpy(), ref["ay"].cpu().numpy(), ref["az"].cpu().numpy()], 1)
-    res = {"workload": f"clustered box 256^3 (evaluation seed 2001), R_cut {args.rcut} r_s, leaf {args.leaf}",
-           "n": n, "weights": os.path.basename(wfile), "train_residual_rms_dex": meta.get("residual_rms")}
-    for variant in ("plain", "learned"):
-        cal, chosen = {}, None
-        for a in ALPHAS:
-            step(variant, a)
-            cal[a] = workloads.percentiles(workloads.relative_errors(torch.stack(outs, 1)[tg].cpu().numpy(), ref))
-            if cal[a]["p99"] <= ERR_BOUND:
-                chosen = a
-                break
-        if chosen is None:
-            res[variant] = {"error": "no alpha in the grid met the error bound"}
-            continue
-        for _ in range(2):
-            step(variant, chosen)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        for _ in range(5):
-            step(variant, chosen)
-        torch.cuda.synchronize()
-        ms = (time.perf_counter() - t0) * 1e3 / 5
-        s = step(variant, chosen, want_stats=True)["stats"]
-        res[variant] = {"alpha": chosen, "ms_per_step": ms, "forces_per_s": n / (ms * 1e-3),
-                        "errors_vs_direct": cal[chosen], "alpha_calibration": {str(k): v["p99"] for k, v in cal.items()},
-                        "per_particle": {"p2p": s["n_p2p"] / n, "p2m": s["n_p2m"] / n, "visit": s["n_visit"] / n,
-                                         "prewalk_p2p": s["n_seed_p2p"] / n, "prewalk_p2m": s["n_seed_p2m"] / n}}
-        log(f"[bench] 256^3 {variant}: {ms:.2f} ms/step at alpha {chosen}, errors {cal[chosen]}")
-    if "ms_per_step" in res.get("plain", {}) and "ms_per_step" in res.get("learned", {}):
-        res["speedup_learned_vs_plain"] = res["plain"]["ms_per_step"] / res["learned"]["ms_per_step"]
-    del ws, outs, featbuf, aseed
-    torch.cuda.empty_cache()
-    return res
-
-
-def bench_fmm(args, g, ctx, n):
-    """Symmetric FMM (p = 3, theta = 0.5) on the clustered box drawn with its own
-    seed, short-range kernel at the same split, R_cut = 4.5 r_s: leaf 16 as the
-    configuration states (atomic-sum mode timed per step, the sorted-list,
-    bitwise reproducible mode timed alongside), and the atomic-sum mode again at
-    the leaf size that measured fastest (--fmm-leaf)."""
-    import torch
-    import workloads
-    scale = (128 ** 3 / n) ** (1.0 / 3.0)
-    r_s, eps0 = 1.25 / 256 * scale, scale / (40 * 128)
+    n = SMALL_N
+    r_s, eps0 = treepm_scales(n)
     ps = workloads.clustered_box(n, seed=3)
     dev = ctx.device
     pos = torch.from_numpy(ps.pos).to(dev)
@@ -458,11 +478,16 @@ def bench_fmm(args, g, ctx, n):
                                   targets=torch.from_numpy(tg).to(dev), want_pot=False)
             ref["a"] = np.stack([r["ax"].cpu().numpy(), r["ay"].cpu().numpy(), r["az"].cpu().numpy()], 1)
         st = state["stats"]
+        alg = flops.fmm_flops_algorithmic(st["n_pp"], st["n_pn"], st["n_nn"], st["n_nodes"], n)
         res = {"workload": f"fmm_clustered_box_128^3 (seed 3), p=3, theta=0.5, leaf {leaf}, R_cut 4.5 r_s",
                "forces_per_s": n / (ms * 1e-3), "ms_per_step": ms, "fmm_ms": fmm_ms,
                "interactions_per_particle": {"pp": st["n_pp"] / n, "pn": st["n_pn"] / n, "nn": st["n_nn"] / n},
                "net_force_over_sum_abs": net, "list_factor": state["factor"],
-               "errors_vs_direct": workloads.percentiles(workloads.relative_errors(a[tg], ref["a"]))}
+               "errors_vs_direct": workloads.percentiles(workloads.relative_errors(a[tg], ref["a"])),
+               "roofline": {"bound": "alu", "kernel": "whole FMM call (all kernels)", "unit": "TFLOP/s",
+                            "achieved": alg / (fmm_ms * 1e-3) / 1e12, "peak": PEAK_FP32_VECTOR / 1e12,
+                            "frac": alg / (fmm_ms * 1e-3) / PEAK_FP32_VECTOR, "flop_per_call": alg,
+                            "flop_units": flops.FMM_ALG}}
         msg = f"[bench] fmm leaf {leaf}: {ms:.3f} ms/step (fmm {fmm_ms:.3f} ms"
         if with_sorted:
             ms_det, fmm_det_ms, _ = run(1, 2)
@@ -480,147 +505,85 @@ def bench_fmm(args, g, ctx, n):
 def bench_forest(args, g, ctx):
     """Batched persistent walk over 64 independent clustered boxes (N log-uniform
     in [32768, 1048576], seeds 3000+b, concentration spread x3), leaf and group
-    size from the autotuner's table when present."""
+    size from the autotuner's table when present; force errors against FP64
+    direct summation on random targets spread over all boxes."""
     import workloads
     from paper_2010_03567_amd.autotune import ForestStep
     boxes = workloads.forest(64, seed=3000)
     r_s = 1.25 / 256
     tf = os.path.join(ROOT, "paper_2010_03567_amd", "weights", "autotune_forest.json")
-    B, G, tuned = 8, 64, False
+    B, G, alpha, tuned = 8, 64, 0.001, False
     if os.path.exists(tf):
         with open(tf) as fh:
             t = json.load(fh)
         B, G, tuned = int(t["B"]), int(t["G"]), True
-    step = ForestStep(ctx, boxes, r_s, args.rcut * r_s, 1.0 / (40 * 128), 0.001)
+        alpha = float(t.get("alpha_chosen", t.get("alpha", alpha)))
+    step = ForestStep(ctx, boxes, r_s, args.rcut * r_s, 1.0 / (40 * 128), alpha)
     ms, pre, walk = step.time(B, G, steps=max(3, args.steps // 2))
-    log(f"[bench] forest: {step.n} particles in 64 boxes, {ms:.3f} ms/step (B={B}, G={G})")
+    err = step.errors(B, G, args.err_sample)
+    log(f"[bench] forest: {step.n} particles in 64 boxes, {ms:.3f} ms/step (B={B}, G={G}), errors {err}")
     return {"workload": "forest of 64 clustered boxes", "n": step.n, "forces_per_s": step.n / (ms * 1e-3),
             "ms_per_step": ms, "prewalk_ms": pre, "walk_ms": walk, "leaf_max": B, "group_size": G,
-            "autotuned": tuned, "R_cut": args.rcut, "alpha": 0.001}
+            "autotuned": tuned, "R_cut": args.rcut, "alpha": alpha, "errors_vs_direct": err}
 
 
-def learned_step(args, g, ctx, n, r_s, eps0, tp, ws, pos, mass, out, stream, state):
-    """(lparams, lstep, wfile, meta) of the learned variant: features -> MLP ->
-    |a| seed -> relative walk; None if no weights for this particle count."""
-    import torch
-    wdir = os.path.join(ROOT, "paper_2010_03567_amd", "weights")
-    wfile = args.weights or os.path.join(wdir, f"seed_mlp_{n}.npz" if args.leaf == 8 else f"seed_mlp_{n}_leaf{args.leaf}.npz")
-    if args.no_learned or not os.path.exists(wfile):
-        return None
-    from paper_2010_03567_amd import train_seed
-    wl, norm, meta = train_seed.load(wfile, ctx.device)
-    if int(meta.get("leaf", 8)) != args.leaf:
-        log(f"[bench] {os.path.basename(wfile)} was trained on leaf size {meta.get('leaf', 8)}, not {args.leaf}")
-        return None
-    aseed = torch.empty(n, dtype=torch.float32, device=ctx.device)
-    featbuf = torch.empty((n, 8), dtype=torch.float32, device=ctx.device)
-    fwp = g.walk_params(kernel=1, r_s=r_s, eps0=eps0)
-
-    def lparams(alpha):
-        return g.walk_params(kernel=1, criterion=1, alpha=alpha, r_s=r_s, r_cut=args.rcut * r_s, eps0=eps0,
-                             a_seed=aseed, group_size=args.group, sr_table=args.sr_table)
-
-    def lstep(wp, evs=None):
-        x, y, z = g.g4_quantize(ctx, pos, tp)
-        p = g.particles(x, y, z, mass)
-        tree = g.g4_build_tree(ctx, p, tp, ws=ws)
-        g.g4_compute_multipoles(ctx, tree, 3)
-        if evs is not None:
-            evs[0].record(stream)
-        feat = g.g4_mlp_features(ctx, tree, fwp, norm, out=featbuf)
-        g.g4_mlp_forward(ctx, wl, feat, shift=0.0, mode=1, out=aseed)
-        if evs is not None:
-            evs[1].record(stream)
-        g.g4_treepm_shortrange(ctx, tree, wp, out=out)
-        if evs is not None:
-            evs[2].record(stream)
-        state["tree"] = tree
-
-    return lparams, lstep, wfile, meta
-
-
-def learned_variant(args, g, ctx, n, r_s, eps0, tp, ws, pos, mass, out, outs, stream, state, tg, ref, plain_ms):
-    """The same step with the geometric pre-walk replaced by the trained network:
-    features -> MLP -> |a| seed -> relative walk; alpha calibrated like the plain walk."""
-    import torch
-    import workloads
-    made = learned_step(args, g, ctx, n, r_s, eps0, tp, ws, pos, mass, out, stream, state)
-    if made is None:
-        return None
-    lparams, lstep, wfile, meta = made
-
-    lcal, lalpha = {}, None
-    for a in ALPHAS:
-        lstep(lparams(a))
-        lcal[a] = workloads.percentiles(workloads.relative_errors(torch.stack(outs, 1)[tg].cpu().numpy(), ref))
-        log(f"[bench] learned alpha={a}: {lcal[a]}")
-        if lcal[a]["p99"] <= ERR_BOUND:
-            lalpha = a
-            break
-    if lalpha is None:
-        return {"error": "no alpha in the grid met the error bound",
-                "alpha_calibration": {str(k): v["p99"] for k, v in lcal.items()}}
-    wpl = lparams(lalpha)
-    for _ in range(args.warmup):
-        lstep(wpl)
-    torch.cuda.synchronize()
-    evl = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(args.steps)]
-    t0 = time.perf_counter()
-    for k in range(args.steps):
-        lstep(wpl, evl[k])
-    torch.cuda.synchronize()
-    ms_l = (time.perf_counter() - t0) * 1e3 / args.steps
-    mlp_ms = float(np.mean([e[0].elapsed_time(e[1]) for e in evl]))
-    lwalk_ms = float(np.mean([e[1].elapsed_time(e[2]) for e in evl]))
-    stl = g.g4_treepm_shortrange(ctx, state["tree"], wpl, out=out, want_stats=True)["stats"]
-    log(f"[bench] learned: {ms_l:.3f} ms/step (seed {mlp_ms:.3f} ms, walk {lwalk_ms:.3f} ms), alpha={lalpha}, "
-        f"speedup {plain_ms / ms_l:.2f}x")
-    return {"forces_per_s": n / (ms_l * 1e-3), "ms_per_step": ms_l, "alpha": lalpha, "seed_ms": mlp_ms,
-            "walk_ms": lwalk_ms, "errors_vs_direct": lcal[lalpha],
-            "alpha_calibration": {str(k): v["p99"] for k, v in lcal.items()},
-            "per_particle_p2p": stl["n_p2p"] / n, "per_particle_p2m": stl["n_p2m"] / n, "stats": stl,
-            "speedup_vs_plain": plain_ms / ms_l, "weights": os.path.basename(wfile),
-            "trained_on": {k: meta.get(k) for k in ("n", "leaf", "seeds", "rcut", "alpha", "steps", "tau")},
-            "train_residual_rms_dex": meta.get("residual_rms")}
-
-
-def cpu_baseline(ps, n, B, r_s, r_cut, eps0, alpha, args):
-    """The FP64 oracle timed on the host cores: tree build + moments over all n
-    particles, then pre-walk + relative walk on a random sample of targets,
-    scaled per particle to n."""
+def cpu_baseline(ps, r_s, r_cut, eps0, alpha, args):
+    """The FP64 oracle (built -O3 -march=native on this host) on all host
+    cores: quantise + tree + moments over every particle, then pre-walk +
+    relative walk for a random sample of targets sized to about
+    --cpu-seconds of walking, scaled per particle to the whole box."""
+    import platform
     import oracle
     import workloads
-    threads = min(16, os.cpu_count() or 1)
+    oracle.select(native=True)
+    threads = os.cpu_count() or 1
+    try:
+        model = next((ln.split(":", 1)[1].strip() for ln in open("/proc/cpuinfo") if ln.startswith("model name")),
+                     platform.processor())
+    except OSError:
+        model = platform.processor()
+    n = ps.pos.shape[0]
+    B = args.leaf
     t0 = time.perf_counter()
     st, X, Y, Z = oracle.quantize(ps.pos, True, ps.box)
-    t = oracle.Tree(X, Y, Z, ps.mass.astype(np.float32).astype(np.float64), True, ps.box, B)
-    t.compute_moments()
+    t = oracle.Tree(X, Y, Z, ps.mass.astype(np.float32).astype(np.float64), True, ps.box, B, nthreads=threads)
+    t.compute_moments(nthreads=threads)
     t1 = time.perf_counter()
-    tg = workloads.sample_indices(n, args.cpu_sample, seed=5)
-    kw = dict(kernel=1, r_s=r_s, r_cut=r_cut, eps0=eps0, nthreads=threads, targets=tg, want_pot=False)
-    a0, _, _ = t.walk(criterion=0, theta=0.7, **kw)
-    seed = np.zeros(n)
-    seed[tg] = np.linalg.norm(a0, axis=1)
-    t.walk(criterion=1, alpha=alpha, aseed=seed, **kw)
+    kw = dict(kernel=1, r_s=r_s, r_cut=r_cut, eps0=eps0, nthreads=threads, want_pot=False)
+
+    def walks(tg, nth):
+        k = dict(kw, targets=tg, nthreads=nth)
+        a0, _, _ = t.walk(criterion=0, theta=0.7, **k)
+        seed = np.zeros(n)
+        seed[tg] = np.linalg.norm(a0, axis=1)
+        t.walk(criterion=1, alpha=alpha, aseed=seed, **k)
+
+    # a small probe sizes the sample to the requested CPU time
+    probe = workloads.sample_indices(n, 20 * threads, seed=4)
+    tp0 = time.perf_counter()
+    walks(probe, threads)
+    per = (time.perf_counter() - tp0) / len(probe)
+    k = int(min(n, max(1000, args.cpu_seconds / max(per, 1e-9))))
+    tg = workloads.sample_indices(n, k, seed=5)
     t2 = time.perf_counter()
-    total = (t1 - t0) + (t2 - t1) * n / len(tg)
-    log(f"[bench] oracle: build+moments {t1 - t0:.2f} s, walks on {len(tg)} targets {t2 - t1:.2f} s")
-    # one thread, as the paper's single-core timings: the same walks on a tenth of the sample
-    tg1 = tg[: max(1, len(tg) // 10)]
-    kw1 = dict(kw, nthreads=1, targets=tg1)
+    walks(tg, threads)
     t3 = time.perf_counter()
-    b0, _, _ = t.walk(criterion=0, theta=0.7, **kw1)
-    seed1 = np.zeros(n)
-    seed1[tg1] = np.linalg.norm(b0, axis=1)
-    t.walk(criterion=1, alpha=alpha, aseed=seed1, **kw1)
+    total = (t1 - t0) + (t3 - t2) * n / len(tg)
+    log(f"[bench] oracle ({threads} threads, {model}): build+moments {t1 - t0:.2f} s, walks on {len(tg)} targets "
+        f"{t3 - t2:.2f} s")
+    # one thread, as the paper's single-core timings: the walks on a slice of the sample
+    tg1 = tg[: max(1, len(tg) // threads)]
     t4 = time.perf_counter()
-    total1 = (t1 - t0) + (t4 - t3) * n / len(tg1)
-    return {"value": n / total, "unit": "forces/s", "cores": threads, "kind": "oracle",
-            "sample": f"quantise+tree+moments over all {n} particles ({t1 - t0:.1f} s) + pre-walk and relative "
-                      f"walk (same R_cut, alpha) for {len(tg)} random targets ({t2 - t1:.1f} s), scaled to {n}",
-            "single_thread": {"value": n / total1, "unit": "forces/s", "cores": 1,
-                              "sample": f"the same build + walks for {len(tg1)} of the targets on one thread "
-                                        f"({t4 - t3:.1f} s), scaled to {n}"}}
+    walks(tg1, 1)
+    t5 = time.perf_counter()
+    return {"value": n / total, "unit": "forces/s", "cores": threads, "kind": "oracle", "cpu_model": model,
+            "build": "gcc -O3 -march=native, pthreads",
+            "sample": f"quantise+tree+moments over all {n} particles of the headline box ({t1 - t0:.1f} s) + "
+                      f"pre-walk and relative walk (same R_cut, alpha {alpha}) for {len(tg)} random targets "
+                      f"({t3 - t2:.1f} s), scaled to {n}",
+            "single_thread_walk": {"forces_per_s_walk_only": len(tg1) / (t5 - t4), "cores": 1,
+                                   "sample": f"pre-walk + relative walk for {len(tg1)} of the targets on one thread "
+                                             f"({t5 - t4:.1f} s)"}}
 
 
 if __name__ == "__main__":

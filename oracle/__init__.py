@@ -16,16 +16,31 @@ import numpy as np
 HERE = os.path.dirname(os.path.abspath(__file__))
 SRC = os.path.join(HERE, "g4oracle.c")
 LIB = os.path.join(HERE, "libg4oracle.so")
+LIB_NATIVE = os.path.join(HERE, "libg4oracle_native.so")
 
 
-def build(force: bool = True) -> str:
-    """Compile the oracle with gcc (plain -O2, portable code)."""
-    if force or not os.path.exists(LIB):
-        tmp = LIB + ".tmp"
-        subprocess.check_call(["gcc", "-O2", "-std=c99", "-D_GNU_SOURCE", "-fPIC", "-shared", "-Wall",
+def build(force: bool = True, native: bool = False) -> str:
+    """Compile the oracle with gcc: plain -O2 portable code (tests), or -O3
+    -march=native for timing it on the host it runs on."""
+    out = LIB_NATIVE if native else LIB
+    if force or not os.path.exists(out):
+        tmp = out + ".tmp"
+        opt = ["-O3", "-march=native"] if native else ["-O2"]
+        subprocess.check_call(["gcc", *opt, "-std=c99", "-D_GNU_SOURCE", "-fPIC", "-shared", "-Wall",
                                "-o", tmp, SRC, "-lm", "-lpthread"])
-        os.replace(tmp, LIB)
-    return LIB
+        os.replace(tmp, out)
+    return out
+
+
+def select(native: bool) -> None:
+    """Load the -O3 -march=native build (compiled here, for this host) instead of
+    the portable one; call before the first oracle function."""
+    global _lib, _which
+    if _lib is not None and _which == native:
+        return
+    if native:
+        build(force=True, native=True)
+    _lib, _which = None, native
 
 
 class WalkParams(C.Structure):
@@ -40,14 +55,16 @@ class FmmParams(C.Structure):
 
 
 _lib = None
+_which = False
 
 
 def lib():
     global _lib
     if _lib is None:
-        if not os.path.exists(LIB):
-            build(force=True)
-        L = C.CDLL(LIB)
+        path = LIB_NATIVE if _which else LIB
+        if not os.path.exists(path):
+            build(force=True, native=_which)
+        L = C.CDLL(path)
         d, p, i64, i32 = C.c_double, C.c_void_p, C.c_int64, C.c_int
         L.orc_soft_K.restype = d; L.orc_soft_K.argtypes = [d, d]
         L.orc_soft_W.restype = d; L.orc_soft_W.argtypes = [d, d]
@@ -63,6 +80,9 @@ def lib():
         L.orc_tree_nnodes.restype = i64; L.orc_tree_nnodes.argtypes = [p]
         L.orc_tree_nodes.argtypes = [p, p, p, p, p]
         L.orc_moments.argtypes = [p]
+        L.orc_build_mt.restype = p
+        L.orc_build_mt.argtypes = [i64, p, p, p, p, i32, d, i32, i32, i32]
+        L.orc_moments_mt.argtypes = [p, i32]
         L.orc_tree_moments.argtypes = [p, p, p, p, p]
         L.orc_walk.restype = i32
         L.orc_walk.argtypes = [p, C.POINTER(WalkParams), p, p, i64, p, p, p, i32]
@@ -137,15 +157,19 @@ def quantize(pos, periodic, box, origin=(0.0, 0.0, 0.0)):
 class Tree:
     """Oracle octree over integer positions (recursive index partition)."""
 
-    def __init__(self, X, Y, Z, mass, periodic, box, leaf_max, max_depth=21):
+    def __init__(self, X, Y, Z, mass, periodic, box, leaf_max, max_depth=21, nthreads=1):
         self.X, self.Y, self.Z = _u32(X), _u32(Y), _u32(Z)
         self.mass = _f64(mass)
         self.n = self.X.shape[0]
         self.periodic = bool(periodic)
         self.box = float(box)
         self.unit = self.box / (2.0 ** 32 if periodic else 2.0 ** 31)
-        self._h = lib().orc_build(self.n, _ptr(self.X), _ptr(self.Y), _ptr(self.Z), _ptr(self.mass),
-                                  int(periodic), self.box, int(leaf_max), int(max_depth))
+        if nthreads > 1:
+            self._h = lib().orc_build_mt(self.n, _ptr(self.X), _ptr(self.Y), _ptr(self.Z), _ptr(self.mass),
+                                         int(periodic), self.box, int(leaf_max), int(max_depth), int(nthreads))
+        else:
+            self._h = lib().orc_build(self.n, _ptr(self.X), _ptr(self.Y), _ptr(self.Z), _ptr(self.mass),
+                                      int(periodic), self.box, int(leaf_max), int(max_depth))
         self.has_moments = False
 
     def __del__(self):
@@ -165,8 +189,8 @@ class Tree:
         lib().orc_tree_nodes(self._h, _ptr(level), _ptr(cell), _ptr(count), _ptr(leaf))
         return level, cell, count, leaf
 
-    def compute_moments(self):
-        lib().orc_moments(self._h)
+    def compute_moments(self, nthreads=1):
+        lib().orc_moments_mt(self._h, int(nthreads))
         self.has_moments = True
 
     def moments(self):

@@ -242,28 +242,36 @@ struct orc_tree {
     int has_moments;
 };
 
-static int64_t new_nodes(orc_tree *t, int k)
+/* Node storage: the tree's own array, or a private buffer of one thread. */
+typedef struct {
+    onode *nodes;
+    int64_t nnodes, cap;
+} node_store;
+
+static int64_t new_nodes(node_store *st, int k)
 {
-    if (t->nnodes + k > t->cap) {
-        t->cap = 2 * (t->nnodes + k) + 64;
-        t->nodes = (onode *)realloc(t->nodes, (size_t)t->cap * sizeof(onode));
+    if (st->nnodes + k > st->cap) {
+        st->cap = 2 * (st->nnodes + k) + 64;
+        st->nodes = (onode *)realloc(st->nodes, (size_t)st->cap * sizeof(onode));
     }
-    int64_t first = t->nnodes;
-    memset(t->nodes + first, 0, (size_t)k * sizeof(onode));
-    t->nnodes += k;
+    int64_t first = st->nnodes;
+    memset(st->nodes + first, 0, (size_t)k * sizeof(onode));
+    st->nnodes += k;
     return first;
 }
 
 static uint32_t rel_coord(const orc_tree *t, uint32_t X) { return X - t->corner; }
 
-/* Split node `ni` if it holds more than B particles and is above the depth cap. */
-static void split_node(orc_tree *t, int64_t ni)
+/* Split node `ni` of store `st` into its occupied octants if it holds more
+ * than B particles and lies above the depth cap (the particle indices of the
+ * node are regrouped by octant, stably).  Returns the number of children. */
+static int split_one(const orc_tree *t, node_store *st, int64_t ni)
 {
-    onode nd = t->nodes[ni];
+    onode nd = st->nodes[ni];
     if (nd.count <= t->leaf_max || nd.level >= t->max_depth) {
-        t->nodes[ni].leaf = 1;
-        t->nodes[ni].child0 = -1;
-        return;
+        st->nodes[ni].leaf = 1;
+        st->nodes[ni].child0 = -1;
+        return 0;
     }
     int bit = t->S - nd.level - 1;  /* bit selecting the child half */
     int64_t cnt[8] = {0};
@@ -288,15 +296,15 @@ static void split_node(orc_tree *t, int64_t ni)
 
     int nch = 0;
     for (int c = 0; c < 8; c++) nch += cnt[c] > 0;
-    int64_t c0 = new_nodes(t, nch);
-    onode *parent = &t->nodes[ni];
+    int64_t c0 = new_nodes(st, nch);
+    onode *parent = &st->nodes[ni];
     parent->child0 = c0;
     parent->nchild = nch;
     parent->leaf = 0;
     int k = 0;
     for (int c = 0; c < 8; c++) {
         if (!cnt[c]) continue;
-        onode *ch = &t->nodes[c0 + k++];
+        onode *ch = &st->nodes[c0 + k++];
         ch->level = nd.level + 1;
         ch->cell[0] = 2 * nd.cell[0] + ((c >> 2) & 1);
         ch->cell[1] = 2 * nd.cell[1] + ((c >> 1) & 1);
@@ -304,11 +312,95 @@ static void split_node(orc_tree *t, int64_t ni)
         ch->first = nd.first + off[c];
         ch->count = cnt[c];
     }
-    for (int q = 0; q < nch; q++) split_node(t, c0 + q);
+    return nch;
+}
+
+/* Split recursively, depth first. */
+static void split_node(const orc_tree *t, node_store *st, int64_t ni)
+{
+    int nch = split_one(t, st, ni);
+    int64_t c0 = st->nodes[ni].child0;
+    for (int q = 0; q < nch; q++) split_node(t, st, c0 + q);
+}
+
+/* Parallel build: the top levels are split in order on one thread; each
+ * node left unsplit there roots a subtree that one thread builds into its
+ * own store (the subtrees own disjoint ranges of t->idx); the subtrees are
+ * then appended to the tree's array with their child indices shifted.  The
+ * node set and every node's particles are those of the serial build; only
+ * the numbering of the nodes differs. */
+typedef struct {
+    const orc_tree *t;
+    int64_t *roots;        /* main-store indices of the subtree roots */
+    node_store *stores;    /* one per root */
+    int64_t nroots;
+    int64_t next;          /* shared work counter */
+} sub_job;
+
+static void *subtree_thread(void *arg)
+{
+    sub_job *J = (sub_job *)arg;
+    for (;;) {
+        int64_t k = __sync_fetch_and_add(&J->next, 1);
+        if (k >= J->nroots) break;
+        split_node(J->t, &J->stores[k], 0);
+    }
+    return NULL;
+}
+
+static void build_parallel(orc_tree *t, node_store *main, int nthreads)
+{
+    /* breadth-first split of the top until there are enough subtrees */
+    int64_t lo = 0, hi = main->nnodes;
+    while (hi - lo < 8 * (int64_t)nthreads && hi > lo) {
+        for (int64_t q = lo; q < hi; q++) split_one(t, main, q);
+        lo = hi;
+        hi = main->nnodes;
+    }
+    int64_t nr = hi - lo;
+    sub_job J;
+    J.t = t;
+    J.nroots = nr;
+    J.next = 0;
+    J.roots = (int64_t *)malloc((size_t)(nr > 0 ? nr : 1) * sizeof(int64_t));
+    J.stores = (node_store *)calloc((size_t)(nr > 0 ? nr : 1), sizeof(node_store));
+    for (int64_t k = 0; k < nr; k++) {
+        J.roots[k] = lo + k;
+        new_nodes(&J.stores[k], 1);
+        J.stores[k].nodes[0] = main->nodes[lo + k];
+    }
+    pthread_t *th = (pthread_t *)malloc(sizeof(pthread_t) * nthreads);
+    for (int k = 0; k < nthreads; k++) pthread_create(&th[k], NULL, subtree_thread, &J);
+    for (int k = 0; k < nthreads; k++) pthread_join(th[k], NULL);
+    free(th);
+    for (int64_t k = 0; k < nr; k++) {
+        node_store *sb = &J.stores[k];
+        int64_t base = main->nnodes - 1;  /* local index i >= 1 goes to base + i */
+        if (main->nnodes + sb->nnodes - 1 > main->cap) {
+            main->cap = main->nnodes + sb->nnodes + 64;
+            main->nodes = (onode *)realloc(main->nodes, (size_t)main->cap * sizeof(onode));
+        }
+        for (int64_t i = 0; i < sb->nnodes; i++) {
+            onode nd = sb->nodes[i];
+            if (!nd.leaf) nd.child0 += base;
+            if (i == 0) main->nodes[J.roots[k]] = nd;
+            else main->nodes[base + i] = nd;
+        }
+        main->nnodes += sb->nnodes - 1;
+        free(sb->nodes);
+    }
+    free(J.roots);
+    free(J.stores);
 }
 
 orc_tree *orc_build(int64_t n, const uint32_t *X, const uint32_t *Y, const uint32_t *Z, const double *mass,
                     int periodic, double box, int leaf_max, int max_depth)
+{
+    return orc_build_mt(n, X, Y, Z, mass, periodic, box, leaf_max, max_depth, 1);
+}
+
+orc_tree *orc_build_mt(int64_t n, const uint32_t *X, const uint32_t *Y, const uint32_t *Z, const double *mass,
+                       int periodic, double box, int leaf_max, int max_depth, int nthreads)
 {
     orc_tree *t = (orc_tree *)calloc(1, sizeof(orc_tree));
     t->n = n;
@@ -329,10 +421,15 @@ orc_tree *orc_build(int64_t n, const uint32_t *X, const uint32_t *Y, const uint3
     memcpy(t->Z, Z, (size_t)n * 4);
     memcpy(t->m, mass, (size_t)n * 8);
     for (int64_t i = 0; i < n; i++) t->idx[i] = i;
-    int64_t r = new_nodes(t, 1);
-    t->nodes[r].first = 0;
-    t->nodes[r].count = n;
-    split_node(t, r);
+    node_store st = {NULL, 0, 0};
+    int64_t r = new_nodes(&st, 1);
+    st.nodes[r].first = 0;
+    st.nodes[r].count = n;
+    if (nthreads > 1) build_parallel(t, &st, nthreads);
+    else split_node(t, &st, r);
+    t->nodes = st.nodes;
+    t->nnodes = st.nnodes;
+    t->cap = st.cap;
     /* geometric centres */
     for (int64_t q = 0; q < t->nnodes; q++) {
         onode *nd = &t->nodes[q];
@@ -379,9 +476,9 @@ static uint64_t half_side_int(const orc_tree *t, int level)
  * 5. Multipole moments by direct sums over each node's particles
  * ====================================================================== */
 
-void orc_moments(orc_tree *t)
+static void node_moments(orc_tree *t, int64_t q)
 {
-    for (int64_t q = 0; q < t->nnodes; q++) {
+    {
         onode *nd = &t->nodes[q];
         double M = 0.0, c[3] = {0, 0, 0};
         for (int64_t a = 0; a < nd->count; a++) {
@@ -408,6 +505,40 @@ void orc_moments(orc_tree *t)
                 }
         }
     }
+}
+
+void orc_moments(orc_tree *t)
+{
+    for (int64_t q = 0; q < t->nnodes; q++) node_moments(t, q);
+    t->has_moments = 1;
+}
+
+/* The same direct sums with the nodes shared out to threads (each node's
+ * sums are independent of every other node's). */
+typedef struct { orc_tree *t; int64_t next; } mom_job;
+
+static void *moments_thread(void *arg)
+{
+    mom_job *J = (mom_job *)arg;
+    for (;;) {
+        int64_t q = __sync_fetch_and_add(&J->next, 1);
+        if (q >= J->t->nnodes) break;
+        node_moments(J->t, q);
+    }
+    return NULL;
+}
+
+void orc_moments_mt(orc_tree *t, int nthreads)
+{
+    if (nthreads <= 1) {
+        orc_moments(t);
+        return;
+    }
+    mom_job J = {t, 0};
+    pthread_t *th = (pthread_t *)malloc(sizeof(pthread_t) * nthreads);
+    for (int k = 0; k < nthreads; k++) pthread_create(&th[k], NULL, moments_thread, &J);
+    for (int k = 0; k < nthreads; k++) pthread_join(th[k], NULL);
+    free(th);
     t->has_moments = 1;
 }
 

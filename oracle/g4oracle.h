@@ -46,6 +46,11 @@ void orc_free(orc_tree *t);
 int64_t orc_tree_nnodes(const orc_tree *t);
 void orc_tree_nodes(const orc_tree *t, int32_t *level, uint32_t *cell3, int64_t *count, int32_t *leaf);
 void orc_moments(orc_tree *t);
+/* the same, with the work shared out to nthreads threads (the serial code
+ * above for nthreads <= 1; the threaded build numbers the nodes differently) */
+orc_tree *orc_build_mt(int64_t n, const uint32_t *X, const uint32_t *Y, const uint32_t *Z, const double *mass,
+                       int periodic, double box, int leaf_max, int max_depth, int nthreads);
+void orc_moments_mt(orc_tree *t, int nthreads);
 void orc_tree_moments(const orc_tree *t, double *mass, double *com3, double *q2p, double *q3p);
 
 /* one-sided walk; aseed (|a| per particle, caller order) needed for criterion 1.

@@ -1,7 +1,12 @@
 """Autotuner for the batched persistent walk: picks the leaf size B of the
 tree and the particle-group size G of the walk's wavefront groups by timing
 the whole step (forest build, multipoles, geometric pre-walk, relative walk)
-on the workload itself.  The table and the choice are written as JSON.
+on the workload itself, at equal accuracy: the leaf size changes the tree and
+so the error at a given alpha, so for every B the largest alpha of a sqrt(2)
+grid whose 99th-percentile force error against FP64 direct summation is at
+most 1e-3 is found first, and the group sizes are timed at that alpha (the
+group size changes the work packing, not the decisions).  G is capped at the
+64 lanes of a wavefront.  The table and the choice are written as JSON.
 
     python -m paper_2010_03567_amd.autotune --out paper_2010_03567_amd/weights/autotune_forest.json
 """
@@ -26,6 +31,8 @@ import paper_2010_03567_amd.g4hip as g  # noqa: E402
 
 LEAVES = (4, 8, 16, 24, 32)
 GROUPS = (16, 32, 48, 64)
+ALPHAS = (0.004, 0.0028, 0.002, 0.0014, 0.001, 0.0007, 0.0005, 0.00035)
+ERR_BOUND = 1e-3
 
 
 class ForestStep:
@@ -42,6 +49,37 @@ class ForestStep:
         self.alpha, self.theta_seed = alpha, theta_seed
         self.outs = [torch.empty(self.n, dtype=torch.float64, device=dev) for _ in range(3)]
         self.ws = {}
+        self.ref = None
+
+    def reference(self, nsample):
+        """FP64 direct summation (untruncated short-range sum within each box) on
+        random targets spread over the boxes in proportion to their size."""
+        if self.ref is None:
+            ctx, dev = self.ctx, self.ctx.device
+            tp = g.tree_params(True, 1.0, leaf_max=8)
+            x, y, z = g.g4_quantize(ctx, self.pos, tp)
+            wpd = g.walk_params(kernel=1, r_s=self.kw["r_s"], r_cut=1e30, eps0=self.kw["eps0"])
+            tg_all, ref = [], []
+            for b in range(len(self.off) - 1):
+                lo, hi = int(self.off[b]), int(self.off[b + 1])
+                k = max(8, int(round(nsample * (hi - lo) / self.n)))
+                tg = workloads.sample_indices(hi - lo, k, seed=500 + b)
+                p = g.particles(x[lo:hi], y[lo:hi], z[lo:hi], self.mass[lo:hi])
+                r = g.g4_direct_force(ctx, p, tp, wpd, targets=torch.from_numpy(tg).to(dev), want_pot=False)
+                ref.append(torch.stack([r["ax"], r["ay"], r["az"]], 1).cpu().numpy())
+                tg_all.append(tg + lo)
+            self.tg = torch.from_numpy(np.concatenate(tg_all)).to(dev)
+            self.ref = np.concatenate(ref)
+        return self.ref
+
+    def errors(self, B, G, nsample=10000, alpha=None):
+        """Percentiles of the relative force error of one step against the reference."""
+        ref = self.reference(nsample)
+        if alpha is not None:
+            self.alpha = alpha
+        self.run(B, G)
+        a = torch.stack(self.outs, 1)[self.tg].cpu().numpy()
+        return workloads.percentiles(workloads.relative_errors(a, ref))
 
     def run(self, B, G, evs=None):
         ctx = self.ctx
@@ -81,15 +119,25 @@ class ForestStep:
             np.mean([e[1].elapsed_time(e[2]) for e in evs]))
 
 
-def tune(step: ForestStep, leaves=LEAVES, groups=GROUPS, steps=3, log=print):
+def tune(step: ForestStep, leaves=LEAVES, groups=GROUPS, steps=3, log=print, nsample=10000):
     table = []
     for B in leaves:
+        alpha, err = None, None
+        for a in ALPHAS:
+            e = step.errors(B, 64, nsample, alpha=a)
+            log(f"[autotune] B={B} alpha={a}: {e}")
+            if e["p99"] <= ERR_BOUND:
+                alpha, err = a, e
+                break
+        if alpha is None:
+            continue
+        step.alpha = alpha
         for G in groups:
             ms, pre, walk = step.time(B, G, steps=steps)
-            table.append(dict(B=B, G=G, ms_per_step=ms, prewalk_ms=pre, walk_ms=walk))
-            log(f"[autotune] B={B} G={G}: {ms:.2f} ms/step (pre-walk {pre:.2f}, walk {walk:.2f})")
+            table.append(dict(B=B, G=G, alpha=alpha, errors=err, ms_per_step=ms, prewalk_ms=pre, walk_ms=walk))
+            log(f"[autotune] B={B} G={G} alpha={alpha}: {ms:.2f} ms/step (pre-walk {pre:.2f}, walk {walk:.2f})")
     best = min(table, key=lambda r: r["ms_per_step"])
-    return dict(B=best["B"], G=best["G"], table=table)
+    return dict(B=best["B"], G=best["G"], alpha_chosen=best["alpha"], errors=best["errors"], table=table)
 
 
 def main():

@@ -1,28 +1,40 @@
 """Algorithmic floating-point operation counts per interaction (frozen).
 
-Counted from the formulas as the kernels evaluate them: an add, multiply,
-subtract or max of floats counts 1, a fused multiply-add counts 2, a hardware
-transcendental (rsqrt, rcp, exp2) counts 1; integer differences,
-int-to-float conversions and compares count 0.
+The roofline fractions are reported at these per-interaction units, counted
+from the formulas of the interactions themselves (a fused multiply-add counts
+2, a transcendental 1), independent of how a kernel schedules them:
 
-* visit: the per-lane cost of looking at one node: relative vector to the
-  centre of mass (3), r^2 (5), rsqrt (1), the opening test (geometric 2,
-  relative 7: l^3, r^5, M l^3, alpha|a| r^5) and, for the short-range
-  kernel, the nearest-edge distance against r_cut (15).
-* p2m: a particle-node interaction beyond the visit that precedes it:
-  g_1..g_3 of the kernel (Newtonian 6; short-range 47 including exp and the
-  Hastings erfc: rcp + 4 FMA) and the quadrupole force M D1 + Q2:D3 / 2 (40).
-* p2p: a whole particle-particle interaction: relative vector (3), r^2 (5),
-  rsqrt (1), 1/r^2 (1), kernel factor (Newtonian 1; short-range 24),
-  m K (1), accumulation (3 FMA = 6).
+* P2P_ALG: one particle-particle interaction: separation, r^2, 1/r, the
+  softened kernel factor and the accumulation (Newtonian ~19); the TreePM
+  short-range factor adds ~25 (erfc, exp and the polynomial around them).
+* P2M_ALG: one particle-node interaction at p = 3 (monopole + quadrupole
+  force, -G [M D1 + Q2:D3 / 2]) with Newtonian g_n; the same ~25 for the
+  short-range g_n.
+* FMM_ALG: symmetric node-node interaction (field expansions to order 3 in
+  both nodes) ~275, particle-node pair (M2P + P2L) ~120, particle pair 44,
+  downward shift per node ~100, evaluation per particle ~40.
+
+The opening decisions are not algorithmic work of the interactions: the
+per-lane cost of one criterion evaluation is listed as VISIT_BOOKKEEPING
+(relative vector, r^2, the criterion and, for TreePM, the nearest-edge test
+against r_cut) and reported beside the fraction, never inside it.
 """
 
-VISIT = {("newton", "geometric"): 11, ("newton", "relative"): 16,
-         ("treepm", "geometric"): 26, ("treepm", "relative"): 31}
-P2M = {"newton": 46, "treepm": 87}
-P2P = {"newton": 18, "treepm": 40}
+P2P_ALG = {"newton": 19, "treepm": 44}
+P2M_ALG = {"newton": 60, "treepm": 85}
+FMM_ALG = {"nn": 275, "pn": 120, "pp": 44, "l2l_per_node": 100, "l2p_per_particle": 40}
+VISIT_BOOKKEEPING = {("newton", "geometric"): 11, ("newton", "relative"): 16,
+                     ("treepm", "geometric"): 26, ("treepm", "relative"): 31}
 MLP_FORWARD = 64 * 8 * 2 + 64 * 64 * 2 + 64 * 2 + 128 * 5  # per particle (FMA = 2, SiLU = 5)
 
 
-def walk_flops(kernel: str, criterion: str, n_visit: int, n_p2m: int, n_p2p: int) -> float:
-    return (VISIT[(kernel, criterion)] * float(n_visit) + P2M[kernel] * float(n_p2m) + P2P[kernel] * float(n_p2p))
+def walk_flops_algorithmic(kernel: str, n_p2m: int, n_p2p: int) -> float:
+    """FLOPs of the interactions of one walk (decisions not counted)."""
+    return P2M_ALG[kernel] * float(n_p2m) + P2P_ALG[kernel] * float(n_p2p)
+
+
+def fmm_flops_algorithmic(n_pp: int, n_pn: int, n_nn: int, n_nodes: int, n_particles: int) -> float:
+    """FLOPs of one FMM call: interactions, downward pass and evaluation."""
+    f = FMM_ALG
+    return (f["pp"] * float(n_pp) + f["pn"] * float(n_pn) + f["nn"] * float(n_nn)
+            + f["l2l_per_node"] * float(n_nodes) + f["l2p_per_particle"] * float(n_particles))

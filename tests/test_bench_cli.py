@@ -18,10 +18,12 @@ def test_more_than_one_gpu_is_refused():
 
 
 def test_walk_flop_counts_are_additive():
-    """walk_flops is the per-event counts times the event numbers (no hidden terms)."""
+    """The reported FLOPs are the per-interaction units times the interaction
+    counts, with no term for the opening decisions."""
     sys.path.insert(0, ROOT)
     from paper_2010_03567_amd import flops
-    assert flops.walk_flops("treepm", "relative", 1, 0, 0) == flops.VISIT[("treepm", "relative")]
-    assert flops.walk_flops("treepm", "relative", 0, 1, 0) == flops.P2M["treepm"]
-    assert flops.walk_flops("treepm", "relative", 0, 0, 1) == flops.P2P["treepm"]
-    assert flops.walk_flops("newton", "geometric", 2, 3, 5) == 2 * 11 + 3 * 46 + 5 * 18
+    assert flops.walk_flops_algorithmic("treepm", 1, 0) == flops.P2M_ALG["treepm"] == 85
+    assert flops.walk_flops_algorithmic("treepm", 0, 1) == flops.P2P_ALG["treepm"] == 44
+    assert flops.walk_flops_algorithmic("newton", 3, 5) == 3 * 60 + 5 * 19
+    assert flops.fmm_flops_algorithmic(1, 0, 0, 0, 0) == 44
+    assert flops.fmm_flops_algorithmic(0, 2, 3, 4, 5) == 2 * 120 + 3 * 275 + 4 * 100 + 5 * 40

@@ -554,3 +554,25 @@ def test_adam_first_step_is_signed_lr():
     g = np.array([3.0, -0.5, 1e-3, -7.0, 2.0])
     oracle.adam(w, g, m, v, lr=0.01, step=1, eps=0.0)
     np.testing.assert_allclose(w, -0.01 * np.sign(g), rtol=1e-12)
+
+
+def test_threaded_build_and_moments_equal_serial():
+    """The threaded tree build and moment sums (used to time the oracle on many
+    cores) give the serial code's node set and, node by node, its moments."""
+    ps = workloads.clustered_box(20000, seed=77, nhalo=40)
+    _, X, Y, Z = oracle.quantize(ps.pos, True, 1.0)
+    t1 = oracle.Tree(X, Y, Z, ps.mass, True, 1.0, 8)
+    t1.compute_moments()
+    t4 = oracle.Tree(X, Y, Z, ps.mass, True, 1.0, 8, nthreads=4)
+    t4.compute_moments(nthreads=4)
+    k1 = {(int(l), *map(int, c), int(k)): i for i, (l, c, k) in enumerate(zip(*t1.nodes()[:3]))}
+    k4 = {(int(l), *map(int, c), int(k)): i for i, (l, c, k) in enumerate(zip(*t4.nodes()[:3]))}
+    assert k1.keys() == k4.keys()
+    m1, m4 = t1.moments(), t4.moments()
+    i1 = np.array([k1[k] for k in k1]); i4 = np.array([k4[k] for k in k1])
+    for a, b in zip(m1, m4):
+        np.testing.assert_allclose(a[i1], b[i4], rtol=1e-12, atol=1e-300)
+    a1, _, c1 = t1.walk(criterion=0, theta=0.6, eps0=1e-4, targets=np.arange(0, 20000, 97))
+    a4, _, c4 = t4.walk(criterion=0, theta=0.6, eps0=1e-4, targets=np.arange(0, 20000, 97), nthreads=4)
+    np.testing.assert_allclose(a1, a4, rtol=1e-12)
+    assert np.array_equal(c1, c4)
