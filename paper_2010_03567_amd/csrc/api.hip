@@ -411,10 +411,8 @@ int g4_fmm_workspace_bytes(const g4_tree *tree, const g4_fmm_params *fp, double 
     return g4_fmm_layout_bytes(tree, fp, list_factor, bytes);
 }
 
-int g4_fmm_force(g4_ctx *ctx, g4_tree *tree, const g4_fmm_params *fp, double list_factor, void *ws, size_t ws_bytes,
-                 double *ax, double *ay, double *az, double *pot, g4_stats *stats)
+static int fmm_checks(g4_ctx *ctx, g4_tree *tree, const g4_fmm_params *fp, double *ax, double *ay, double *az)
 {
-    if (!ctx || !tree || !fp || !ws) return G4_EINVAL;
     if (!ax || !ay || !az) return g4_set_err(ctx, G4_EINVAL, "null output");
     if (tree->moments_order < 3) return g4_set_err(ctx, G4_ESTATE, "FMM needs moments to order 3");
     if (fp->kernel != 0 && fp->kernel != 1) return g4_set_err(ctx, G4_EINVAL, "kernel must be 0 or 1");
@@ -422,8 +420,13 @@ int g4_fmm_force(g4_ctx *ctx, g4_tree *tree, const g4_fmm_params *fp, double lis
         return g4_set_err(ctx, G4_EINVAL, "r_s and r_cut must be positive");
     if (fp->kernel == 1 && !tree->tp.periodic) return g4_set_err(ctx, G4_EINVAL, "short-range kernel needs a periodic box");
     if (!(fp->theta > 0) || fp->eps0 < 0) return g4_set_err(ctx, G4_EINVAL, "bad theta or eps0");
-    if (((uintptr_t)ws & 255) != 0) return g4_set_err(ctx, G4_EINVAL, "workspace must be 256-byte aligned");
     if (tree->n >= (1ll << 27)) return g4_set_err(ctx, G4_EINVAL, "FMM supports up to 2^27 particles per call");
+    return G4_OK;
+}
+
+static int fmm_run(g4_ctx *ctx, g4_tree *tree, const g4_fmm_params *fp, double list_factor, void *ws,
+                   size_t ws_bytes, double *ax, double *ay, double *az, double *pot, g4_stats *stats)
+{
     int st = g4_phase_begin(ctx, tree, 3);
     if (st) return st;
     st = g4_launch_fmm(ctx, tree, fp, list_factor, ws, ws_bytes, ax, ay, az, pot, stats);
@@ -439,6 +442,16 @@ int g4_fmm_force(g4_ctx *ctx, g4_tree *tree, const g4_fmm_params *fp, double lis
     }
     if (flags & G4_FLAG_FMM_STACK) return g4_set_err(ctx, G4_ENOMEM, "FMM leaf-node stack overflowed");
     return G4_OK;
+}
+
+int g4_fmm_force(g4_ctx *ctx, g4_tree *tree, const g4_fmm_params *fp, double list_factor, void *ws, size_t ws_bytes,
+                 double *ax, double *ay, double *az, double *pot, g4_stats *stats)
+{
+    if (!ctx || !tree || !fp || !ws) return G4_EINVAL;
+    int st = fmm_checks(ctx, tree, fp, ax, ay, az);
+    if (st) return st;
+    if (((uintptr_t)ws & 255) != 0) return g4_set_err(ctx, G4_EINVAL, "workspace must be 256-byte aligned");
+    return fmm_run(ctx, tree, fp, list_factor, ws, ws_bytes, ax, ay, az, pot, stats);
 }
 
 int g4_mlp_features(g4_ctx *ctx, const g4_tree *tree, const g4_walk_params *wp, const float *norm, float *feat)

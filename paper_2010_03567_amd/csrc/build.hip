@@ -15,8 +15,7 @@
 // inside a level varies run to run, results do not: traversal and moment
 // sums follow each node's own children in octant order.
 #include <cstring>
-
-#include <rocprim/rocprim.hpp>
+#include <utility>
 
 #include "g4_internal.h"
 
@@ -33,14 +32,6 @@ static inline int grid_for(int64_t work, int max_blocks = 4096)
     if (b > max_blocks) b = max_blocks;
     return (int)b;
 }
-
-// The key sort: onesweep radix sort with 9-bit digits, so the 63-bit keys take
-// 7 passes instead of 8 (measured 11 % faster than the 8-bit default at 2^21
-// keys on gfx950; 10 bits is slower again and 11 bits does not fit in LDS).
-using KeySortConfig = rocprim::radix_sort_config<
-    rocprim::default_config, rocprim::default_config,
-    rocprim::radix_sort_onesweep_config<rocprim::kernel_config<1024, 12>, rocprim::kernel_config<1024, 12>, 9,
-                                        rocprim::block_radix_rank_algorithm::match>>;
 
 // ------------------------------------------------------------------ layout
 int g4_layout(const g4_tree_params *tp, int64_t n, WsLayout *L)
@@ -77,17 +68,9 @@ int g4_layout(const g4_tree_params *tp, int64_t n, WsLayout *L)
     L->spill_waves = waves;
     L->spill = take((size_t)waves * G4_WALK_SPILL * 16);
     L->srtab = take((size_t)G4_SRTAB_FUNCS * G4_SRTAB_MAX * 16);
-    // scratch for the key sort and for the forest's sort by box (32-bit keys)
-    size_t sb = 0, sb2 = 0;
-    if (rocprim::radix_sort_pairs<KeySortConfig>((void *)nullptr, sb, (uint64_t *)nullptr, (uint64_t *)nullptr,
-                                                 (uint32_t *)nullptr, (uint32_t *)nullptr, (size_t)(n > 0 ? n : 1),
-                                                 0, 63) != hipSuccess ||
-        rocprim::radix_sort_pairs((void *)nullptr, sb2, (uint32_t *)nullptr, (uint32_t *)nullptr,
-                                  (uint32_t *)nullptr, (uint32_t *)nullptr, (size_t)(n > 0 ? n : 1), 0, 32) !=
-            hipSuccess)
-        return G4_EHIP;
-    L->sort_bytes = sb > sb2 ? sb : sb2;
-    L->sort_tmp = take(sb);
+    // digit tables of the key sort and of the forest's sort by box
+    L->sort_bytes = g4_radix_sort_temp_bytes(n > 0 ? n : 1);
+    L->sort_tmp = take(L->sort_bytes);
     L->total = off;
     return G4_OK;
 }
@@ -495,6 +478,22 @@ __global__ void k_count_nodes(DevCounters *C)
     }
 }
 
+// stable sort of the 63-bit curve keys (keys0, values perm0); the result is
+// left in keys1 / perm1 (the views are swapped when the passes end in the
+// first pair)
+static int sort_keys(g4_ctx *ctx, g4_tree *t)
+{
+    int alt = 0;
+    if (int st = g4_radix_sort_u64(ctx, t->keys0, t->keys1, t->perm0, t->perm1, t->n, 0, 3 * G4_MAXLEV, t->sort_tmp,
+                                   t->sort_tmp_bytes, &alt))
+        return st;
+    if (!alt) {
+        std::swap(t->keys0, t->keys1);
+        std::swap(t->perm0, t->perm1);
+    }
+    return G4_OK;
+}
+
 int g4_launch_build(g4_ctx *ctx, g4_tree *t, const g4_particles *p)
 {
     hipStream_t s = ctx->stream;
@@ -503,10 +502,8 @@ int g4_launch_build(g4_ctx *ctx, g4_tree *t, const g4_particles *p)
     k_keys<<<grid_for(n), kBlock, 0, s>>>(p->x, p->y, p->z, p->mass, n, t->S - G4_MAXLEV, t->corner,
                                           t->tp.key_kind, t->keys0, t->perm0, packed_staging(t));
     G4_HIP(ctx, hipGetLastError());
-    size_t sb = t->sort_tmp_bytes;
-    G4_HIP(ctx, rocprim::radix_sort_pairs<KeySortConfig>(t->sort_tmp, sb, t->keys0, t->keys1, t->perm0, t->perm1,
-                                                         (size_t)n, 0, 63, s));
-    // sorted keys now live in keys1; keep that name for the split kernels
+    if (int st = sort_keys(ctx, t)) return st;
+    // sorted keys now live in keys1, the permutation in perm1
     k_gather<<<grid_for(n), kBlock, 0, s>>>(packed_staging(t), t->perm1, n, t->parts);
     k_init<<<1, 64, 0, s>>>(t->ctr, t->bfirst, t->bcount, t->parent, (uint32_t)n);
     G4_HIP(ctx, hipGetLastError());
@@ -804,18 +801,16 @@ int g4_launch_build_forest(g4_ctx *ctx, g4_tree *t, const g4_particles *p, const
     k_keys<<<grid_for(n), kBlock, 0, s>>>(p->x, p->y, p->z, p->mass, n, t->S - G4_MAXLEV, t->corner,
                                           t->tp.key_kind, t->keys0, t->perm0, packed_staging(t));
     G4_HIP(ctx, hipGetLastError());
-    size_t sb = t->sort_tmp_bytes;
-    G4_HIP(ctx, rocprim::radix_sort_pairs<KeySortConfig>(t->sort_tmp, sb, t->keys0, t->keys1, t->perm0, t->perm1,
-                                                         (size_t)n, 0, 63, s));
+    if (int st = sort_keys(ctx, t)) return st;
     k_boxkey<<<grid_for(n), kBlock, 0, s>>>(t->perm1, n, off_dev, t->nbox, bkey0);
     int bits = 1;
     while ((1 << bits) < t->nbox) bits++;
-    sb = t->sort_tmp_bytes;
-    // stable: particles of a box keep their Morton order
-    G4_HIP(ctx, rocprim::radix_sort_pairs(t->sort_tmp, sb, bkey0, bkey1, t->perm1, t->perm0, (size_t)n, 0, bits, s));
-    uint32_t *tmp = t->perm0;
-    t->perm0 = t->perm1;
-    t->perm1 = tmp;
+    // stable: particles of a box keep their curve order
+    int alt = 0;
+    if (int st = g4_radix_sort_u32(ctx, bkey0, bkey1, t->perm1, t->perm0, n, 0, bits, t->sort_tmp, t->sort_tmp_bytes,
+                                   &alt))
+        return st;
+    if (alt) std::swap(t->perm0, t->perm1);
     k_gather_keys<<<grid_for(n), kBlock, 0, s>>>(packed_staging(t), t->perm1, n, t->S - G4_MAXLEV, t->corner,
                                                   t->tp.key_kind, t->parts, t->keys1);
     k_init_forest<<<(t->nbox + 255) / 256, 256, 0, s>>>(t->ctr, t->bfirst, t->bcount, t->parent, off_dev, t->nbox);

@@ -26,7 +26,6 @@
 // M2P + P2P + L2P with FP64 accumulation.
 #include <cstring>
 
-#include <rocprim/rocprim.hpp>
 
 #include "g4_device.h"
 #include "g4_internal.h"
@@ -1619,14 +1618,7 @@ static int fmm_layout(int64_t n, int64_t cap_nodes, double factor, FmmLayout *L)
     L->pend = take((size_t)n * 4);
     L->F = take((size_t)cap_nodes * 20 * 4);
     L->leafid = take((size_t)n * 4);
-    size_t sb1 = 0, sb2 = 0;
-    if (rocprim::radix_sort_pairs((void *)nullptr, sb1, (uint64_t *)nullptr, (uint64_t *)nullptr,
-                                  (uint32_t *)nullptr, (uint32_t *)nullptr, (size_t)L->cap_node, 0, 64) != hipSuccess)
-        return G4_EHIP;
-    if (rocprim::radix_sort_pairs((void *)nullptr, sb2, (uint64_t *)nullptr, (uint64_t *)nullptr,
-                                  (uint32_t *)nullptr, (uint32_t *)nullptr, (size_t)L->cap_part, 0, 64) != hipSuccess)
-        return G4_EHIP;
-    L->sort_bytes = std::max(sb1, sb2);
+    L->sort_bytes = g4_radix_sort_temp_bytes((int64_t)std::max(L->cap_node, L->cap_part));
     L->sort_tmp = take(L->sort_bytes);
     L->total = off;
     return G4_OK;
@@ -1883,14 +1875,26 @@ int g4_launch_fmm(g4_ctx *ctx, g4_tree *t, const g4_fmm_params *fp, double facto
     // independent of the order in which the walk appended its entries
     uint64_t *nk2 = (uint64_t *)(b + L.nkey2), *pk2 = (uint64_t *)(b + L.pkey2);
     uint32_t *nv2 = (uint32_t *)(b + L.nval2), *pv2 = (uint32_t *)(b + L.pval2);
-    size_t sb = L.sort_bytes;
-    if (n_node)
-        G4_HIP(ctx, rocprim::radix_sort_pairs((void *)(b + L.sort_tmp), sb, A.nkey, nk2, A.nval, nv2, (size_t)n_node,
-                                              0, 32 + bits_for((uint64_t)nn_host), s));
-    sb = L.sort_bytes;
-    if (n_part)
-        G4_HIP(ctx, rocprim::radix_sort_pairs((void *)(b + L.sort_tmp), sb, A.pkey, pk2, A.pval, pv2, (size_t)n_part,
-                                              0, 32 + bits_for((uint64_t)t->n), s));
+    int alt = 0;
+    if (n_node) {
+        if (int st = g4_radix_sort_u64(ctx, A.nkey, nk2, A.nval, nv2, n_node, 0, 32 + bits_for((uint64_t)nn_host),
+                                       b + L.sort_tmp, L.sort_bytes, &alt))
+            return st;
+        if (!alt) {
+            std::swap(A.nkey, nk2);
+            std::swap(A.nval, nv2);
+        }
+    }
+    if (n_part) {
+        if (int st = g4_radix_sort_u64(ctx, A.pkey, pk2, A.pval, pv2, n_part, 0, 32 + bits_for((uint64_t)t->n),
+                                       b + L.sort_tmp, L.sort_bytes, &alt))
+            return st;
+        if (!alt) {
+            std::swap(A.pkey, pk2);
+            std::swap(A.pval, pv2);
+        }
+    }
+    // sorted entries: keys in nk2 / pk2, sources in nv2 / pv2
     uint32_t *nstart = (uint32_t *)(b + L.nstart), *nend = (uint32_t *)(b + L.nend);
     uint32_t *pstart = (uint32_t *)(b + L.pstart), *pend = (uint32_t *)(b + L.pend);
     if (int zst = g4_launch_zero(ctx, nstart, (size_t)t->cap * 4)) return zst;

@@ -156,6 +156,15 @@ int g4_launch_direct(g4_ctx *ctx, const g4_particles *p, const g4_tree_params *t
 int g4_launch_quantize(g4_ctx *ctx, const double *pos, int64_t n, const g4_tree_params *tp, uint32_t *x,
                        uint32_t *y, uint32_t *z, int32_t *flag);
 int g4_launch_gather_seed(g4_ctx *ctx, g4_tree *t, const float *a_seed_caller);
+// stable LSD radix sort of (key, value) pairs over bits [bit_lo, bit_hi) in
+// 8-bit digits, ping-ponging between (k0, v0) and (k1, v1); *in_alt = 1 when
+// the sorted pairs end in (k1, v1), 0 when in (k0, v0).  temp: device bytes of
+// g4_radix_sort_temp_bytes(n).  Enqueued on the context's stream.
+size_t g4_radix_sort_temp_bytes(int64_t n);
+int g4_radix_sort_u64(g4_ctx *ctx, uint64_t *k0, uint64_t *k1, uint32_t *v0, uint32_t *v1, int64_t n, int bit_lo,
+                      int bit_hi, void *temp, size_t temp_bytes, int *in_alt);
+int g4_radix_sort_u32(g4_ctx *ctx, uint32_t *k0, uint32_t *k1, uint32_t *v0, uint32_t *v1, int64_t n, int bit_lo,
+                      int bit_hi, void *temp, size_t temp_bytes, int *in_alt);
 // zero `bytes` (a multiple of 4) of device memory with a kernel, so that the
 // calls stay valid under stream capture (no memset nodes in a graph)
 int g4_launch_zero(g4_ctx *ctx, void *p, size_t bytes);
