@@ -301,6 +301,22 @@ int g4_fmm_workspace_bytes(const g4_tree *tree, const g4_fmm_params *fp, double 
 int g4_fmm_force(g4_ctx *ctx, g4_tree *tree, const g4_fmm_params *fp, double list_factor, void *ws, size_t ws_bytes,
                  double *ax, double *ay, double *az, double *pot, g4_stats *stats);
 
+/* g4_fmm_force without a workspace argument, for callers that cannot
+ * allocate device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid allocation).  The FMM's lists, field expansions and
+ * accumulators live in a static 64 MiB device array that the library holds
+ * on every device it runs on until the process ends; the call itself
+ * allocates nothing.  It uses the largest list factor (4, 2 or 1) whose
+ * workspace fits and returns G4_EINVAL with the sizes in the message when
+ * even factor 1 does not (about 500 bytes per particle at leaf 16: trees up
+ * to roughly 10^5 particles), G4_ENOMEM when the interaction lists outgrow
+ * the chosen factor.  All calls on one device share that device's array:
+ * calls that overlap on one device (two streams, two host threads) race and
+ * must be serialised by the caller.  Same results as g4_fmm_force: bitwise
+ * for deterministic = 1, to round-off for deterministic = 0. */
+int g4_fmm_force_noalloc(g4_ctx *ctx, g4_tree *tree, const g4_fmm_params *fp, double *ax, double *ay, double *az,
+                         double *pot, g4_stats *stats);
+
 #ifdef __cplusplus
 }
 #endif

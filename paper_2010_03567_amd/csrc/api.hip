@@ -1,9 +1,41 @@
 // api.hip -- the extern "C" entry points of libg4hip.so declared in
 // include/g4hip.h: argument checks, workspace carving, and the order of the
 // kernel launches on the context's stream.
+#include <cstdio>
+#include <mutex>
 #include <new>
 
 #include "g4_internal.h"
+
+// Static device scratch of the FMM entry point that allocates nothing
+// (g4_fmm_force_noalloc).  Every device the library runs on holds one copy
+// until the process ends.  In host code `scratch` is only a stand-in symbol:
+// its device address comes from hipGetSymbolAddress, once per device.
+#define G4_NOALLOC_SCRATCH_BYTES ((size_t)64 << 20)
+#define G4_MAX_DEVICES 64
+static __device__ __align__(256) unsigned char scratch[G4_NOALLOC_SCRATCH_BYTES];
+static void *g_scratch_ptr[G4_MAX_DEVICES];
+static std::mutex g_scratch_mu;
+
+// Device address of this context's device's scratch (looked up on the first
+// call on that device, with that device current).
+static int scratch_address(g4_ctx *ctx, void **out)
+{
+    if (ctx->device < 0 || ctx->device >= G4_MAX_DEVICES) return g4_set_err(ctx, G4_EINVAL, "device index out of range");
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[ctx->device]) {
+        int cur = -1;
+        G4_HIP(ctx, hipGetDevice(&cur));
+        if (cur != ctx->device) G4_HIP(ctx, hipSetDevice(ctx->device));
+        void *p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (cur != ctx->device) hipSetDevice(cur);
+        if (e != hipSuccess || !p) return g4_set_err(ctx, G4_EHIP, "hipGetSymbolAddress of the static scratch failed");
+        g_scratch_ptr[ctx->device] = p;
+    }
+    *out = g_scratch_ptr[ctx->device];
+    return G4_OK;
+}
 
 static int check_tp(g4_ctx *ctx, const g4_tree_params *tp)
 {
@@ -452,6 +484,36 @@ int g4_fmm_force(g4_ctx *ctx, g4_tree *tree, const g4_fmm_params *fp, double lis
     if (st) return st;
     if (((uintptr_t)ws & 255) != 0) return g4_set_err(ctx, G4_EINVAL, "workspace must be 256-byte aligned");
     return fmm_run(ctx, tree, fp, list_factor, ws, ws_bytes, ax, ay, az, pot, stats);
+}
+
+int g4_fmm_force_noalloc(g4_ctx *ctx, g4_tree *tree, const g4_fmm_params *fp, double *ax, double *ay, double *az,
+                         double *pot, g4_stats *stats)
+{
+    if (!ctx || !tree || !fp) return G4_EINVAL;
+    int st = fmm_checks(ctx, tree, fp, ax, ay, az);
+    if (st) return st;
+    // the largest list factor (4, 2 or 1) whose workspace fits in the scratch
+    double factor = 0.0;
+    size_t need1 = 0;
+    for (double f : {4.0, 2.0, 1.0}) {
+        size_t b = 0;
+        if ((st = g4_fmm_layout_bytes(tree, fp, f, &b))) return g4_set_err(ctx, st, "fmm workspace layout failed");
+        if (f == 1.0) need1 = b;
+        if (b <= G4_NOALLOC_SCRATCH_BYTES) {
+            factor = f;
+            break;
+        }
+    }
+    if (factor == 0.0) {
+        char msg[200];
+        snprintf(msg, sizeof msg,
+                 "tree too large for the static FMM scratch: %zu bytes needed at list factor 1, %zu available",
+                 need1, G4_NOALLOC_SCRATCH_BYTES);
+        return g4_set_err(ctx, G4_EINVAL, msg);
+    }
+    void *ws = nullptr;
+    if ((st = scratch_address(ctx, &ws))) return st;
+    return fmm_run(ctx, tree, fp, factor, ws, G4_NOALLOC_SCRATCH_BYTES, ax, ay, az, pot, stats);
 }
 
 int g4_mlp_features(g4_ctx *ctx, const g4_tree *tree, const g4_walk_params *wp, const float *norm, float *feat)

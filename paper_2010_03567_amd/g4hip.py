@@ -83,6 +83,7 @@ _SIGS = {
     "g4_build_forest": [_p, _i32, _p, C.POINTER(g4_particles), C.POINTER(g4_tree_params), _p, _sz,
                         C.POINTER(C.c_void_p)],
     "g4_fmm_force": [_p, _p, C.POINTER(g4_fmm_params), C.c_double, _p, _sz, _p, _p, _p, _p, C.POINTER(g4_stats)],
+    "g4_fmm_force_noalloc": [_p, _p, C.POINTER(g4_fmm_params), _p, _p, _p, _p, C.POINTER(g4_stats)],
     "g4_mlp_forward": [_p, _p, _p, _i64, _p, C.c_float, _i32],
     "g4_mlp_grad": [_p, _p, _p, _p, _i64, C.c_float, _p, _p],
     "g4_mlp_adam": [_p, _p, _p, _p, _p, _p, C.c_float, C.c_float, C.c_float, C.c_float, _i64],
@@ -361,6 +362,15 @@ def g4_fmm_force(ctx, tree, fp, list_factor=1.0, ws=None, want_pot=False, want_s
         break
     return dict(ax=ax, ay=ay, az=az, pot=pot, stats=st.as_dict() if st is not None else None, ws=ws,
                 list_factor=list_factor)
+
+
+def g4_fmm_force_noalloc(ctx, tree, fp, want_pot=False, want_stats=False, out=None):
+    """FMM forces with the library's static device scratch (no workspace)."""
+    ax, ay, az, pot, _, _ = out if out is not None else _force_outputs(tree.n, ctx.device, want_pot, False, False)
+    st = g4_stats() if want_stats else None
+    ctx.check(_L.g4_fmm_force_noalloc(ctx.h, tree.h, C.byref(fp), _ptr(ax), _ptr(ay), _ptr(az), _ptr(pot),
+                                      C.byref(st) if st is not None else None))
+    return dict(ax=ax, ay=ay, az=az, pot=pot, stats=st.as_dict() if st is not None else None)
 
 
 # ------------------------------------------------------------------ forest
