@@ -121,6 +121,14 @@ typedef struct {
     int deterministic;
 } g4_fmm_params;
 
+/* Long-range (particle-mesh) part of the TreePM split (Sec. "TreePM
+ * approach"): ng^3 mesh over the periodic box, split scale r_s (the same as
+ * the short-range walk's), G. */
+typedef struct {
+    int ng;
+    double r_s, G;
+} g4_pm_params;
+
 /* Counters and phase times filled by the force calls (host struct).
  * t_build, t_moments: duration of the tree's last g4_build_tree /
  * g4_build_forest and g4_compute_multipoles (HIP events on the context's
@@ -229,6 +237,24 @@ int g4_tree_force(g4_ctx *ctx, g4_tree *tree, const g4_walk_params *wp, double *
 /* The TreePM short-range force (kernel forced to 1). */
 int g4_treepm_shortrange(g4_ctx *ctx, g4_tree *tree, const g4_walk_params *wp, double *ax, double *ay,
                          double *az, double *pot, uint32_t *counts, float *a_out, g4_stats *stats);
+
+/* Workspace bytes of g4_pm_longrange for an ng^3 mesh (12 bytes per mesh
+ * point: the complex FP32 mesh and the real potential). */
+int g4_pm_workspace_bytes(int ng, size_t *bytes);
+
+/* Long-range TreePM force and potential of every particle of a built
+ * periodic tree (Sec. "TreePM approach"): clouds-in-cell assignment of the
+ * masses to the mesh (mesh point c at c L/ng), FFT, multiplication with the
+ * Green's function -G (4 pi / V) exp(-k^2 r_s^2) / k^2 divided twice by the
+ * CIC window prod_d sinc^2(pi n_d / ng) (deconvolution of assignment and
+ * interpolation; zero at k = 0), inverse FFT, 4th-order central differences
+ * for the gradient, CIC interpolation.  ng: power of two in [8, 1024].
+ * ax, ay, az (pot nullable): device n float64, caller order; accumulate = 0
+ * writes them, 1 adds to them (e.g. to the short-range walk's output, giving
+ * the total TreePM force).  FP32 mesh arithmetic, FP64 outputs.  Needs no
+ * moments; a forest (several boxes) is refused.  Asynchronous. */
+int g4_pm_longrange(g4_ctx *ctx, const g4_tree *tree, const g4_pm_params *pp, void *ws, size_t ws_bytes,
+                    int accumulate, double *ax, double *ay, double *az, double *pot);
 
 /* Direct summation on the device (the exact reference of Sec. "Softened
  * potential in periodic systems"): forces on `ntargets` particles (device

@@ -423,6 +423,24 @@ int g4_treepm_shortrange(g4_ctx *ctx, g4_tree *tree, const g4_walk_params *wp, d
     return tree_force_impl(ctx, tree, &w, 1, ax, ay, az, pot, counts, a_out, stats);
 }
 
+int g4_pm_workspace_bytes(int ng, size_t *bytes)
+{
+    if (!bytes) return G4_EINVAL;
+    return g4_pm_layout_bytes(ng, bytes);
+}
+
+int g4_pm_longrange(g4_ctx *ctx, const g4_tree *tree, const g4_pm_params *pp, void *ws, size_t ws_bytes,
+                    int accumulate, double *ax, double *ay, double *az, double *pot)
+{
+    if (!ctx || !tree || !pp || !ws) return G4_EINVAL;
+    if (!ax || !ay || !az) return g4_set_err(ctx, G4_EINVAL, "null output");
+    if (!tree->tp.periodic) return g4_set_err(ctx, G4_EINVAL, "the PM force needs a periodic box");
+    if (tree->nbox != 1) return g4_set_err(ctx, G4_EINVAL, "the PM force takes one box, not a forest");
+    if (!(pp->r_s > 0)) return g4_set_err(ctx, G4_EINVAL, "r_s must be positive");
+    if (((uintptr_t)ws & 255) != 0) return g4_set_err(ctx, G4_EINVAL, "workspace must be 256-byte aligned");
+    return g4_launch_pm(ctx, tree, pp, ws, ws_bytes, accumulate ? 1 : 0, ax, ay, az, pot);
+}
+
 int g4_direct_force(g4_ctx *ctx, const g4_particles *p, const g4_tree_params *tp, const g4_walk_params *wp,
                     int truncate, const int64_t *targets, int64_t ntargets, double *ax, double *ay, double *az,
                     double *pot)

@@ -48,6 +48,10 @@ class g4_fmm_params(C.Structure):
                 ("r_cut", C.c_double), ("theta", C.c_double), ("deterministic", C.c_int)]
 
 
+class g4_pm_params(C.Structure):
+    _fields_ = [("ng", C.c_int), ("r_s", C.c_double), ("G", C.c_double)]
+
+
 class g4_stats(C.Structure):
     _fields_ = [("t_build", C.c_double), ("t_moments", C.c_double), ("t_seed", C.c_double),
                 ("t_walk", C.c_double),
@@ -78,6 +82,8 @@ _SIGS = {
     "g4_direct_force": [_p, C.POINTER(g4_particles), C.POINTER(g4_tree_params), C.POINTER(g4_walk_params), _i32,
                         _p, _i64, _p, _p, _p, _p],
     "g4_mlp_features": [_p, _p, C.POINTER(g4_walk_params), _p, _p],
+    "g4_pm_workspace_bytes": [_i32, C.POINTER(_sz)],
+    "g4_pm_longrange": [_p, _p, C.POINTER(g4_pm_params), _p, _sz, _i32, _p, _p, _p, _p],
     "g4_fmm_workspace_bytes": [_p, C.POINTER(g4_fmm_params), C.c_double, C.POINTER(_sz)],
     "g4_forest_workspace_bytes": [C.POINTER(g4_tree_params), _i32, _i64, C.POINTER(_sz)],
     "g4_build_forest": [_p, _i32, _p, C.POINTER(g4_particles), C.POINTER(g4_tree_params), _p, _sz,
@@ -287,6 +293,38 @@ def g4_direct_force(ctx, p, tp, wp, targets=None, truncate=False, want_pot=True)
     ctx.check(_L.g4_direct_force(ctx.h, C.byref(p), C.byref(tp), C.byref(wp), int(truncate), _ptr(targets), int(nt),
                                  _ptr(ax), _ptr(ay), _ptr(az), _ptr(pot)))
     return dict(ax=ax, ay=ay, az=az, pot=pot)
+
+
+# ------------------------------------------------------------------ PM long range
+def pm_params(ng, r_s, G=1.0):
+    pp = g4_pm_params()
+    pp.ng, pp.r_s, pp.G = int(ng), float(r_s), float(G)
+    return pp
+
+
+def g4_pm_workspace_bytes(ng):
+    b = C.c_size_t()
+    code = _L.g4_pm_workspace_bytes(int(ng), C.byref(b))
+    if code != G4_OK:
+        raise G4Error(code, "pm workspace size query failed")
+    return int(b.value)
+
+
+def g4_pm_longrange(ctx, tree, pp, ws=None, accumulate=False, want_pot=False, out=None):
+    """Long-range TreePM accelerations (and potential); with accumulate they are
+    added to `out` (ax, ay, az, pot) instead of written."""
+    if out is None:
+        ax, ay, az, pot, _, _ = _force_outputs(tree.n, ctx.device, want_pot, False, False)
+    else:
+        ax, ay, az, pot = out[:4]
+    nbytes = g4_pm_workspace_bytes(pp.ng)
+    if ws is None or ws.numel() < nbytes + 256:
+        ws = torch.empty(nbytes + 256, dtype=torch.uint8, device=ctx.device)
+    off = (-ws.data_ptr()) % 256
+    wsv = ws[off:]
+    ctx.check(_L.g4_pm_longrange(ctx.h, tree.h, C.byref(pp), C.c_void_p(wsv.data_ptr()), wsv.numel(),
+                                 int(bool(accumulate)), _ptr(ax), _ptr(ay), _ptr(az), _ptr(pot)))
+    return dict(ax=ax, ay=ay, az=az, pot=pot, ws=ws)
 
 
 # ------------------------------------------------------------------ learned seed
