@@ -23,7 +23,8 @@ measured 99th percentile (10^4 random targets, FP64 direct summation on the
 device) meets the bound.  `value` is the faster variant that meets it.
 
 Extra keys: the same comparison on the 128^3 box (seed 2), the as-stated
-R_cut = 4.5 r_s, alpha = 0.005 line, the FMM at p = 3, theta = 0.5, the
+R_cut = 4.5 r_s, alpha = 0.005 line, the total TreePM force (that walk plus
+the long-range PM force on the 256^3 mesh), the FMM at p = 3, theta = 0.5, the
 batched forest of 64 boxes, and the FP64 oracle on the host cores.  Prints one
 JSON line.
 """
@@ -71,6 +72,7 @@ def parse():
     ap.add_argument("--fmm-leaf", type=int, default=32,
                     help="leaf size of the second, tuned FMM line (the first keeps the configuration's leaf 16)")
     ap.add_argument("--no-forest", action="store_true")
+    ap.add_argument("--no-pm", action="store_true", help="skip the total TreePM (walk + PM) line")
     ap.add_argument("--err-sample", type=int, default=10000)
     ap.add_argument("--group", type=int, default=64)
     ap.add_argument("--leaf", type=int, default=24, help="leaf size B of the tree")
@@ -408,6 +410,8 @@ def main():
                                                           "ms_per_step": ms45, "phases": ph45,
                                                           "errors_vs_direct": e45}
             log(f"[bench] as stated (128^3, R_cut 4.5, alpha 0.005): {ms45:.3f} ms/step, errors {e45}")
+        if not args.no_pm:
+            result["treepm_total_128^3"] = bench_total_treepm(args, g, ctx, small)
         small.free()
         del small
     if not args.no_fmm:
@@ -417,6 +421,56 @@ def main():
     if not args.no_cpu_baseline:
         result["cpu_baseline"] = cpu_baseline(*cpu_input, args)
     print(json.dumps(result), flush=True)
+
+
+def bench_total_treepm(args, g, ctx, case):
+    """Total TreePM force on the 128^3 box as the configuration states it:
+    short-range walk at R_cut = 4.5 r_s (geometric pre-walk, relative
+    criterion at alpha = 0.005) plus the long-range PM force on the 256^3 mesh
+    (r_s = 1.25 L/256).  Errors of the total force against the untruncated
+    short-range direct sum plus the PM force on a 512^3 mesh at the same
+    split (A_smth = 2.5: its own long-range error is about four times
+    smaller, see the PM oracle's convergence pin), on 10^4 random targets."""
+    import torch
+    import workloads
+    n = case.n
+    sr_ref = case.reference()
+    wps = case.params("plain", 0.005, r_cut=4.5 * case.r_s)
+    pp = g.pm_params(256, case.r_s)
+    state = {"ws": None}
+
+    def step(evs=None):
+        case.step("plain", wps, evs[:4] if evs else None)
+        o = g.g4_pm_longrange(ctx, case.state["tree"], pp, ws=state["ws"], accumulate=True, out=case.outs + [None])
+        state["ws"] = o["ws"]
+        if evs:
+            evs[4].record(case.stream)
+
+    step()
+    torch.cuda.synchronize()
+    steps = max(5, args.steps // 2)
+    evs = [[torch.cuda.Event(enable_timing=True) for _ in range(5)] for _ in range(steps)]
+    t0 = time.perf_counter()
+    for k in range(steps):
+        step(evs[k])
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / steps
+    pm_ms = float(np.median([e[3].elapsed_time(e[4]) for e in evs]))
+    walk_ms = float(np.median([e[2].elapsed_time(e[3]) for e in evs]))
+    a = torch.stack(case.outs, 1)
+    # long-range reference: PM at twice the resolution, same split
+    fine = g.g4_pm_longrange(ctx, case.state["tree"], g.pm_params(512, case.r_s))
+    lr_fine = torch.stack([fine["ax"], fine["ay"], fine["az"]], 1)[case.tg].cpu().numpy()
+    del fine
+    torch.cuda.empty_cache()
+    tot = a[case.tg].cpu().numpy()
+    err = workloads.percentiles(workloads.relative_errors(tot, sr_ref + lr_fine))
+    log(f"[bench] total TreePM 128^3 (R_cut 4.5, alpha 0.005, PM 256^3): {ms:.3f} ms/step (PM {pm_ms:.3f} ms), "
+        f"errors {err}")
+    return {"workload": "total TreePM force, clustered 128^3 box (seed 2), R_cut 4.5 r_s, alpha 0.005, PM mesh 256^3",
+            "forces_per_s": n / (ms * 1e-3), "ms_per_step": ms, "pm_ms": pm_ms, "walk_ms": walk_ms,
+            "errors_vs_reference": err,
+            "reference": "untruncated short-range FP64 direct sum + PM at mesh 512^3 (A_smth 2.5)"}
 
 
 def bench_fmm(args, g, ctx, flops):

@@ -28,7 +28,7 @@
 #include "g4_internal.h"
 
 #define PM_THREADS 256
-#define PM_TILE_CELLS 8192  // complex cells per FFT tile (64 KiB of LDS)
+#define PM_TILE_CELLS 4096  // complex cells per FFT tile (32 KiB of LDS, plus the twiddles)
 
 __global__ void k_pm_twiddle(float2 *__restrict__ tw, int ng)
 {
@@ -52,12 +52,21 @@ __device__ __forceinline__ void pm_cell(uint32_t X, int shift, float wscale, int
     f = (float)(X & ((1u << shift) - 1u)) * wscale;
 }
 
+// Particles arrive in curve order, so particles that share a mesh cell sit
+// in consecutive lanes (the cell index is a prefix of the curve key; each CIC
+// corner is the same shift of it).  Every corner's contributions are summed
+// over such runs by a segmented scan across the wavefront and the last lane
+// of a run issues the one atomic: in haloes most atomics disappear.
 __global__ void k_pm_deposit(const uint4 *__restrict__ parts, int64_t n, int ng, int shift, float wscale,
                              float2 *__restrict__ mesh)
 {
-    for (int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; p < n; p += (int64_t)gridDim.x * blockDim.x) {
-        const uint4 q = parts[p];
-        const float m = __uint_as_float(q.w);
+    const int lane = threadIdx.x & 63;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t base = blockIdx.x * (int64_t)blockDim.x; base < n; base += stride) {
+        const int64_t p = base + threadIdx.x;
+        const bool act = p < n;
+        const uint4 q = act ? parts[p] : make_uint4(0u, 0u, 0u, 0u);
+        const float m = act ? __uint_as_float(q.w) : 0.f;
         int ix, iy, iz;
         float fx, fy, fz;
         pm_cell(q.x, shift, wscale, ix, fx);
@@ -67,9 +76,17 @@ __global__ void k_pm_deposit(const uint4 *__restrict__ parts, int64_t n, int ng,
 #pragma unroll
         for (int c = 0; c < 8; c++) {
             const int dx = c >> 2, dy = (c >> 1) & 1, dz = c & 1;
-            const float w = (dx ? fx : 1.f - fx) * (dy ? fy : 1.f - fy) * (dz ? fz : 1.f - fz);
-            const size_t idx = ((size_t)((ix + dx) & mask) * ng + ((iy + dy) & mask)) * ng + ((iz + dz) & mask);
-            atomicAdd(&mesh[idx].x, m * w);
+            float v = m * (dx ? fx : 1.f - fx) * (dy ? fy : 1.f - fy) * (dz ? fz : 1.f - fz);
+            const uint32_t key = act ? (uint32_t)((((ix + dx) & mask) * ng + ((iy + dy) & mask)) * ng + ((iz + dz) & mask))
+                                     : 0xffffffffu;
+#pragma unroll
+            for (int off = 1; off < 64; off <<= 1) {
+                const uint32_t ku = (uint32_t)__shfl_up((int)key, off);
+                const float vu = __shfl_up(v, off);
+                if (lane >= off && ku == key) v += vu;
+            }
+            const uint32_t kd = (uint32_t)__shfl_down((int)key, 1);
+            if (act && (lane == 63 || kd != key)) atomicAdd(&mesh[key].x, v);
         }
     }
 }
@@ -88,6 +105,11 @@ __global__ __launch_bounds__(PM_THREADS) void k_pm_fft(float2 *__restrict__ data
     extern __shared__ float2 sm[];
     const int tid = threadIdx.x;
     const int cells = tl * ng;
+    float2 *tws = sm + cells;  // twiddles of this direction: exp(sign 2 pi i k / ng), k < ng/2
+    for (int k = tid; k < ng / 2; k += PM_THREADS) {
+        const float2 w = tw[k];
+        tws[k] = make_float2(w.x, -sign * w.y);
+    }
     size_t base;
     size_t estride;  // distance between consecutive points of one line
     size_t lstride;  // distance between the tile's lines
@@ -116,18 +138,37 @@ __global__ __launch_bounds__(PM_THREADS) void k_pm_fft(float2 *__restrict__ data
         sm[t * ng + kr] = data[base + (size_t)t * lstride + (size_t)k * estride];
     }
     __syncthreads();
-    const int hb = ng >> 1;
-    for (int s = 0; s < lg; s++) {
+    auto cmul = [](float2 a, float2 w) { return make_float2(a.x * w.x - a.y * w.y, a.x * w.y + a.y * w.x); };
+    // radix-2 stages s and s + 1 fused: each thread takes the 4 points
+    // i0, i0 + h, i0 + 2h, i0 + 3h (h = 2^s) through both stages in registers
+    const int qb = ng >> 2;
+    int s = 0;
+    for (; s + 1 < lg; s += 2) {
         const int half = 1 << s;
-        const int tstep = ng >> (s + 1);  // twiddle index step of this stage
+        for (int b = tid; b < tl * qb; b += PM_THREADS) {
+            const int t = b / qb, j = b - t * qb;
+            const int grp = j >> s, pos = j & (half - 1);
+            const int i0 = t * ng + (grp << (s + 2)) + pos;
+            const float2 a0 = sm[i0], a1 = sm[i0 + half], a2 = sm[i0 + 2 * half], a3 = sm[i0 + 3 * half];
+            const float2 w1 = tws[pos << (lg - s - 1)];
+            const float2 b1 = cmul(a1, w1), b3 = cmul(a3, w1);
+            const float2 c0 = make_float2(a0.x + b1.x, a0.y + b1.y), c1 = make_float2(a0.x - b1.x, a0.y - b1.y);
+            const float2 c2 = make_float2(a2.x + b3.x, a2.y + b3.y), c3 = make_float2(a2.x - b3.x, a2.y - b3.y);
+            const float2 d2 = cmul(c2, tws[pos << (lg - s - 2)]), d3 = cmul(c3, tws[(pos + half) << (lg - s - 2)]);
+            sm[i0] = make_float2(c0.x + d2.x, c0.y + d2.y);
+            sm[i0 + 2 * half] = make_float2(c0.x - d2.x, c0.y - d2.y);
+            sm[i0 + half] = make_float2(c1.x + d3.x, c1.y + d3.y);
+            sm[i0 + 3 * half] = make_float2(c1.x - d3.x, c1.y - d3.y);
+        }
+        __syncthreads();
+    }
+    if (s < lg) {  // odd lg: one radix-2 stage left
+        const int half = 1 << s, hb = ng >> 1;
         for (int b = tid; b < tl * hb; b += PM_THREADS) {
             const int t = b / hb, j = b - t * hb;
             const int grp = j >> s, pos = j & (half - 1);
             const int i0 = t * ng + (grp << (s + 1)) + pos, i1 = i0 + half;
-            float2 w = tw[pos * tstep];
-            w.y *= -sign;  // table holds exp(-2 pi i k/ng): forward uses it, inverse its conjugate
-            const float2 a = sm[i0], c = sm[i1];
-            const float2 bw = make_float2(c.x * w.x - c.y * w.y, c.x * w.y + c.y * w.x);
+            const float2 a = sm[i0], bw = cmul(sm[i1], tws[pos << (lg - s - 1)]);
             sm[i0] = make_float2(a.x + bw.x, a.y + bw.y);
             sm[i1] = make_float2(a.x - bw.x, a.y - bw.y);
         }
@@ -268,7 +309,7 @@ int g4_launch_pm(g4_ctx *ctx, const g4_tree *t, const g4_pm_params *pp, void *ws
     k_pm_deposit<<<pblocks, 256, 0, s>>>(t->parts, n, ng, shift, wscale, mesh);
     const int tl = std::min(ng, std::max(1, PM_TILE_CELLS / ng));
     const unsigned tiles = (unsigned)((size_t)ng * ng / tl);
-    const size_t lds = (size_t)tl * ng * sizeof(float2);
+    const size_t lds = ((size_t)tl * ng + ng / 2) * sizeof(float2);
     for (int axis = 2; axis >= 0; axis--)
         k_pm_fft<<<tiles, PM_THREADS, lds, s>>>(mesh, tw, ng, lg, tl, axis, -1.f, nullptr);
     k_pm_green<<<4096, 256, 0, s>>>(mesh, ng, lg, t->tp.box, pp->r_s, pp->G);
