@@ -129,6 +129,26 @@ typedef struct {
     double r_s, G;
 } g4_pm_params;
 
+/* Hierarchical time integration (Sec. "Hierarchical time integration"). */
+#define G4_KDK_MAX_LEVEL 30
+typedef struct {
+    int solver;          /* force of a set sourced by itself: 0 FP64 direct sum (wp: kernel, G, eps0, r_s),
+                            1 tree walk (wp), 2 FMM (fp) */
+    g4_tree_params tp;   /* root of every force calculation: a periodic box (positions are wrapped into it),
+                            or an isolated root cube that must hold every position during the step */
+    g4_walk_params wp;
+    g4_fmm_params fp;
+    double eta, eps;     /* step criterion sqrt(2 eta eps / |a|) */
+    int max_level;       /* deepest level of the step hierarchy, 0..G4_KDK_MAX_LEVEL */
+} g4_kdk_params;
+
+typedef struct {
+    uint64_t force_evals;          /* particles that received a force (the paper's force computations) */
+    uint32_t force_calls;          /* force calculations (one tree per call) */
+    uint32_t deepest_level;        /* deepest level entered */
+    uint64_t evals_per_level[32];  /* force evaluations by the level of the set */
+} g4_kdk_stats;
+
 /* Counters and phase times filled by the force calls (host struct).
  * t_build, t_moments: duration of the tree's last g4_build_tree /
  * g4_build_forest and g4_compute_multipoles (HIP events on the context's
@@ -255,6 +275,28 @@ int g4_pm_workspace_bytes(int ng, size_t *bytes);
  * moments; a forest (several boxes) is refused.  Asynchronous. */
 int g4_pm_longrange(g4_ctx *ctx, const g4_tree *tree, const g4_pm_params *pp, void *ws, size_t ws_bytes,
                     int accumulate, double *ax, double *ay, double *az, double *pot);
+
+/* Workspace bytes of g4_kdk_step for n particles (index lists and forces of
+ * every level, one tree workspace, the FMM's lists for solver 2). */
+int g4_kdk_workspace_bytes(const g4_kdk_params *kp, int64_t n, size_t *bytes);
+
+/* One step dt of the hierarchical time integration of n particles: a set P
+ * whose forces (sourced by P) are known is advanced by
+ * K_P^P(dt/2) K_F^F(-dt/2) E(H_F, dt/2) D_S(dt) E(H_F, dt/2) K_F^F(-dt/2) K_P^P(dt/2),
+ * F the particles whose step sqrt(2 eta eps / |a|) is below dt, S the rest,
+ * E(H_F, dt/2) the same step applied to F alone with dt/2 (its first forces
+ * are the F-sourced forces computed to split it), and a plain kick-drift-kick
+ * when F is empty or the level is max_level.  Every force is sourced by the
+ * set it acts on, so momentum is conserved to round-off by the FMM (solver 2)
+ * and by direct sums.
+ * pos, vel: device n x 3 float64 (row-major, physical), updated in place;
+ * mass: device n float32; ax, ay, az: device n float64: the forces of all
+ * particles at the start (have_acc = 1) -- else computed first -- and at the
+ * end on return.  Synchronises (the size of every fast set is read back).
+ * Returns G4_EROOT when an isolated root no longer holds a particle. */
+int g4_kdk_step(g4_ctx *ctx, const g4_kdk_params *kp, int64_t n, double *pos, double *vel, const float *mass,
+                double dt, double *ax, double *ay, double *az, int have_acc, void *ws, size_t ws_bytes,
+                g4_kdk_stats *stats);
 
 /* Direct summation on the device (the exact reference of Sec. "Softened
  * potential in periodic systems"): forces on `ntargets` particles (device

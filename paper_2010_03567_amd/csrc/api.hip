@@ -441,6 +441,39 @@ int g4_pm_longrange(g4_ctx *ctx, const g4_tree *tree, const g4_pm_params *pp, vo
     return g4_launch_pm(ctx, tree, pp, ws, ws_bytes, accumulate ? 1 : 0, ax, ay, az, pot);
 }
 
+static int check_kdk(g4_ctx *ctx, const g4_kdk_params *kp)
+{
+    if (!kp) return g4_set_err(ctx, G4_EINVAL, "null kdk params");
+    if (check_tp(ctx, &kp->tp)) return G4_EINVAL;
+    if (kp->solver < 0 || kp->solver > 2) return g4_set_err(ctx, G4_EINVAL, "solver must be 0, 1 or 2");
+    if (kp->max_level < 0 || kp->max_level > G4_KDK_MAX_LEVEL) return g4_set_err(ctx, G4_EINVAL, "max_level out of range");
+    if (!(kp->eta > 0) || !(kp->eps > 0)) return g4_set_err(ctx, G4_EINVAL, "eta and eps must be positive");
+    const int kernel = kp->solver == 2 ? kp->fp.kernel : kp->wp.kernel;
+    if (kernel == 1 && !kp->tp.periodic) return g4_set_err(ctx, G4_EINVAL, "short-range kernel needs a periodic box");
+    return G4_OK;
+}
+
+int g4_kdk_workspace_bytes(const g4_kdk_params *kp, int64_t n, size_t *bytes)
+{
+    if (!kp || !bytes || n < 1 || n > 0xFFFFFFF0ll) return G4_EINVAL;
+    if (check_kdk(nullptr, kp)) return G4_EINVAL;
+    return g4_kdk_layout_bytes(kp, n, bytes);
+}
+
+int g4_kdk_step(g4_ctx *ctx, const g4_kdk_params *kp, int64_t n, double *pos, double *vel, const float *mass,
+                double dt, double *ax, double *ay, double *az, int have_acc, void *ws, size_t ws_bytes,
+                g4_kdk_stats *stats)
+{
+    if (!ctx) return G4_EINVAL;
+    int st = check_kdk(ctx, kp);
+    if (st) return st;
+    if (n < 1 || n > 0xFFFFFFF0ll) return g4_set_err(ctx, G4_EINVAL, "particle count out of range");
+    if (!pos || !vel || !mass || !ax || !ay || !az || !ws) return g4_set_err(ctx, G4_EINVAL, "null argument");
+    if (!(dt > 0)) return g4_set_err(ctx, G4_EINVAL, "dt must be positive");
+    if (((uintptr_t)ws & 255) != 0) return g4_set_err(ctx, G4_EINVAL, "workspace must be 256-byte aligned");
+    return g4_launch_kdk(ctx, kp, n, pos, vel, mass, dt, ax, ay, az, have_acc, ws, ws_bytes, stats);
+}
+
 int g4_direct_force(g4_ctx *ctx, const g4_particles *p, const g4_tree_params *tp, const g4_walk_params *wp,
                     int truncate, const int64_t *targets, int64_t ntargets, double *ax, double *ay, double *az,
                     double *pot)

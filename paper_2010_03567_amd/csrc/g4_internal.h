@@ -17,6 +17,9 @@
 #define G4_WALK_SPILL G4_WALK_STACK
 #define G4_WALK_MAX_WAVES 8192
 
+// levels of the hierarchical time integration (index lists kept per level)
+#define G4_KDK_LEVELS (G4_KDK_MAX_LEVEL + 1)
+
 struct g4_ctx {
     int device;
     hipStream_t stream;

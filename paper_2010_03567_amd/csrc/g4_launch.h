@@ -52,3 +52,7 @@ int g4_launch_fmm(g4_ctx *ctx, g4_tree *t, const g4_fmm_params *fp, double facto
                   double *ax, double *ay, double *az, double *pot, g4_stats *stats);
 int g4_launch_mlp_adam(g4_ctx *ctx, uint16_t *w, float *master, float *m, float *v, const float *grad, float lr,
                        float b1, float b2, float eps, int64_t step);
+int g4_kdk_layout_bytes(const g4_kdk_params *kp, int64_t n, size_t *bytes);
+int g4_launch_kdk(g4_ctx *ctx, const g4_kdk_params *kp, int64_t n, double *pos, double *vel, const float *mass,
+                  double dt, double *ax, double *ay, double *az, int have_acc, void *ws, size_t ws_bytes,
+                  g4_kdk_stats *stats);

@@ -52,6 +52,20 @@ class g4_pm_params(C.Structure):
     _fields_ = [("ng", C.c_int), ("r_s", C.c_double), ("G", C.c_double)]
 
 
+class g4_kdk_params(C.Structure):
+    _fields_ = [("solver", C.c_int), ("tp", g4_tree_params), ("wp", g4_walk_params), ("fp", g4_fmm_params),
+                ("eta", C.c_double), ("eps", C.c_double), ("max_level", C.c_int)]
+
+
+class g4_kdk_stats(C.Structure):
+    _fields_ = [("force_evals", C.c_uint64), ("force_calls", C.c_uint32), ("deepest_level", C.c_uint32),
+                ("evals_per_level", C.c_uint64 * 32)]
+
+    def as_dict(self):
+        return {"force_evals": int(self.force_evals), "force_calls": int(self.force_calls),
+                "deepest_level": int(self.deepest_level), "evals_per_level": [int(v) for v in self.evals_per_level]}
+
+
 class g4_stats(C.Structure):
     _fields_ = [("t_build", C.c_double), ("t_moments", C.c_double), ("t_seed", C.c_double),
                 ("t_walk", C.c_double),
@@ -83,6 +97,9 @@ _SIGS = {
                         _p, _i64, _p, _p, _p, _p],
     "g4_mlp_features": [_p, _p, C.POINTER(g4_walk_params), _p, _p],
     "g4_pm_workspace_bytes": [_i32, C.POINTER(_sz)],
+    "g4_kdk_workspace_bytes": [C.POINTER(g4_kdk_params), _i64, C.POINTER(_sz)],
+    "g4_kdk_step": [_p, C.POINTER(g4_kdk_params), _i64, _p, _p, _p, C.c_double, _p, _p, _p, _i32, _p, _sz,
+                    C.POINTER(g4_kdk_stats)],
     "g4_pm_longrange": [_p, _p, C.POINTER(g4_pm_params), _p, _sz, _i32, _p, _p, _p, _p],
     "g4_fmm_workspace_bytes": [_p, C.POINTER(g4_fmm_params), C.c_double, C.POINTER(_sz)],
     "g4_forest_workspace_bytes": [C.POINTER(g4_tree_params), _i32, _i64, C.POINTER(_sz)],
@@ -325,6 +342,46 @@ def g4_pm_longrange(ctx, tree, pp, ws=None, accumulate=False, want_pot=False, ou
     ctx.check(_L.g4_pm_longrange(ctx.h, tree.h, C.byref(pp), C.c_void_p(wsv.data_ptr()), wsv.numel(),
                                  int(bool(accumulate)), _ptr(ax), _ptr(ay), _ptr(az), _ptr(pot)))
     return dict(ax=ax, ay=ay, az=az, pot=pot, ws=ws)
+
+
+# ------------------------------------------------------------------ time integration
+def kdk_params(solver, tp, eta, eps, max_level=10, wp=None, fp=None):
+    kp = g4_kdk_params()
+    kp.solver, kp.tp, kp.eta, kp.eps, kp.max_level = int(solver), tp, float(eta), float(eps), int(max_level)
+    if wp is not None:
+        kp.wp = wp
+    if fp is not None:
+        kp.fp = fp
+    kp._keep = (wp,)
+    return kp
+
+
+def g4_kdk_workspace_bytes(kp, n):
+    b = C.c_size_t()
+    code = _L.g4_kdk_workspace_bytes(C.byref(kp), int(n), C.byref(b))
+    if code != G4_OK:
+        raise G4Error(code, "kdk workspace size query failed")
+    return int(b.value)
+
+
+def g4_kdk_step(ctx, kp, pos, vel, mass, dt, acc=None, ws=None):
+    """One hierarchical step; pos, vel (n, 3) float64 updated in place; acc:
+    (ax, ay, az) float64 tensors holding the forces at the start, or None to
+    compute them.  Returns (acc, stats, ws)."""
+    n = pos.shape[0]
+    have = acc is not None
+    if acc is None:
+        acc = tuple(torch.empty(n, dtype=torch.float64, device=ctx.device) for _ in range(3))
+    nbytes = g4_kdk_workspace_bytes(kp, n)
+    if ws is None or ws.numel() < nbytes + 256:
+        ws = torch.empty(nbytes + 256, dtype=torch.uint8, device=ctx.device)
+    off = (-ws.data_ptr()) % 256
+    wsv = ws[off:]
+    st = g4_kdk_stats()
+    ctx.check(_L.g4_kdk_step(ctx.h, C.byref(kp), n, _ptr(pos), _ptr(vel), _ptr(mass), float(dt), _ptr(acc[0]),
+                             _ptr(acc[1]), _ptr(acc[2]), int(have), C.c_void_p(wsv.data_ptr()), wsv.numel(),
+                             C.byref(st)))
+    return acc, st.as_dict(), ws
 
 
 # ------------------------------------------------------------------ learned seed

@@ -66,7 +66,8 @@ def test_binding_structs_match_header(tmp_path):
         spec.loader.exec_module(mod)
     except ImportError:
         pytest.skip("libg4hip.so not built")
-    structs = ("g4_tree_params", "g4_particles", "g4_walk_params", "g4_fmm_params", "g4_stats")
+    structs = ("g4_tree_params", "g4_particles", "g4_walk_params", "g4_fmm_params", "g4_stats", "g4_pm_params",
+               "g4_kdk_params", "g4_kdk_stats")
     lines = ['#include <stdio.h>', '#include <stddef.h>', f'#include "{HEADER}"', 'int main(void) {']
     for s in structs:
         lines.append(f'printf("{s} size %zu\\n", sizeof({s}));')
