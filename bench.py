@@ -73,6 +73,7 @@ def parse():
                     help="leaf size of the second, tuned FMM line (the first keeps the configuration's leaf 16)")
     ap.add_argument("--no-forest", action="store_true")
     ap.add_argument("--no-pm", action="store_true", help="skip the total TreePM (walk + PM) line")
+    ap.add_argument("--no-kdk", action="store_true", help="skip the hierarchical time-integration line")
     ap.add_argument("--err-sample", type=int, default=10000)
     ap.add_argument("--group", type=int, default=64)
     ap.add_argument("--leaf", type=int, default=24, help="leaf size B of the tree")
@@ -416,6 +417,8 @@ def main():
         del small
     if not args.no_fmm:
         result["fmm"] = bench_fmm(args, g, ctx, flops)
+    if not args.no_kdk:
+        result["hierarchical_step"] = bench_kdk(args, g, ctx)
     if not args.no_forest:
         result["forest"] = bench_forest(args, g, ctx)
     if not args.no_cpu_baseline:
@@ -471,6 +474,57 @@ def bench_total_treepm(args, g, ctx, case):
             "forces_per_s": n / (ms * 1e-3), "ms_per_step": ms, "pm_ms": pm_ms, "walk_ms": walk_ms,
             "errors_vs_reference": err,
             "reference": "untruncated short-range FP64 direct sum + PM at mesh 512^3 (A_smth 2.5)"}
+
+
+def bench_kdk(args, g, ctx):
+    """Hierarchical time integration on the clustered 128^3 box (seed 2, cold
+    start): FMM forces (p = 3, theta = 0.5, leaf 16, short-range kernel at
+    R_cut = 4.5 r_s), step criterion sqrt(2 eta eps / |a|) with eta = 0.025,
+    eps = eps0, and dt_max = 8 x the median criterion step, so the haloes
+    split over several levels.  Reported: time per step of dt_max, the levels
+    used, force evaluations (every particle that received a force), the
+    force-evaluation rate, and the paper's cost comparison with one-sided
+    nesting (K_onesided = N_0 + sum_k 2^(k-1) N_k)."""
+    import torch
+    import workloads
+    n = SMALL_N
+    r_s, eps0 = treepm_scales(n)
+    ps = workloads.clustered_box(n, seed=2)
+    dev = ctx.device
+    tp = g.tree_params(True, 1.0, leaf_max=16)
+    fp = g.fmm_params(kernel=1, theta=0.5, r_s=r_s, r_cut=4.5 * r_s, eps0=eps0)
+    eta = 0.025
+    kp = g.kdk_params(2, tp, eta, eps0, max_level=12, fp=fp)
+    pos0 = torch.from_numpy(ps.pos).to(dev)
+    mass = torch.from_numpy(ps.mass.astype(np.float32)).to(dev)
+    pos, vel = pos0.clone(), torch.zeros_like(pos0)
+    acc, st, ws = g.g4_kdk_step(ctx, kp, pos, vel, mass, 1e-12)  # forces of the whole box (tiny step)
+    amag = torch.sqrt(acc[0] ** 2 + acc[1] ** 2 + acc[2] ** 2).cpu().numpy()
+    dt = 8.0 * float(np.median(np.sqrt(2 * eta * eps0 / np.maximum(amag, 1e-30))))
+    acc0 = tuple(a.clone() for a in acc)  # forces at the start (the tiny step moved nothing measurably)
+    pos.copy_(pos0)
+    vel.zero_()
+    acc, _, ws = g.g4_kdk_step(ctx, kp, pos, vel, mass, dt, acc=tuple(a.clone() for a in acc0), ws=ws)  # warm-up
+    pos.copy_(pos0)
+    vel.zero_()
+    acc = tuple(a.clone() for a in acc0)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    acc, st, ws = g.g4_kdk_step(ctx, kp, pos, vel, mass, dt, acc=acc, ws=ws)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3
+    lv = st["evals_per_level"]
+    # N_k: particles on level k or deeper = the set sizes of the first sub-step of each level
+    nk = [n] + [lv[k] // (3 * 2 ** (k - 1)) for k in range(1, st["deepest_level"] + 1)]
+    onesided = n + sum(2 ** (k - 1) * nk[k] for k in range(1, len(nk)))
+    log(f"[bench] hierarchical step (FMM, 128^3): {ms:.1f} ms, levels {st['deepest_level']}, "
+        f"force evaluations {st['force_evals']}")
+    return {"workload": "hierarchical KDK step, clustered 128^3 box (seed 2), FMM p=3 theta 0.5 leaf 16, R_cut 4.5 r_s",
+            "dt_max": dt, "ms_per_step": ms, "deepest_level": st["deepest_level"],
+            "force_evals": st["force_evals"], "force_calls": st["force_calls"],
+            "force_evals_per_s": st["force_evals"] / (ms * 1e-3), "evals_per_level": lv[: st["deepest_level"] + 1],
+            "cost_vs_onesided": st["force_evals"] / onesided if onesided else None,
+            "note": "one step from rest; the forces at the start are given (as in a running integration)"}
 
 
 def bench_fmm(args, g, ctx, flops):
