@@ -72,6 +72,7 @@ def lib():
         L.orc_sr_W.restype = d; L.orc_sr_W.argtypes = [d, d, d]
         L.orc_gn.argtypes = [i32, d, d, p]
         L.orc_Dn.argtypes = [i32, p, d, p, p, p, p]
+        L.orc_ewald_psi.argtypes = [p, d, d, p, p, p, p]
         L.orc_quantize.restype = i32
         L.orc_quantize.argtypes = [i64, p, i32, d, p, p, p, p]
         L.orc_build.restype = p
@@ -248,6 +249,23 @@ def direct(X, Y, Z, mass, unit, kernel=0, G=1.0, eps0=0.0, r_s=1.0, r_cut=np.inf
     lib().orc_direct(n, _ptr(X), _ptr(Y), _ptr(Z), _ptr(mass), float(unit), C.byref(P), int(truncate),
                      _ptr(tg), nt, _ptr(acc), _ptr(pot), int(nthreads))
     return acc, pot
+
+
+def ewald_psi(x, L=1.0, alpha=0.0):
+    """Periodic correction potential psi of a cube of side L (Sec. "Periodic
+    boundary conditions", eq. eqnewal) and its derivatives at the points x
+    (n x 3): D0 (n,), D1 (n, 3), D2 (n, 3, 3), D3 (n, 3, 3, 3).  alpha <= 0
+    selects alpha = 2/L; the result does not depend on alpha."""
+    x = np.atleast_2d(np.asarray(x, dtype=np.float64))
+    n = x.shape[0]
+    D0 = np.zeros(n); D1 = np.zeros((n, 3)); D2 = np.zeros((n, 3, 3)); D3 = np.zeros((n, 3, 3, 3))
+    for q in range(n):
+        xq = np.ascontiguousarray(x[q])
+        d0 = C.c_double(0.0)
+        d1 = np.zeros(3); d2 = np.zeros(9); d3 = np.zeros(27)
+        lib().orc_ewald_psi(_ptr(xq), float(L), float(alpha), C.byref(d0), _ptr(d1), _ptr(d2), _ptr(d3))
+        D0[q] = d0.value; D1[q] = d1; D2[q] = d2.reshape(3, 3); D3[q] = d3.reshape(3, 3, 3)
+    return D0, D1, D2, D3
 
 
 def two_groups(posA, mA, posB, mB):

@@ -179,6 +179,118 @@ void orc_Dn(int kernel, const double rv[3], double alpha, double *D0, double D1[
 }
 
 /* ======================================================================
+ * 2b. Periodic correction potential psi (Sec. "Periodic boundary
+ *     conditions", eqs. (eqnpo1), (eqnpo2), (eqnewal))
+ * ====================================================================== */
+
+/* For a cube of side L, V = L^3:
+ *   psi(x) = 1/|x| + pi/(alpha^2 V) - sum_n erfc(alpha |x + q_n|)/|x + q_n|
+ *            - (4 pi / V) sum_{k != 0} exp(-k^2/(4 alpha^2))/k^2 cos(k.x),
+ * q_n = L n, k = 2 pi n / L.  The n = 0 image and 1/|x| combine into
+ * erf(alpha r)/r, which is regular at r = 0.  The result does not depend on
+ * alpha (a pin); the sums stop where their terms fall below ~1e-22 of the
+ * leading ones: real images with (NR + 1/2) alpha L >= 7, wave vectors with
+ * pi (NK + 1)/(alpha L) >= 7.5.  A periodic mass distribution then has the
+ * potential phi(x) = -sum_j m_j [1/|d_j| - psi(d_j)] with d_j = x_j - x
+ * reduced to the nearest image (eq. eqnpo1, softening of the nearest image
+ * aside), and the force a = sum_j m_j [d_j/|d_j|^3 + grad psi(d_j)].       */
+
+/* g_k = (r^-1 d/dr)^k of erf(alpha r)/r, k = 0..3: the series
+ * erf(ar)/r = (2a/sqrt(pi)) sum_m (-a^2)^m r^(2m) / (m! (2m+1)) for small
+ * alpha r, Newtonian minus the erfc closed forms otherwise. */
+static void erf_over_r_gn(double r, double alpha, double g[4])
+{
+    if (alpha * r < 0.5) {
+        /* with u = r^2, r^-1 d/dr = 2 d/du: g_k = (2a/sqrt(pi)) 2^k sum_{m>=k} (-a^2)^m u^(m-k) / ((m-k)! (2m+1)) */
+        double u = r * r, a2 = alpha * alpha;
+        for (int k = 0; k < 4; k++) {
+            double sum = 0.0, am = 1.0;              /* (-a^2)^m */
+            for (int m = 0; m < k; m++) am *= -a2;
+            double um = 1.0, fact = 1.0;            /* u^(m-k), (m-k)! */
+            for (int m = k; m < k + 30; m++) {
+                sum += am * um / (fact * (2.0 * m + 1.0));
+                am *= -a2;
+                um *= u;
+                fact *= (double)(m - k + 1);
+            }
+            g[k] = 2.0 * alpha / SQRTPI * ldexp(sum, k);
+        }
+        return;
+    }
+    double gn[4], ge[4];
+    orc_gn(0, r, alpha, gn);
+    orc_gn(1, r, alpha, ge);
+    for (int k = 0; k < 4; k++) g[k] = gn[k] - ge[k];
+}
+
+/* add c * (D0..D3 of a radial function with scalars g at offset rv) */
+static void add_radial(const double g[4], const double rv[3], double c, double *D0, double D1[3], double D2[9],
+                       double D3[27])
+{
+    *D0 += c * g[0];
+    for (int i = 0; i < 3; i++) {
+        D1[i] += c * g[1] * rv[i];
+        for (int j = 0; j < 3; j++) {
+            D2[i * 3 + j] += c * ((i == j ? g[1] : 0.0) + g[2] * rv[i] * rv[j]);
+            for (int k = 0; k < 3; k++) {
+                double t = 0.0;
+                if (i == j) t += rv[k];
+                if (j == k) t += rv[i];
+                if (i == k) t += rv[j];
+                D3[(i * 3 + j) * 3 + k] += c * (g[2] * t + g[3] * rv[i] * rv[j] * rv[k]);
+            }
+        }
+    }
+}
+
+/* psi and its derivative tensors D1_i = d_i psi, D2_ij, D3_ijk at x (any x;
+ * alpha <= 0 selects alpha = 2/L). */
+void orc_ewald_psi(const double x[3], double L, double alpha, double *D0, double D1[3], double D2[9], double D3[27])
+{
+    if (alpha <= 0.0) alpha = 2.0 / L;
+    double V = L * L * L;
+    int NR = (int)ceil(7.0 / (alpha * L) - 0.5), NK = (int)ceil(7.5 * alpha * L / M_PI - 1.0);
+    if (NR < 1) NR = 1;
+    if (NK < 1) NK = 1;
+    *D0 = M_PI / (alpha * alpha * V);
+    memset(D1, 0, 3 * sizeof(double));
+    memset(D2, 0, 9 * sizeof(double));
+    memset(D3, 0, 27 * sizeof(double));
+    double g[4];
+    /* n = 0: 1/|x| - erfc(alpha r)/r = erf(alpha r)/r */
+    erf_over_r_gn(sqrt(x[0] * x[0] + x[1] * x[1] + x[2] * x[2]), alpha, g);
+    add_radial(g, x, 1.0, D0, D1, D2, D3);
+    /* the other real-space images */
+    for (int nx = -NR; nx <= NR; nx++)
+        for (int ny = -NR; ny <= NR; ny++)
+            for (int nz = -NR; nz <= NR; nz++) {
+                if (!nx && !ny && !nz) continue;
+                double rv[3] = {x[0] + nx * L, x[1] + ny * L, x[2] + nz * L};
+                double r = sqrt(rv[0] * rv[0] + rv[1] * rv[1] + rv[2] * rv[2]);
+                orc_gn(1, r, alpha, g);
+                add_radial(g, rv, -1.0, D0, D1, D2, D3);
+            }
+    /* Fourier space: d/dx_i cos(k.x) = -k_i sin(k.x), and so on */
+    for (int nx = -NK; nx <= NK; nx++)
+        for (int ny = -NK; ny <= NK; ny++)
+            for (int nz = -NK; nz <= NK; nz++) {
+                if (!nx && !ny && !nz) continue;
+                double k[3] = {2.0 * M_PI * nx / L, 2.0 * M_PI * ny / L, 2.0 * M_PI * nz / L};
+                double k2 = k[0] * k[0] + k[1] * k[1] + k[2] * k[2];
+                double w = 4.0 * M_PI / V * exp(-k2 / (4.0 * alpha * alpha)) / k2;
+                double th = k[0] * x[0] + k[1] * x[1] + k[2] * x[2], c = cos(th), sn = sin(th);
+                *D0 -= w * c;
+                for (int i = 0; i < 3; i++) {
+                    D1[i] += w * sn * k[i];
+                    for (int j = 0; j < 3; j++) {
+                        D2[i * 3 + j] += w * c * k[i] * k[j];
+                        for (int l = 0; l < 3; l++) D3[(i * 3 + j) * 3 + l] -= w * sn * k[i] * k[j] * k[l];
+                    }
+                }
+            }
+}
+
+/* ======================================================================
  * 3. Integer coordinates
  * ====================================================================== */
 
@@ -582,7 +694,7 @@ static void p2p_one(const orc_tree *t, const orc_walk_params *P, int64_t i, int6
     double r = sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
     double h = 2.8 * P->eps0;
     double K, W;
-    if (P->kernel == 0) {
+    if (P->kernel != 1) {
         K = orc_soft_K(r, h);
         W = (r > 0.0 || h > 0.0) ? orc_soft_W(r, h) : 0.0;
     } else {
@@ -592,15 +704,32 @@ static void p2p_one(const orc_tree *t, const orc_walk_params *P, int64_t i, int6
     }
     for (int k = 0; k < 3; k++) a[k] += t->m[j] * d[k] * K;
     *phi -= t->m[j] * W;
+    if (P->kernel == 2) {
+        /* the other images: + m grad psi(d), potential + m psi(d) (eq. eqnpo1) */
+        double D0, D1[3], D2[9], D3[27];
+        orc_ewald_psi(d, t->box, 0.0, &D0, D1, D2, D3);
+        for (int k = 0; k < 3; k++) a[k] += t->m[j] * D1[k];
+        *phi += t->m[j] * D0;
+    }
 }
 
 /* Accepted node: eqs. (eqonesidetreeacc) and (eqonesidetreepotential) with
  * p = 3 and vanishing dipole: a = -[M D1 + Q2:D3 / 2],
  * phi = -[M D0 + Q2:D2 / 2 + Q3.D3 / 6], D evaluated at r = s - x. */
-static void p2m_one(const orc_walk_params *P, const onode *nd, const double rv[3], double a[3], double *phi)
+static void p2m_one(const orc_walk_params *P, const onode *nd, const double rv[3], double box, double a[3],
+                    double *phi)
 {
     double D0, D1[3], D2[9], D3[27];
-    orc_Dn(P->kernel, rv, 0.5 / (P->kernel ? P->r_s : 1.0), &D0, D1, D2, D3);
+    orc_Dn(P->kernel == 1, rv, 0.5 / (P->kernel == 1 ? P->r_s : 1.0), &D0, D1, D2, D3);
+    if (P->kernel == 2) {
+        /* periodic: g = 1/r - psi, so D_n(g) = D_n(1/r) - D_n(psi) (eqs. eqnpo1, eqnpo2) */
+        double E0, E1[3], E2[9], E3[27];
+        orc_ewald_psi(rv, box, 0.0, &E0, E1, E2, E3);
+        D0 -= E0;
+        for (int i = 0; i < 3; i++) D1[i] -= E1[i];
+        for (int i = 0; i < 9; i++) D2[i] -= E2[i];
+        for (int i = 0; i < 27; i++) D3[i] -= E3[i];
+    }
     for (int i = 0; i < 3; i++) {
         double s = nd->mass * D1[i];
         if (P->order >= 3)
@@ -662,7 +791,7 @@ static void walk_node(const walk_job *J, int64_t i, double aseed, int64_t q, dou
                                    : nd->mass * l * l < P->alpha * aseed * r2 * r2;
     }
     if (accept) {
-        p2m_one(P, nd, rv, a, phi);
+        p2m_one(P, nd, rv, t->box, a, phi);
         cnt[1]++;
         return;
     }
@@ -747,9 +876,9 @@ static void *direct_thread(void *arg)
     direct_chunk *C = (direct_chunk *)arg;
     direct_job *J = C->J;
     const orc_walk_params *P = &J->P;
-    double h = 2.8 * P->eps0, alpha = P->kernel ? 0.5 / P->r_s : 0.0;
+    double h = 2.8 * P->eps0, alpha = P->kernel == 1 ? 0.5 / P->r_s : 0.0;
     /* beyond x = alpha r = 6 erfc(x) < 3e-17: such sources add nothing in FP64 */
-    double rskip2 = P->kernel ? (6.0 / alpha) * (6.0 / alpha) : INFINITY;
+    double rskip2 = P->kernel == 1 ? (6.0 / alpha) * (6.0 / alpha) : INFINITY;
     double rc2 = P->r_cut * P->r_cut;
     for (int64_t q = C->lo; q < C->hi; q++) {
         int64_t i = J->targets ? J->targets[q] : q;
@@ -763,10 +892,16 @@ static void *direct_thread(void *arg)
             if (r2 > rskip2) continue;
             if (J->truncate && r2 > rc2) continue;
             double r = sqrt(r2), K, W;
-            if (P->kernel == 0) { K = orc_soft_K(r, h); W = orc_soft_W(r, h); }
+            if (P->kernel != 1) { K = orc_soft_K(r, h); W = orc_soft_W(r, h); }
             else { K = orc_sr_K(r, h, alpha); W = orc_sr_W(r, h, alpha); }
             for (int k = 0; k < 3; k++) a[k] += J->m[j] * d[k] * K;
             phi -= J->m[j] * W;
+            if (P->kernel == 2) {
+                double D0, D1[3], D2[9], D3[27];
+                orc_ewald_psi(d, J->unit * TWO32, 0.0, &D0, D1, D2, D3);
+                for (int k = 0; k < 3; k++) a[k] += J->m[j] * D1[k];
+                phi += J->m[j] * D0;
+            }
         }
         for (int k = 0; k < 3; k++) J->acc[3 * q + k] = P->G * a[k];
         if (J->pot) J->pot[q] = P->G * phi;
@@ -1252,7 +1387,7 @@ void orc_two_groups(int64_t nA, const double *posA, const double *mA, int64_t nB
         field_acc(&FA, a, accA_fmm + 3 * i);
         double r[3] = {sB[0] - posA[3 * i], sB[1] - posA[3 * i + 1], sB[2] - posA[3 * i + 2]};
         double acc[3] = {0, 0, 0}, phi = 0.0;
-        p2m_one(&P, &nB_, r, acc, &phi);
+        p2m_one(&P, &nB_, r, 0.0, acc, &phi);
         memcpy(accA_tree + 3 * i, acc, sizeof(acc));
     }
     for (int64_t i = 0; i < nB; i++) {
@@ -1260,7 +1395,7 @@ void orc_two_groups(int64_t nA, const double *posA, const double *mA, int64_t nB
         field_acc(&FB, a, accB_fmm + 3 * i);
         double r[3] = {sA[0] - posB[3 * i], sA[1] - posB[3 * i + 1], sA[2] - posB[3 * i + 2]};
         double acc[3] = {0, 0, 0}, phi = 0.0;
-        p2m_one(&P, &nA_, r, acc, &phi);
+        p2m_one(&P, &nA_, r, 0.0, acc, &phi);
         memcpy(accB_tree + 3 * i, acc, sizeof(acc));
     }
 }

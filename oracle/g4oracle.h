@@ -15,7 +15,8 @@ extern "C" {
 typedef struct orc_tree orc_tree;
 
 typedef struct {
-    int kernel;      /* 0 softened Newtonian, 1 TreePM short-range (eq. eqnpo4) */
+    int kernel;      /* 0 softened Newtonian, 1 TreePM short-range (eq. eqnpo4),
+                        2 periodic softened Newtonian + Ewald correction (eq. eqnpo1) */
     int criterion;   /* 0 geometric l/r < theta, 1 relative (eq. eqnrelcriterion) */
     int order;       /* expansion order p (2 or 3) */
     int exclusion;   /* 1: never accept a node whose 2l-cube holds the target */
@@ -34,6 +35,9 @@ double orc_sr_K(double r, double h, double alpha);
 double orc_sr_W(double r, double h, double alpha);
 void orc_gn(int kernel, double r, double alpha, double g[4]);
 void orc_Dn(int kernel, const double rv[3], double alpha, double *D0, double D1[3], double D2[9], double D3[27]);
+/* periodic correction potential psi of a cube of side L and its derivative
+ * tensors (full 3, 3x3, 3x3x3 arrays), exact Ewald sums; alpha <= 0: 2/L */
+void orc_ewald_psi(const double x[3], double L, double alpha, double *D0, double D1[3], double D2[9], double D3[27]);
 
 /* integer mapping: pos is n x 3 row-major; returns 0 or -5 (outside root) */
 int orc_quantize(int64_t n, const double *pos, int periodic, double box, const double origin[3],
