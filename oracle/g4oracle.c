@@ -737,11 +737,13 @@ static void p2m_one(const orc_walk_params *P, const onode *nd, const double rv[3
                 for (int k = 0; k < 3; k++) s += 0.5 * nd->q2[j * 3 + k] * D3[(i * 3 + j) * 3 + k];
         a[i] -= s;
     }
+    /* potential to order p: the octupole term only at p = 3 */
     double ph = nd->mass * D0;
     for (int i = 0; i < 3; i++)
         for (int j = 0; j < 3; j++) {
             ph += 0.5 * nd->q2[i * 3 + j] * D2[i * 3 + j];
-            for (int k = 0; k < 3; k++) ph += nd->q3[(i * 3 + j) * 3 + k] * D3[(i * 3 + j) * 3 + k] / 6.0;
+            if (P->order >= 3)
+                for (int k = 0; k < 3; k++) ph += nd->q3[(i * 3 + j) * 3 + k] * D3[(i * 3 + j) * 3 + k] / 6.0;
         }
     *phi -= ph;
 }
@@ -763,9 +765,16 @@ static void walk_node(const walk_job *J, int64_t i, double aseed, int64_t q, dou
         }
         if (e2 > P->r_cut * P->r_cut) return;
     }
+    /* the node's centre of mass, the point its expansion is about, taken at
+     * its nearest periodic image (Sec. "Periodic boundary conditions"); it can
+     * lie on the other side of the half-box plane than the geometric centre */
     double rv[3], r2 = 0.0;
     for (int k = 0; k < 3; k++) {
         rv[k] = (double)dc[k] * t->unit + nd->dcom[k];
+        if (t->periodic) {
+            if (rv[k] >= 0.5 * t->box) rv[k] -= t->box;
+            else if (rv[k] < -0.5 * t->box) rv[k] += t->box;
+        }
         r2 += rv[k] * rv[k];
     }
     /* exclusion zone: cube of side 2l centred on the node's geometric centre */
