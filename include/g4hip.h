@@ -68,8 +68,12 @@ typedef struct {
 } g4_particles;
 
 /* One-sided walk (Sec. "One-sided multipole expansion", "Tree walk and
- * opening criterion", "TreePM approach").
- * kernel:    0 softened Newtonian, 1 TreePM short-range (eq. eqnpo4 force).
+ * opening criterion", "TreePM approach", "Periodic boundary conditions").
+ * kernel:    0 softened Newtonian, 1 TreePM short-range (eq. eqnpo4 force),
+ *            2 periodic Newtonian: every node and particle at its nearest
+ *            image with the softened Newtonian kernel, plus the correction
+ *            potential psi of the other images (eq. eqnpo1) expanded to the
+ *            same order, its derivatives from ewald_table (periodic trees).
  * criterion: 0 geometric l/r < theta; 1 relative M l^p < alpha |a| r^(p+2)
  *            (eq. eqnrelcriterion) with |a| from a_seed, or, when a_seed is
  *            NULL, from a geometric pre-walk with theta_seed.
@@ -94,7 +98,9 @@ typedef struct {
  *            alpha_split r = 6 (factor < 2e-15) get the value at 6.  The
  *            table lives in the tree workspace and is rebuilt when its
  *            length changes.  Node decisions and interaction counts do not
- *            depend on it. */
+ *            depend on it.
+ * ewald_table, ewald_n: kernel 2 only: a table that g4_ewald_table built for
+ *            the tree's box side with ewald_n intervals (device, read only). */
 typedef struct {
     int kernel;
     int criterion;
@@ -105,6 +111,8 @@ typedef struct {
     int group_size;
     int seed_from_tree;
     int sr_table;
+    const void *ewald_table;
+    int ewald_n;
 } g4_walk_params;
 
 /* FMM (Sec. "Fast multipole method", "The FMM-PM approach"), p = 3.
@@ -257,6 +265,32 @@ int g4_tree_force(g4_ctx *ctx, g4_tree *tree, const g4_walk_params *wp, double *
 /* The TreePM short-range force (kernel forced to 1). */
 int g4_treepm_shortrange(g4_ctx *ctx, g4_tree *tree, const g4_walk_params *wp, double *ax, double *ay,
                          double *az, double *pot, uint32_t *counts, float *a_out, g4_stats *stats);
+
+/* Table of the periodic correction potential psi for kernel 2 of the walk
+ * (Sec. "Periodic boundary conditions", eqs. eqnpo2 and eqnewal):
+ *   psi(x) = 1/|x| + pi/(alpha^2 V) - sum_n erfc(alpha|x + q_n|)/|x + q_n|
+ *            - (4 pi/V) sum_{k != 0} exp(-k^2/(4 alpha^2))/k^2 cos(k.x),
+ * the potential of a unit mass's periodic images other than the nearest one
+ * (with the sign of eq. eqnpo1: phi = -m/r + m psi).  psi is even in every
+ * coordinate, so one octant is stored: the derivatives D^(a,b,c) psi of
+ * orders 0..6 (84 FP32 values) at the (ne + 1)^3 points (i, j, k) box/(2 ne),
+ * i, j, k = 0..ne, each computed in FP64 from the Ewald sums (alpha = 2/box).
+ * The walk evaluates psi's derivatives of order n at an offset d from the
+ * nearest grid point d0 by the third-order Taylor expansion
+ * D_n(d) = sum_{|b| <= 3} D_{n+b}(d0) (d - d0)^b / b! that the paper uses in
+ * place of trilinear interpolation.  ne: 4..128 (error of the expansion about
+ * (box / 4 ne)^4 relative; 32 keeps it near FP32 round-off).  table: device,
+ * 256-byte aligned, at least g4_ewald_table_bytes(ne) bytes (12 MB at ne 32),
+ * owned by the caller.  Asynchronous. */
+size_t g4_ewald_table_bytes(int ne);
+int g4_ewald_table(g4_ctx *ctx, double box, int ne, void *table, size_t bytes);
+
+/* psi and grad psi at n offsets through the table's Taylor expansion (the
+ * lookup the walk uses for a single particle).  dx, dy, dz: device float64,
+ * each component in [-box/2, box/2]; psi, gx, gy, gz: device float64 outputs.
+ * Asynchronous. */
+int g4_ewald_eval(g4_ctx *ctx, const void *table, int ne, double box, int64_t n, const double *dx, const double *dy,
+                  const double *dz, double *psi, double *gx, double *gy, double *gz);
 
 /* Workspace bytes of g4_pm_longrange for an ng^3 mesh (12 bytes per mesh
  * point: the complex FP32 mesh and the real potential). */

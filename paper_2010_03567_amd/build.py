@@ -15,7 +15,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libg4hip.so")
-SOURCES = ["build.hip", "sort.hip", "walk.hip", "direct.hip", "fmm.hip", "mlp.hip", "pm.hip", "kdk.hip", "api.hip"]
+SOURCES = ["build.hip", "sort.hip", "walk.hip", "direct.hip", "fmm.hip", "mlp.hip", "pm.hip", "kdk.hip", "ewald.hip", "api.hip"]
 ARCH = os.environ.get("G4_OFFLOAD_ARCH", "gfx950")
 FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}", "-Xclang", "-target-feature", "-Xclang",
          "-packed-fp32-ops", "-Wno-unused-command-line-argument", "-ffp-contract=fast"]

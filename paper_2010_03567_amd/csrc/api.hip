@@ -5,6 +5,7 @@
 #include <mutex>
 #include <new>
 
+#include "ewald.h"
 #include "g4_internal.h"
 
 // Static device scratch of the FMM entry point that allocates nothing
@@ -346,6 +347,12 @@ static int tree_force_impl(g4_ctx *ctx, g4_tree *tree, const g4_walk_params *wp,
     if (wp->sr_table != 0 && (wp->sr_table < 8 || wp->sr_table > G4_SRTAB_MAX))
         return g4_set_err(ctx, G4_EINVAL, "sr_table must be 0 or 8..512");
     if (!tree->tp.periodic && kernel == 1) return g4_set_err(ctx, G4_EINVAL, "short-range kernel needs a periodic box");
+    if (kernel == 2) {
+        if (!tree->tp.periodic) return g4_set_err(ctx, G4_EINVAL, "the Ewald-corrected kernel needs a periodic box");
+        if (!wp->ewald_table) return g4_set_err(ctx, G4_EINVAL, "kernel 2 needs ewald_table");
+        if (wp->ewald_n < G4_EWALD_NE_MIN || wp->ewald_n > G4_EWALD_NE_MAX)
+            return g4_set_err(ctx, G4_EINVAL, "ewald_n must be 4..128");
+    }
     if (stats) {
         const int zs = g4_launch_zero(ctx, tree->ctr->stat, sizeof(tree->ctr->stat));
         if (zs) return zs;
@@ -410,7 +417,7 @@ int g4_tree_force(g4_ctx *ctx, g4_tree *tree, const g4_walk_params *wp, double *
                   double *pot, uint32_t *counts, float *a_out, g4_stats *stats)
 {
     if (!wp) return G4_EINVAL;
-    if (wp->kernel != 0 && wp->kernel != 1) return g4_set_err(ctx, G4_EINVAL, "kernel must be 0 or 1");
+    if (wp->kernel < 0 || wp->kernel > 2) return g4_set_err(ctx, G4_EINVAL, "kernel must be 0, 1 or 2");
     return tree_force_impl(ctx, tree, wp, wp->kernel, ax, ay, az, pot, counts, a_out, stats);
 }
 
@@ -421,6 +428,32 @@ int g4_treepm_shortrange(g4_ctx *ctx, g4_tree *tree, const g4_walk_params *wp, d
     g4_walk_params w = *wp;
     w.kernel = 1;
     return tree_force_impl(ctx, tree, &w, 1, ax, ay, az, pot, counts, a_out, stats);
+}
+
+size_t g4_ewald_table_bytes(int ne)
+{
+    if (ne < G4_EWALD_NE_MIN || ne > G4_EWALD_NE_MAX) return 0;
+    return g4_ewald_layout_bytes(ne);
+}
+
+int g4_ewald_table(g4_ctx *ctx, double box, int ne, void *table, size_t bytes)
+{
+    if (!ctx) return G4_EINVAL;
+    if (!(box > 0)) return g4_set_err(ctx, G4_EINVAL, "box must be positive");
+    if (ne < G4_EWALD_NE_MIN || ne > G4_EWALD_NE_MAX) return g4_set_err(ctx, G4_EINVAL, "ne must be 4..128");
+    if (!table || ((uintptr_t)table & 255)) return g4_set_err(ctx, G4_EINVAL, "table must be 256-byte aligned");
+    if (bytes < g4_ewald_layout_bytes(ne)) return g4_set_err(ctx, G4_EINVAL, "table too small");
+    return g4_launch_ewald_table(ctx, box, ne, static_cast<float *>(table));
+}
+
+int g4_ewald_eval(g4_ctx *ctx, const void *table, int ne, double box, int64_t n, const double *dx, const double *dy,
+                  const double *dz, double *psi, double *gx, double *gy, double *gz)
+{
+    if (!ctx) return G4_EINVAL;
+    if (!table || !(box > 0) || ne < G4_EWALD_NE_MIN || ne > G4_EWALD_NE_MAX || n < 0)
+        return g4_set_err(ctx, G4_EINVAL, "bad table, box, ne or n");
+    if (n > 0 && (!dx || !dy || !dz || !psi || !gx || !gy || !gz)) return g4_set_err(ctx, G4_EINVAL, "null array");
+    return g4_launch_ewald_eval(ctx, static_cast<const float *>(table), ne, box, n, dx, dy, dz, psi, gx, gy, gz);
 }
 
 int g4_pm_workspace_bytes(int ng, size_t *bytes)
@@ -449,7 +482,8 @@ static int check_kdk(g4_ctx *ctx, const g4_kdk_params *kp)
     if (kp->max_level < 0 || kp->max_level > G4_KDK_MAX_LEVEL) return g4_set_err(ctx, G4_EINVAL, "max_level out of range");
     if (!(kp->eta > 0) || !(kp->eps > 0)) return g4_set_err(ctx, G4_EINVAL, "eta and eps must be positive");
     const int kernel = kp->solver == 2 ? kp->fp.kernel : kp->wp.kernel;
-    if (kernel == 1 && !kp->tp.periodic) return g4_set_err(ctx, G4_EINVAL, "short-range kernel needs a periodic box");
+    if ((kernel == 1 || (kp->solver != 2 && kernel == 2)) && !kp->tp.periodic)
+        return g4_set_err(ctx, G4_EINVAL, "this kernel needs a periodic box");
     return G4_OK;
 }
 

@@ -56,3 +56,7 @@ int g4_kdk_layout_bytes(const g4_kdk_params *kp, int64_t n, size_t *bytes);
 int g4_launch_kdk(g4_ctx *ctx, const g4_kdk_params *kp, int64_t n, double *pos, double *vel, const float *mass,
                   double dt, double *ax, double *ay, double *az, int have_acc, void *ws, size_t ws_bytes,
                   g4_kdk_stats *stats);
+size_t g4_ewald_layout_bytes(int ne);
+int g4_launch_ewald_table(g4_ctx *ctx, double box, int ne, float *tab);
+int g4_launch_ewald_eval(g4_ctx *ctx, const float *tab, int ne, double box, int64_t n, const double *dx,
+                         const double *dy, const double *dz, double *psi, double *gx, double *gy, double *gz);

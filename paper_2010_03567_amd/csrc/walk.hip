@@ -19,6 +19,7 @@
 #include <new>
 #include <vector>
 
+#include "ewald.h"
 #include "g4_device.h"
 #include "g4_internal.h"
 
@@ -40,6 +41,9 @@ struct WalkArgs {
     const float4 *tab;  // short-range factor table (kernel 2), tn intervals, t = r * tscale
     uint32_t tn;
     float tscale;
+    const float *ew;    // periodic correction table (kernel 3): ew_n intervals of ew_h over [0, L/2]
+    int ew_n;
+    float ew_h, ew_hinv;
     float rcut2;
     float theta2;
     float alpha;      // relative-criterion accuracy parameter
@@ -58,13 +62,17 @@ struct WalkArgs {
     uint32_t *flags;            // tree flags: G4_FLAG_WALK_STACK if the stack bound is ever broken
 };
 
+// Kernels: 0 Newtonian (isolated), 1 TreePM short range, 2 the same with the
+// short-range factors from a table, 3 periodic Newtonian: the nearest image
+// with the Newtonian kernel plus the correction potential psi of every node
+// and particle (eq. eqnpo1), its derivatives from the Taylor table.
 // g1, g2, g3 (and g0) of the interaction kernel at r (r2, rinv given), r >= h.
 template <int KER>
 __device__ __forceinline__ void gfun(float r2, float rinv, const WalkArgs &A, float &g0, float &g1, float &g2,
                                      float &g3)
 {
     float ri2 = rinv * rinv;
-    if (KER == 0) {
+    if (KER == 0 || KER == 3) {
         g0 = rinv;
         g1 = -rinv * ri2;
         g2 = -3.0f * g1 * ri2;
@@ -235,6 +243,16 @@ __device__ __forceinline__ void eval_p2m(const WalkArgs &A, WaveLds<POT> &W, uin
         fz = fac * dz;
         if (POT) fp = mass * g0 + 0.5f * (g1 * tr + g2 * rqr);
     }
+    if constexpr (KER == 3) {
+        // the other images: g = 1/r - psi, so the node adds +f (force) and +phi_psi (potential)
+        float cx, cy, cz, cp = 0.f;
+        ew_node<POT, ORD3>(A.ew, A.ew_n, A.ew_h, A.ew_hinv, dx, dy, dz, mass, qa, qb, A.q3 + (size_t)node * 10, cx, cy,
+                           cz, cp);
+        fx -= cx;
+        fy -= cy;
+        fz -= cz;
+        if (POT) fp -= cp;
+    }
     lds_add(&W.acc[0][t], -(double)fx);
     lds_add(&W.acc[1][t], -(double)fy);
     lds_add(&W.acc[2][t], -(double)fz);
@@ -311,12 +329,21 @@ __global__ __launch_bounds__(256) void k_walk(const WalkArgs A)
         const float s2 = fmaf(sx, sx, fmaf(sy, sy, sz * sz));
         float K, Wp;
         if constexpr (KER == 2) pair_kernel_tab<POT>(s2, A.tab, A.tn, A.tscale, A.asplit, A.h2, A.hinv, K, Wp);
-        else pair_kernel<KER, POT>(s2, A.asplit, A.h2, A.hinv, K, Wp);
+        else pair_kernel<KER == 3 ? 0 : KER, POT>(s2, A.asplit, A.h2, A.hinv, K, Wp);
         const float mk = mj * K;
         q_fx = fmaf(mk, sx, q_fx);
         q_fy = fmaf(mk, sy, q_fy);
         q_fz = fmaf(mk, sz, q_fz);
         if (POT) q_fp = fmaf(-mj, Wp, q_fp);
+        if constexpr (KER == 3) {
+            // + m grad psi(d), + m psi(d) (grad psi(0) = 0, so the target's own slot adds nothing)
+            float ex, ey, ez, ep = 0.f;
+            ew_grad<POT>(A.ew, A.ew_n, A.ew_h, A.ew_hinv, sx, sy, sz, ex, ey, ez, ep);
+            q_fx = fmaf(mj, ex, q_fx);
+            q_fy = fmaf(mj, ey, q_fy);
+            q_fz = fmaf(mj, ez, q_fz);
+            if (POT) q_fp = fmaf(mj, ep, q_fp);
+        }
         q_src++;
         q_rem--;
         if (q_rem == 0) {
@@ -425,7 +452,7 @@ __global__ __launch_bounds__(256) void k_walk(const WalkArgs A)
             // exclusion zone; the nearest-edge distance is max(|d| unit - l/2, 0) per axis
             const int32_t gx = (int32_t)(R.gx - T.x), gy = (int32_t)(R.gy - T.y), gz = (int32_t)(R.gz - T.z);
             bool ok = valid;
-            if (KER >= 1) {
+            if (KER == 1 || KER == 2) {
                 // nearest edge of the node's cube farther than r_cut: drop it
                 const float qx = fmaxf(fabsf((float)gx) * A.unit - R.hl, 0.f);
                 const float qy = fmaxf(fabsf((float)gy) * A.unit - R.hl, 0.f);
@@ -637,6 +664,10 @@ int g4_launch_walk(g4_ctx *ctx, g4_tree *t, const g4_walk_params *wp, int kernel
         G4_HIP(ctx, hipGetLastError());
         t->tab_n = wp->sr_table;
     }
+    A.ew = static_cast<const float *>(wp->ewald_table);
+    A.ew_n = wp->ewald_n;
+    A.ew_h = kernel == 2 ? (float)(0.5 * t->tp.box / wp->ewald_n) : 0.f;
+    A.ew_hinv = kernel == 2 ? (float)(2.0 * wp->ewald_n / t->tp.box) : 0.f;
     A.rcut2 = (float)(wp->r_cut * wp->r_cut);
     A.theta2 = (float)(criterion == 0 ? (wp->criterion == 0 ? wp->theta * wp->theta : wp->theta_seed * wp->theta_seed)
                                       : 0.0);
@@ -699,6 +730,9 @@ int g4_launch_walk(g4_ctx *ctx, g4_tree *t, const g4_walk_params *wp, int kernel
     if (kernel == 0) {
         if (criterion == 0) { if (P) launch_walk<0, 0, true>(A, s); else launch_walk<0, 0, false>(A, s); }
         else { if (P) launch_walk<0, 1, true>(A, s); else launch_walk<0, 1, false>(A, s); }
+    } else if (kernel == 2) {
+        if (criterion == 0) { if (P) launch_walk<3, 0, true>(A, s); else launch_walk<3, 0, false>(A, s); }
+        else { if (P) launch_walk<3, 1, true>(A, s); else launch_walk<3, 1, false>(A, s); }
     } else if (tabulated) {
         if (criterion == 0) { if (P) launch_walk<2, 0, true>(A, s); else launch_walk<2, 0, false>(A, s); }
         else { if (P) launch_walk<2, 1, true>(A, s); else launch_walk<2, 1, false>(A, s); }

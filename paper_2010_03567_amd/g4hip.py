@@ -40,7 +40,7 @@ class g4_walk_params(C.Structure):
                 ("G", C.c_double), ("eps0", C.c_double), ("r_s", C.c_double), ("r_cut", C.c_double),
                 ("theta", C.c_double), ("alpha", C.c_double), ("theta_seed", C.c_double),
                 ("a_seed", C.c_void_p), ("group_size", C.c_int), ("seed_from_tree", C.c_int),
-                ("sr_table", C.c_int)]
+                ("sr_table", C.c_int), ("ewald_table", C.c_void_p), ("ewald_n", C.c_int)]
 
 
 class g4_fmm_params(C.Structure):
@@ -101,6 +101,8 @@ _SIGS = {
     "g4_kdk_step": [_p, C.POINTER(g4_kdk_params), _i64, _p, _p, _p, C.c_double, _p, _p, _p, _i32, _p, _sz,
                     C.POINTER(g4_kdk_stats)],
     "g4_pm_longrange": [_p, _p, C.POINTER(g4_pm_params), _p, _sz, _i32, _p, _p, _p, _p],
+    "g4_ewald_table": [_p, C.c_double, _i32, _p, _sz],
+    "g4_ewald_eval": [_p, _p, _i32, C.c_double, _i64, _p, _p, _p, _p, _p, _p, _p],
     "g4_fmm_workspace_bytes": [_p, C.POINTER(g4_fmm_params), C.c_double, C.POINTER(_sz)],
     "g4_forest_workspace_bytes": [C.POINTER(g4_tree_params), _i32, _i64, C.POINTER(_sz)],
     "g4_build_forest": [_p, _i32, _p, C.POINTER(g4_particles), C.POINTER(g4_tree_params), _p, _sz,
@@ -118,13 +120,15 @@ for _name, _args in _SIGS.items():
     f.restype = C.c_int
 _L.g4_last_error.argtypes = [_p]
 _L.g4_last_error.restype = C.c_char_p
+_L.g4_ewald_table_bytes.argtypes = [_i32]
+_L.g4_ewald_table_bytes.restype = _sz
 
 OPTIONAL_SYMBOLS = []  # filled by extensions below when present
 
 
 def exported_symbols():
     """Names of the entry points this binding found in the library."""
-    return sorted(_SIGS) + ["g4_last_error"] + OPTIONAL_SYMBOLS
+    return sorted(_SIGS) + ["g4_last_error", "g4_ewald_table_bytes"] + OPTIONAL_SYMBOLS
 
 
 class G4Error(RuntimeError):
@@ -183,7 +187,8 @@ def tree_params(periodic, box, origin=(0.0, 0.0, 0.0), leaf_max=8, max_depth=21,
 
 
 def walk_params(kernel=0, criterion=0, order=3, exclusion=1, G=1.0, eps0=0.0, r_s=1.0, r_cut=1e30, theta=0.7,
-                alpha=0.005, theta_seed=0.7, a_seed=None, group_size=64, seed_from_tree=0, sr_table=0):
+                alpha=0.005, theta_seed=0.7, a_seed=None, group_size=64, seed_from_tree=0, sr_table=0, ewald=None):
+    """ewald: the EwaldTable of the box for kernel 2."""
     wp = g4_walk_params()
     wp.kernel, wp.criterion, wp.order, wp.exclusion = int(kernel), int(criterion), int(order), int(exclusion)
     wp.G, wp.eps0, wp.r_s, wp.r_cut = float(G), float(eps0), float(r_s), float(r_cut)
@@ -192,7 +197,9 @@ def walk_params(kernel=0, criterion=0, order=3, exclusion=1, G=1.0, eps0=0.0, r_
     wp.group_size = int(group_size)
     wp.seed_from_tree = int(seed_from_tree)
     wp.sr_table = int(sr_table)
-    wp._keep = a_seed
+    if ewald is not None:
+        wp.ewald_table, wp.ewald_n = ewald.ptr, int(ewald.ne)
+    wp._keep = (a_seed, ewald)
     return wp
 
 
@@ -317,6 +324,38 @@ def pm_params(ng, r_s, G=1.0):
     pp = g4_pm_params()
     pp.ng, pp.r_s, pp.G = int(ng), float(r_s), float(G)
     return pp
+
+
+class EwaldTable:
+    """Device table of the periodic correction potential psi of a cube of side
+    `box` (g4_ewald_table); keeps its buffer alive."""
+
+    def __init__(self, ctx, box, ne=32):
+        nbytes = int(_L.g4_ewald_table_bytes(int(ne)))
+        if nbytes == 0:
+            raise G4Error(G4_EINVAL, "ne must be 4..128")
+        self.buf = torch.empty(nbytes + 256, dtype=torch.uint8, device=ctx.device)
+        off = (-self.buf.data_ptr()) % 256
+        self.ptr = self.buf.data_ptr() + off
+        self.box, self.ne, self.nbytes = float(box), int(ne), nbytes
+        ctx.check(_L.g4_ewald_table(ctx.h, self.box, self.ne, C.c_void_p(self.ptr), nbytes))
+
+    def values(self):
+        """The table as a ((ne+1)^3, 84) float32 tensor (a view)."""
+        off = self.ptr - self.buf.data_ptr()
+        return self.buf[off:off + self.nbytes].view(torch.float32).view(-1, 84)
+
+
+def g4_ewald_eval(ctx, table, d):
+    """psi and grad psi at offsets d ((n, 3) float64 device tensor) through the
+    table's Taylor lookup: returns (psi (n,), grad (n, 3)) float64."""
+    n = d.shape[0]
+    dx, dy, dz = (d[:, k].contiguous() for k in range(3))
+    psi = torch.empty(n, dtype=torch.float64, device=ctx.device)
+    g = [torch.empty(n, dtype=torch.float64, device=ctx.device) for _ in range(3)]
+    ctx.check(_L.g4_ewald_eval(ctx.h, C.c_void_p(table.ptr), table.ne, table.box, n, _ptr(dx), _ptr(dy), _ptr(dz),
+                               _ptr(psi), _ptr(g[0]), _ptr(g[1]), _ptr(g[2])))
+    return psi, torch.stack(g, 1)
 
 
 def g4_pm_workspace_bytes(ng):
