@@ -74,6 +74,7 @@ def parse():
     ap.add_argument("--no-forest", action="store_true")
     ap.add_argument("--no-pm", action="store_true", help="skip the total TreePM (walk + PM) line")
     ap.add_argument("--no-kdk", action="store_true", help="skip the hierarchical time-integration line")
+    ap.add_argument("--no-ewald", action="store_true", help="skip the periodic tree + Ewald line")
     ap.add_argument("--err-sample", type=int, default=10000)
     ap.add_argument("--group", type=int, default=64)
     ap.add_argument("--leaf", type=int, default=24, help="leaf size B of the tree")
@@ -419,6 +420,8 @@ def main():
         result["fmm"] = bench_fmm(args, g, ctx, flops)
     if not args.no_kdk:
         result["hierarchical_step"] = bench_kdk(args, g, ctx)
+    if not args.no_ewald:
+        result["periodic_ewald"] = bench_ewald(args, g, ctx, flops)
     if not args.no_forest:
         result["forest"] = bench_forest(args, g, ctx)
     if not args.no_cpu_baseline:
@@ -525,6 +528,74 @@ def bench_kdk(args, g, ctx):
             "force_evals_per_s": st["force_evals"] / (ms * 1e-3), "evals_per_level": lv[: st["deepest_level"] + 1],
             "cost_vs_onesided": st["force_evals"] / onesided if onesided else None,
             "note": "one step from rest; the forces at the start are given (as in a running integration)"}
+
+
+def bench_ewald(args, g, ctx, flops):
+    """Periodic gravity by the pure tree with the Ewald correction (kernel 2)
+    on the clustered 128^3 box (seed 2): the correction table (ne = 32) built
+    once per box size, then per step build, moments, geometric pre-walk
+    (theta 0.7) and the relative walk (p = 3, alpha 0.002); errors against the
+    exact Ewald direct sum (FP64, every pair summed by Ewald's method) on
+    sampled targets."""
+    import torch
+    import workloads
+    n = SMALL_N
+    _, eps0 = treepm_scales(n)
+    ps = workloads.clustered_box(n, seed=2)
+    dev = ctx.device
+    pos = torch.from_numpy(ps.pos).to(dev)
+    mass = torch.from_numpy(ps.mass.astype(np.float32)).to(dev)
+    tp = g.tree_params(True, 1.0, leaf_max=args.leaf)
+    ws = torch.empty(g.g4_workspace_bytes(tp, n) + 256, dtype=torch.uint8, device=dev)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    table = g.EwaldTable(ctx, 1.0, 32)
+    torch.cuda.synchronize()
+    table_ms = (time.perf_counter() - t0) * 1e3
+    log(f"[bench] periodic tree + Ewald: table (ne 32) built in {table_ms:.1f} ms")
+    alpha = 0.002
+    wp = g.walk_params(kernel=2, criterion=1, alpha=alpha, theta_seed=0.7, eps0=eps0, group_size=args.group,
+                       ewald=table)
+    outs = tuple(torch.empty(n, dtype=torch.float64, device=dev) for _ in range(3)) + (None, None, None)
+    state = {}
+
+    def step(want_stats=False):
+        x, y, z = g.g4_quantize(ctx, pos, tp)
+        p = g.particles(x, y, z, mass)
+        t = g.g4_build_tree(ctx, p, tp, ws=ws)
+        g.g4_compute_multipoles(ctx, t, 3)
+        o = g.g4_tree_force(ctx, t, wp, out=outs, want_stats=want_stats)
+        state["p"], state["o"] = p, o
+        if want_stats:
+            state["stats"] = o["stats"]
+
+    step(want_stats=True)
+    log(f"[bench] periodic tree + Ewald: first step done")
+    steps = max(2, args.steps // 3)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        step()
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / steps
+    st = state["stats"]
+    log(f"[bench] periodic tree + Ewald: {ms:.2f} ms/step; exact Ewald direct sums on 256 targets")
+    a = np.stack([outs[0].cpu().numpy(), outs[1].cpu().numpy(), outs[2].cpu().numpy()], 1)
+    tg = workloads.sample_indices(n, 256, seed=97)
+    r = g.g4_direct_force(ctx, state["p"], tp, g.walk_params(kernel=2, eps0=eps0),
+                          targets=torch.from_numpy(tg).to(dev), want_pot=False)
+    ref = np.stack([r["ax"].cpu().numpy(), r["ay"].cpu().numpy(), r["az"].cpu().numpy()], 1)
+    err = workloads.percentiles(workloads.relative_errors(a[tg], ref))
+    walk_ms, seed_ms = 1e3 * st["t_walk"], 1e3 * st["t_seed"]
+    log(f"[bench] periodic tree + Ewald 128^3: {ms:.2f} ms/step (walk {walk_ms:.2f} ms, pre-walk "
+        f"{seed_ms:.2f} ms; table {table_ms:.1f} ms once), errors {err}")
+    return {"workload": "periodic_tree_ewald_clustered_box_128^3 (seed 2), p=3, relative alpha 0.002 "
+                        "(pre-walk theta 0.7), leaf %d, Ewald table ne 32" % args.leaf,
+            "forces_per_s": n / (ms * 1e-3), "ms_per_step": ms, "walk_ms": walk_ms, "seed_ms": seed_ms,
+            "table_build_ms": table_ms,
+            "interactions_per_particle": {"pp": st["n_p2p"] / n, "pn": st["n_p2m"] / n,
+                                          "seed_pp": st["n_seed_p2p"] / n, "seed_pn": st["n_seed_p2m"] / n},
+            "errors_vs_ewald_direct": err, "error_sample": len(tg)}
 
 
 def bench_fmm(args, g, ctx, flops):

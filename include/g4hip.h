@@ -335,7 +335,11 @@ int g4_kdk_step(g4_ctx *ctx, const g4_kdk_params *kp, int64_t n, double *pos, do
 /* Direct summation on the device (the exact reference of Sec. "Softened
  * potential in periodic systems"): forces on `ntargets` particles (device
  * int64 indices into the caller order, or NULL for all) from all n particles,
- * FP64 arithmetic.  kernel/eps0/r_s from wp; r_cut used only if truncate. */
+ * FP64 arithmetic.  kernel/eps0/r_s from wp; r_cut used only if truncate.
+ * kernel 2 (periodic): the softened nearest image plus psi of the other
+ * images by exact Ewald sums per pair (Sec. "Periodic boundary conditions";
+ * ~10^3 terms per pair, meant for sampled targets).  Kernels 1 and 2 need a
+ * periodic tp. */
 int g4_direct_force(g4_ctx *ctx, const g4_particles *p, const g4_tree_params *tp, const g4_walk_params *wp,
                     int truncate, const int64_t *targets, int64_t ntargets, double *ax, double *ay, double *az,
                     double *pot);

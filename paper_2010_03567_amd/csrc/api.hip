@@ -518,7 +518,9 @@ int g4_direct_force(g4_ctx *ctx, const g4_particles *p, const g4_tree_params *tp
     if (!p || !wp || !ax || !ay || !az) return g4_set_err(ctx, G4_EINVAL, "null argument");
     if (p->n < 1 || !p->x || !p->y || !p->z || !p->mass) return g4_set_err(ctx, G4_EINVAL, "bad particles");
     if (targets && ntargets < 0) return g4_set_err(ctx, G4_EINVAL, "negative target count");
+    if (wp->kernel < 0 || wp->kernel > 2) return g4_set_err(ctx, G4_EINVAL, "kernel must be 0, 1 or 2");
     if (wp->kernel == 1 && !(wp->r_s > 0)) return g4_set_err(ctx, G4_EINVAL, "r_s must be positive");
+    if (wp->kernel >= 1 && !tp->periodic) return g4_set_err(ctx, G4_EINVAL, "this kernel needs a periodic box");
     return g4_launch_direct(ctx, p, tp, wp, truncate, targets, ntargets, ax, ay, az, pot);
 }
 

@@ -2,8 +2,12 @@
 // reference against which the paper measures every force algorithm (Sec.
 // "Softened potential in periodic systems").  Kernel 0: spline-softened
 // Newtonian; kernel 1: the short-range force of eq. (eqnpo4) over the nearest
-// image only, optionally truncated at r_cut.  One thread per target; source
-// particles are staged through LDS tiles shared by the block.
+// image only, optionally truncated at r_cut; kernel 2: periodic gravity, the
+// softened nearest image plus the correction psi of the other images summed
+// exactly by Ewald's method for every pair (Sec. "Periodic boundary
+// conditions", eqs. eqnpo1, eqnewal) -- about a thousand terms per pair, for
+// sampled targets.  One thread per target; source particles are staged
+// through LDS tiles shared by the block.
 #include "g4_internal.h"
 
 #define DT 256
@@ -14,7 +18,7 @@ struct DirectArgs {
     int64_t n;
     const int64_t *targets;
     int64_t nt;
-    double unit, h, hinv, asplit, rskip2, rcut2, G;
+    double unit, h, hinv, asplit, rskip2, rcut2, G, L;
     int kernel, truncate;
     double *ax, *ay, *az, *pot;
 };
@@ -49,6 +53,50 @@ __device__ __forceinline__ double erfx(double x)
         return 2.0 / 1.7724538509055160273 * s;
     }
     return erf(x) / x;
+}
+
+// psi(d) and grad psi(d) of a cube of side L by the Ewald sums with alpha = 2/L:
+// the n = 0 image combined with 1/|d| as erf(alpha r)/r, 342 further real
+// images (|n_i| <= 3) and 728 wave vectors (|n_i| <= 4).
+__device__ void ewald_exact(double dx, double dy, double dz, double L, double &psi, double &gx, double &gy,
+                            double &gz)
+{
+    const double alpha = 2.0 / L, V = L * L * L, c2 = 2.0 * alpha / 1.7724538509055160273;
+    const double r2 = dx * dx + dy * dy + dz * dz, r = sqrt(r2);
+    // erf(alpha r)/r and its r^-1 d/dr = -(erf(ar) - 2ar e^{-a^2 r^2}/sqrt(pi))/r^3
+    psi = alpha * erfx(alpha * r) + M_PI / (alpha * alpha * V);
+    double g1 = -alpha * alpha * alpha * lrf(alpha * r);
+    gx = g1 * dx;
+    gy = g1 * dy;
+    gz = g1 * dz;
+    for (int nx = -3; nx <= 3; nx++)
+        for (int ny = -3; ny <= 3; ny++)
+            for (int nz = -3; nz <= 3; nz++) {
+                if (!nx && !ny && !nz) continue;
+                const double px = dx + nx * L, py = dy + ny * L, pz = dz + nz * L;
+                const double q2 = px * px + py * py + pz * pz, q = sqrt(q2), x = alpha * q;
+                const double ec = erfc(x);
+                psi -= ec / q;
+                // d/dx_i [erfc(alpha q)/q] = -(erfc + 2 x e^{-x^2}/sqrt(pi)) x_i / q^3
+                const double f = (ec + c2 * q * exp(-x * x)) / (q2 * q);
+                gx += f * px;
+                gy += f * py;
+                gz += f * pz;
+            }
+    const double tp = 2.0 * M_PI / L;
+    for (int nx = -4; nx <= 4; nx++)
+        for (int ny = -4; ny <= 4; ny++)
+            for (int nz = -4; nz <= 4; nz++) {
+                if (!nx && !ny && !nz) continue;
+                const double kx = tp * nx, ky = tp * ny, kz = tp * nz, k2 = kx * kx + ky * ky + kz * kz;
+                const double w = 4.0 * M_PI / V * exp(-k2 / (4.0 * alpha * alpha)) / k2;
+                double sn, cs;
+                sincos(kx * dx + ky * dy + kz * dz, &sn, &cs);
+                psi -= w * cs;
+                gx += w * sn * kx;
+                gy += w * sn * ky;
+                gz += w * sn * kz;
+            }
 }
 
 __global__ __launch_bounds__(DT) void k_direct(const DirectArgs A)
@@ -105,6 +153,54 @@ __global__ __launch_bounds__(DT) void k_direct(const DirectArgs A)
     }
 }
 
+// Kernel 2 costs about a thousand terms per pair, so a target gets a whole
+// block: its threads split the sources and their FP64 sums are reduced in LDS.
+__global__ __launch_bounds__(DT) void k_direct_ewald(const DirectArgs A)
+{
+    __shared__ double red[4][DT];
+    const int64_t q = blockIdx.x;
+    const int64_t i = A.targets ? A.targets[q] : q;
+    const uint32_t xi = A.x[i], yi = A.y[i], zi = A.z[i];
+    double ax = 0, ay = 0, az = 0, ph = 0;
+    for (int64_t j = threadIdx.x; j < A.n; j += DT) {
+        if (j == i) continue;
+        const double dx = (double)(int32_t)(A.x[j] - xi) * A.unit;
+        const double dy = (double)(int32_t)(A.y[j] - yi) * A.unit;
+        const double dz = (double)(int32_t)(A.z[j] - zi) * A.unit;
+        const double r2 = dx * dx + dy * dy + dz * dz, r = sqrt(r2);
+        const double m = (double)A.m[j];
+        double K, W;
+        if (r >= A.h) {
+            K = 1.0 / (r2 * r);
+            W = 1.0 / r;
+        } else {
+            soft_kw(r * A.hinv, A.hinv, K, W);
+        }
+        double ps, gx, gy, gz;
+        ewald_exact(dx, dy, dz, A.L, ps, gx, gy, gz);
+        ax += m * (K * dx + gx);
+        ay += m * (K * dy + gy);
+        az += m * (K * dz + gz);
+        ph += m * (ps - W);
+    }
+    red[0][threadIdx.x] = ax;
+    red[1][threadIdx.x] = ay;
+    red[2][threadIdx.x] = az;
+    red[3][threadIdx.x] = ph;
+    __syncthreads();
+    for (int s = DT / 2; s > 0; s >>= 1) {
+        if (threadIdx.x < s)
+            for (int c = 0; c < 4; c++) red[c][threadIdx.x] += red[c][threadIdx.x + s];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        A.ax[q] = A.G * red[0][0];
+        A.ay[q] = A.G * red[1][0];
+        A.az[q] = A.G * red[2][0];
+        if (A.pot) A.pot[q] = A.G * red[3][0];
+    }
+}
+
 int g4_launch_direct(g4_ctx *ctx, const g4_particles *p, const g4_tree_params *tp, const g4_walk_params *wp,
                      int truncate, const int64_t *targets, int64_t ntargets, double *ax, double *ay, double *az,
                      double *pot)
@@ -114,6 +210,7 @@ int g4_launch_direct(g4_ctx *ctx, const g4_particles *p, const g4_tree_params *t
     A.targets = targets;
     A.nt = targets ? ntargets : p->n;
     A.unit = tp->box / (tp->periodic ? 4294967296.0 : 2147483648.0);
+    A.L = tp->box;
     A.h = 2.8 * wp->eps0;
     A.hinv = A.h > 0 ? 1.0 / A.h : 0.0;
     A.kernel = wp->kernel;
@@ -124,7 +221,8 @@ int g4_launch_direct(g4_ctx *ctx, const g4_particles *p, const g4_tree_params *t
     A.rcut2 = wp->r_cut * wp->r_cut;
     A.G = wp->G;
     A.ax = ax; A.ay = ay; A.az = az; A.pot = pot;
-    if (A.nt > 0) k_direct<<<(unsigned)((A.nt + DT - 1) / DT), DT, 0, ctx->stream>>>(A);
+    if (A.nt > 0 && A.kernel == 2) k_direct_ewald<<<(unsigned)A.nt, DT, 0, ctx->stream>>>(A);
+    else if (A.nt > 0) k_direct<<<(unsigned)((A.nt + DT - 1) / DT), DT, 0, ctx->stream>>>(A);
     G4_HIP(ctx, hipGetLastError());
     return G4_OK;
 }
