@@ -51,7 +51,7 @@ class WalkParams(C.Structure):
 
 class FmmParams(C.Structure):
     _fields_ = [("kernel", C.c_int), ("G", C.c_double), ("eps0", C.c_double), ("r_s", C.c_double),
-                ("r_cut", C.c_double), ("theta", C.c_double)]
+                ("r_cut", C.c_double), ("theta", C.c_double), ("criterion", C.c_int), ("alpha", C.c_double)]
 
 
 _lib = None
@@ -89,7 +89,7 @@ def lib():
         L.orc_walk.argtypes = [p, C.POINTER(WalkParams), p, p, i64, p, p, p, i32]
         L.orc_direct.argtypes = [i64, p, p, p, p, d, C.POINTER(WalkParams), i32, p, i64, p, p, i32]
         L.orc_fmm.restype = i32
-        L.orc_fmm.argtypes = [p, C.POINTER(FmmParams), p, p, p]
+        L.orc_fmm.argtypes = [p, C.POINTER(FmmParams), p, p, p, p]
         L.orc_mlp_forward.argtypes = [p, p, i64, p]
         L.orc_mlp_loss_grad.restype = d
         L.orc_mlp_loss_grad.argtypes = [p, p, p, i64, d, p]
@@ -227,12 +227,16 @@ class Tree:
             raise RuntimeError("orc_features failed")
         return f
 
-    def fmm(self, kernel=0, G=1.0, eps0=0.0, r_s=1.0, r_cut=np.inf, theta=0.5):
+    def fmm(self, kernel=0, G=1.0, eps0=0.0, r_s=1.0, r_cut=np.inf, theta=0.5, criterion=0, alpha=0.005,
+            aseed=None):
+        """criterion 1: the relative node-node criterion with |a| per particle from aseed."""
         if not self.has_moments:
             self.compute_moments()
-        P = FmmParams(int(kernel), float(G), float(eps0), float(r_s), float(r_cut), float(theta))
+        P = FmmParams(int(kernel), float(G), float(eps0), float(r_s), float(r_cut), float(theta), int(criterion),
+                      float(alpha))
+        asd = None if aseed is None else _f64(aseed)
         acc = np.zeros((self.n, 3)); pot = np.zeros(self.n); st = np.zeros(3, np.int64)
-        s = lib().orc_fmm(self._h, C.byref(P), _ptr(acc), _ptr(pot), _ptr(st))
+        s = lib().orc_fmm(self._h, C.byref(P), _ptr(asd), _ptr(acc), _ptr(pot), _ptr(st))
         if s != 0:
             raise RuntimeError(f"orc_fmm failed with status {s}")
         return acc, pot, st

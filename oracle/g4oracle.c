@@ -948,8 +948,24 @@ typedef struct {
     orc_fmm_params P;
     field *F;              /* per node */
     double *acc, *pot;     /* per particle (caller order), unscaled by G */
+    const double *aseed;   /* |a| per particle (caller order), relative criterion */
+    double *amin;          /* smallest |a| among each node's particles */
     int64_t n_pp, n_pn, n_nn;
 } fmm_ctx;
+
+/* |a|_min of every node: the smallest seed among its particles */
+static double node_amin(fmm_ctx *C, int64_t q)
+{
+    const onode *nd = &C->t->nodes[q];
+    double m = INFINITY;
+    if (nd->leaf) {
+        for (int64_t s = 0; s < nd->count; s++) m = fmin(m, C->aseed[C->t->idx[nd->first + s]]);
+    } else {
+        for (int c = 0; c < nd->nchild; c++) m = fmin(m, node_amin(C, nd->child0 + c));
+    }
+    C->amin[q] = m;
+    return m;
+}
 
 /* Entity: node q >= 0, particle j encoded as -(j+1). */
 typedef struct {
@@ -957,6 +973,7 @@ typedef struct {
     uint32_t gc[3];        /* integer centre (position for a particle) */
     double dcom[3];        /* COM minus centre */
     double mass, q2[9], q3[27];
+    double amin;           /* smallest |a| of its particles (relative criterion) */
 } entity;
 
 static void get_entity(const fmm_ctx *C, int64_t e, entity *E)
@@ -970,6 +987,7 @@ static void get_entity(const fmm_ctx *C, int64_t e, entity *E)
         E->mass = nd->mass;
         memcpy(E->q2, nd->q2, sizeof(E->q2));
         memcpy(E->q3, nd->q3, sizeof(E->q3));
+        E->amin = C->amin ? C->amin[e] : 0.0;
     } else {
         int64_t j = -e - 1;
         E->level = -1;
@@ -978,6 +996,7 @@ static void get_entity(const fmm_ctx *C, int64_t e, entity *E)
         E->mass = t->m[j];
         memset(E->q2, 0, sizeof(E->q2));
         memset(E->q3, 0, sizeof(E->q3));
+        E->amin = C->aseed ? C->aseed[j] : 0.0;
     }
 }
 
@@ -1078,7 +1097,15 @@ static void fmm_interact(fmm_ctx *C, int64_t A, int64_t B)
     double r = sqrt(r2);
     double lA = EA.level < 0 ? 0.0 : node_side(t, EA.level), lB = EB.level < 0 ? 0.0 : node_side(t, EB.level);
     double h = 2.8 * P->eps0;
-    if (!touching && lA + lB < P->theta * r && r >= h) {
+    int accept;
+    if (P->criterion == 0) {
+        accept = lA + lB < P->theta * r;                               /* eq. (eqnNodeDec) */
+    } else {
+        /* relative: (M_max / r^2)(l_max / r)^(p-1) < alpha |a|_min, p = 3 */
+        double Mmax = fmax(EA.mass, EB.mass), lmax = fmax(lA, lB), amin = fmin(EA.amin, EB.amin);
+        accept = Mmax * lmax * lmax < P->alpha * amin * r2 * r2;
+    }
+    if (!touching && accept && r >= h) {
         double D0, D1[3], D2[9], D3[27], D[4][27];
         orc_Dn(P->kernel, rv, P->kernel ? 0.5 / P->r_s : 0.0, &D0, D1, D2, D3);
         memset(D, 0, sizeof(D));
@@ -1194,15 +1221,23 @@ static void fmm_down(fmm_ctx *C, int64_t q)
     }
 }
 
-int orc_fmm(const orc_tree *t, const orc_fmm_params *P, double *acc, double *pot, int64_t stats[3])
+int orc_fmm(const orc_tree *t, const orc_fmm_params *P, const double *aseed, double *acc, double *pot,
+            int64_t stats[3])
 {
     if (!t->has_moments) return -4;
+    if (P->criterion == 1 && !aseed) return -1;
     fmm_ctx C;
     C.t = t;
     C.P = *P;
     C.F = (field *)calloc((size_t)t->nnodes, sizeof(field));
     C.acc = (double *)calloc((size_t)t->n * 3, sizeof(double));
     C.pot = (double *)calloc((size_t)t->n, sizeof(double));
+    C.aseed = P->criterion == 1 ? aseed : NULL;
+    C.amin = NULL;
+    if (C.aseed) {
+        C.amin = (double *)malloc((size_t)t->nnodes * sizeof(double));
+        node_amin(&C, 0);
+    }
     C.n_pp = C.n_pn = C.n_nn = 0;
     fmm_interact(&C, 0, 0);
     fmm_down(&C, 0);
@@ -1214,6 +1249,7 @@ int orc_fmm(const orc_tree *t, const orc_fmm_params *P, double *acc, double *pot
     free(C.F);
     free(C.acc);
     free(C.pot);
+    free(C.amin);
     return 0;
 }
 

@@ -26,6 +26,8 @@ typedef struct {
 typedef struct {
     int kernel;      /* 0 Newtonian (isolated), 1 short-range (FMM-PM short-range pass) */
     double G, eps0, r_s, r_cut, theta;
+    int criterion;   /* 0 geometric (l_A + l_B)/r < theta, 1 relative (M_max/r^2)(l_max/r)^2 < alpha |a|_min */
+    double alpha;
 } orc_fmm_params;
 
 /* softening and kernels (scalar closed forms) */
@@ -68,8 +70,10 @@ void orc_direct(int64_t n, const uint32_t *X, const uint32_t *Y, const uint32_t 
                 double unit, const orc_walk_params *P, int truncate, const int64_t *targets, int64_t ntargets,
                 double *acc, double *pot, int nthreads);
 
-/* FMM, p = 3; acc n x 3 (caller order); stats: pp, pn, nn interaction counts */
-int orc_fmm(const orc_tree *t, const orc_fmm_params *P, double *acc, double *pot, int64_t stats[3]);
+/* FMM, p = 3; acc n x 3 (caller order); stats: pp, pn, nn interaction counts;
+ * aseed: |a| per particle (caller order), needed by criterion 1 */
+int orc_fmm(const orc_tree *t, const orc_fmm_params *P, const double *aseed, double *acc, double *pot,
+            int64_t stats[3]);
 
 /* MLP 8 -> 64 -> 64 -> 1 (SiLU), 4801 parameters */
 void orc_mlp_forward(const double *w, const double *feat, int64_t n, double *out);

@@ -224,6 +224,63 @@ def test_fmm_criterion_sums_both_sides():
     assert int(st[2]) == 2 and int(st[0]) == 4
 
 
+def _fmm_relative_thresholds(t, m, aseed):
+    """alpha at which each non-touching pair of the four-cell line switches:
+    the relative node-node criterion (M_max / r^2)(l_max / r)^(p-1) < alpha |a|_min
+    at p = 3, written out from the positions (l = the level-5 side)."""
+    side = 2.0 ** -5
+    X, Y, Z = t.X.astype(np.float64), t.Y.astype(np.float64), t.Z.astype(np.float64)
+    out = {}
+    for a, b in ((0, 2), (0, 3), (1, 3)):
+        r = math.sqrt((X[b] - X[a]) ** 2 + (Y[b] - Y[a]) ** 2 + (Z[b] - Z[a]) ** 2) * UNIT
+        out[(a, b)] = max(m[a], m[b]) * side ** 2 / (min(aseed[a], aseed[b]) * r ** 4)
+    return out
+
+
+def test_fmm_relative_criterion_threshold():
+    """Four single-particle leaves in a row (masses and |a| all different):
+    every non-touching pair becomes a node-node interaction exactly when alpha
+    passes M_max l_max^2 / (|a|_min r^4), probed at 1 +- 1e-6 of each pair's
+    threshold; the touching pairs stay particle pairs.  The thresholds differ
+    by factors of 2-10, so a wrong power of l or r, the sum instead of the
+    maximum of the masses, or the larger instead of the smaller |a| moves
+    every switch."""
+    X, Y, Z, _ = fmm_positions([(0, 0, 0), (1, 0, 0), (2, 0, 0), (3, 0, 0)])
+    m = np.array([1.0, 2.0, 3.0, 0.5])
+    aseed = np.array([5.0, 0.7, 3.0, 2.0])
+    t = oracle.Tree(X, Y, Z, m, True, 1.0, 1)
+    thr = _fmm_relative_thresholds(t, m, aseed)
+    vals = sorted(thr.values())
+    assert vals[1] / vals[0] > 1.5 and vals[2] / vals[1] > 1.5
+    for k, a in enumerate(vals):
+        _, _, st = t.fmm(kernel=0, eps0=0.0, criterion=1, alpha=a * (1 + 1e-6), aseed=aseed)
+        assert int(st[2]) == k + 1, (k, st)
+        _, _, st = t.fmm(kernel=0, eps0=0.0, criterion=1, alpha=a * (1 - 1e-6), aseed=aseed)
+        assert int(st[2]) == k, (k, st)
+    _, _, st = t.fmm(kernel=0, eps0=0.0, criterion=1, alpha=vals[-1] * 2, aseed=aseed)
+    assert tuple(int(v) for v in st) == (3, 0, 3)
+
+
+def test_fmm_relative_criterion_uses_the_smallest_a_of_either_node():
+    """Lowering one particle's |a| fourfold delays the switch of every pair
+    that holds it by the same factor (|a|_min is the smaller of the two
+    nodes' minima), and only of those pairs."""
+    X, Y, Z, _ = fmm_positions([(0, 0, 0), (1, 0, 0), (2, 0, 0), (3, 0, 0)])
+    m = np.ones(4)
+    base = np.full(4, 2.0)
+    t = oracle.Tree(X, Y, Z, m, True, 1.0, 1)
+    thr = _fmm_relative_thresholds(t, m, base)
+    a03 = thr[(0, 3)]
+    _, _, st = t.fmm(kernel=0, eps0=0.0, criterion=1, alpha=a03 * 1.01, aseed=base)
+    n_before = int(st[2])
+    low = base.copy()
+    low[3] = 0.5                      # |a|_min of pair (0, 3) and (1, 3) drops 4x
+    _, _, st = t.fmm(kernel=0, eps0=0.0, criterion=1, alpha=a03 * 1.01, aseed=low)
+    assert int(st[2]) < n_before
+    _, _, st = t.fmm(kernel=0, eps0=0.0, criterion=1, alpha=a03 * 4.04, aseed=low)
+    assert int(st[2]) >= n_before
+
+
 # ------------------------------------------------------------------ learned-seed features
 def _features_by_definition(X, Y, Z, m, B, kernel, eps0, r_s):
     """The eight seed features of every particle, recomputed in NumPy from

@@ -509,6 +509,31 @@ def test_fmm_momentum_conservation(kernel):
     assert np.percentile(err, 50) < 2e-2
 
 
+def test_fmm_relative_criterion_limits_and_accuracy():
+    """Relative node-node criterion (Sec. "Fast multipole method"): alpha -> 0
+    opens every pair down to particles (the direct sum); at finite alpha the
+    interactions stay symmetric (momentum to round-off) and the errors shrink
+    as alpha does, with the 90th percentile following alpha within a factor
+    of a few (the criterion bounds the error of each interaction relative to
+    the target's |a|)."""
+    ps, t, side = _plummer_tree(1500, seed=45, B=16)
+    ref, _ = oracle.direct(t.X, t.Y, t.Z, t.mass, t.unit, G=1.0, eps0=0.01, nthreads=8)
+    aseed = np.linalg.norm(ref, axis=1)
+    acc, _, st = t.fmm(kernel=0, eps0=0.01, criterion=1, alpha=1e-14, aseed=aseed)
+    np.testing.assert_allclose(acc, ref, rtol=1e-10, atol=1e-12 * np.abs(ref).max())
+    assert st[1] == 0 and st[2] == 0
+    p90 = []
+    for alpha in (0.01, 0.001):
+        acc, _, st = t.fmm(kernel=0, eps0=0.01, criterion=1, alpha=alpha, aseed=aseed)
+        net = (t.mass[:, None] * acc).sum(0)
+        assert np.abs(net).max() < 1e-13 * (t.mass[:, None] * np.abs(acc)).sum()
+        assert st[2] > 0
+        err = workloads.relative_errors(acc, ref)
+        p90.append(np.percentile(err, 90))
+        assert alpha / 30 < p90[-1] < alpha * 3, (alpha, p90[-1])
+    assert p90[1] < p90[0] / 3
+
+
 def test_tree_is_not_momentum_conserving():
     """The one-sided tree does not conserve momentum (the contrast the paper draws)."""
     ps, t, side = _plummer_tree(3000, seed=43, B=16)
