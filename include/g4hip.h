@@ -116,17 +116,27 @@ typedef struct {
 } g4_walk_params;
 
 /* FMM (Sec. "Fast multipole method", "The FMM-PM approach"), p = 3.
- * Node pairs interact when (l_A + l_B)/r < theta and the cubes do not touch
- * and r >= h; kernel 1 drops pairs whose nearest sides are farther apart than
- * r_cut.  deterministic = 1 sums every target's sources in a fixed order
- * (bitwise reproducible, slower: per-interaction lists are sorted); 0 gives
- * the same interactions with sums accumulated by atomics (round-off may
- * differ from run to run; the section on deterministic outcomes allows giving
- * up binary invariance for speed). */
+ * Node pairs interact when the opening criterion holds, the cubes do not
+ * touch and r >= h; kernel 1 drops pairs whose nearest sides are farther
+ * apart than r_cut.  criterion 0: (l_A + l_B)/r < theta (eq. eqnNodeDec);
+ * criterion 1: (M_max / r^2)(l_max / r)^(p-1) < alpha |a|_min, M_max and
+ * l_max the larger mass and side of the two, |a|_min the smallest |a| of any
+ * particle in either (a particle counts with l = 0, its own mass and |a|);
+ * a_seed: device, caller order, |a| per particle (needed by criterion 1; the
+ * per-node minima are formed in the call; it uses the tree's seed buffer, so
+ * a later walk with seed_from_tree needs a new geometric call first).
+ * deterministic = 1 sums every target's sources in a fixed order (bitwise
+ * reproducible, slower: per-interaction lists are sorted); 0 gives the same
+ * interactions with sums accumulated by atomics (round-off may differ from
+ * run to run; the section on deterministic outcomes allows giving up binary
+ * invariance for speed). */
 typedef struct {
     int kernel;
     double G, eps0, r_s, r_cut, theta;
     int deterministic;
+    int criterion;
+    double alpha;
+    const float *a_seed;
 } g4_fmm_params;
 
 /* Long-range (particle-mesh) part of the TreePM split (Sec. "TreePM

@@ -484,6 +484,9 @@ static int check_kdk(g4_ctx *ctx, const g4_kdk_params *kp)
     const int kernel = kp->solver == 2 ? kp->fp.kernel : kp->wp.kernel;
     if ((kernel == 1 || (kp->solver != 2 && kernel == 2)) && !kp->tp.periodic)
         return g4_set_err(ctx, G4_EINVAL, "this kernel needs a periodic box");
+    // every force call acts on a subset: seeds given per particle of the whole set cannot be used
+    if ((kp->solver == 1 && kp->wp.a_seed) || (kp->solver == 2 && kp->fp.criterion != 0))
+        return g4_set_err(ctx, G4_EINVAL, "per-particle seeds are not supported by the hierarchical step");
     return G4_OK;
 }
 
@@ -535,6 +538,9 @@ static int fmm_checks(g4_ctx *ctx, g4_tree *tree, const g4_fmm_params *fp, doubl
     if (!ax || !ay || !az) return g4_set_err(ctx, G4_EINVAL, "null output");
     if (tree->moments_order < 3) return g4_set_err(ctx, G4_ESTATE, "FMM needs moments to order 3");
     if (fp->kernel != 0 && fp->kernel != 1) return g4_set_err(ctx, G4_EINVAL, "kernel must be 0 or 1");
+    if (fp->criterion != 0 && fp->criterion != 1) return g4_set_err(ctx, G4_EINVAL, "criterion must be 0 or 1");
+    if (fp->criterion == 1 && (!fp->a_seed || !(fp->alpha > 0)))
+        return g4_set_err(ctx, G4_EINVAL, "the relative criterion needs a_seed and alpha > 0");
     if (fp->kernel == 1 && (!(fp->r_s > 0) || !(fp->r_cut > 0)))
         return g4_set_err(ctx, G4_EINVAL, "r_s and r_cut must be positive");
     if (fp->kernel == 1 && !tree->tp.periodic) return g4_set_err(ctx, G4_EINVAL, "short-range kernel needs a periodic box");

@@ -48,6 +48,10 @@ struct FmmArgs {
     float unit, box;
     float theta, h2, asplit, hinv, rcut2;
     int kernel;
+    int crit;            // 0 geometric, 1 relative node-node criterion
+    float alpha;
+    const float *pseed;  // |a| per particle (sorted order), criterion 1
+    const float *amin;   // smallest |a| of each node's particles, criterion 1
     // frontier and entry lists
     const uint2 *fin;
     uint2 *fout;
@@ -72,7 +76,36 @@ struct Ent {
     float mass;
     bool part, leaf;
     uint32_t next, num;      // node: children or particle range
+    float amin;              // smallest |a| of its particles (relative criterion)
 };
+
+// The node-node opening criterion (p = 3): geometric (l_a + l_b)/r < theta
+// (eq. eqnNodeDec), or relative (M_max / r^2)(l_max / r)^(p-1) < alpha |a|_min.
+__device__ __forceinline__ bool fmm_accept(int crit, float theta2, float alpha, float la, float lb, float ma,
+                                           float mb, float aa, float ab, float r2)
+{
+    if (crit == 0) {
+        const float ls = la + lb;
+        return ls * ls < theta2 * r2;
+    }
+    const float lm = fmaxf(la, lb);
+    return fmaxf(ma, mb) * lm * lm < alpha * fminf(aa, ab) * (r2 * r2);
+}
+
+// |a|_min of every node of one level: the smallest seed of a leaf's particles,
+// or of the children's minima (levels are processed from the deepest up)
+__global__ void k_fmm_amin(const DevCounters *__restrict__ C, const WNode *__restrict__ wn,
+                           const float *__restrict__ pseed, float *__restrict__ amin, int level)
+{
+    const uint32_t beg = C->lvl_start[level], end = beg + C->lvl_count[level];
+    for (uint32_t q = beg + blockIdx.x * blockDim.x + threadIdx.x; q < end; q += gridDim.x * blockDim.x) {
+        const WNode w = wn[q];
+        const float *src = (w.meta & WN_LEAF) ? pseed : amin;
+        float m = __builtin_huge_valf();
+        for (uint32_t k = 0; k < w.num; k++) m = fminf(m, src[w.next + k]);
+        amin[q] = m;
+    }
+}
 
 __device__ __forceinline__ Ent load_ent(const FmmArgs &A, uint32_t e)
 {
@@ -88,6 +121,7 @@ __device__ __forceinline__ Ent load_ent(const FmmArgs &A, uint32_t e)
         E.part = true;
         E.leaf = false;
         E.next = E.num = 0;
+        E.amin = A.crit ? A.pseed[e & ~PF] : 0.f;
     } else {
         const WNode w = A.wn[e];
         const int lev = (int)(w.meta & 0xffu);
@@ -100,6 +134,7 @@ __device__ __forceinline__ Ent load_ent(const FmmArgs &A, uint32_t e)
         E.leaf = (w.meta & WN_LEAF) != 0;
         E.next = w.next;
         E.num = w.num;
+        E.amin = A.crit ? A.amin[e] : 0.f;
     }
     return E;
 }
@@ -168,8 +203,8 @@ __device__ Act classify(const FmmArgs &A, uint32_t ea, uint32_t eb)
     const float rx = (float)(int32_t)(b.cx - a.cx) * A.unit, ry = (float)(int32_t)(b.cy - a.cy) * A.unit,
                 rz = (float)(int32_t)(b.cz - a.cz) * A.unit;
     const float r2 = rx * rx + ry * ry + rz * rz;
-    const float ls = a.l + b.l;
-    if (!touching && ls * ls < A.theta * A.theta * r2 && r2 >= A.h2) {
+    if (!touching && fmm_accept(A.crit, A.theta * A.theta, A.alpha, a.l, b.l, a.mass, b.mass, a.amin, b.amin, r2) &&
+        r2 >= A.h2) {
         if (!a.part && !b.part) {
             X.kind = ACT_NN;
             X.n_node = 2;
@@ -718,6 +753,10 @@ struct FastArgs {
     int S;
     float unit, box, theta2, h2, asplit, hinv, rcut2;
     int kernel;
+    int crit;            // 0 geometric, 1 relative node-node criterion
+    float alpha;
+    const float *pseed;  // |a| per particle (sorted order), criterion 1
+    const float *amin;   // smallest |a| of each node's particles, criterion 1
     const uint2 *fin;
     uint2 *fout;
     uint32_t *cnt;  // [0] frontier in, [1] frontier out, [2] leaf pairs, [3] leaf-node pairs, [4] overflow
@@ -747,7 +786,8 @@ __device__ __forceinline__ void fm_sync()
 
 // Two nodes: 0 dropped (beyond r_cut), 1 interact, 2 open.  Same arithmetic
 // as classify() above; r = s_b - s_a.
-__device__ __forceinline__ int fm_classify(const FastArgs &A, const WNode &a, const WNode &b, float r[3], float &r2)
+__device__ __forceinline__ int fm_classify(const FastArgs &A, const WNode &a, const WNode &b, uint32_t ia,
+                                           uint32_t ib, float r[3], float &r2)
 {
     const int la = (int)(a.meta & 0xffu), lb = (int)(b.meta & 0xffu);
     const int64_t dc[3] = {(int32_t)(b.gx - a.gx), (int32_t)(b.gy - a.gy), (int32_t)(b.gz - a.gz)};
@@ -770,8 +810,10 @@ __device__ __forceinline__ int fm_classify(const FastArgs &A, const WNode &a, co
     r[1] = (float)(int32_t)(b.cy - a.cy) * A.unit;
     r[2] = (float)(int32_t)(b.cz - a.cz) * A.unit;
     r2 = r[0] * r[0] + r[1] * r[1] + r[2] * r[2];
-    const float ls = ldexpf(A.box, -la) + ldexpf(A.box, -lb);
-    return (!touching && ls * ls < A.theta2 * r2 && r2 >= A.h2) ? 1 : 2;
+    const float aa = A.crit ? A.amin[ia] : 0.f, ab = A.crit ? A.amin[ib] : 0.f;
+    const bool acc = fmm_accept(A.crit, A.theta2, A.alpha, ldexpf(A.box, -la), ldexpf(A.box, -lb), a.mass, b.mass,
+                                aa, ab, r2);
+    return (!touching && acc && r2 >= A.h2) ? 1 : 2;
 }
 
 // the walk starts from the self pair of every internal root (a root leaf only
@@ -898,7 +940,7 @@ __global__ __launch_bounds__(256) void k_fast_open(FastArgs A)
         if (valid) {
             w1 = A.wn[ca + i];
             w2 = A.wn[cb + j];
-            act = (self && i == j) ? 3 : fm_classify(A, w1, w2, r, r2);
+            act = (self && i == j) ? 3 : fm_classify(A, w1, w2, ca + i, cb + j, r, r2);
         }
         const bool inter = act == 1;
         const uint64_t im = fm_ballot(inter);
@@ -1395,7 +1437,9 @@ __global__ __launch_bounds__(256) void k_fast_ln(FastArgs A, uint32_t npairs)
                             (float)(int32_t)(w.cz - me.z) * A.unit};
         const float r2 = r[0] * r[0] + r[1] * r[1] + r[2] * r[2];
         const float l = ldexpf(A.box, -lev);
-        const bool inter = mine && !drop && !touching && l * l < A.theta2 * r2 && r2 >= A.h2;
+        const float a_t = A.crit ? A.pseed[act ? t : ja] : 0.f, a_n = A.crit ? A.amin[live ? node : 0u] : 0.f;
+        const bool inter = mine && !drop && !touching &&
+                           fmm_accept(A.crit, A.theta2, A.alpha, 0.f, l, mt, w.mass, a_t, a_n, r2) && r2 >= A.h2;
         const bool open = mine && !drop && !inter;
         const uint64_t im = fm_ballot(inter);
         if (im) {
@@ -1585,7 +1629,7 @@ __global__ void k_fast_finish(const FastArgs A, const uint32_t *__restrict__ lea
 // ------------------------------------------------------------------ host side
 struct FmmLayout {
     size_t cnt, f0, f1, nkey, nkey2, nval, nval2, pkey, pkey2, pval, pval2, nstart, nend, pstart, pend, F, leafid,
-        sort_tmp, sort_bytes, total;
+        amin, sort_tmp, sort_bytes, total;
     uint32_t cap_pairs, cap_node, cap_part;
 };
 
@@ -1618,6 +1662,7 @@ static int fmm_layout(int64_t n, int64_t cap_nodes, double factor, FmmLayout *L)
     L->pend = take((size_t)n * 4);
     L->F = take((size_t)cap_nodes * 20 * 4);
     L->leafid = take((size_t)n * 4);
+    L->amin = take((size_t)cap_nodes * 4);
     L->sort_bytes = g4_radix_sort_temp_bytes((int64_t)std::max(L->cap_node, L->cap_part));
     L->sort_tmp = take(L->sort_bytes);
     L->total = off;
@@ -1625,7 +1670,7 @@ static int fmm_layout(int64_t n, int64_t cap_nodes, double factor, FmmLayout *L)
 }
 
 struct FastLayout {
-    size_t cnt, f0, f1, ll, ln, pstart, cursor, bsum, plist, F, acc, leafid, total;
+    size_t cnt, f0, f1, ll, ln, pstart, cursor, bsum, plist, F, acc, leafid, amin, total;
     uint32_t cap_pairs, cap_ll, cap_ln;
 };
 
@@ -1653,6 +1698,7 @@ static void fast_layout(int64_t n, int64_t cap_nodes, double factor, FastLayout 
     L->F = take((size_t)cap_nodes * 20 * 4);
     L->acc = take((size_t)n * 4 * 8);
     L->leafid = take((size_t)n * 4);
+    L->amin = take((size_t)cap_nodes * 4);
     L->total = off;
 }
 
@@ -1668,6 +1714,18 @@ int g4_fmm_layout_bytes(const g4_tree *t, const g4_fmm_params *fp, double factor
     int st = fmm_layout(t->n, t->cap, factor, &L);
     if (st) return st;
     *bytes = L.total;
+    return G4_OK;
+}
+
+// Relative criterion: the caller's |a| in sorted order (the tree's seed
+// buffer) and each node's minimum, levels from the deepest up.
+static int fmm_seed_minima(g4_ctx *ctx, g4_tree *t, const g4_fmm_params *fp, float *amin)
+{
+    if (int st = g4_launch_gather_seed(ctx, t, fp->a_seed)) return st;
+    t->seed_valid = 0;
+    const int maxd = t->tp.max_depth;
+    for (int l = maxd; l >= 0; l--) k_fmm_amin<<<256, 256, 0, ctx->stream>>>(t->ctr, t->wn, t->aseed, amin, l);
+    G4_HIP(ctx, hipGetLastError());
     return G4_OK;
 }
 
@@ -1701,6 +1759,12 @@ static int fmm_fast(g4_ctx *ctx, g4_tree *t, const g4_fmm_params *fp, double fac
     A.asplit = fp->kernel == 1 ? (float)(0.5 / fp->r_s) : 0.f;
     A.rcut2 = (float)(fp->r_cut * fp->r_cut);
     A.kernel = fp->kernel;
+    A.crit = fp->criterion;
+    A.alpha = (float)fp->alpha;
+    A.pseed = t->aseed;
+    A.amin = (float *)(b + L.amin);
+    if (A.crit)
+        if (int st = fmm_seed_minima(ctx, t, fp, (float *)(b + L.amin))) return st;
     A.cnt = (uint32_t *)(b + L.cnt);
     A.cap_pairs = L.cap_pairs;
     A.ll = (uint2 *)(b + L.ll);
@@ -1827,6 +1891,12 @@ int g4_launch_fmm(g4_ctx *ctx, g4_tree *t, const g4_fmm_params *fp, double facto
     A.asplit = fp->kernel == 1 ? (float)(0.5 / fp->r_s) : 0.f;
     A.rcut2 = (float)(fp->r_cut * fp->r_cut);
     A.kernel = fp->kernel;
+    A.crit = fp->criterion;
+    A.alpha = (float)fp->alpha;
+    A.pseed = t->aseed;
+    A.amin = (float *)(b + L.amin);
+    if (A.crit)
+        if (int st2 = fmm_seed_minima(ctx, t, fp, (float *)(b + L.amin))) return st2;
     A.cnt = (uint32_t *)(b + L.cnt);
     A.cap_pairs = L.cap_pairs;
     A.nkey = (uint64_t *)(b + L.nkey);

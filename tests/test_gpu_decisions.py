@@ -13,7 +13,7 @@ import numpy as np
 import pytest
 import torch
 
-from test_oracle_decisions import ACCEPTED, DROPPED, OPENED, fmm_positions, walk_positions
+from test_oracle_decisions import ACCEPTED, DROPPED, OPENED, _fmm_relative_thresholds, fmm_positions, walk_positions
 
 pytestmark = pytest.mark.gpu
 MARGIN = 1e-4
@@ -125,6 +125,25 @@ def test_gpu_fmm_touching_cells_never_interact(g, ctx, cells, expect, det):
     out = g.g4_fmm_force(ctx, tree, fp, want_stats=True)
     s = out["stats"]
     assert (s["n_pp"], s["n_pn"], s["n_nn"]) == expect
+
+
+@pytest.mark.parametrize("det", [0, 1])
+def test_gpu_fmm_relative_criterion_threshold(g, ctx, det):
+    """The oracle's four-leaf line with unequal masses and seeds: each
+    non-touching pair switches to a node-node interaction as alpha passes its
+    threshold M_max l_max^2 / (|a|_min r^4), probed at 1 +- 1e-4."""
+    import oracle
+    X, Y, Z, _ = fmm_positions([(0, 0, 0), (1, 0, 0), (2, 0, 0), (3, 0, 0)])
+    m = np.array([1.0, 2.0, 3.0, 0.5])
+    aseed = np.array([5.0, 0.7, 3.0, 2.0], np.float32)
+    tree = _tree(g, ctx, X, Y, Z, m, 1)
+    thr = sorted(_fmm_relative_thresholds(oracle.Tree(X, Y, Z, m, True, 1.0, 1), m, aseed.astype(np.float64)).values())
+    sd = torch.from_numpy(aseed).cuda()
+    for k, a in enumerate(thr):
+        for f, want in ((1 + MARGIN, k + 1), (1 - MARGIN, k)):
+            fp = g.fmm_params(kernel=0, eps0=0.0, deterministic=det, criterion=1, alpha=a * f, a_seed=sd)
+            s = g.g4_fmm_force(ctx, tree, fp, want_stats=True)["stats"]
+            assert s["n_nn"] == want, (k, f, s["n_nn"])
 
 
 def test_gpu_stats_phase_times(g, ctx):

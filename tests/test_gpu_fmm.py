@@ -174,3 +174,42 @@ def test_fmm_full_size(g, ctx, B):
     e = workloads.relative_errors(a[tg], ref)
     print("fmm 128^3 vs direct:", workloads.percentiles(e), out["stats"])
     assert np.median(e) < 2e-3 and np.percentile(e, 90) < 2e-2
+
+
+@pytest.mark.parametrize("det", [0, 1])
+@pytest.mark.parametrize("kind,n", [("plummer", 3000), ("box", 30001)])
+def test_fmm_relative_criterion_parity(g, ctx, kind, n, det):
+    """The relative node-node criterion (M_max / r^2)(l_max / r)^2 < alpha
+    |a|_min, both summation modes, against the oracle given the same seeds
+    (|a| of the direct sum, rounded to FP32): the same interactions up to
+    FP32-vs-FP64 threshold flips, forces at FP32 round-off, momentum kept."""
+    if kind == "plummer":
+        ps = workloads.plummer(n, seed=53)
+        kw = dict(kernel=0, eps0=0.01)
+    else:
+        ps = workloads.clustered_box(n, seed=54, nhalo=max(10, n // 500))
+        kw = dict(kernel=1, **sr(n))
+    tree, ot, p, tp, m32 = build(g, ctx, ps, kind == "box", 16)
+    ref = g.g4_direct_force(ctx, p, tp, g.walk_params(**kw))
+    seed = np.linalg.norm(st3(ref), axis=1).astype(np.float32)
+    fp = g.fmm_params(theta=0.5, deterministic=det, criterion=1, alpha=0.002, a_seed=torch.from_numpy(seed).cuda(),
+                      **kw)
+    out = g.g4_fmm_force(ctx, tree, fp, want_pot=True, want_stats=True)
+    acc, pot, stt = ot.fmm(criterion=1, alpha=0.002, aseed=seed.astype(np.float64), **kw)
+    check(st3(out), acc, f"fmm relative {kind} {n} det={det}")
+    s = out["stats"]
+    for k, v in zip(("n_pp", "n_pn", "n_nn"), stt):
+        assert abs(s[k] - int(v)) <= 1e-3 * max(1, int(v)), (k, s[k], int(v))
+    a = st3(out)
+    net = np.abs((m32[:, None].astype(np.float64) * a).sum(0)).max()
+    assert net <= 1e-6 * (m32[:, None] * np.abs(a)).sum()
+    err = workloads.relative_errors(a, st3(ref))
+    print(f"relative FMM vs direct: p50 {np.median(err):.2e} p90 {np.percentile(err, 90):.2e}")
+    assert np.percentile(err, 90) < 0.02
+
+
+def test_fmm_relative_criterion_needs_seeds(g, ctx):
+    ps = workloads.plummer(500, seed=55)
+    tree, ot, p, tp, m32 = build(g, ctx, ps, False, 16)
+    with pytest.raises(g.G4Error):
+        g.g4_fmm_force(ctx, tree, g.fmm_params(theta=0.5, criterion=1, alpha=0.002, eps0=0.01))
