@@ -129,7 +129,12 @@ typedef struct {
  * reproducible, slower: per-interaction lists are sorted); 0 gives the same
  * interactions with sums accumulated by atomics (round-off may differ from
  * run to run; the section on deterministic outcomes allows giving up binary
- * invariance for speed). */
+ * invariance for speed).
+ * kernel 2 (periodic trees): Newtonian between the nearest images of the two
+ * sides plus the correction potential psi of the other images in every
+ * interaction's expansion (Sec. "Fast multipole method", periodic case), its
+ * derivatives from ewald_table (built by g4_ewald_table for the tree's box
+ * side with ewald_n intervals); no r_cut. */
 typedef struct {
     int kernel;
     double G, eps0, r_s, r_cut, theta;
@@ -137,6 +142,8 @@ typedef struct {
     int criterion;
     double alpha;
     const float *a_seed;
+    const void *ewald_table;
+    int ewald_n;
 } g4_fmm_params;
 
 /* Long-range (particle-mesh) part of the TreePM split (Sec. "TreePM

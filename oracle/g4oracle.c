@@ -1089,9 +1089,14 @@ static void fmm_interact(fmm_ctx *C, int64_t A, int64_t B)
     int touching = 1;
     for (int k = 0; k < 3; k++)
         if ((uint64_t)llabs(dc[k]) > hsum) touching = 0;
+    /* the offset of the two centres of mass, at its nearest periodic image */
     double rv[3], r2 = 0.0;
     for (int k = 0; k < 3; k++) {
         rv[k] = (double)dc[k] * t->unit + EB.dcom[k] - EA.dcom[k];
+        if (t->periodic) {
+            if (rv[k] >= 0.5 * t->box) rv[k] -= t->box;
+            else if (rv[k] < -0.5 * t->box) rv[k] += t->box;
+        }
         r2 += rv[k] * rv[k];
     }
     double r = sqrt(r2);
@@ -1107,7 +1112,16 @@ static void fmm_interact(fmm_ctx *C, int64_t A, int64_t B)
     }
     if (!touching && accept && r >= h) {
         double D0, D1[3], D2[9], D3[27], D[4][27];
-        orc_Dn(P->kernel, rv, P->kernel ? 0.5 / P->r_s : 0.0, &D0, D1, D2, D3);
+        orc_Dn(P->kernel == 1, rv, P->kernel == 1 ? 0.5 / P->r_s : 0.0, &D0, D1, D2, D3);
+        if (P->kernel == 2) {
+            /* periodic: the Green's function 1/r - psi (eqs. eqnpo1, eqnpo2) */
+            double E0, E1[3], E2[9], E3[27];
+            orc_ewald_psi(rv, t->box, 0.0, &E0, E1, E2, E3);
+            D0 -= E0;
+            for (int i = 0; i < 3; i++) D1[i] -= E1[i];
+            for (int i = 0; i < 9; i++) D2[i] -= E2[i];
+            for (int i = 0; i < 27; i++) D3[i] -= E3[i];
+        }
         memset(D, 0, sizeof(D));
         D[0][0] = D0;
         memcpy(D[1], D1, sizeof(D1));

@@ -24,7 +24,8 @@ typedef struct {
 } orc_walk_params;
 
 typedef struct {
-    int kernel;      /* 0 Newtonian (isolated), 1 short-range (FMM-PM short-range pass) */
+    int kernel;      /* 0 Newtonian (isolated), 1 short-range (FMM-PM short-range pass),
+                        2 periodic Newtonian + Ewald correction */
     double G, eps0, r_s, r_cut, theta;
     int criterion;   /* 0 geometric (l_A + l_B)/r < theta, 1 relative (M_max/r^2)(l_max/r)^2 < alpha |a|_min */
     double alpha;

@@ -482,8 +482,7 @@ static int check_kdk(g4_ctx *ctx, const g4_kdk_params *kp)
     if (kp->max_level < 0 || kp->max_level > G4_KDK_MAX_LEVEL) return g4_set_err(ctx, G4_EINVAL, "max_level out of range");
     if (!(kp->eta > 0) || !(kp->eps > 0)) return g4_set_err(ctx, G4_EINVAL, "eta and eps must be positive");
     const int kernel = kp->solver == 2 ? kp->fp.kernel : kp->wp.kernel;
-    if ((kernel == 1 || (kp->solver != 2 && kernel == 2)) && !kp->tp.periodic)
-        return g4_set_err(ctx, G4_EINVAL, "this kernel needs a periodic box");
+    if (kernel >= 1 && !kp->tp.periodic) return g4_set_err(ctx, G4_EINVAL, "this kernel needs a periodic box");
     // every force call acts on a subset: seeds given per particle of the whole set cannot be used
     if ((kp->solver == 1 && kp->wp.a_seed) || (kp->solver == 2 && kp->fp.criterion != 0))
         return g4_set_err(ctx, G4_EINVAL, "per-particle seeds are not supported by the hierarchical step");
@@ -537,7 +536,12 @@ static int fmm_checks(g4_ctx *ctx, g4_tree *tree, const g4_fmm_params *fp, doubl
 {
     if (!ax || !ay || !az) return g4_set_err(ctx, G4_EINVAL, "null output");
     if (tree->moments_order < 3) return g4_set_err(ctx, G4_ESTATE, "FMM needs moments to order 3");
-    if (fp->kernel != 0 && fp->kernel != 1) return g4_set_err(ctx, G4_EINVAL, "kernel must be 0 or 1");
+    if (fp->kernel < 0 || fp->kernel > 2) return g4_set_err(ctx, G4_EINVAL, "kernel must be 0, 1 or 2");
+    if (fp->kernel == 2) {
+        if (!tree->tp.periodic) return g4_set_err(ctx, G4_EINVAL, "the Ewald-corrected kernel needs a periodic box");
+        if (!fp->ewald_table || fp->ewald_n < G4_EWALD_NE_MIN || fp->ewald_n > G4_EWALD_NE_MAX)
+            return g4_set_err(ctx, G4_EINVAL, "kernel 2 needs ewald_table and ewald_n in 4..128");
+    }
     if (fp->criterion != 0 && fp->criterion != 1) return g4_set_err(ctx, G4_EINVAL, "criterion must be 0 or 1");
     if (fp->criterion == 1 && (!fp->a_seed || !(fp->alpha > 0)))
         return g4_set_err(ctx, G4_EINVAL, "the relative criterion needs a_seed and alpha > 0");

@@ -151,3 +151,33 @@ __device__ __forceinline__ void ew_node(const float *__restrict__ tab, int ne, f
         fp = M * ew_taylor<0, 0, 0>(p) + d2 + (ORD3 ? d3 * (1.f / 6.f) : 0.f);
     }
 }
+
+// D0..D3 of psi at offset d, packed as 1 + 3 + 6 + 10 values in the order of
+// the components above (D2: xx xy xz yy yz zz; D3: xxx xxy xxz xyy xyz xzz
+// yyy yyz yzz zzz), for the field expansions of the periodic FMM.
+__device__ __forceinline__ void ew_d20(const float *__restrict__ tab, int ne, float h, float hinv, float dx, float dy,
+                                       float dz, float D[20])
+{
+    const EwPoint p = ew_locate(tab, ne, h, hinv, dx, dy, dz);
+    const float sx = p.sx, sy = p.sy, sz = p.sz;
+    D[0] = ew_taylor<0, 0, 0>(p);
+    D[1] = sx * ew_taylor<1, 0, 0>(p);
+    D[2] = sy * ew_taylor<0, 1, 0>(p);
+    D[3] = sz * ew_taylor<0, 0, 1>(p);
+    D[4] = ew_taylor<2, 0, 0>(p);
+    D[5] = sx * sy * ew_taylor<1, 1, 0>(p);
+    D[6] = sx * sz * ew_taylor<1, 0, 1>(p);
+    D[7] = ew_taylor<0, 2, 0>(p);
+    D[8] = sy * sz * ew_taylor<0, 1, 1>(p);
+    D[9] = ew_taylor<0, 0, 2>(p);
+    D[10] = sx * ew_taylor<3, 0, 0>(p);
+    D[11] = sy * ew_taylor<2, 1, 0>(p);
+    D[12] = sz * ew_taylor<2, 0, 1>(p);
+    D[13] = sx * ew_taylor<1, 2, 0>(p);
+    D[14] = sx * sy * sz * ew_taylor<1, 1, 1>(p);
+    D[15] = sx * ew_taylor<1, 0, 2>(p);
+    D[16] = sy * ew_taylor<0, 3, 0>(p);
+    D[17] = sz * ew_taylor<0, 2, 1>(p);
+    D[18] = sy * ew_taylor<0, 1, 2>(p);
+    D[19] = sz * ew_taylor<0, 0, 3>(p);
+}

@@ -27,6 +27,7 @@
 #include <cstring>
 
 
+#include "ewald.h"
 #include "g4_device.h"
 #include "g4_internal.h"
 
@@ -52,6 +53,9 @@ struct FmmArgs {
     float alpha;
     const float *pseed;  // |a| per particle (sorted order), criterion 1
     const float *amin;   // smallest |a| of each node's particles, criterion 1
+    const float *ew;     // periodic correction table (kernel 2)
+    int ew_n;
+    float ew_h, ew_hinv;
     // frontier and entry lists
     const uint2 *fin;
     uint2 *fout;
@@ -429,11 +433,12 @@ __device__ __forceinline__ int i3(int i, int j, int k)
     return 9;
 }
 
-// g0..g3 of the interaction kernel (Newtonian or short-range) at r
+// g0..g3 of the interaction kernel at r: short-range for kernel 1, Newtonian
+// otherwise (kernel 2 adds the periodic correction psi separately)
 __device__ __forceinline__ void gfun_f(int kernel, float r2, float asplit, float &g0, float &g1, float &g2, float &g3)
 {
     const float rinv = rsq(r2), ri2 = rinv * rinv;
-    if (kernel == 0) {
+    if (kernel != 1) {
         g0 = rinv;
         g1 = -rinv * ri2;
         g2 = -3.0f * g1 * ri2;
@@ -506,7 +511,61 @@ __device__ __forceinline__ void add_field_f(float F[20], const float r[3], float
     for (int a = 0; a < 10; a++) F[10 + a] += M * D3[a];
 }
 
+// Periodic FMM (kernel 2): the Green's function is 1/r - psi, so the field of
+// a source gets the same expansion with psi's derivatives D (packed D0..D3 at
+// r = s_source - s_sink) subtracted: F0 -= M D0 + Q2:D2/2 + Q3.D3/6,
+// F1 -= M D1 + Q2:D3/2, F2 -= M D2, F3 -= M D3.
+__device__ __forceinline__ void sub_field_psi(float F[20], const float D[20], float M, const float *Q2,
+                                              const float *Q3)
+{
+    const float *D1 = D + 1, *D2 = D + 4, *D3 = D + 10;
+    float f0 = M * D[0];
+    float f1[3] = {M * D1[0], M * D1[1], M * D1[2]};
+    if (Q2) {
+        // symmetric contractions in packed storage (off-diagonal terms twice)
+        f0 += 0.5f * (Q2[0] * D2[0] + Q2[3] * D2[3] + Q2[5] * D2[5]) + Q2[1] * D2[1] + Q2[2] * D2[2] +
+              Q2[4] * D2[4];
+#pragma unroll
+        for (int i = 0; i < 3; i++) {
+            float c = 0.f;
+#pragma unroll
+            for (int j = 0; j < 3; j++)
+#pragma unroll
+                for (int k = 0; k < 3; k++) c += Q2[i2(j, k)] * D3[i3(i, j, k)];
+            f1[i] += 0.5f * c;
+        }
+        if (Q3) {
+            float c3 = 0.f;
+#pragma unroll
+            for (int i = 0; i < 3; i++)
+#pragma unroll
+                for (int j = 0; j < 3; j++)
+#pragma unroll
+                    for (int k = 0; k < 3; k++) c3 += Q3[i3(i, j, k)] * D3[i3(i, j, k)];
+            f0 += c3 * (1.0f / 6.0f);
+        }
+    }
+    F[0] -= f0;
+    F[1] -= f1[0];
+    F[2] -= f1[1];
+    F[3] -= f1[2];
+#pragma unroll
+    for (int a = 0; a < 6; a++) F[4 + a] -= M * D2[a];
+#pragma unroll
+    for (int a = 0; a < 10; a++) F[10 + a] -= M * D3[a];
+}
+
+// psi's packed D0..D3 at -r from those at r (psi is even: odd orders change sign)
+__device__ __forceinline__ void psi_mirror(float D[20])
+{
+#pragma unroll
+    for (int a = 1; a < 4; a++) D[a] = -D[a];
+#pragma unroll
+    for (int a = 10; a < 20; a++) D[a] = -D[a];
+}
+
 // M2L / P2L: each node sums the fields of its sources
+template <bool EW>
 __global__ __launch_bounds__(256) void k_fmm_m2l(FmmArgs A, const uint32_t *__restrict__ start,
                                                  const uint32_t *__restrict__ end, float *__restrict__ F)
 {
@@ -544,6 +603,11 @@ __global__ __launch_bounds__(256) void k_fmm_m2l(FmmArgs A, const uint32_t *__re
             float g0, g1, g2, g3;
             gfun_f(A.kernel, r[0] * r[0] + r[1] * r[1] + r[2] * r[2], A.asplit, g0, g1, g2, g3);
             add_field_f(f, r, g0, g1, g2, g3, M, Q2, Q3);
+            if constexpr (EW) {
+                float D[20];
+                ew_d20(A.ew, A.ew_n, A.ew_h, A.ew_hinv, r[0], r[1], r[2], D);
+                sub_field_psi(f, D, M, Q2, Q3);
+            }
         }
 #pragma unroll
         for (int a = 0; a < 20; a++) F[(size_t)q * 20 + a] = f[a];
@@ -652,6 +716,11 @@ __global__ __launch_bounds__(256) void k_fmm_particles(FmmArgs A, const uint32_t
                 for (int a = 0; a < 10; a++) q3[a] = A.q3[(size_t)id * 10 + a];
             }
             add_field_f(f, r, g0, g1, g2, g3, s.mass, q2, POT ? q3 : nullptr);
+            if constexpr (KER == 2) {
+                float D[20];
+                ew_d20(A.ew, A.ew_n, A.ew_h, A.ew_hinv, r[0], r[1], r[2], D);
+                sub_field_psi(f, D, s.mass, q2, POT ? q3 : nullptr);
+            }
             fx = -f[1];
             fy = -f[2];
             fz = -f[3];
@@ -665,12 +734,20 @@ __global__ __launch_bounds__(256) void k_fmm_particles(FmmArgs A, const uint32_t
                 const float sx = (float)(int32_t)(p.x - me.x) * A.unit, sy = (float)(int32_t)(p.y - me.y) * A.unit,
                             sz = (float)(int32_t)(p.z - me.z) * A.unit;
                 float K, W;
-                pair_kernel<KER, POT>(sx * sx + sy * sy + sz * sz, A.asplit, A.h2, A.hinv, K, W);
-                const float mk = __uint_as_float(p.w) * K;
+                pair_kernel<KER == 2 ? 0 : KER, POT>(sx * sx + sy * sy + sz * sz, A.asplit, A.h2, A.hinv, K, W);
+                const float mj = __uint_as_float(p.w), mk = mj * K;
                 fx += mk * sx;
                 fy += mk * sy;
                 fz += mk * sz;
-                if (POT) fp -= __uint_as_float(p.w) * W;
+                if (POT) fp -= mj * W;
+                if constexpr (KER == 2) {
+                    float ex, ey, ez, ep = 0.f;
+                    ew_grad<POT>(A.ew, A.ew_n, A.ew_h, A.ew_hinv, sx, sy, sz, ex, ey, ez, ep);
+                    fx += mj * ex;
+                    fy += mj * ey;
+                    fz += mj * ez;
+                    if (POT) fp += mj * ep;
+                }
             }
         }
         dx_ += fx;
@@ -757,6 +834,9 @@ struct FastArgs {
     float alpha;
     const float *pseed;  // |a| per particle (sorted order), criterion 1
     const float *amin;   // smallest |a| of each node's particles, criterion 1
+    const float *ew;     // periodic correction table (kernel 2)
+    int ew_n;
+    float ew_h, ew_hinv;
     const uint2 *fin;
     uint2 *fout;
     uint32_t *cnt;  // [0] frontier in, [1] frontier out, [2] leaf pairs, [3] leaf-node pairs, [4] overflow
@@ -893,7 +973,7 @@ __device__ __forceinline__ void fm_combine(float f[20], uint32_t take)
     }
 }
 
-template <bool POT>
+template <bool POT, bool EW>
 __global__ __launch_bounds__(256) void k_fast_open(FastArgs A)
 {
     // field sums of the daughters, FT_NC copies: the lanes of one daughter spread over the
@@ -986,6 +1066,10 @@ __global__ __launch_bounds__(256) void k_fast_open(FastArgs A)
             if (inter) gfun_f(A.kernel, r2, A.asplit, g0, g1, g2, g3);
             float f[20], q2[6], q3[10];
             const float mr[3] = {-r[0], -r[1], -r[2]};
+            float Dp[20];  // psi's D0..D3 at +r (kernel 2)
+            if constexpr (EW) {
+                if (inter) ew_d20(A.ew, A.ew_n, A.ew_h, A.ew_hinv, r[0], r[1], r[2], Dp);
+            }
             // daughter i sees daughter j at +r ...
 #pragma unroll
             for (int k = 0; k < 20; k++) f[k] = 0.f;
@@ -997,6 +1081,7 @@ __global__ __launch_bounds__(256) void k_fast_open(FastArgs A)
                     for (int k = 0; k < 10; k++) q3[k] = A.q3[(size_t)(cb + j) * 10 + k];
                 }
                 add_field_f(f, r, g0, g1, g2, g3, w2.mass, q2, POT ? q3 : nullptr);
+                if constexpr (EW) sub_field_psi(f, Dp, w2.mass, q2, POT ? q3 : nullptr);
             }
             if (!self) {
                 fm_combine<1, 0>(f, lvl_take);
@@ -1030,6 +1115,10 @@ __global__ __launch_bounds__(256) void k_fast_open(FastArgs A)
                     for (int k = 0; k < 10; k++) q3[k] = A.q3[(size_t)(ca + i) * 10 + k];
                 }
                 add_field_f(f, mr, g0, g1, g2, g3, w1.mass, q2, POT ? q3 : nullptr);
+                if constexpr (EW) {
+                    psi_mirror(Dp);
+                    sub_field_psi(f, Dp, w1.mass, q2, POT ? q3 : nullptr);
+                }
             }
             if (self) {
                 fm_combine<1, 0>(f, lvl_take);
@@ -1203,12 +1292,20 @@ __device__ __forceinline__ void fm_pair(const FastArgs &A, const uint4 &t, const
     const float sy = (float)(int32_t)(s.y - t.y) * A.unit;
     const float sz = (float)(int32_t)(s.z - t.z) * A.unit;
     float K, W;
-    pair_kernel<KER, POT>(sx * sx + sy * sy + sz * sz, A.asplit, A.h2, A.hinv, K, W);
+    pair_kernel<KER == 2 ? 0 : KER, POT>(sx * sx + sy * sy + sz * sz, A.asplit, A.h2, A.hinv, K, W);
     const float mk = m * K;
     fx += mk * sx;
     fy += mk * sy;
     fz += mk * sz;
     if (POT) fp -= m * W;
+    if constexpr (KER == 2) {
+        float ex, ey, ez, ep = 0.f;
+        ew_grad<POT>(A.ew, A.ew_n, A.ew_h, A.ew_hinv, sx, sy, sz, ex, ey, ez, ep);
+        fx += m * ex;
+        fy += m * ey;
+        fz += m * ez;
+        if (POT) fp += m * ep;
+    }
 }
 
 // Phase 2: all particle pairs of one leaf per wavefront.  Lane = (particle a,
@@ -1460,6 +1557,11 @@ __global__ __launch_bounds__(256) void k_fast_ln(FastArgs A, uint32_t npairs)
                     for (int q = 0; q < 10; q++) q3[q] = A.q3[(size_t)node * 10 + q];
                 }
                 add_field_f(f, r, g0, g1, g2, g3, w.mass, q2, POT ? q3 : nullptr);
+                float Dp[20];
+                if constexpr (KER == 2) {
+                    ew_d20(A.ew, A.ew_n, A.ew_h, A.ew_hinv, r[0], r[1], r[2], Dp);
+                    sub_field_psi(f, Dp, w.mass, q2, POT ? q3 : nullptr);
+                }
                 fx -= f[1];
                 fy -= f[2];
                 fz -= f[3];
@@ -1467,6 +1569,10 @@ __global__ __launch_bounds__(256) void k_fast_ln(FastArgs A, uint32_t npairs)
                 // the particle's field at the node (source at -r)
                 const float mr[3] = {-r[0], -r[1], -r[2]};
                 add_field_f(pf, mr, g0, g1, g2, g3, mt, nullptr, nullptr);
+                if constexpr (KER == 2) {
+                    psi_mirror(Dp);
+                    sub_field_psi(pf, Dp, mt, nullptr, nullptr);
+                }
                 n_pn++;
             }
 #pragma unroll
@@ -1533,15 +1639,26 @@ __global__ __launch_bounds__(256) void k_fast_ln(FastArgs A, uint32_t npairs)
                             const float sy = (float)(int32_t)(src.y - T.y) * A.unit;
                             const float sz = (float)(int32_t)(src.z - T.z) * A.unit;
                             float K, W;
-                            pair_kernel<KER, POT>(sx * sx + sy * sy + sz * sz, A.asplit, A.h2, A.hinv, K, W);
+                            pair_kernel<KER == 2 ? 0 : KER, POT>(sx * sx + sy * sy + sz * sz, A.asplit, A.h2,
+                                                                 A.hinv, K, W);
+                            // force per unit source mass on the target (the source gets minus it)
+                            float vx = K * sx, vy = K * sy, vz = K * sz;
+                            if constexpr (KER == 2) {
+                                float ex, ey, ez, ep = 0.f;
+                                ew_grad<POT>(A.ew, A.ew_n, A.ew_h, A.ew_hinv, sx, sy, sz, ex, ey, ez, ep);
+                                vx += ex;
+                                vy += ey;
+                                vz += ez;
+                                if (POT) W -= ep;
+                            }
                             const float ms = __uint_as_float(src.w), mo = __uint_as_float(T.w);
-                            atomicAdd(&tacc[wv][tl][0], ms * K * sx);
-                            atomicAdd(&tacc[wv][tl][1], ms * K * sy);
-                            atomicAdd(&tacc[wv][tl][2], ms * K * sz);
+                            atomicAdd(&tacc[wv][tl][0], ms * vx);
+                            atomicAdd(&tacc[wv][tl][1], ms * vy);
+                            atomicAdd(&tacc[wv][tl][2], ms * vz);
                             if (POT) atomicAdd(&tacc[wv][tl][3], -ms * W);
-                            atomicAdd(&sacc[wv][gg][ks][0], -mo * K * sx);
-                            atomicAdd(&sacc[wv][gg][ks][1], -mo * K * sy);
-                            atomicAdd(&sacc[wv][gg][ks][2], -mo * K * sz);
+                            atomicAdd(&sacc[wv][gg][ks][0], -mo * vx);
+                            atomicAdd(&sacc[wv][gg][ks][1], -mo * vy);
+                            atomicAdd(&sacc[wv][gg][ks][2], -mo * vz);
                             if (POT) atomicAdd(&sacc[wv][gg][ks][3], -mo * W);
                         }
                     }
@@ -1759,6 +1876,10 @@ static int fmm_fast(g4_ctx *ctx, g4_tree *t, const g4_fmm_params *fp, double fac
     A.asplit = fp->kernel == 1 ? (float)(0.5 / fp->r_s) : 0.f;
     A.rcut2 = (float)(fp->r_cut * fp->r_cut);
     A.kernel = fp->kernel;
+    A.ew = static_cast<const float *>(fp->ewald_table);
+    A.ew_n = fp->ewald_n;
+    A.ew_h = fp->kernel == 2 ? (float)(0.5 * t->tp.box / fp->ewald_n) : 0.f;
+    A.ew_hinv = fp->kernel == 2 ? (float)(2.0 * fp->ewald_n / t->tp.box) : 0.f;
     A.crit = fp->criterion;
     A.alpha = (float)fp->alpha;
     A.pseed = t->aseed;
@@ -1793,8 +1914,13 @@ static int fmm_fast(g4_ctx *ctx, g4_tree *t, const g4_fmm_params *fp, double fac
     for (int pass = 0; pass < 64; pass++) {
         A.fin = fr[cur];
         A.fout = fr[cur ^ 1];
-        if (P) k_fast_open<true><<<2048, 256, 0, s>>>(A);
-        else k_fast_open<false><<<2048, 256, 0, s>>>(A);
+        if (fp->kernel == 2) {
+            if (P) k_fast_open<true, true><<<2048, 256, 0, s>>>(A);
+            else k_fast_open<false, true><<<2048, 256, 0, s>>>(A);
+        } else {
+            if (P) k_fast_open<true, false><<<2048, 256, 0, s>>>(A);
+            else k_fast_open<false, false><<<2048, 256, 0, s>>>(A);
+        }
         k_fmm_rotate<<<1, 64, 0, s>>>(A.cnt);
         cur ^= 1;
         if ((pass & 3) == 3) {
@@ -1826,6 +1952,9 @@ static int fmm_fast(g4_ctx *ctx, g4_tree *t, const g4_fmm_params *fp, double fac
     if (fp->kernel == 1) {
         if (P) launch_fast_particles<1, true>(A, nnodes, nln, s);
         else launch_fast_particles<1, false>(A, nnodes, nln, s);
+    } else if (fp->kernel == 2) {
+        if (P) launch_fast_particles<2, true>(A, nnodes, nln, s);
+        else launch_fast_particles<2, false>(A, nnodes, nln, s);
     } else {
         if (P) launch_fast_particles<0, true>(A, nnodes, nln, s);
         else launch_fast_particles<0, false>(A, nnodes, nln, s);
@@ -1891,6 +2020,10 @@ int g4_launch_fmm(g4_ctx *ctx, g4_tree *t, const g4_fmm_params *fp, double facto
     A.asplit = fp->kernel == 1 ? (float)(0.5 / fp->r_s) : 0.f;
     A.rcut2 = (float)(fp->r_cut * fp->r_cut);
     A.kernel = fp->kernel;
+    A.ew = static_cast<const float *>(fp->ewald_table);
+    A.ew_n = fp->ewald_n;
+    A.ew_h = fp->kernel == 2 ? (float)(0.5 * t->tp.box / fp->ewald_n) : 0.f;
+    A.ew_hinv = fp->kernel == 2 ? (float)(2.0 * fp->ewald_n / t->tp.box) : 0.f;
     A.crit = fp->criterion;
     A.alpha = (float)fp->alpha;
     A.pseed = t->aseed;
@@ -1976,13 +2109,17 @@ int g4_launch_fmm(g4_ctx *ctx, g4_tree *t, const g4_fmm_params *fp, double facto
     A.nval = nv2;
     A.pval = pv2;
     float *F = (float *)(b + L.F);
-    k_fmm_m2l<<<(unsigned)((nn_host + 255) / 256), 256, 0, s>>>(A, nstart, nend, F);
+    if (fp->kernel == 2) k_fmm_m2l<true><<<(unsigned)((nn_host + 255) / 256), 256, 0, s>>>(A, nstart, nend, F);
+    else k_fmm_m2l<false><<<(unsigned)((nn_host + 255) / 256), 256, 0, s>>>(A, nstart, nend, F);
     const int maxd = t->tp.max_depth;
     for (int l = 1; l <= maxd; l++) k_fmm_l2l<<<1024, 256, 0, s>>>(A, l, F);
     uint32_t *leafid = (uint32_t *)(b + L.leafid);
     k_fmm_leafmap<<<(unsigned)((nn_host + 255) / 256), 256, 0, s>>>(t->ctr, t->wn, leafid);
     const unsigned pb = (unsigned)((t->n + 255) / 256);
-    if (fp->kernel == 1) {
+    if (fp->kernel == 2) {
+        if (pot) k_fmm_particles<2, true><<<pb, 256, 0, s>>>(A, pstart, pend, F, leafid, t->perm1, t->n, fp->G, ax, ay, az, pot);
+        else k_fmm_particles<2, false><<<pb, 256, 0, s>>>(A, pstart, pend, F, leafid, t->perm1, t->n, fp->G, ax, ay, az, pot);
+    } else if (fp->kernel == 1) {
         if (pot) k_fmm_particles<1, true><<<pb, 256, 0, s>>>(A, pstart, pend, F, leafid, t->perm1, t->n, fp->G, ax, ay, az, pot);
         else k_fmm_particles<1, false><<<pb, 256, 0, s>>>(A, pstart, pend, F, leafid, t->perm1, t->n, fp->G, ax, ay, az, pot);
     } else {

@@ -46,7 +46,7 @@ class g4_walk_params(C.Structure):
 class g4_fmm_params(C.Structure):
     _fields_ = [("kernel", C.c_int), ("G", C.c_double), ("eps0", C.c_double), ("r_s", C.c_double),
                 ("r_cut", C.c_double), ("theta", C.c_double), ("deterministic", C.c_int), ("criterion", C.c_int),
-                ("alpha", C.c_double), ("a_seed", C.c_void_p)]
+                ("alpha", C.c_double), ("a_seed", C.c_void_p), ("ewald_table", C.c_void_p), ("ewald_n", C.c_int)]
 
 
 class g4_pm_params(C.Structure):
@@ -462,15 +462,18 @@ def g4_mlp_train_step(ctx, w_bf16, master, adam_state, grad, feat, target, lr, s
 
 # ------------------------------------------------------------------ FMM
 def fmm_params(kernel=0, G=1.0, eps0=0.0, r_s=1.0, r_cut=1e30, theta=0.5, deterministic=0, criterion=0,
-               alpha=0.005, a_seed=None):
+               alpha=0.005, a_seed=None, ewald=None):
     """criterion 1: the relative node-node criterion with |a| per particle
-    (a_seed, float32 device tensor in caller order)."""
+    (a_seed, float32 device tensor in caller order); ewald: the EwaldTable of
+    the box for kernel 2."""
     fp = g4_fmm_params()
     fp.kernel, fp.G, fp.eps0, fp.r_s, fp.r_cut, fp.theta = int(kernel), float(G), float(eps0), float(r_s), float(r_cut), float(theta)
     fp.deterministic = int(deterministic)
     fp.criterion, fp.alpha = int(criterion), float(alpha)
     fp.a_seed = None if a_seed is None else a_seed.data_ptr()
-    fp._keep = a_seed
+    if ewald is not None:
+        fp.ewald_table, fp.ewald_n = ewald.ptr, int(ewald.ne)
+    fp._keep = (a_seed, ewald)
     return fp
 
 

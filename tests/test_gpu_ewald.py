@@ -198,3 +198,30 @@ def test_gpu_ewald_direct_sum_matches_the_oracle(g, ctx):
     tg = np.array([0, 17, 299], dtype=np.int64)
     o2 = g.g4_direct_force(ctx, p, tp, wp, targets=torch.from_numpy(tg).cuda(), want_pot=False)
     np.testing.assert_allclose(_stack(o2), ref[tg], rtol=1e-9, atol=1e-11 * np.abs(ref).max())
+
+
+@pytest.mark.parametrize("det", [0, 1])
+def test_periodic_fmm_parity_with_the_oracle(g, ctx, table, det):
+    """The FMM with the Ewald correction (kernel 2), both summation modes,
+    against the oracle's periodic FMM: the same interactions, forces and
+    potentials at FP32 round-off, total momentum kept."""
+    ps = workloads.clustered_box(4000, seed=46, nhalo=12)
+    tp = g.tree_params(True, 1.0, leaf_max=16)
+    x, y, z = g.g4_quantize(ctx, torch.from_numpy(ps.pos).cuda(), tp)
+    m32 = ps.mass.astype(np.float32)
+    p = g.particles(x, y, z, torch.from_numpy(m32).cuda())
+    tree = g.g4_build_tree(ctx, p, tp)
+    g.g4_compute_multipoles(ctx, tree, 3)
+    st, X, Y, Z = oracle.quantize(ps.pos, True, 1.0)
+    ot = oracle.Tree(X, Y, Z, m32.astype(np.float64), True, 1.0, 16)
+    eps = (128 ** 3 / 4000) ** (1 / 3) / (40 * 128)
+    out = g.g4_fmm_force(ctx, tree, g.fmm_params(kernel=2, theta=0.5, eps0=eps, deterministic=det, ewald=table),
+                         want_pot=True, want_stats=True)
+    acc, pot, stt = ot.fmm(kernel=2, theta=0.5, eps0=eps)
+    _parity(_stack(out), acc, label=f"periodic fmm det={det}")
+    assert np.median(np.abs(out["pot"].cpu().numpy() - pot) / np.abs(pot)) < 1e-5
+    s = out["stats"]
+    for k, v in zip(("n_pp", "n_pn", "n_nn"), stt):
+        assert abs(s[k] - int(v)) <= 1e-3 * max(1, int(v)), (k, s[k], int(v))
+    a = _stack(out)
+    assert np.abs((m32[:, None].astype(np.float64) * a).sum(0)).max() <= 1e-6 * (m32[:, None] * np.abs(a)).sum()

@@ -168,3 +168,27 @@ def test_tree_walk_converges_to_the_ewald_direct_sum():
     approx, _, cnt = t.walk(kernel=2, criterion=0, theta=0.5, eps0=1e-3, nthreads=8)
     err = np.linalg.norm(approx - ref, axis=1) / np.linalg.norm(ref, axis=1)
     assert np.median(err) < 2e-3 and cnt[:, 1].sum() > 0
+
+
+def test_periodic_fmm_with_ewald_correction():
+    """The FMM with the Ewald correction in every interaction's expansion:
+    theta -> 0 is the Ewald direct sum, the symmetric expansion keeps the
+    total momentum at round-off (psi is even, so every correction is
+    antisymmetric), and theta = 0.5 stays close to the exact sum."""
+    rng = np.random.default_rng(7)
+    n = 300
+    pos = np.concatenate([rng.uniform(0, 1, size=(n // 2, 3)), (0.3 + 0.05 * rng.normal(size=(n // 2, 3))) % 1.0])
+    m = rng.uniform(0.5, 1.5, n) / n
+    st, X, Y, Z = oracle.quantize(pos, True, 1.0)
+    ref, pref = oracle.direct(X, Y, Z, m, 1.0 / 2 ** 32, kernel=2, eps0=1e-3, nthreads=8)
+    t = oracle.Tree(X, Y, Z, m, True, 1.0, 8)
+    a0, p0, s0 = t.fmm(kernel=2, theta=1e-9, eps0=1e-3)
+    np.testing.assert_allclose(a0, ref, rtol=1e-10, atol=1e-12 * np.abs(ref).max())
+    np.testing.assert_allclose(p0, pref, rtol=1e-10)
+    assert s0[1] == 0 and s0[2] == 0
+    a, pa, s1 = t.fmm(kernel=2, theta=0.5, eps0=1e-3)
+    assert s1[1] > 0 and s1[2] > 0
+    assert np.abs((m[:, None] * a).sum(0)).max() < 1e-13 * (m[:, None] * np.abs(a)).sum()
+    err = np.linalg.norm(a - ref, axis=1) / np.linalg.norm(ref, axis=1)
+    assert np.median(err) < 2e-3
+    assert np.median(np.abs(pa - pref) / np.abs(pref)) < 1e-3
