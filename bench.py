@@ -586,6 +586,30 @@ def bench_ewald(args, g, ctx, flops):
                           targets=torch.from_numpy(tg).to(dev), want_pot=False)
     ref = np.stack([r["ax"].cpu().numpy(), r["ay"].cpu().numpy(), r["az"].cpu().numpy()], 1)
     err = workloads.percentiles(workloads.relative_errors(a[tg], ref))
+    # the periodic FMM with the same table (theta 0.5, leaf 32, atomic-sum mode)
+    tpf = g.tree_params(True, 1.0, leaf_max=32)
+    wsf = torch.empty(g.g4_workspace_bytes(tpf, n) + 256, dtype=torch.uint8, device=dev)
+    fp = g.fmm_params(kernel=2, theta=0.5, eps0=eps0, ewald=table)
+    fst = {"factor": 1.0, "fws": None}
+
+    def fstep():
+        x, y, z = g.g4_quantize(ctx, pos, tpf)
+        t = g.g4_build_tree(ctx, g.particles(x, y, z, mass), tpf, ws=wsf)
+        g.g4_compute_multipoles(ctx, t, 3)
+        o = g.g4_fmm_force(ctx, t, fp, list_factor=fst["factor"], ws=fst["fws"])
+        fst["factor"], fst["fws"], fst["o"] = o["list_factor"], o["ws"], o
+
+    fstep()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        fstep()
+    torch.cuda.synchronize()
+    fmm_ms = (time.perf_counter() - t0) * 1e3 / steps
+    o = fst["o"]
+    af = np.stack([o["ax"].cpu().numpy(), o["ay"].cpu().numpy(), o["az"].cpu().numpy()], 1)
+    ferr = workloads.percentiles(workloads.relative_errors(af[tg], ref))
+    log(f"[bench] periodic FMM + Ewald 128^3 (theta 0.5, leaf 32): {fmm_ms:.2f} ms/step, errors {ferr}")
     walk_ms, seed_ms = 1e3 * st["t_walk"], 1e3 * st["t_seed"]
     log(f"[bench] periodic tree + Ewald 128^3: {ms:.2f} ms/step (walk {walk_ms:.2f} ms, pre-walk "
         f"{seed_ms:.2f} ms; table {table_ms:.1f} ms once), errors {err}")
@@ -595,7 +619,9 @@ def bench_ewald(args, g, ctx, flops):
             "table_build_ms": table_ms,
             "interactions_per_particle": {"pp": st["n_p2p"] / n, "pn": st["n_p2m"] / n,
                                           "seed_pp": st["n_seed_p2p"] / n, "seed_pn": st["n_seed_p2m"] / n},
-            "errors_vs_ewald_direct": err, "error_sample": len(tg)}
+            "errors_vs_ewald_direct": err, "error_sample": len(tg),
+            "fmm": {"workload": "periodic FMM + Ewald, same box, p=3, theta 0.5, leaf 32, atomic-sum mode",
+                    "ms_per_step": fmm_ms, "forces_per_s": n / (fmm_ms * 1e-3), "errors_vs_ewald_direct": ferr}}
 
 
 def bench_fmm(args, g, ctx, flops):
