@@ -73,6 +73,9 @@ def lib():
         L.orc_gn.argtypes = [i32, d, d, p]
         L.orc_Dn.argtypes = [i32, p, d, p, p, p, p]
         L.orc_ewald_psi.argtypes = [p, d, d, p, p, p, p]
+        L.orc_gn_ext.argtypes = [i32, d, d, i32, p]
+        L.orc_Dfull.argtypes = [p, p, i32, p]
+        L.orc_moments4.argtypes = [p]
         L.orc_quantize.restype = i32
         L.orc_quantize.argtypes = [i64, p, i32, d, p, p, p, p]
         L.orc_build.restype = p
@@ -204,6 +207,9 @@ class Tree:
              theta=0.7, alpha=0.005, aseed=None, targets=None, nthreads=1, want_pot=True):
         if not self.has_moments:
             self.compute_moments()
+        if order >= 4 and not getattr(self, "has_moments4", False):
+            lib().orc_moments4(self._h)
+            self.has_moments4 = True
         P = WalkParams(int(kernel), int(criterion), int(order), int(exclusion), float(G), float(eps0),
                        float(r_s), float(r_cut), float(theta), float(alpha))
         tg = None if targets is None else np.ascontiguousarray(targets, dtype=np.int64)
@@ -253,6 +259,22 @@ def direct(X, Y, Z, mass, unit, kernel=0, G=1.0, eps0=0.0, r_s=1.0, r_cut=np.inf
     lib().orc_direct(n, _ptr(X), _ptr(Y), _ptr(Z), _ptr(mass), float(unit), C.byref(P), int(truncate),
                      _ptr(tg), nt, _ptr(acc), _ptr(pot), int(nthreads))
     return acc, pot
+
+
+def gn_ext(kernel, r, alpha=0.0, nmax=6):
+    """g_0..g_nmax of the Newtonian (kernel 0) or erfc(alpha r)/r (kernel 1) kernel."""
+    g = np.zeros(nmax + 1)
+    lib().orc_gn_ext(int(kernel), float(r), float(alpha), int(nmax), _ptr(g))
+    return g
+
+
+def d_full(kernel, rv, n, alpha=0.0):
+    """The full derivative tensor D_n (shape (3,)*n) of the kernel at offset rv."""
+    rv = np.ascontiguousarray(rv, dtype=np.float64)
+    g = gn_ext(kernel, float(np.linalg.norm(rv)), alpha, 7)
+    D = np.zeros(3 ** n)
+    lib().orc_Dfull(_ptr(g), _ptr(rv), int(n), _ptr(D))
+    return D.reshape((3,) * n) if n else D[0]
 
 
 def ewald_psi(x, L=1.0, alpha=0.0):

@@ -178,6 +178,76 @@ void orc_Dn(int kernel, const double rv[3], double alpha, double *D0, double D1[
     }
 }
 
+/* g_0..g_nmax (nmax <= 7) of the Newtonian kernel (Appendix A: g_n =
+ * (-1)^n (2n-1)!! / r^(2n+1)) or of erfc(alpha r)/r, whose g_n follow from
+ * the recursion g_{n+1} = r^-1 d g_n/dr with
+ * g_n = A_n erfc(alpha r) r^-(2n+1) + E sum_j b_nj r^-2j,
+ * E = (2 alpha/sqrt(pi)) exp(-alpha^2 r^2), A_{n+1} = -(2n+1) A_n,
+ * b_{n+1,j} += -2 alpha^2 b_nj, b_{n+1,j+1} += -2j b_nj, b_{n+1,n+1} += -A_n. */
+void orc_gn_ext(int kernel, double r, double alpha, int nmax, double *g)
+{
+    double ri2 = 1.0 / (r * r), rp = 1.0 / r, A = 1.0;
+    if (kernel == 0) {
+        for (int n = 0; n <= nmax; n++) {
+            g[n] = A * rp;
+            A *= -(2.0 * n + 1.0);
+            rp *= ri2;
+        }
+        return;
+    }
+    double ec = erfc(alpha * r), E = 2.0 * alpha / SQRTPI * exp(-alpha * alpha * r * r), a2 = alpha * alpha;
+    double b[9] = {0}, nb[9];
+    for (int n = 0; n <= nmax; n++) {
+        double sum = 0.0, rj = 1.0;
+        for (int j = 1; j <= n; j++) {
+            rj *= ri2;
+            sum += b[j] * rj;
+        }
+        g[n] = A * ec * rp + E * sum;
+        for (int j = 0; j <= n + 1; j++) nb[j] = 0.0;
+        for (int j = 1; j <= n; j++) {
+            nb[j] += -2.0 * a2 * b[j];
+            nb[j + 1] += -2.0 * j * b[j];
+        }
+        nb[n + 1] += -A;
+        memcpy(b, nb, sizeof(double) * (size_t)(n + 2));
+        A *= -(2.0 * n + 1.0);
+        rp *= ri2;
+    }
+}
+
+/* sum over the ways to pair up some of the indices idx[k..n-1] that are not
+ * yet used: each pair gives a Kronecker delta, each index left alone gives
+ * the component of r; a term with m pairs carries g_{n-m} */
+static double pairings_sum(const int *idx, int n, unsigned used, int npairs, const double *r, const double *g)
+{
+    int k = 0;
+    while (k < n && (used >> k & 1u)) k++;
+    if (k == n) return g[n - npairs];
+    used |= 1u << k;
+    double s = r[idx[k]] * pairings_sum(idx, n, used, npairs, r, g);   /* idx[k] alone */
+    for (int l = k + 1; l < n; l++)
+        if (!(used >> l & 1u) && idx[l] == idx[k]) s += pairings_sum(idx, n, used | 1u << l, npairs + 1, r, g);
+    return s;
+}
+
+/* the full derivative tensor D_n (3^n components, row-major) of a radial
+ * kernel with scalars g at offset r:  d^n g / dx_i1 .. dx_in =
+ * sum over pairings of Kronecker deltas and r-components, times g_{n - #pairs} */
+void orc_Dfull(const double *g, const double r[3], int n, double *D)
+{
+    int total = 1;
+    for (int k = 0; k < n; k++) total *= 3;
+    for (int c = 0; c < total; c++) {
+        int idx[8], v = c;
+        for (int k = n - 1; k >= 0; k--) {
+            idx[k] = v % 3;
+            v /= 3;
+        }
+        D[c] = pairings_sum(idx, n, 0u, 0, r, g);
+    }
+}
+
 /* ======================================================================
  * 2b. Periodic correction potential psi (Sec. "Periodic boundary
  *     conditions", eqs. (eqnpo1), (eqnpo2), (eqnewal))
@@ -352,6 +422,7 @@ struct orc_tree {
     onode *nodes;
     int64_t nnodes, cap;
     int has_moments;
+    double *q4;            /* 81 per node: fourth moments about the centre of mass (orc_moments4) */
 };
 
 /* Node storage: the tree's own array, or a private buffer of one thread. */
@@ -557,7 +628,7 @@ orc_tree *orc_build_mt(int64_t n, const uint32_t *X, const uint32_t *Y, const ui
 void orc_free(orc_tree *t)
 {
     if (!t) return;
-    free(t->X); free(t->Y); free(t->Z); free(t->m); free(t->idx); free(t->nodes);
+    free(t->X); free(t->Y); free(t->Z); free(t->m); free(t->idx); free(t->nodes); free(t->q4);
     free(t);
 }
 
@@ -615,6 +686,25 @@ static void node_moments(orc_tree *t, int64_t q)
                     nd->q2[i * 3 + j] += t->m[p] * d[i] * d[j];
                     for (int k = 0; k < 3; k++) nd->q3[(i * 3 + j) * 3 + k] += t->m[p] * d[i] * d[j] * d[k];
                 }
+        }
+    }
+}
+
+/* fourth moments Q4_ijkl = sum m d_i d_j d_k d_l about each node's centre of
+ * mass (direct sums; needed from p = 4 on) */
+void orc_moments4(orc_tree *t)
+{
+    free(t->q4);
+    t->q4 = (double *)calloc((size_t)t->nnodes * 81, sizeof(double));
+    for (int64_t q = 0; q < t->nnodes; q++) {
+        const onode *nd = &t->nodes[q];
+        double *Q = t->q4 + (size_t)q * 81;
+        for (int64_t a = 0; a < nd->count; a++) {
+            int64_t p = t->idx[nd->first + a];
+            double d[3] = {(double)(int32_t)(t->X[p] - nd->gc[0]) * t->unit - nd->dcom[0],
+                           (double)(int32_t)(t->Y[p] - nd->gc[1]) * t->unit - nd->dcom[1],
+                           (double)(int32_t)(t->Z[p] - nd->gc[2]) * t->unit - nd->dcom[2]};
+            for (int c = 0; c < 81; c++) Q[c] += t->m[p] * d[c / 27] * d[(c / 9) % 3] * d[(c / 3) % 3] * d[c % 3];
         }
     }
 }
@@ -716,6 +806,33 @@ static void p2p_one(const orc_tree *t, const orc_walk_params *P, int64_t i, int6
 /* Accepted node: eqs. (eqonesidetreeacc) and (eqonesidetreepotential) with
  * p = 3 and vanishing dipole: a = -[M D1 + Q2:D3 / 2],
  * phi = -[M D0 + Q2:D2 / 2 + Q3.D3 / 6], D evaluated at r = s - x. */
+/* Accepted node at p = 4 or 5 (Appendix A): the force
+ * a = -[M D1 + Q2:D3/2 + Q3:D4/6 (+ Q4:D5/24 at p = 5)] and the potential
+ * phi = -[M D0 + Q2:D2/2 + Q3:D3/6 + Q4:D4/24] (the p = 5 term Q5:D5/120 is
+ * left out, as the paper does in practice: it is constant over the target's
+ * neighbourhood and adds no force), full tensors at r = s - x. */
+static void p2m_high(const orc_walk_params *P, const onode *nd, const double *q4, const double rv[3], double a[3],
+                     double *phi)
+{
+    double g[8], r = sqrt(rv[0] * rv[0] + rv[1] * rv[1] + rv[2] * rv[2]);
+    orc_gn_ext(P->kernel == 1, r, P->kernel == 1 ? 0.5 / P->r_s : 0.0, 6, g);
+    static __thread double D[6][243];
+    for (int n = 0; n <= 5; n++) orc_Dfull(g, rv, n, D[n]);
+    for (int i = 0; i < 3; i++) {
+        double s = nd->mass * D[1][i];
+        for (int c = 0; c < 9; c++) s += 0.5 * nd->q2[c] * D[3][i * 9 + c];
+        for (int c = 0; c < 27; c++) s += nd->q3[c] * D[4][i * 27 + c] / 6.0;
+        if (P->order >= 5)
+            for (int c = 0; c < 81; c++) s += q4[c] * D[5][i * 81 + c] / 24.0;
+        a[i] -= s;
+    }
+    double ph = nd->mass * D[0][0];
+    for (int c = 0; c < 9; c++) ph += 0.5 * nd->q2[c] * D[2][c];
+    for (int c = 0; c < 27; c++) ph += nd->q3[c] * D[3][c] / 6.0;
+    for (int c = 0; c < 81; c++) ph += q4[c] * D[4][c] / 24.0;
+    *phi -= ph;
+}
+
 static void p2m_one(const orc_walk_params *P, const onode *nd, const double rv[3], double box, double a[3],
                     double *phi)
 {
@@ -796,11 +913,12 @@ static void walk_node(const walk_job *J, int64_t i, double aseed, int64_t q, dou
         if (P->criterion == 0)
             accept = l < P->theta * r;
         else
-            accept = P->order >= 3 ? nd->mass * l * l * l < P->alpha * aseed * r2 * r2 * r
-                                   : nd->mass * l * l < P->alpha * aseed * r2 * r2;
+            /* M l^p < alpha |a| r^(p+2) (eq. eqnrelcriterion) */
+            accept = nd->mass * pow(l, P->order) < P->alpha * aseed * pow(r, P->order + 2);
     }
     if (accept) {
-        p2m_one(P, nd, rv, t->box, a, phi);
+        if (P->order >= 4) p2m_high(P, nd, t->q4 + (size_t)q * 81, rv, a, phi);
+        else p2m_one(P, nd, rv, t->box, a, phi);
         cnt[1]++;
         return;
     }
@@ -862,6 +980,7 @@ static void walk_chunk_init(void *c, void *job, int64_t lo, int64_t hi)
 int orc_walk(const orc_tree *t, const orc_walk_params *P, const double *aseed, const int64_t *targets,
              int64_t ntargets, double *acc, double *pot, int64_t *counts, int nthreads)
 {
+    if (P->order >= 4 && (!t->q4 || P->kernel == 2)) return -4;  /* fourth moments needed; no Ewald beyond p = 3 */
     if (!t->has_moments) return -4;
     if (P->criterion == 1 && !aseed) return -1;
     walk_job J = {t, *P, aseed, targets, targets ? ntargets : t->n, acc, pot, counts};

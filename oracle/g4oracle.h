@@ -18,7 +18,7 @@ typedef struct {
     int kernel;      /* 0 softened Newtonian, 1 TreePM short-range (eq. eqnpo4),
                         2 periodic softened Newtonian + Ewald correction (eq. eqnpo1) */
     int criterion;   /* 0 geometric l/r < theta, 1 relative (eq. eqnrelcriterion) */
-    int order;       /* expansion order p (2 or 3) */
+    int order;       /* expansion order p (2..5; 4 and 5 need orc_moments4) */
     int exclusion;   /* 1: never accept a node whose 2l-cube holds the target */
     double G, eps0, r_s, r_cut, theta, alpha;
 } orc_walk_params;
@@ -38,6 +38,9 @@ double orc_sr_K(double r, double h, double alpha);
 double orc_sr_W(double r, double h, double alpha);
 void orc_gn(int kernel, double r, double alpha, double g[4]);
 void orc_Dn(int kernel, const double rv[3], double alpha, double *D0, double D1[3], double D2[9], double D3[27]);
+/* g_0..g_nmax (nmax <= 7) and the full tensor D_n (3^n values) from them */
+void orc_gn_ext(int kernel, double r, double alpha, int nmax, double *g);
+void orc_Dfull(const double *g, const double r[3], int n, double *D);
 /* periodic correction potential psi of a cube of side L and its derivative
  * tensors (full 3, 3x3, 3x3x3 arrays), exact Ewald sums; alpha <= 0: 2/L */
 void orc_ewald_psi(const double x[3], double L, double alpha, double *D0, double D1[3], double D2[9], double D3[27]);
@@ -53,6 +56,8 @@ void orc_free(orc_tree *t);
 int64_t orc_tree_nnodes(const orc_tree *t);
 void orc_tree_nodes(const orc_tree *t, int32_t *level, uint32_t *cell3, int64_t *count, int32_t *leaf);
 void orc_moments(orc_tree *t);
+/* fourth moments (81 per node) for walks at p = 4, 5 */
+void orc_moments4(orc_tree *t);
 /* the same, with the work shared out to nthreads threads (the serial code
  * above for nthreads <= 1; the threaded build numbers the nodes differently) */
 orc_tree *orc_build_mt(int64_t n, const uint32_t *X, const uint32_t *Y, const uint32_t *Z, const double *mass,

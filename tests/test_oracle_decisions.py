@@ -86,7 +86,7 @@ def test_exclusion_zone_is_cube_of_side_2l(lev_n):
     assert _target_counts(t, **geo) == ACCEPTED
 
 
-@pytest.mark.parametrize("order", [3, 2])
+@pytest.mark.parametrize("order", [3, 2, 4, 5])
 def test_relative_criterion_threshold_and_exponent(order):
     """eq. eqnrelcriterion: accept iff (M/r^2)(l/r)^p < alpha |a| with p the
     expansion order; equality and anything above open.  The threshold alpha
