@@ -78,7 +78,9 @@ typedef struct {
  *            (eq. eqnrelcriterion) with |a| from a_seed, or, when a_seed is
  *            NULL, from a geometric pre-walk with theta_seed.
  * order:     p = 2 (monopole force) or 3 (monopole + quadrupole force;
- *            octupole enters the potential).
+ *            octupole enters the potential); 4 and 5 (kernels 0 and 1
+ *            evaluated, after g4_compute_moments4) add the octupole and
+ *            hexadecapole force terms; the criterion takes l^p / r^(p+2).
  * exclusion: 1 = never accept a node whose cube of side 2l centred on the
  *            node holds the target.  Nodes closer than h = 2.8 eps0 are
  *            always opened.  TreePM drops nodes whose nearest edge is farther
@@ -253,6 +255,20 @@ int g4_build_forest(g4_ctx *ctx, int nbox, const int64_t *box_offsets, const g4_
  * phase): leaves from their particles, parents from their children by the
  * parallel-axis shift.  FP64 accumulation at levels <= 8, FP32 below. */
 int g4_compute_multipoles(g4_ctx *ctx, g4_tree *tree, int order);
+
+/* Fourth moments (15 per node, FP64) about each node's centre of mass, for
+ * walks at p = 4 and 5 (Appendix A, "Multipole extensions at different
+ * order"): leaves from their particles, parents from their children's
+ * moments of orders 0..4 shifted to the parent's centre of mass.  Needs
+ * g4_compute_multipoles(order 3) of the same tree; ws: device, 256-byte
+ * aligned, at least g4_moments4_bytes(tree) bytes, owned by the caller and kept
+ * by the tree (until the next g4_compute_multipoles) for its walks.  Then
+ * walks may take order 4 (force with the octupole term, potential to the
+ * fourth moments) or 5 (force with the hexadecapole term as well; the
+ * potential's fifth-moment term is left out, as in the paper's practice).
+ * Asynchronous. */
+size_t g4_moments4_bytes(const g4_tree *tree);
+int g4_compute_moments4(g4_ctx *ctx, g4_tree *tree, void *ws, size_t bytes);
 
 /* Node count and level ranges of a built tree (host outputs; synchronises).
  * level_start: host array of max_depth + 2 int64 (may be NULL). */

@@ -173,6 +173,7 @@ static int g4_build_tree_views(g4_ctx *ctx, const g4_particles *p, const g4_tree
     t->unit = tp->box / (tp->periodic ? 4294967296.0 : 2147483648.0);
     t->cap = L.cap;
     t->moments_order = 0;
+    t->q4d = nullptr;
     t->seed_valid = 0;
     t->nbox = 1;
     t->items = nullptr;
@@ -216,7 +217,26 @@ int g4_compute_multipoles(g4_ctx *ctx, g4_tree *tree, int order)
     if (!st) st = g4_phase_end(ctx, tree, 1);
     if (st) return st;
     tree->moments_order = order;
+    tree->q4d = nullptr;
     tree->seed_valid = 0;
+    return G4_OK;
+}
+
+size_t g4_moments4_bytes(const g4_tree *tree)
+{
+    return tree ? (size_t)tree->cap * 15 * sizeof(double) : 0;
+}
+
+int g4_compute_moments4(g4_ctx *ctx, g4_tree *tree, void *ws, size_t bytes)
+{
+    if (!ctx || !tree) return G4_EINVAL;
+    if (tree->moments_order < 3) return g4_set_err(ctx, G4_ESTATE, "compute the multipoles to order 3 first");
+    if (!ws || ((uintptr_t)ws & 255)) return g4_set_err(ctx, G4_EINVAL, "workspace must be 256-byte aligned");
+    if (bytes < g4_moments4_bytes(tree)) return g4_set_err(ctx, G4_EINVAL, "workspace too small");
+    int st = g4_launch_moments4(ctx, tree, static_cast<double *>(ws));
+    if (st) return st;
+    tree->q4d = static_cast<double *>(ws);
+    tree->moments_order = 5;
     return G4_OK;
 }
 
@@ -337,8 +357,10 @@ static int tree_force_impl(g4_ctx *ctx, g4_tree *tree, const g4_walk_params *wp,
     if (!ctx || !tree || !wp) return G4_EINVAL;
     if (!ax || !ay || !az) return g4_set_err(ctx, G4_EINVAL, "null output");
     if (!tree->moments_order) return g4_set_err(ctx, G4_ESTATE, "moments not computed");
-    if (wp->order != 2 && wp->order != 3) return g4_set_err(ctx, G4_EINVAL, "order must be 2 or 3");
+    if (wp->order < 2 || wp->order > 5) return g4_set_err(ctx, G4_EINVAL, "order must be 2..5");
     if (wp->order > tree->moments_order) return g4_set_err(ctx, G4_ESTATE, "moments computed at a lower order");
+    if (wp->order >= 4 && (kernel == 2 || (kernel == 1 && wp->sr_table > 0)))
+        return g4_set_err(ctx, G4_EINVAL, "orders 4 and 5 take the evaluated Newtonian or short-range kernel");
     if (wp->criterion != 0 && wp->criterion != 1) return g4_set_err(ctx, G4_EINVAL, "criterion must be 0 or 1");
     if (kernel == 1 && !(wp->r_s > 0)) return g4_set_err(ctx, G4_EINVAL, "r_s must be positive");
     if (kernel == 1 && !(wp->r_cut > 0)) return g4_set_err(ctx, G4_EINVAL, "r_cut must be positive");

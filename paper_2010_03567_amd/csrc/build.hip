@@ -669,6 +669,91 @@ int g4_launch_moments(g4_ctx *ctx, g4_tree *t)
     return G4_OK;
 }
 
+// Fourth moments Q4 (15 packed components, multi-index order xxxx xxxy ...
+// zzzz) about every node's centre of mass, for the walk at p = 4, 5; FP64, one
+// thread per node, levels from the deepest up.  A leaf sums m d^(a,b,c) over its
+// particles; an internal node shifts its children's moments to its own centre
+// of mass: for d = s_child - s,
+//   Q4_alpha = sum_{beta <= alpha} C(alpha, beta) Qc_beta d^(alpha - beta),
+// C the product of binomial coefficients per axis, Qc_beta the child's moment
+// of order |beta| (its mass for 0, zero for 1 about its centre of mass).
+__device__ __forceinline__ int m4_idx(int a, int b, int c)
+{
+    // position of a multi-index within its order: (b + c)(b + c + 1)/2 + c
+    return (b + c) * (b + c + 1) / 2 + c;
+}
+
+__global__ void k_moments4(const DevCounters *__restrict__ C, const uint4 *__restrict__ parts,
+                           const WNode *__restrict__ wn, const double *__restrict__ mom, double *__restrict__ q4,
+                           int level, double unit)
+{
+    const uint32_t beg = C->lvl_start[level], end = beg + C->lvl_count[level];
+    const double binom[5][5] = {{1, 0, 0, 0, 0}, {1, 1, 0, 0, 0}, {1, 2, 1, 0, 0}, {1, 3, 3, 1, 0}, {1, 4, 6, 4, 1}};
+    for (uint32_t q = beg + blockIdx.x * blockDim.x + threadIdx.x; q < end; q += gridDim.x * blockDim.x) {
+        const WNode w = wn[q];
+        const double *mo = mom + (size_t)q * MOM_STRIDE;
+        double Q[15];
+        for (int k = 0; k < 15; k++) Q[k] = 0.0;
+        if (w.meta & WN_LEAF) {
+            for (uint32_t j = w.next; j < w.next + w.num; j++) {
+                const uint4 p = parts[j];
+                const double m = (double)__uint_as_float(p.w);
+                const double d[3] = {(double)(int32_t)(p.x - w.gx) * unit - mo[1], (double)(int32_t)(p.y - w.gy) * unit - mo[2],
+                                     (double)(int32_t)(p.z - w.gz) * unit - mo[3]};
+                for (int a = 4; a >= 0; a--)
+                    for (int b = 4 - a; b >= 0; b--) {
+                        const int c = 4 - a - b;
+                        double v = m;
+                        for (int k = 0; k < a; k++) v *= d[0];
+                        for (int k = 0; k < b; k++) v *= d[1];
+                        for (int k = 0; k < c; k++) v *= d[2];
+                        Q[m4_idx(a, b, c)] += v;
+                    }
+            }
+        } else {
+            for (uint32_t ch = w.next; ch < w.next + w.num; ch++) {
+                const WNode wc = wn[ch];
+                const double *mc = mom + (size_t)ch * MOM_STRIDE;
+                const double *qc4 = q4 + (size_t)ch * 15;
+                const double d[3] = {(double)(int32_t)(wc.gx - w.gx) * unit + mc[1] - mo[1],
+                                     (double)(int32_t)(wc.gy - w.gy) * unit + mc[2] - mo[2],
+                                     (double)(int32_t)(wc.gz - w.gz) * unit + mc[3] - mo[3]};
+                for (int a = 4; a >= 0; a--)
+                    for (int b = 4 - a; b >= 0; b--) {
+                        const int c = 4 - a - b;
+                        double sum = 0.0;
+                        for (int ba = 0; ba <= a; ba++)
+                            for (int bb = 0; bb <= b; bb++)
+                                for (int bc = 0; bc <= c; bc++) {
+                                    const int n = ba + bb + bc;
+                                    double qv;
+                                    if (n == 0) qv = mc[0];
+                                    else if (n == 1) continue;
+                                    else if (n == 2) qv = mc[4 + m4_idx(ba, bb, bc)];
+                                    else if (n == 3) qv = mc[10 + m4_idx(ba, bb, bc)];
+                                    else qv = qc4[m4_idx(ba, bb, bc)];
+                                    double v = binom[a][ba] * binom[b][bb] * binom[c][bc] * qv;
+                                    for (int k = 0; k < a - ba; k++) v *= d[0];
+                                    for (int k = 0; k < b - bb; k++) v *= d[1];
+                                    for (int k = 0; k < c - bc; k++) v *= d[2];
+                                    sum += v;
+                                }
+                        Q[m4_idx(a, b, c)] += sum;
+                    }
+            }
+        }
+        for (int k = 0; k < 15; k++) q4[(size_t)q * 15 + k] = Q[k];
+    }
+}
+
+int g4_launch_moments4(g4_ctx *ctx, g4_tree *t, double *q4)
+{
+    const int maxd = t->tp.max_depth < 1 ? 1 : (t->tp.max_depth > G4_MAXLEV ? G4_MAXLEV : t->tp.max_depth);
+    for (int l = maxd; l >= 0; l--) k_moments4<<<1024, 128, 0, ctx->stream>>>(t->ctr, t->parts, t->wn, t->mom, q4, l, t->unit);
+    G4_HIP(ctx, hipGetLastError());
+    return G4_OK;
+}
+
 // ------------------------------------------------------------------ export
 __global__ void k_export(const DevCounters *__restrict__ C, const WNode *__restrict__ wn,
                          const uint32_t *__restrict__ bfirst, const uint32_t *__restrict__ bcount,

@@ -72,7 +72,8 @@ struct g4_tree {
     uint32_t corner;    // integer lower corner of the root
     double unit;        // physical length of one integer step
     int64_t cap;        // node capacity
-    int moments_order;  // 0 until g4_compute_multipoles
+    int moments_order;  // 0 until g4_compute_multipoles; 5 once g4_compute_moments4 has run
+    double *q4d;        // fourth moments, 15 per node (caller's buffer, g4_compute_moments4), or null
     int seed_valid;     // aseed holds |a| of a geometric walk over this tree
     // workspace views
     DevCounters *ctr;

@@ -60,3 +60,4 @@ size_t g4_ewald_layout_bytes(int ne);
 int g4_launch_ewald_table(g4_ctx *ctx, double box, int ne, float *tab);
 int g4_launch_ewald_eval(g4_ctx *ctx, const float *tab, int ne, double box, int64_t n, const double *dx,
                          const double *dy, const double *dz, double *psi, double *gx, double *gy, double *gz);
+int g4_launch_moments4(g4_ctx *ctx, g4_tree *t, double *q4);

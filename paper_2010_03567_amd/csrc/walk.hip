@@ -41,6 +41,7 @@ struct WalkArgs {
     const float4 *tab;  // short-range factor table (kernel 2), tn intervals, t = r * tscale
     uint32_t tn;
     float tscale;
+    const double *q4;   // fourth moments (15 per node, packed), orders p = 4, 5
     const float *ew;    // periodic correction table (kernel 3): ew_n intervals of ew_h over [0, L/2]
     int ew_n;
     float ew_h, ew_hinv;
@@ -103,6 +104,107 @@ __device__ __forceinline__ void gfun(float r2, float rinv, const WalkArgs &A, fl
         g2 = 3.0f * t1 * ri2 + e2 * (3.0f * ri2 + 2.0f * a2);
         g3 = -(15.0f * t1 * ri2 * ri2 + e2 * (ri2 * (15.0f * ri2 + 10.0f * a2) + 4.0f * a2 * a2));
     }
+}
+
+// g4 and g5 of the Newtonian or short-range kernel (orders p = 4, 5):
+// Newtonian g4 = 105/r^9, g5 = -945/r^11; short range from the recursion
+// g_{n+1} = r^-1 d g_n/dr applied to erfc(alpha r)/r:
+//   g4 = 105 erfc r^-9 + E (105 r^-8 + 70 a2 r^-6 + 28 a2^2 r^-4 + 8 a2^3 r^-2),
+//   g5 = -945 erfc r^-11 - E (945 r^-10 + 630 a2 r^-8 + 252 a2^2 r^-6 + 72 a2^3 r^-4 + 16 a2^4 r^-2),
+// E = (2 alpha / sqrt(pi)) exp(-alpha^2 r^2), a2 = alpha^2.
+template <int KER>
+__device__ __forceinline__ void gfun_hi(float r2, float rinv, const WalkArgs &A, float &g4, float &g5)
+{
+    const float ri2 = rinv * rinv;
+    if (KER == 0) {
+        const float r9 = rinv * ri2 * ri2 * ri2 * ri2;
+        g4 = 105.f * r9;
+        g5 = -945.f * r9 * ri2;
+    } else {
+        const float r = r2 * rinv, x = A.asplit * r;
+        const float ex = expneg(x * x), ec = erfc_hastings(x, ex);
+        const float E = 2.0f * INV_SQRTPI * A.asplit * ex, a2 = A.asplit * A.asplit;
+        const float r9 = rinv * ri2 * ri2 * ri2 * ri2;
+        g4 = 105.f * ec * r9 + E * ri2 * (8.f * a2 * a2 * a2 + ri2 * (28.f * a2 * a2 + ri2 * (70.f * a2 + ri2 * 105.f)));
+        g5 = -945.f * ec * r9 * ri2 -
+             E * ri2 * (16.f * a2 * a2 * a2 * a2 +
+                        ri2 * (72.f * a2 * a2 * a2 + ri2 * (252.f * a2 * a2 + ri2 * (630.f * a2 + ri2 * 945.f))));
+    }
+}
+
+// Terms of the orders above p = 3 for a node at r from the target (Appendix A):
+// the force adds Q3:D4/6 (p >= 4) and Q4:D5/24 (p = 5), the potential
+// Q4:D4/24 (p >= 4), all with the radial D_n written through g_n:
+//   Q3:D4 (vector) = 3 g2 t + 3 g3 (T:rr + (t.r) r) + g4 (T.rrr) r,  t_i = T_ikk,
+//   Q4:D5 (vector) = g3 (12 W r + 3 w r) + g4 (4 U.rrr + 6 (r.W.r) r) + g5 (U.rrrr) r,
+//   Q4:D4 (scalar) = 3 g2 w + 6 g3 (r.W.r) + g4 (U.rrrr),  W_ij = U_ijkk, w = W_ii,
+// with T, U the packed third and fourth moments about the node's centre of mass.
+template <int HI, bool POT>
+__device__ __forceinline__ void eval_high(const float *o, const double *u4, float dx, float dy, float dz, float g2,
+                                          float g3, float g4, float g5, float &fx, float &fy, float &fz, float &fp)
+{
+    const float r[3] = {dx, dy, dz};
+    // T:rr and t
+    float T[10];
+#pragma unroll
+    for (int a = 0; a < 10; a++) T[a] = o[a];
+    auto t3 = [&](int i, int j, int k) {
+        const int c[3] = {(i == 0) + (j == 0) + (k == 0), (i == 1) + (j == 1) + (k == 1), (i == 2) + (j == 2) + (k == 2)};
+        return T[ew_idx(c[0], c[1], c[2]) - 10];
+    };
+    float trr[3], tv[3];
+#pragma unroll
+    for (int i = 0; i < 3; i++) {
+        float sacc = 0.f;
+#pragma unroll
+        for (int j = 0; j < 3; j++)
+#pragma unroll
+            for (int k = 0; k < 3; k++) sacc = fmaf(t3(i, j, k), r[j] * r[k], sacc);
+        trr[i] = sacc;
+        tv[i] = t3(i, 0, 0) + t3(i, 1, 1) + t3(i, 2, 2);
+    }
+    const float trrr = dx * trr[0] + dy * trr[1] + dz * trr[2], tr = dx * tv[0] + dy * tv[1] + dz * tv[2];
+    const float c4 = (3.f * g3 * tr + g4 * trrr) * (1.f / 6.f);
+    fx += 0.5f * (g2 * tv[0] + g3 * trr[0]) + c4 * dx;
+    fy += 0.5f * (g2 * tv[1] + g3 * trr[1]) + c4 * dy;
+    fz += 0.5f * (g2 * tv[2] + g3 * trr[2]) + c4 * dz;
+    // fourth moments: W, w, V_ij = U_ijkl r_k r_l
+    float U[15];
+#pragma unroll
+    for (int a = 0; a < 15; a++) U[a] = (float)u4[a];
+    auto u = [&](int i, int j, int k, int l) {
+        const int c[3] = {(i == 0) + (j == 0) + (k == 0) + (l == 0), (i == 1) + (j == 1) + (k == 1) + (l == 1),
+                          (i == 2) + (j == 2) + (k == 2) + (l == 2)};
+        return U[ew_idx(c[0], c[1], c[2]) - 20];
+    };
+    float Wm[3][3], V[3][3];
+#pragma unroll
+    for (int i = 0; i < 3; i++)
+#pragma unroll
+        for (int j = 0; j < 3; j++) {
+            Wm[i][j] = u(i, j, 0, 0) + u(i, j, 1, 1) + u(i, j, 2, 2);
+            float sacc = 0.f;
+#pragma unroll
+            for (int k = 0; k < 3; k++)
+#pragma unroll
+                for (int l = 0; l < 3; l++) sacc = fmaf(u(i, j, k, l), r[k] * r[l], sacc);
+            V[i][j] = sacc;
+        }
+    float wr[3], vr[3];
+#pragma unroll
+    for (int i = 0; i < 3; i++) {
+        wr[i] = Wm[i][0] * dx + Wm[i][1] * dy + Wm[i][2] * dz;
+        vr[i] = V[i][0] * dx + V[i][1] * dy + V[i][2] * dz;
+    }
+    const float w = Wm[0][0] + Wm[1][1] + Wm[2][2];
+    const float rwr = dx * wr[0] + dy * wr[1] + dz * wr[2], urrrr = dx * vr[0] + dy * vr[1] + dz * vr[2];
+    if (HI >= 5) {
+        const float c5 = (3.f * g3 * w + 6.f * g4 * rwr + g5 * urrrr) * (1.f / 24.f);
+        fx += (12.f * g3 * wr[0] + 4.f * g4 * vr[0]) * (1.f / 24.f) + c5 * dx;
+        fy += (12.f * g3 * wr[1] + 4.f * g4 * vr[1]) * (1.f / 24.f) + c5 * dy;
+        fz += (12.f * g3 * wr[2] + 4.f * g4 * vr[2]) * (1.f / 24.f) + c5 * dz;
+    }
+    if (POT) fp += (3.f * g2 * w + 6.f * g3 * rwr + g4 * urrrr) * (1.f / 24.f);
 }
 
 // ---------------------------------------------------------------------------
@@ -193,7 +295,7 @@ __device__ __forceinline__ void lds_add(double *p, double v)
 }
 
 // 64 particle-node interactions from the node ring, one per lane (lanes >= n idle).
-template <int KER, bool POT, bool ORD3>
+template <int KER, bool POT, bool ORD3, int HI = 0>
 __device__ __forceinline__ void eval_p2m(const WalkArgs &A, WaveLds<POT> &W, uint32_t head, uint32_t n, int lane)
 {
     if ((uint32_t)lane >= n) return;
@@ -243,6 +345,12 @@ __device__ __forceinline__ void eval_p2m(const WalkArgs &A, WaveLds<POT> &W, uin
         fz = fac * dz;
         if (POT) fp = mass * g0 + 0.5f * (g1 * tr + g2 * rqr);
     }
+    if constexpr (HI >= 4) {
+        float g4, g5;
+        gfun_hi<KER>(r2, rinv, A, g4, g5);
+        eval_high<HI, POT>(A.q3 + (size_t)node * 10, A.q4 + (size_t)node * 15, dx, dy, dz, g2, g3, g4, g5, fx, fy,
+                           fz, fp);
+    }
     if constexpr (KER == 3) {
         // the other images: g = 1/r - psi, so the node adds +f (force) and +phi_psi (potential)
         float cx, cy, cz, cp = 0.f;
@@ -259,8 +367,9 @@ __device__ __forceinline__ void eval_p2m(const WalkArgs &A, WaveLds<POT> &W, uin
     if constexpr (POT) lds_add(&W.acc[3][t], -(double)fp);
 }
 
-// ORD3: p = 3, the force includes the quadrupole term (p = 2: monopole force)
-template <int KER, int CRIT, bool POT, bool ORD3>
+// ORD3: p = 3, the force includes the quadrupole term (p = 2: monopole force);
+// HI = 4 or 5: the orders above (ORD3 set as well)
+template <int KER, int CRIT, bool POT, bool ORD3, int HI = 0>
 __global__ __launch_bounds__(256) void k_walk(const WalkArgs A)
 {
     __shared__ WaveLds<POT> lds[4];
@@ -419,7 +528,7 @@ __global__ __launch_bounds__(256) void k_walk(const WalkArgs A)
             r.cz = nd.cz;
             if (level == 0) r.crit = __builtin_huge_valf();
             else if (CRIT == 0) r.crit = l * l;
-            else r.crit = nd.mass * (ORD3 ? l * l * l : l * l);
+            else r.crit = nd.mass * (HI == 5 ? l * l * l * l * l : (HI == 4 ? l * l * l * l : (ORD3 ? l * l * l : l * l)));
             r.gx = nd.gx;
             r.gy = nd.gy;
             r.gz = nd.gz;
@@ -466,7 +575,8 @@ __global__ __launch_bounds__(256) void k_walk(const WalkArgs A)
                 accept = accept && (R.crit < A.theta2 * r2);
             } else {
                 // M (l/r)^p / r^2 < alpha |a|  <=>  M l^p < alpha |a| r^(p+2)
-                const float rp = ORD3 ? r2 * r2 * r2 * rinv : r2 * r2;
+                const float rp = HI == 5 ? r2 * r2 * r2 * r2 * rinv
+                                         : (HI == 4 ? r2 * r2 * r2 : (ORD3 ? r2 * r2 * r2 * rinv : r2 * r2));
                 accept = accept && (R.crit < __uint_as_float(T.w) * rp);
             }
             const bool use = ok && accept;
@@ -500,7 +610,7 @@ __global__ __launch_bounds__(256) void k_walk(const WalkArgs A)
             w_pass++;
             if (pm_t - pm_h >= 64) {
                 wave_sync_lds();
-                eval_p2m<KER, POT, ORD3>(A, W, pm_h, 64u, lane);
+                eval_p2m<KER, POT, ORD3, HI>(A, W, pm_h, 64u, lane);
                 pm_h += 64;
                 w_pm++;
             }
@@ -544,7 +654,7 @@ __global__ __launch_bounds__(256) void k_walk(const WalkArgs A)
     wave_sync_lds();
     while (pm_t != pm_h) {
         const uint32_t n = min(pm_t - pm_h, 64u);
-        eval_p2m<KER, POT, ORD3>(A, W, pm_h, n, lane);
+        eval_p2m<KER, POT, ORD3, HI>(A, W, pm_h, n, lane);
         pm_h += n;
         w_pm++;
     }
@@ -600,6 +710,16 @@ static void launch_walk(const WalkArgs &A, hipStream_t s)
     int64_t blocks = ((int64_t)A.nitems + 3) / 4;
     if (blocks > A.spill_waves / 4) blocks = A.spill_waves / 4;
     if (blocks < 1) blocks = 1;
+    if constexpr (KER <= 1) {
+        if (A.order == 5) {
+            k_walk<KER, CRIT, POT, true, 5><<<(unsigned)blocks, 256, 0, s>>>(A);
+            return;
+        }
+        if (A.order == 4) {
+            k_walk<KER, CRIT, POT, true, 4><<<(unsigned)blocks, 256, 0, s>>>(A);
+            return;
+        }
+    }
     if (A.order >= 3) k_walk<KER, CRIT, POT, true><<<(unsigned)blocks, 256, 0, s>>>(A);
     else k_walk<KER, CRIT, POT, false><<<(unsigned)blocks, 256, 0, s>>>(A);
 }
@@ -664,6 +784,7 @@ int g4_launch_walk(g4_ctx *ctx, g4_tree *t, const g4_walk_params *wp, int kernel
         G4_HIP(ctx, hipGetLastError());
         t->tab_n = wp->sr_table;
     }
+    A.q4 = t->q4d;
     A.ew = static_cast<const float *>(wp->ewald_table);
     A.ew_n = wp->ewald_n;
     A.ew_h = kernel == 2 ? (float)(0.5 * t->tp.box / wp->ewald_n) : 0.f;

@@ -103,6 +103,7 @@ _SIGS = {
                     C.POINTER(g4_kdk_stats)],
     "g4_pm_longrange": [_p, _p, C.POINTER(g4_pm_params), _p, _sz, _i32, _p, _p, _p, _p],
     "g4_ewald_table": [_p, C.c_double, _i32, _p, _sz],
+    "g4_compute_moments4": [_p, _p, _p, _sz],
     "g4_ewald_eval": [_p, _p, _i32, C.c_double, _i64, _p, _p, _p, _p, _p, _p, _p],
     "g4_fmm_workspace_bytes": [_p, C.POINTER(g4_fmm_params), C.c_double, C.POINTER(_sz)],
     "g4_forest_workspace_bytes": [C.POINTER(g4_tree_params), _i32, _i64, C.POINTER(_sz)],
@@ -123,13 +124,15 @@ _L.g4_last_error.argtypes = [_p]
 _L.g4_last_error.restype = C.c_char_p
 _L.g4_ewald_table_bytes.argtypes = [_i32]
 _L.g4_ewald_table_bytes.restype = _sz
+_L.g4_moments4_bytes.argtypes = [_p]
+_L.g4_moments4_bytes.restype = _sz
 
 OPTIONAL_SYMBOLS = []  # filled by extensions below when present
 
 
 def exported_symbols():
     """Names of the entry points this binding found in the library."""
-    return sorted(_SIGS) + ["g4_last_error", "g4_ewald_table_bytes"] + OPTIONAL_SYMBOLS
+    return sorted(_SIGS) + ["g4_last_error", "g4_ewald_table_bytes", "g4_moments4_bytes"] + OPTIONAL_SYMBOLS
 
 
 class G4Error(RuntimeError):
@@ -325,6 +328,17 @@ def pm_params(ng, r_s, G=1.0):
     pp = g4_pm_params()
     pp.ng, pp.r_s, pp.G = int(ng), float(r_s), float(G)
     return pp
+
+
+def g4_compute_moments4(ctx, tree):
+    """Fourth moments of every node (for walks at p = 4, 5); the buffer is
+    kept on the tree object."""
+    nbytes = int(_L.g4_moments4_bytes(tree.h))
+    buf = torch.empty(nbytes + 256, dtype=torch.uint8, device=ctx.device)
+    off = (-buf.data_ptr()) % 256
+    ctx.check(_L.g4_compute_moments4(ctx.h, tree.h, C.c_void_p(buf.data_ptr() + off), nbytes))
+    tree._moments4 = buf
+    return buf
 
 
 class EwaldTable:
