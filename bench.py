@@ -75,6 +75,7 @@ def parse():
     ap.add_argument("--no-pm", action="store_true", help="skip the total TreePM (walk + PM) line")
     ap.add_argument("--no-kdk", action="store_true", help="skip the hierarchical time-integration line")
     ap.add_argument("--no-ewald", action="store_true", help="skip the periodic tree + Ewald line")
+    ap.add_argument("--no-orders", action="store_true", help="skip the expansion-order (p = 3, 4, 5) comparison")
     ap.add_argument("--err-sample", type=int, default=10000)
     ap.add_argument("--group", type=int, default=64)
     ap.add_argument("--leaf", type=int, default=24, help="leaf size B of the tree")
@@ -178,14 +179,16 @@ class TreePMCase:
         self.ref = None
         self.tg = None
 
-    def params(self, variant, alpha, r_cut=None):
+    def params(self, variant, alpha, r_cut=None, order=3):
+        """Walk parameters (pre-walk, relative walk); `order` is the relative
+        walk's expansion order p (the pre-walk stays at p = 3)."""
         g, a = self.g, self.args
         kw = dict(kernel=1, r_s=self.r_s, r_cut=self.r_cut if r_cut is None else r_cut, eps0=self.eps0,
                   group_size=a.group, sr_table=a.sr_table)
         if variant == "plain":
             return (g.walk_params(criterion=0, theta=0.7, **kw),
-                    g.walk_params(criterion=1, alpha=alpha, seed_from_tree=1, **kw))
-        return (None, g.walk_params(criterion=1, alpha=alpha, a_seed=self.learned["aseed"], **kw))
+                    g.walk_params(criterion=1, alpha=alpha, seed_from_tree=1, order=order, **kw))
+        return (None, g.walk_params(criterion=1, alpha=alpha, a_seed=self.learned["aseed"], order=order, **kw))
 
     def step(self, variant, wps, evs=None, want_stats=False):
         """One pass of the path; evs: 4 events (start, after moments, after seed, after walk)."""
@@ -196,6 +199,11 @@ class TreePMCase:
         p = g.particles(x, y, z, self.mass)
         tree = g.g4_build_tree(ctx, p, self.tp, ws=self.ws)
         g.g4_compute_multipoles(ctx, tree, 3)
+        if wps[1].order >= 4:
+            import torch
+            if self.state.get("m4") is None:
+                self.state["m4"] = torch.empty(g.g4_moments4_bytes(tree) + 256, dtype=torch.uint8, device=ctx.device)
+            g.g4_compute_moments4(ctx, tree, ws=self.state["m4"])
         if evs is not None:
             evs[1].record(self.stream)
         seed_stats = None
@@ -235,11 +243,11 @@ class TreePMCase:
         a = torch.stack(self.outs, 1)[self.tg].cpu().numpy()
         return workloads.percentiles(workloads.relative_errors(a, ref))
 
-    def calibrate(self, variant, fixed=0.0):
+    def calibrate(self, variant, fixed=0.0, order=3):
         cal, chosen = {}, None
         for a in ((fixed,) if fixed > 0 else ALPHAS):
-            cal[a] = self.errors(variant, self.params(variant, a))
-            log(f"[bench] n={self.n} {variant} alpha={a}: {cal[a]}")
+            cal[a] = self.errors(variant, self.params(variant, a, order=order))
+            log(f"[bench] n={self.n} {variant} p={order} alpha={a}: {cal[a]}")
             if cal[a]["p99"] <= ERR_BOUND or fixed > 0:
                 chosen = a
                 break
@@ -414,6 +422,8 @@ def main():
             log(f"[bench] as stated (128^3, R_cut 4.5, alpha 0.005): {ms45:.3f} ms/step, errors {e45}")
         if not args.no_pm:
             result["treepm_total_128^3"] = bench_total_treepm(args, g, ctx, small)
+        if not args.no_orders:
+            result["orders_128^3"] = bench_orders(args, small)
         small.free()
         del small
     if not args.no_fmm:
@@ -427,6 +437,29 @@ def main():
     if not args.no_cpu_baseline:
         result["cpu_baseline"] = cpu_baseline(*cpu_input, args)
     print(json.dumps(result), flush=True)
+
+
+def bench_orders(args, case):
+    """The relative TreePM walk at expansion orders p = 3, 4, 5 on the 128^3
+    box (geometric pre-walk seeds, the pre-walk at p = 3), each at the largest
+    alpha of the grid whose p99 error against the FP64 direct sum is <= 1e-3:
+    a higher order costs more per interaction and allows a larger alpha."""
+    out = {}
+    for order in (3, 4, 5):
+        alpha, cal = case.calibrate("plain", order=order)
+        if alpha is None:
+            out[f"p{order}"] = {"error": "no alpha in the grid met the error bound"}
+            continue
+        wps = case.params("plain", alpha, order=order)
+        ms, ph = case.timed("plain", wps, max(3, args.steps // 2), 1)
+        _, st = case.step("plain", wps, want_stats=True)
+        n = case.n
+        out[f"p{order}"] = {"alpha": alpha, "ms_per_step": ms, "walk_ms": ph["walk_ms"],
+                            "errors_vs_direct": cal[alpha],
+                            "per_particle": {"p2p": st["n_p2p"] / n, "p2m": st["n_p2m"] / n}}
+        log(f"[bench] 128^3 plain p={order}: {ms:.3f} ms/step at alpha {alpha} (walk {ph['walk_ms']:.3f} ms), "
+            f"p2m {st['n_p2m'] / n:.0f}, p2p {st['n_p2p'] / n:.0f} per particle")
+    return out
 
 
 def bench_total_treepm(args, g, ctx, case):

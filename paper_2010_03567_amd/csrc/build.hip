@@ -683,32 +683,36 @@ __device__ __forceinline__ int m4_idx(int a, int b, int c)
     return (b + c) * (b + c + 1) / 2 + c;
 }
 
-__global__ void k_moments4(const DevCounters *__restrict__ C, const uint4 *__restrict__ parts,
-                           const WNode *__restrict__ wn, const double *__restrict__ mom, double *__restrict__ q4,
-                           int level, double unit)
+__global__ __launch_bounds__(128) void k_moments4(const DevCounters *__restrict__ C, const uint4 *__restrict__ parts,
+                                                  const WNode *__restrict__ wn, const double *__restrict__ mom,
+                                                  double *__restrict__ q4, int level, double unit)
 {
     const uint32_t beg = C->lvl_start[level], end = beg + C->lvl_count[level];
-    const double binom[5][5] = {{1, 0, 0, 0, 0}, {1, 1, 0, 0, 0}, {1, 2, 1, 0, 0}, {1, 3, 3, 1, 0}, {1, 4, 6, 4, 1}};
+    constexpr double binom[5][5] = {{1, 0, 0, 0, 0}, {1, 1, 0, 0, 0}, {1, 2, 1, 0, 0}, {1, 3, 3, 1, 0}, {1, 4, 6, 4, 1}};
     for (uint32_t q = beg + blockIdx.x * blockDim.x + threadIdx.x; q < end; q += gridDim.x * blockDim.x) {
         const WNode w = wn[q];
         const double *mo = mom + (size_t)q * MOM_STRIDE;
         double Q[15];
+#pragma unroll
         for (int k = 0; k < 15; k++) Q[k] = 0.0;
         if (w.meta & WN_LEAF) {
             for (uint32_t j = w.next; j < w.next + w.num; j++) {
                 const uint4 p = parts[j];
                 const double m = (double)__uint_as_float(p.w);
-                const double d[3] = {(double)(int32_t)(p.x - w.gx) * unit - mo[1], (double)(int32_t)(p.y - w.gy) * unit - mo[2],
+                const double d[3] = {(double)(int32_t)(p.x - w.gx) * unit - mo[1],
+                                     (double)(int32_t)(p.y - w.gy) * unit - mo[2],
                                      (double)(int32_t)(p.z - w.gz) * unit - mo[3]};
+                double pw[3][5];
+#pragma unroll
+                for (int k = 0; k < 3; k++) {
+                    pw[k][0] = 1.0;
+#pragma unroll
+                    for (int e = 1; e < 5; e++) pw[k][e] = pw[k][e - 1] * d[k];
+                }
+#pragma unroll
                 for (int a = 4; a >= 0; a--)
-                    for (int b = 4 - a; b >= 0; b--) {
-                        const int c = 4 - a - b;
-                        double v = m;
-                        for (int k = 0; k < a; k++) v *= d[0];
-                        for (int k = 0; k < b; k++) v *= d[1];
-                        for (int k = 0; k < c; k++) v *= d[2];
-                        Q[m4_idx(a, b, c)] += v;
-                    }
+#pragma unroll
+                    for (int b = 4 - a; b >= 0; b--) Q[m4_idx(a, b, 4 - a - b)] += m * pw[0][a] * pw[1][b] * pw[2][4 - a - b];
             }
         } else {
             for (uint32_t ch = w.next; ch < w.next + w.num; ch++) {
@@ -718,30 +722,43 @@ __global__ void k_moments4(const DevCounters *__restrict__ C, const uint4 *__res
                 const double d[3] = {(double)(int32_t)(wc.gx - w.gx) * unit + mc[1] - mo[1],
                                      (double)(int32_t)(wc.gy - w.gy) * unit + mc[2] - mo[2],
                                      (double)(int32_t)(wc.gz - w.gz) * unit + mc[3] - mo[3]};
+                double pw[3][5], qc[5][15];
+#pragma unroll
+                for (int k = 0; k < 3; k++) {
+                    pw[k][0] = 1.0;
+#pragma unroll
+                    for (int e = 1; e < 5; e++) pw[k][e] = pw[k][e - 1] * d[k];
+                }
+                // the child's moments by order: mass, (no dipole), Q2, Q3, Q4 (packed)
+                qc[0][0] = mc[0];
+#pragma unroll
+                for (int k = 0; k < 6; k++) qc[2][k] = mc[4 + k];
+#pragma unroll
+                for (int k = 0; k < 10; k++) qc[3][k] = mc[10 + k];
+#pragma unroll
+                for (int k = 0; k < 15; k++) qc[4][k] = qc4[k];
+#pragma unroll
                 for (int a = 4; a >= 0; a--)
+#pragma unroll
                     for (int b = 4 - a; b >= 0; b--) {
                         const int c = 4 - a - b;
                         double sum = 0.0;
-                        for (int ba = 0; ba <= a; ba++)
-                            for (int bb = 0; bb <= b; bb++)
-                                for (int bc = 0; bc <= c; bc++) {
+#pragma unroll
+                        for (int ba = 0; ba <= 4; ba++)
+#pragma unroll
+                            for (int bb = 0; bb <= 4; bb++)
+#pragma unroll
+                                for (int bc = 0; bc <= 4; bc++) {
                                     const int n = ba + bb + bc;
-                                    double qv;
-                                    if (n == 0) qv = mc[0];
-                                    else if (n == 1) continue;
-                                    else if (n == 2) qv = mc[4 + m4_idx(ba, bb, bc)];
-                                    else if (n == 3) qv = mc[10 + m4_idx(ba, bb, bc)];
-                                    else qv = qc4[m4_idx(ba, bb, bc)];
-                                    double v = binom[a][ba] * binom[b][bb] * binom[c][bc] * qv;
-                                    for (int k = 0; k < a - ba; k++) v *= d[0];
-                                    for (int k = 0; k < b - bb; k++) v *= d[1];
-                                    for (int k = 0; k < c - bc; k++) v *= d[2];
-                                    sum += v;
+                                    if (ba > a || bb > b || bc > c || n == 1) continue;
+                                    sum += binom[a][ba] * binom[b][bb] * binom[c][bc] * qc[n][m4_idx(ba, bb, bc)] *
+                                           pw[0][a - ba] * pw[1][b - bb] * pw[2][c - bc];
                                 }
                         Q[m4_idx(a, b, c)] += sum;
                     }
             }
         }
+#pragma unroll
         for (int k = 0; k < 15; k++) q4[(size_t)q * 15 + k] = Q[k];
     }
 }
@@ -749,7 +766,8 @@ __global__ void k_moments4(const DevCounters *__restrict__ C, const uint4 *__res
 int g4_launch_moments4(g4_ctx *ctx, g4_tree *t, double *q4)
 {
     const int maxd = t->tp.max_depth < 1 ? 1 : (t->tp.max_depth > G4_MAXLEV ? G4_MAXLEV : t->tp.max_depth);
-    for (int l = maxd; l >= 0; l--) k_moments4<<<1024, 128, 0, ctx->stream>>>(t->ctr, t->parts, t->wn, t->mom, q4, l, t->unit);
+    for (int l = maxd; l >= 0; l--)
+        k_moments4<<<2048, 128, 0, ctx->stream>>>(t->ctr, t->parts, t->wn, t->mom, q4, l, t->unit);
     G4_HIP(ctx, hipGetLastError());
     return G4_OK;
 }

@@ -106,45 +106,48 @@ __device__ __forceinline__ void gfun(float r2, float rinv, const WalkArgs &A, fl
     }
 }
 
-// g4 and g5 of the Newtonian or short-range kernel (orders p = 4, 5):
-// Newtonian g4 = 105/r^9, g5 = -945/r^11; short range from the recursion
-// g_{n+1} = r^-1 d g_n/dr applied to erfc(alpha r)/r:
-//   g4 = 105 erfc r^-9 + E (105 r^-8 + 70 a2 r^-6 + 28 a2^2 r^-4 + 8 a2^3 r^-2),
-//   g5 = -945 erfc r^-11 - E (945 r^-10 + 630 a2 r^-8 + 252 a2^2 r^-6 + 72 a2^3 r^-4 + 16 a2^4 r^-2),
-// E = (2 alpha / sqrt(pi)) exp(-alpha^2 r^2), a2 = alpha^2.
+// Dimensionless s_n = g_n r^(2n+1), n = 2..5, of the Newtonian kernel
+// ((-1)^n (2n-1)!!) or of erfc(alpha r)/r, from the recursion
+// g_{n+1} = r^-1 d g_n/dr; with x = alpha r and e = (2/sqrt(pi)) exp(-x^2):
+//   s2 = 3 erfc(x) + e (3x + 2x^3),  s3 = -15 erfc(x) - e (15x + 10x^3 + 4x^5),
+//   s4 = 105 erfc(x) + e (105x + 70x^3 + 28x^5 + 8x^7),
+//   s5 = -945 erfc(x) - e (945x + 630x^3 + 252x^5 + 72x^7 + 16x^9).
+// The orders above p = 3 are written with them and the unit vector of r, the
+// power of 1/r applied last: g5 itself (~ 1/r^11) leaves the FP32 range at the
+// node distances of a 128^3 box.
 template <int KER>
-__device__ __forceinline__ void gfun_hi(float r2, float rinv, const WalkArgs &A, float &g4, float &g5)
+__device__ __forceinline__ void sfun_hi(float r, const WalkArgs &A, float &s2, float &s3, float &s4, float &s5)
 {
-    const float ri2 = rinv * rinv;
     if (KER == 0) {
-        const float r9 = rinv * ri2 * ri2 * ri2 * ri2;
-        g4 = 105.f * r9;
-        g5 = -945.f * r9 * ri2;
+        s2 = 3.f;
+        s3 = -15.f;
+        s4 = 105.f;
+        s5 = -945.f;
     } else {
-        const float r = r2 * rinv, x = A.asplit * r;
-        const float ex = expneg(x * x), ec = erfc_hastings(x, ex);
-        const float E = 2.0f * INV_SQRTPI * A.asplit * ex, a2 = A.asplit * A.asplit;
-        const float r9 = rinv * ri2 * ri2 * ri2 * ri2;
-        g4 = 105.f * ec * r9 + E * ri2 * (8.f * a2 * a2 * a2 + ri2 * (28.f * a2 * a2 + ri2 * (70.f * a2 + ri2 * 105.f)));
-        g5 = -945.f * ec * r9 * ri2 -
-             E * ri2 * (16.f * a2 * a2 * a2 * a2 +
-                        ri2 * (72.f * a2 * a2 * a2 + ri2 * (252.f * a2 * a2 + ri2 * (630.f * a2 + ri2 * 945.f))));
+        const float x = A.asplit * r, x2 = x * x;
+        const float ex = expneg(x2), ec = erfc_hastings(x, ex);
+        const float e = 2.0f * INV_SQRTPI * ex * x;
+        s2 = 3.f * ec + e * (3.f + 2.f * x2);
+        s3 = -15.f * ec - e * (15.f + x2 * (10.f + 4.f * x2));
+        s4 = 105.f * ec + e * (105.f + x2 * (70.f + x2 * (28.f + 8.f * x2)));
+        s5 = -945.f * ec - e * (945.f + x2 * (630.f + x2 * (252.f + x2 * (72.f + 16.f * x2))));
     }
 }
 
-// Terms of the orders above p = 3 for a node at r from the target (Appendix A):
-// the force adds Q3:D4/6 (p >= 4) and Q4:D5/24 (p = 5), the potential
-// Q4:D4/24 (p >= 4), all with the radial D_n written through g_n:
-//   Q3:D4 (vector) = 3 g2 t + 3 g3 (T:rr + (t.r) r) + g4 (T.rrr) r,  t_i = T_ikk,
-//   Q4:D5 (vector) = g3 (12 W r + 3 w r) + g4 (4 U.rrr + 6 (r.W.r) r) + g5 (U.rrrr) r,
-//   Q4:D4 (scalar) = 3 g2 w + 6 g3 (r.W.r) + g4 (U.rrrr),  W_ij = U_ijkk, w = W_ii,
+// Terms of the orders above p = 3 for a node at r = |r| n from the target
+// (Appendix A): the force adds Q3:D4/6 (p >= 4) and Q4:D5/24 (p = 5), the
+// potential Q4:D4/24 (p >= 4), with the radial D_n written through s_n:
+//   Q3:D4 = r^-5 [3 s2 t + 3 s3 (T:nn + (t.n) n) + s4 (T.nnn) n],  t_i = T_ikk,
+//   Q4:D5 = r^-6 [12 s3 W n + 3 s3 w n + 4 s4 U.nnn + 6 s4 (n.W.n) n + s5 (U.nnnn) n],
+//   Q4:D4 = r^-5 [3 s2 w + 6 s3 (n.W.n) + s4 (U.nnnn)],  W_ij = U_ijkk, w = W_ii,
 // with T, U the packed third and fourth moments about the node's centre of mass.
 template <int HI, bool POT>
-__device__ __forceinline__ void eval_high(const float *o, const double *u4, float dx, float dy, float dz, float g2,
-                                          float g3, float g4, float g5, float &fx, float &fy, float &fz, float &fp)
+__device__ __forceinline__ void eval_high(const float *o, const double *u4, float nx, float ny, float nz, float rinv,
+                                          float s2, float s3, float s4, float s5, float &fx, float &fy, float &fz,
+                                          float &fp)
 {
-    const float r[3] = {dx, dy, dz};
-    // T:rr and t
+    const float n[3] = {nx, ny, nz};
+    const float ri2 = rinv * rinv, r5 = ri2 * ri2 * rinv, r6 = ri2 * ri2 * ri2;
     float T[10];
 #pragma unroll
     for (int a = 0; a < 10; a++) T[a] = o[a];
@@ -152,23 +155,23 @@ __device__ __forceinline__ void eval_high(const float *o, const double *u4, floa
         const int c[3] = {(i == 0) + (j == 0) + (k == 0), (i == 1) + (j == 1) + (k == 1), (i == 2) + (j == 2) + (k == 2)};
         return T[ew_idx(c[0], c[1], c[2]) - 10];
     };
-    float trr[3], tv[3];
+    float tnn[3], tv[3];
 #pragma unroll
     for (int i = 0; i < 3; i++) {
         float sacc = 0.f;
 #pragma unroll
         for (int j = 0; j < 3; j++)
 #pragma unroll
-            for (int k = 0; k < 3; k++) sacc = fmaf(t3(i, j, k), r[j] * r[k], sacc);
-        trr[i] = sacc;
+            for (int k = 0; k < 3; k++) sacc = fmaf(t3(i, j, k), n[j] * n[k], sacc);
+        tnn[i] = sacc;
         tv[i] = t3(i, 0, 0) + t3(i, 1, 1) + t3(i, 2, 2);
     }
-    const float trrr = dx * trr[0] + dy * trr[1] + dz * trr[2], tr = dx * tv[0] + dy * tv[1] + dz * tv[2];
-    const float c4 = (3.f * g3 * tr + g4 * trrr) * (1.f / 6.f);
-    fx += 0.5f * (g2 * tv[0] + g3 * trr[0]) + c4 * dx;
-    fy += 0.5f * (g2 * tv[1] + g3 * trr[1]) + c4 * dy;
-    fz += 0.5f * (g2 * tv[2] + g3 * trr[2]) + c4 * dz;
-    // fourth moments: W, w, V_ij = U_ijkl r_k r_l
+    const float tnnn = nx * tnn[0] + ny * tnn[1] + nz * tnn[2], tn = nx * tv[0] + ny * tv[1] + nz * tv[2];
+    const float c4 = (3.f * s3 * tn + s4 * tnnn) * (1.f / 6.f);
+    const float h5 = r5;
+    fx += h5 * (0.5f * (s2 * tv[0] + s3 * tnn[0]) + c4 * nx);
+    fy += h5 * (0.5f * (s2 * tv[1] + s3 * tnn[1]) + c4 * ny);
+    fz += h5 * (0.5f * (s2 * tv[2] + s3 * tnn[2]) + c4 * nz);
     float U[15];
 #pragma unroll
     for (int a = 0; a < 15; a++) U[a] = (float)u4[a];
@@ -187,24 +190,24 @@ __device__ __forceinline__ void eval_high(const float *o, const double *u4, floa
 #pragma unroll
             for (int k = 0; k < 3; k++)
 #pragma unroll
-                for (int l = 0; l < 3; l++) sacc = fmaf(u(i, j, k, l), r[k] * r[l], sacc);
+                for (int l = 0; l < 3; l++) sacc = fmaf(u(i, j, k, l), n[k] * n[l], sacc);
             V[i][j] = sacc;
         }
-    float wr[3], vr[3];
+    float wn[3], vn[3];
 #pragma unroll
     for (int i = 0; i < 3; i++) {
-        wr[i] = Wm[i][0] * dx + Wm[i][1] * dy + Wm[i][2] * dz;
-        vr[i] = V[i][0] * dx + V[i][1] * dy + V[i][2] * dz;
+        wn[i] = Wm[i][0] * nx + Wm[i][1] * ny + Wm[i][2] * nz;
+        vn[i] = V[i][0] * nx + V[i][1] * ny + V[i][2] * nz;
     }
     const float w = Wm[0][0] + Wm[1][1] + Wm[2][2];
-    const float rwr = dx * wr[0] + dy * wr[1] + dz * wr[2], urrrr = dx * vr[0] + dy * vr[1] + dz * vr[2];
+    const float nwn = nx * wn[0] + ny * wn[1] + nz * wn[2], unnnn = nx * vn[0] + ny * vn[1] + nz * vn[2];
     if (HI >= 5) {
-        const float c5 = (3.f * g3 * w + 6.f * g4 * rwr + g5 * urrrr) * (1.f / 24.f);
-        fx += (12.f * g3 * wr[0] + 4.f * g4 * vr[0]) * (1.f / 24.f) + c5 * dx;
-        fy += (12.f * g3 * wr[1] + 4.f * g4 * vr[1]) * (1.f / 24.f) + c5 * dy;
-        fz += (12.f * g3 * wr[2] + 4.f * g4 * vr[2]) * (1.f / 24.f) + c5 * dz;
+        const float c5 = (3.f * s3 * w + 6.f * s4 * nwn + s5 * unnnn) * (1.f / 24.f);
+        fx += r6 * ((12.f * s3 * wn[0] + 4.f * s4 * vn[0]) * (1.f / 24.f) + c5 * nx);
+        fy += r6 * ((12.f * s3 * wn[1] + 4.f * s4 * vn[1]) * (1.f / 24.f) + c5 * ny);
+        fz += r6 * ((12.f * s3 * wn[2] + 4.f * s4 * vn[2]) * (1.f / 24.f) + c5 * nz);
     }
-    if (POT) fp += (3.f * g2 * w + 6.f * g3 * rwr + g4 * urrrr) * (1.f / 24.f);
+    if (POT) fp += r5 * (3.f * s2 * w + 6.f * s3 * nwn + s4 * unnnn) * (1.f / 24.f);
 }
 
 // ---------------------------------------------------------------------------
@@ -346,10 +349,10 @@ __device__ __forceinline__ void eval_p2m(const WalkArgs &A, WaveLds<POT> &W, uin
         if (POT) fp = mass * g0 + 0.5f * (g1 * tr + g2 * rqr);
     }
     if constexpr (HI >= 4) {
-        float g4, g5;
-        gfun_hi<KER>(r2, rinv, A, g4, g5);
-        eval_high<HI, POT>(A.q3 + (size_t)node * 10, A.q4 + (size_t)node * 15, dx, dy, dz, g2, g3, g4, g5, fx, fy,
-                           fz, fp);
+        float s2, s3, s4, s5;
+        sfun_hi<KER>(r2 * rinv, A, s2, s3, s4, s5);
+        eval_high<HI, POT>(A.q3 + (size_t)node * 10, A.q4 + (size_t)node * 15, dx * rinv, dy * rinv, dz * rinv, rinv,
+                           s2, s3, s4, s5, fx, fy, fz, fp);
     }
     if constexpr (KER == 3) {
         // the other images: g = 1/r - psi, so the node adds +f (force) and +phi_psi (potential)

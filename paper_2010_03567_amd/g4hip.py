@@ -330,11 +330,17 @@ def pm_params(ng, r_s, G=1.0):
     return pp
 
 
-def g4_compute_moments4(ctx, tree):
-    """Fourth moments of every node (for walks at p = 4, 5); the buffer is
-    kept on the tree object."""
+def g4_moments4_bytes(tree):
+    return int(_L.g4_moments4_bytes(tree.h))
+
+
+def g4_compute_moments4(ctx, tree, ws=None):
+    """Fourth moments of every node (for walks at p = 4, 5) into `ws` (a uint8
+    device tensor, allocated when missing or too small); the buffer is kept on
+    the tree object."""
     nbytes = int(_L.g4_moments4_bytes(tree.h))
-    buf = torch.empty(nbytes + 256, dtype=torch.uint8, device=ctx.device)
+    buf = ws if ws is not None and ws.numel() >= nbytes + 256 else torch.empty(nbytes + 256, dtype=torch.uint8,
+                                                                                  device=ctx.device)
     off = (-buf.data_ptr()) % 256
     ctx.check(_L.g4_compute_moments4(ctx.h, tree.h, C.c_void_p(buf.data_ptr() + off), nbytes))
     tree._moments4 = buf
