@@ -737,7 +737,50 @@ def bench_fmm(args, g, ctx, flops):
     out = case(16, True)
     if args.fmm_leaf != 16:
         out["tuned_leaf"] = case(args.fmm_leaf, False)
+    out["relative_criterion"] = fmm_relative(args, g, ctx, pos, mass, n, r_s, eps0, tg, ref["a"])
     return out
+
+
+def fmm_relative(args, g, ctx, pos, mass, n, r_s, eps0, tg, ref):
+    """The FMM with the relative node-node criterion at leaf 32 (seeds: |a| of
+    a geometric FMM call on the same box), at alpha 0.004 and 0.002, errors on
+    the same targets."""
+    import torch
+    import workloads
+    dev = ctx.device
+    tp = g.tree_params(True, 1.0, leaf_max=32)
+    ws = torch.empty(g.g4_workspace_bytes(tp, n) + 256, dtype=torch.uint8, device=dev)
+    base = dict(kernel=1, theta=0.5, r_s=r_s, r_cut=4.5 * r_s, eps0=eps0)
+    st = {"factor": 1.0, "fws": None}
+
+    def call(fp):
+        x, y, z = g.g4_quantize(ctx, pos, tp)
+        t = g.g4_build_tree(ctx, g.particles(x, y, z, mass), tp, ws=ws)
+        g.g4_compute_multipoles(ctx, t, 3)
+        o = g.g4_fmm_force(ctx, t, fp, list_factor=st["factor"], ws=st["fws"], want_stats=True)
+        st["factor"], st["fws"] = o["list_factor"], o["ws"]
+        return o
+
+    o = call(g.fmm_params(**base))
+    seed = torch.sqrt(o["ax"] ** 2 + o["ay"] ** 2 + o["az"] ** 2).float()
+    res = {}
+    for alpha in (0.004, 0.002):
+        fp = g.fmm_params(criterion=1, alpha=alpha, a_seed=seed, **base)
+        call(fp)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        steps = max(3, args.steps // 2)
+        for _ in range(steps):
+            o = call(fp)
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) * 1e3 / steps
+        a = np.stack([o["ax"].cpu().numpy(), o["ay"].cpu().numpy(), o["az"].cpu().numpy()], 1)
+        err = workloads.percentiles(workloads.relative_errors(a[tg], ref))
+        s = o["stats"]
+        res[str(alpha)] = {"ms_per_step": ms, "errors_vs_direct": err,
+                           "interactions_per_particle": {"pp": s["n_pp"] / n, "pn": s["n_pn"] / n, "nn": s["n_nn"] / n}}
+        log(f"[bench] fmm relative (leaf 32) alpha {alpha}: {ms:.2f} ms/step, errors {err}")
+    return res
 
 
 def bench_forest(args, g, ctx):
