@@ -95,7 +95,7 @@ def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
-WALK_SOURCES = ("walk.hip", "g4_device.h", "g4_internal.h")
+WALK_SOURCES = ("walk.hip", "ewald.h", "g4_device.h", "g4_internal.h")
 
 
 def traffic_file(n):
