@@ -374,8 +374,10 @@ def main():
     for k in ok:
         ok[k].pop("stats", None)
     roof = walk_roofline(flops, st, chosen["phases"]["walk_ms_mean"], n, best, chosen["alpha"], args.leaf)
-    util = {"pop": st["n_visit"] / max(1, 64 * st["w_pop"]), "p2m": st["n_p2m"] / max(1, 64 * st["w_p2m"]),
-            "p2p": st["n_p2p"] / max(1, 64 * st["w_p2p"])}
+    # visit passes carry the pairs the targets decide one by one; pairs decided for a whole group
+    # (used by every target, or dropped by every target) take no visit slot
+    util = {"pop": (st["n_visit"] - st["n_group_use"]) / max(1, 64 * st["w_pop"]),
+            "p2m": st["n_p2m"] / max(1, 64 * st["w_p2m"]), "p2p": st["n_p2p"] / max(1, 64 * st["w_p2p"])}
     side = round(n ** (1 / 3))
     result = {
         "metric": METRIC,
@@ -400,7 +402,9 @@ def main():
         "roofline": roof,
         "walk_counters": {"lane_utilisation": util,
                           "passes": {k: st[k] for k in ("w_pop", "w_p2m", "w_p2p", "w_entry", "w_leaf", "w_chunk",
-                                                        "max_stack")}},
+                                                        "max_stack")},
+                          "group_decided_per_particle": {"use": st["n_group_use"] / n,
+                                                         "drop": st["n_group_drop"] / n}},
     }
     cpu_input = (head.ps, head.r_s, head.r_cut, head.eps0, chosen["alpha"])
     head.free()

@@ -201,10 +201,14 @@ typedef struct {
      * that reads them (any call with stats, every g4_fmm_force) and
      * g4_tree_info return G4_ENOMEM. */
     uint32_t flags;
-    uint32_t max_stack;  /* deepest traversal stack of the walk (entries; the top 32 are kept in LDS) */
+    uint32_t max_stack;  /* deepest traversal stack of the walk (entries; the first 31 are kept in LDS) */
     /* walk bookkeeping: sibling sets popped, (opened leaf, target) items,
      * particle-pair phases of the lane queue */
     uint64_t w_entry, w_leaf, w_chunk;
+    /* (node, target) pairs of the walk decided once for the whole group of
+     * targets: used by every target (included in n_p2m and n_visit), dropped
+     * beyond r_cut by every target (not in n_visit) */
+    uint64_t n_group_use, n_group_drop;
 } g4_stats;
 
 /* ---------------------------------------------------------------- context */

@@ -430,6 +430,8 @@ static int tree_force_impl(g4_ctx *ctx, g4_tree *tree, const g4_walk_params *wp,
         stats->w_entry = h.stat[13];
         stats->w_leaf = h.stat[14];
         stats->w_chunk = h.stat[15];
+        stats->n_group_use = h.stat[16];
+        stats->n_group_drop = h.stat[17];
         if (h.flags & G4_FLAG_WALK_STACK) return g4_set_err(ctx, G4_ENOMEM, "walk traversal stack overflowed");
     }
     return G4_OK;

@@ -213,7 +213,7 @@ __global__ void k_init(DevCounters *C, uint32_t *bfirst, uint32_t *bcount, uint3
         }
         C->lvl_start[0] = 0;
         C->lvl_count[0] = 1;
-        for (int s = 0; s < 16; s++) C->stat[s] = 0;
+        for (int s = 0; s < 18; s++) C->stat[s] = 0;
         bfirst[0] = 0;
         bcount[0] = n;
         parent[0] = 0xffffffffu;
@@ -886,7 +886,7 @@ __global__ void k_init_forest(DevCounters *C, uint32_t *bfirst, uint32_t *bcount
             C->lvl_count[l] = 0;
         }
         C->lvl_count[0] = (uint32_t)nbox;
-        for (int s = 0; s < 16; s++) C->stat[s] = 0;
+        for (int s = 0; s < 18; s++) C->stat[s] = 0;
     }
     if (b < nbox) {
         bfirst[b] = (uint32_t)off[b];

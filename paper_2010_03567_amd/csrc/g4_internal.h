@@ -13,7 +13,7 @@
 // device spill area per wavefront (room for the whole stack, so any LDS share
 // is safe), and the wavefront cap of the persistent walk grid.
 #define G4_WALK_STACK (1 + 7 * (G4_MAXLEV - 1) + 8)
-#define G4_WALK_LDS_STACK 32
+#define G4_WALK_LDS_STACK 31
 #define G4_WALK_SPILL G4_WALK_STACK
 #define G4_WALK_MAX_WAVES 8192
 
@@ -61,8 +61,9 @@ struct DevCounters {
     uint32_t pad;
     uint32_t lvl_start[G4_MAXLEV + 4];  // first node of each level
     uint32_t lvl_count[G4_MAXLEV + 4];  // nodes of each level (children allocated by atomics)
-    unsigned long long stat[16];  // [0..2] walk p2p/p2m/visits, [3..5] seed walk, [6..8] FMM pp/pn/nn,
-                                  // [9..15] walk passes, deepest stack, entries, leaves, chunks
+    unsigned long long stat[18];  // [0..2] walk p2p/p2m/visits, [3..5] seed walk, [6..8] FMM pp/pn/nn,
+                                  // [9..15] walk passes, deepest stack, entries, leaves, chunks,
+                                  // [16..17] walk pairs used / dropped by a decision for the whole group
 };
 
 struct g4_tree {

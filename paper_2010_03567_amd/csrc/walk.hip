@@ -32,7 +32,7 @@ struct WalkArgs {
     int64_t n;
     int group;
     int S;
-    int exclusion;
+    int exclusion;    // bit 0: exclusion zone around each node; bit 1: per-target decisions only (diagnostic)
     int order;
     float unit;       // physical length per integer step
     float box;        // physical root side
@@ -53,7 +53,7 @@ struct WalkArgs {
     uint32_t *counts;
     float *aout_caller, *aout_sorted;
     unsigned long long *stat;   // 3 counters: p2p, p2m, visits
-    unsigned long long *wstat;  // passes, deepest stack, entries, leaves, chunks (slots 9..15)
+    unsigned long long *wstat;  // passes, deepest stack, entries, leaves, chunks, group decisions (slots 9..17)
     const uint4 *items;         // work items (first particle, count, root node), or null: groups of `group`
     uint32_t nitems;
     uint32_t *item_ctr;         // zeroed before the launch
@@ -226,6 +226,12 @@ __device__ __forceinline__ void eval_high(const float *o, const double *u4, floa
 // item's particles for its target, one pair per lane per step, refilling
 // lanes as their items run out, and adds the item's sum once.  Opened internal
 // nodes are collected per child into the masks of new stack entries.
+// Before the visit passes of a large entry, each sibling is tested once
+// against the bounding box of the group's targets: a sibling that every
+// target would use goes straight into the node ring for all targets of the
+// mask, one that every target would drop (beyond r_cut) is skipped, and only
+// the rest get per-target slots.  The bounds reproduce the per-target tests
+// (see group_decision), so every target's decisions are unchanged.
 // ---------------------------------------------------------------------------
 
 // Stack depth bound (entries of 16 bytes; the constants are in g4_internal.h):
@@ -240,6 +246,9 @@ __device__ __forceinline__ void eval_high(const float *o, const double *u4, floa
 #define WK_RING 128  // ring capacity: < 64 pending before an append of <= 64
 
 #define NUM_LEAF (1u << 31)  // leaf bit of VisitRec::numleaf
+// Entries with fewer (child, target) slots than this skip the decisions for the
+// whole group (their cost per entry outweighs the visit passes they save).
+#define WK_GROUP_MIN_SLOTS 128
 
 // Per-child visit record, staged in LDS for the passes over one entry.
 struct __attribute__((aligned(16))) VisitRec {
@@ -248,14 +257,14 @@ struct __attribute__((aligned(16))) VisitRec {
     uint32_t gx, gy, gz;
     int32_t lm1;        // exclusion: cube half-size on the grid minus 1 (-1: no exclusion zone)
     float hl;           // half side (physical)
-    int32_t nlm1;       // -lm1
+    uint32_t node;      // node index
     uint32_t next;      // first child, or first particle of a leaf
     uint32_t numleaf;   // number of children or particles, NUM_LEAF for a leaf
 };
 static_assert(sizeof(VisitRec) == 48, "VisitRec is 48 bytes");
 
-// One wavefront's LDS: 5824 bytes without the potential (7 wavefronts per
-// SIMD fit in the 160 KiB of a CU), 6336 with it.
+// One wavefront's LDS: 5836 bytes without the potential (7 wavefronts per
+// SIMD fit in the 160 KiB of a CU), 6348 with it.
 #define FLAG_OPEN 1
 #define FLAG_USE 2
 template <bool POT>
@@ -270,6 +279,8 @@ struct __attribute__((aligned(16))) WaveLds {
     VisitRec rec[8];               // children of the current entry
     uint8_t flag[8][64];           // flag[j][t]: FLAG_OPEN / FLAG_USE of child j for target t (t in the mask)
     uint8_t rmap[64];              // rank within the entry mask -> lane
+    int32_t gbox[6];               // the group's bounding box: lower x y z, upper x y z (offsets from target 0)
+    float gamin;                   // its smallest alpha |a| (relative criterion); negative: no group decisions
     uint4 stk[WK_LDS_STK];         // (first node, count, mask lo, mask hi), top of the stack
 };
 
@@ -295,6 +306,60 @@ __device__ __forceinline__ void wave_sync_lds()
 __device__ __forceinline__ void lds_add(double *p, double v)
 {
     __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
+}
+
+// M (l/r)^p / r^2 < alpha |a|  <=>  M l^p < alpha |a| r^(p+2): r^(p+2) from r^2 and 1/r
+template <bool ORD3, int HI>
+__device__ __forceinline__ float crit_rpow(float r2, float rinv)
+{
+    return HI == 5 ? r2 * r2 * r2 * r2 * rinv : (HI == 4 ? r2 * r2 * r2 : (ORD3 ? r2 * r2 * r2 * rinv : r2 * r2));
+}
+
+// The decisions of a visit taken once for every target of the group: 1 if
+// every target uses the node, 2 if every target drops it (beyond r_cut), 0 if
+// the targets must decide one by one.  b0, b1: the group's bounding box on the
+// grid as offsets from target 0 (t0); amin: the group's smallest alpha |a|.
+// Each bound evaluates the per-target expression of the visit pass with the
+// box's least (or most) favourable offsets in place of the target's; rounding
+// is monotonic in every operation there, so a bound that passes implies the
+// same outcome for every target.  The one exception, the hardware reciprocal
+// square root of the relative criterion, is covered by a margin of 1e-5.  The
+// offsets of a target are int32 differences modulo 2^32; the bounds apply only
+// where none of them can wrap (node and centre of mass within 2^30 grid steps
+// of target 0, box within 2^29).
+template <int KER, int CRIT, bool ORD3, int HI>
+__device__ __forceinline__ uint32_t group_decision(const WalkArgs &A, const WNode &nd, float crit, float hl,
+                                                   int32_t lm1, uint4 t0, const int32_t *box, float amin)
+{
+    const int32_t lim = 1 << 30;
+    bool safe = true, outside = false;
+    float sn = 0.f, sf = 0.f, r2 = 0.f;  // sums over the axes z, y, x (the visit's order of operations)
+#pragma unroll
+    for (int a = 2; a >= 0; a--) {
+        const int32_t gq = (int32_t)((a == 0 ? nd.gx : a == 1 ? nd.gy : nd.gz) - (a == 0 ? t0.x : a == 1 ? t0.y : t0.z));
+        const int32_t cq = (int32_t)((a == 0 ? nd.cx : a == 1 ? nd.cy : nd.cz) - (a == 0 ? t0.x : a == 1 ? t0.y : t0.z));
+        const int32_t b0 = box[a], b1 = box[3 + a];
+        safe = safe && gq > -lim && gq < lim && cq > -lim && cq < lim;
+        // nearest and farthest offsets of the box from the node's centre, nearest from its centre of mass
+        const int32_t dmin = max(max(b0 - gq, gq - b1), 0);
+        const int32_t dmax = max(gq - b0, b1 - gq);
+        const int32_t cmin = max(max(b0 - cq, cq - b1), 0);
+        outside = outside || dmin > lm1;  // no target inside the exclusion cube
+        const float qn = fmaxf(fmaf((float)dmin, A.unit, -hl), 0.f);
+        const float qf = fmaxf(fmaf((float)dmax, A.unit, -hl), 0.f);
+        const float cm = (float)cmin * A.unit;
+        sn = a == 2 ? qn * qn : fmaf(qn, qn, sn);
+        sf = a == 2 ? qf * qf : fmaf(qf, qf, sf);
+        r2 = a == 2 ? cm * cm : fmaf(cm, cm, r2);
+    }
+    if (!safe) return 0u;
+    if (KER == 1 || KER == 2) {
+        if (sn > A.rcut2) return 2u;
+        if (!(sf <= A.rcut2)) return 0u;
+    }
+    if (!outside || !(r2 >= A.h2)) return 0u;
+    if (CRIT == 0) return crit < A.theta2 * r2 ? 1u : 0u;
+    return crit < (amin * crit_rpow<ORD3, HI>(r2, rsq(r2))) * 0.99999f ? 1u : 0u;
 }
 
 // 64 particle-node interactions from the node ring, one per lane (lanes >= n idle).
@@ -370,10 +435,16 @@ __device__ __forceinline__ void eval_p2m(const WalkArgs &A, WaveLds<POT> &W, uin
     if constexpr (POT) lds_add(&W.acc[3][t], -(double)fp);
 }
 
+// Wavefronts per SIMD the register budget must allow: the LDS of the walks
+// without the potential leaves room for 7, which the Newtonian and TreePM
+// kernels at p <= 3 reach within 72 VGPRs without spilling; the others keep
+// the compiler's own choice.
+#define WALK_MIN_WAVES(KER, POT, HI) ((!(POT) && (KER) <= 1 && (HI) == 0) ? 7 : 1)
+
 // ORD3: p = 3, the force includes the quadrupole term (p = 2: monopole force);
 // HI = 4 or 5: the orders above (ORD3 set as well)
 template <int KER, int CRIT, bool POT, bool ORD3, int HI = 0>
-__global__ __launch_bounds__(256) void k_walk(const WalkArgs A)
+__global__ __launch_bounds__(256, WALK_MIN_WAVES(KER, POT, HI)) void k_walk(const WalkArgs A)
 {
     __shared__ WaveLds<POT> lds[4];
     const int lane = threadIdx.x & 63;
@@ -384,6 +455,7 @@ __global__ __launch_bounds__(256) void k_walk(const WalkArgs A)
     uint32_t w_pass = 0, w_pm = 0, w_pp = 0;           // 64-lane steps: visits, node pairs, particle pairs
     int max_sp = 0;                                    // deepest stack seen
     uint32_t w_entry = 0, w_leaf = 0, w_phase = 0;     // sibling sets, (leaf, target) items, pair phases
+    uint32_t g_use = 0, g_drop = 0;                    // (node, target) pairs decided for the whole group
 
     for (;;) {
     uint32_t it = 0;
@@ -404,10 +476,38 @@ __global__ __launch_bounds__(256) void k_walk(const WalkArgs A)
     }
     const int64_t i = i0 + lane;
     const bool act = (uint32_t)lane < gcount;
+    uint4 me = make_uint4(0u, 0u, 0u, 0u);
+    float arel = __builtin_huge_valf();
     if (act) {
-        const uint4 me = A.parts[i];
-        const float arel = CRIT == 1 ? A.alpha * A.aseed[i] : 0.f;
+        me = A.parts[i];
+        arel = CRIT == 1 ? A.alpha * A.aseed[i] : 0.f;
         W.tgt[lane] = make_uint4(me.x, me.y, me.z, __float_as_uint(arel));
+    }
+    {
+        // the group's bounding box as offsets from target 0 (every group has it) and its
+        // smallest alpha |a|, for the decisions taken once for the whole group
+        const uint32_t t0x = uni(me.x), t0y = uni(me.y), t0z = uni(me.z);
+        int32_t lo[3] = {act ? (int32_t)(me.x - t0x) : 0, act ? (int32_t)(me.y - t0y) : 0,
+                         act ? (int32_t)(me.z - t0z) : 0};
+        int32_t hi[3] = {lo[0], lo[1], lo[2]};
+        float am = arel;
+        for (int off = 32; off > 0; off >>= 1) {
+#pragma unroll
+            for (int a = 0; a < 3; a++) {
+                lo[a] = min(lo[a], __shfl_xor(lo[a], off));
+                hi[a] = max(hi[a], __shfl_xor(hi[a], off));
+            }
+            am = fminf(am, __shfl_xor(am, off));
+        }
+        const int32_t ext = max(max(max(-lo[0], hi[0]), max(-lo[1], hi[1])), max(-lo[2], hi[2]));
+        if (lane == 0) {
+#pragma unroll
+            for (int a = 0; a < 3; a++) {
+                W.gbox[a] = lo[a];
+                W.gbox[3 + a] = hi[a];
+            }
+            W.gamin = ext < (1 << 29) ? (CRIT == 1 ? am : 0.f) : -1.f;
+        }
     }
     W.acc[0][lane] = 0.0;
     W.acc[1][lane] = 0.0;
@@ -516,16 +616,19 @@ __global__ __launch_bounds__(256) void k_walk(const WalkArgs A)
         const uint32_t first = uni(e.x), c = uni(e.y);
         const uint64_t m = ((uint64_t)uni(e.w) << 32) | (uint64_t)uni(e.z);
         const uint32_t k = (uint32_t)__builtin_popcountll(m);
-        const uint32_t slots = c * k;
         // p / k for p < 576 as the float fma(p, 1/k, 1/2k), exact with the hardware reciprocal
         const float invk = rcp((float)k), hinvk = 0.5f * invk;
         if ((m >> lane) & 1ull) W.rmap[lanes_below(m)] = (uint8_t)lane;
-        uint32_t v_next = 0, v_numleaf = 0;   // lane j < c: child j
+        // lane j < c: child j, and its group decision (bits 0-1: 0 per target, 1 used by every
+        // target, 2 dropped by every target) with its index among the per-target children (bits 2-4)
+        uint32_t v_next = 0, v_numleaf = 0;  // lane j < c: child j (after the decisions below: the
+                                             // j-th of the children the targets decide one by one)
+        uint32_t v_dec = 0;                  // lane j < c: 1 every target uses child j, 2 every target drops it
         if ((uint32_t)lane < c) {
+            VisitRec r;
             const WNode nd = A.wn[first + lane];
             const int level = (int)(nd.meta & 0xffu);
             const float l = ldexpf(A.box, -level);
-            VisitRec r;
             r.cx = nd.cx;
             r.cy = nd.cy;
             r.cz = nd.cz;
@@ -535,20 +638,65 @@ __global__ __launch_bounds__(256) void k_walk(const WalkArgs A)
             r.gx = nd.gx;
             r.gy = nd.gy;
             r.gz = nd.gz;
-            r.lm1 = (A.exclusion && level > 0) ? (int32_t)((1u << (A.S - level)) - 1u) : -1;
+            r.lm1 = ((A.exclusion & 1) && level > 0) ? (int32_t)((1u << (A.S - level)) - 1u) : -1;
             r.hl = 0.5f * l;
-            r.nlm1 = -r.lm1;
+            r.node = first + lane;
             r.next = nd.next;
             r.numleaf = nd.num | ((nd.meta & WN_LEAF) ? NUM_LEAF : 0u);
-            W.rec[lane] = r;
             v_next = r.next;
             v_numleaf = r.numleaf;
+            W.rec[lane] = r;
+            const float gamin = W.gamin;
+            if (c * k >= WK_GROUP_MIN_SLOTS && !(A.exclusion & 2) && level > 0 && gamin >= 0.f)
+                v_dec = group_decision<KER, CRIT, ORD3, HI>(A, nd, r.crit, r.hl, r.lm1, W.tgt[0], W.gbox, gamin);
         }
+        // the children left to the targets get consecutive records, slots and child registers;
+        // the node indices of the children every target uses follow them (in the records' node field)
+        uint32_t cmix = c, uslots = 0;
+        const uint64_t decm = ballot(v_dec != 0);
+        if (decm) {
+            const bool pert = (uint32_t)lane < c && v_dec == 0, guse = v_dec == 1u;
+            const uint64_t mixm = ballot(pert), usem = ballot(guse);
+            cmix = (uint32_t)__builtin_popcountll(mixm);
+            uslots = (uint32_t)__builtin_popcountll(usem) * k;
+            g_drop += k * (uint32_t)__builtin_popcountll(ballot(v_dec == 2u));
+            if (A.counts && ((m >> lane) & 1ull)) n_pm += (uint32_t)__builtin_popcountll(usem);
+            wave_sync_lds();
+            const uint4 *src = reinterpret_cast<const uint4 *>(&W.rec[lane & 7]);
+            const uint4 r0 = src[0], r1 = src[1], r2 = src[2];
+            wave_sync_lds();
+            if (pert) {
+                uint4 *dst = reinterpret_cast<uint4 *>(&W.rec[lanes_below(mixm)]);
+                dst[0] = r0;
+                dst[1] = r1;
+                dst[2] = r2;
+            }
+            if (guse) W.rec[cmix + lanes_below(usem)].node = first + lane;
+            wave_sync_lds();
+            v_next = (uint32_t)lane < cmix ? W.rec[lane].next : 0u;
+            v_numleaf = (uint32_t)lane < cmix ? W.rec[lane].numleaf : 0u;
+        }
+        const uint32_t slots = cmix * k, ubase = (uslots + 63u) & ~63u;
         wave_sync_lds();
 
-        // ---- visit passes: 64 (child, target) slots at a time ----
-        for (uint32_t base = 0; base < slots; base += 64) {
+        // ---- children every target uses: their (node, target) pairs go straight into the node
+        // ring, 64 at a time; then visit passes, 64 (child, target) slots at a time ----
+        for (uint32_t base = 0; base < ubase + slots; base += 64) {
+          if (base < ubase) {
             const uint32_t p = base + lane;
+            if (p < uslots) {
+                const uint32_t u = (uint32_t)fmaf((float)p, invk, hinvk);
+                const uint32_t q = (pm_t + lane) & (WK_RING - 1);
+                W.pm_idx[q] = W.rec[cmix + u].node;
+                W.pm_tgt[q] = W.rmap[p - u * k];
+            }
+            const uint32_t nu = min(64u, uslots - base);
+            pm_t += nu;
+            u_pm += nu;
+            u_visit += nu;
+            g_use += nu;
+          } else {
+            const uint32_t p = base - ubase + lane;
             const bool valid = p < slots;
             uint32_t j = (uint32_t)fmaf((float)p, invk, hinvk);
             uint32_t rank = p - j * k;
@@ -566,28 +714,25 @@ __global__ __launch_bounds__(256) void k_walk(const WalkArgs A)
             bool ok = valid;
             if (KER == 1 || KER == 2) {
                 // nearest edge of the node's cube farther than r_cut: drop it
-                const float qx = fmaxf(fabsf((float)gx) * A.unit - R.hl, 0.f);
-                const float qy = fmaxf(fabsf((float)gy) * A.unit - R.hl, 0.f);
-                const float qz = fmaxf(fabsf((float)gz) * A.unit - R.hl, 0.f);
+                const float qx = fmaxf(fmaf(fabsf((float)gx), A.unit, -R.hl), 0.f);
+                const float qy = fmaxf(fmaf(fabsf((float)gy), A.unit, -R.hl), 0.f);
+                const float qz = fmaxf(fmaf(fabsf((float)gz), A.unit, -R.hl), 0.f);
                 ok = ok && (fmaf(qx, qx, fmaf(qy, qy, qz * qz)) <= A.rcut2);
             }
-            const bool inside = max(gx, max(gy, gz)) <= R.lm1 && min(gx, min(gy, gz)) >= R.nlm1;
+            const bool inside = max(gx, max(gy, gz)) <= R.lm1 && min(gx, min(gy, gz)) >= -R.lm1;
             const float rinv = rsq(r2);
             bool accept = !inside && r2 >= A.h2;
             if (CRIT == 0) {
                 accept = accept && (R.crit < A.theta2 * r2);
             } else {
-                // M (l/r)^p / r^2 < alpha |a|  <=>  M l^p < alpha |a| r^(p+2)
-                const float rp = HI == 5 ? r2 * r2 * r2 * r2 * rinv
-                                         : (HI == 4 ? r2 * r2 * r2 : (ORD3 ? r2 * r2 * r2 * rinv : r2 * r2));
-                accept = accept && (R.crit < __uint_as_float(T.w) * rp);
+                accept = accept && (R.crit < __uint_as_float(T.w) * crit_rpow<ORD3, HI>(r2, rinv));
             }
             const bool use = ok && accept;
             const bool open = ok && !accept;
             const uint64_t um = ballot(use);
             if (use) {
                 const uint32_t q = (pm_t + lanes_below(um)) & (WK_RING - 1);
-                W.pm_idx[q] = first + j;
+                W.pm_idx[q] = R.node;
                 W.pm_tgt[q] = (uint8_t)t;
             }
             // opened leaves become (leaf, target) items
@@ -611,6 +756,7 @@ __global__ __launch_bounds__(256) void k_walk(const WalkArgs A)
             u_pm += nu;
             u_visit += (uint32_t)__builtin_popcountll(ballot(ok));
             w_pass++;
+          }
             if (pm_t - pm_h >= 64) {
                 wave_sync_lds();
                 eval_p2m<KER, POT, ORD3, HI>(A, W, pm_h, 64u, lane);
@@ -626,7 +772,7 @@ __global__ __launch_bounds__(256) void k_walk(const WalkArgs A)
 
         // ---- opened internal children become entries; leaves only need counting ----
         const bool inm = (m >> lane) & 1ull;
-        for (uint32_t jj = 0; jj < c; jj++) {
+        for (uint32_t jj = 0; jj < cmix; jj++) {
             const uint32_t next = lane_val(v_next, jj), nl = lane_val(v_numleaf, jj);
             const bool leaf = (nl & NUM_LEAF) != 0;
             const uint32_t num = nl & ~NUM_LEAF;
@@ -701,6 +847,8 @@ __global__ __launch_bounds__(256) void k_walk(const WalkArgs A)
                 atomicAdd(&A.wstat[4], (unsigned long long)w_entry);
                 atomicAdd(&A.wstat[5], (unsigned long long)w_leaf);
                 atomicAdd(&A.wstat[6], (unsigned long long)w_phase);
+                atomicAdd(&A.wstat[7], (unsigned long long)g_use);  // slots 16, 17
+                atomicAdd(&A.wstat[8], (unsigned long long)g_drop);
             }
         }
     }
@@ -768,7 +916,7 @@ int g4_launch_walk(g4_ctx *ctx, g4_tree *t, const g4_walk_params *wp, int kernel
     A.n = t->n;
     A.group = wp->group_size > 0 && wp->group_size <= 64 ? wp->group_size : 64;
     A.S = t->S;
-    A.exclusion = wp->exclusion;
+    A.exclusion = wp->exclusion ? 1 : 0;
     A.order = wp->order;
     A.unit = (float)t->unit;
     A.box = (float)t->tp.box;
@@ -842,6 +990,10 @@ int g4_launch_walk(g4_ctx *ctx, g4_tree *t, const g4_walk_params *wp, int kernel
     A.spill_waves = t->walk_spill_waves;
     A.lds_stk = WK_LDS_STK;
     A.flags = &t->ctr->flags;
+    if (const char *env = getenv("G4_WALK_PER_TARGET")) {
+        // diagnostic: every (node, target) pair decided in the visit passes, none for the whole group
+        if (atoi(env) != 0) A.exclusion |= 2;
+    }
     if (const char *env = getenv("G4_WALK_LDS_STACK")) {
         // diagnostic: keep fewer entries in LDS so that the spill path runs
         const int v = atoi(env);

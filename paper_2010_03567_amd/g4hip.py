@@ -75,7 +75,8 @@ class g4_stats(C.Structure):
                 ("n_pp", C.c_uint64), ("n_pn", C.c_uint64), ("n_nn", C.c_uint64),
                 ("n_nodes", C.c_uint64), ("w_pop", C.c_uint64), ("w_p2m", C.c_uint64), ("w_p2p", C.c_uint64),
                 ("flags", C.c_uint32), ("max_stack", C.c_uint32),
-                ("w_entry", C.c_uint64), ("w_leaf", C.c_uint64), ("w_chunk", C.c_uint64)]
+                ("w_entry", C.c_uint64), ("w_leaf", C.c_uint64), ("w_chunk", C.c_uint64),
+                ("n_group_use", C.c_uint64), ("n_group_drop", C.c_uint64)]
 
     def as_dict(self):
         return {k: (float if k.startswith("t_") else int)(getattr(self, k)) for k, _ in self._fields_}

@@ -237,7 +237,7 @@ def test_walk_deep_stack_spills(g, ctx, monkeypatch):
     wp = g.walk_params(kernel=0, criterion=0, theta=0.05, eps0=PLUMMER_EPS)
     acc, pot, cnt = c.ot.walk(kernel=0, criterion=0, theta=0.05, eps0=PLUMMER_EPS, nthreads=16)
     results = []
-    for lds in ("32", "8"):
+    for lds in ("31", "8"):
         monkeypatch.setenv("G4_WALK_LDS_STACK", lds)
         out = g.g4_tree_force(ctx, c.tree, wp, want_pot=True, want_counts=True, want_stats=True)
         print("LDS stack", lds, "max stack", out["stats"]["max_stack"])
@@ -250,6 +250,41 @@ def test_walk_deep_stack_spills(g, ctx, monkeypatch):
         results.append((out["counts"].cpu().numpy(), a))
     # the spill changes where entries are kept, not the traversal: same decisions
     assert np.array_equal(results[0][0], results[1][0])
+
+
+@pytest.mark.parametrize("kind,criterion", [("box", 1), ("box", 0), ("plummer", 1), ("plummer", 0)])
+def test_group_decisions_change_no_decision(g, ctx, box_case, plummer_case, monkeypatch, kind, criterion):
+    """Siblings that every target of a group uses (or drops beyond r_cut) are
+    decided once for the group from its bounding box; the bounds reproduce the
+    per-target tests, so every particle keeps exactly its interaction counts
+    against a walk that decides every (node, target) pair in the visit passes
+    (diagnostic environment variable), and the forces differ only by the order
+    of the FP64 sums.  The group decisions must also take part."""
+    if kind == "box":
+        c, kw = box_case, dict(kernel=1, **sr_params(box_case.n))
+        crit = dict(theta=0.7) if criterion == 0 else dict(alpha=0.003)
+    else:
+        c, kw = plummer_case, dict(kernel=0, eps0=PLUMMER_EPS)
+        crit = dict(theta=0.5) if criterion == 0 else dict(alpha=0.002)
+    if criterion == 1:
+        geo = g.g4_tree_force(ctx, c.tree, g.walk_params(criterion=0, theta=0.7, **kw))
+        crit["a_seed"] = torch.sqrt(geo["ax"] ** 2 + geo["ay"] ** 2 + geo["az"] ** 2).float()
+    wp = g.walk_params(criterion=criterion, **crit, **kw)
+    outs = []
+    for per_target in ("0", "1"):
+        monkeypatch.setenv("G4_WALK_PER_TARGET", per_target)
+        outs.append(g.g4_tree_force(ctx, c.tree, wp, want_pot=True, want_counts=True, want_stats=True))
+    grp, ref = outs
+    print(kind, criterion, "pairs decided per group: used", grp["stats"]["n_group_use"], "dropped",
+          grp["stats"]["n_group_drop"], "of", grp["stats"]["n_visit"], "visits")
+    assert grp["stats"]["n_group_use"] > 0 and ref["stats"]["n_group_use"] == 0
+    assert ref["stats"]["n_group_drop"] == 0
+    assert torch.equal(grp["counts"], ref["counts"])
+    for k in ("n_p2p", "n_p2m", "n_visit"):
+        assert grp["stats"][k] == ref["stats"][k], k
+    a, b = stack3(grp), stack3(ref)
+    np.testing.assert_allclose(a, b, rtol=1e-9, atol=1e-12 * np.abs(b).max())
+    np.testing.assert_allclose(grp["pot"].cpu().numpy(), ref["pot"].cpu().numpy(), rtol=1e-9)
 
 
 def sr_params(n):
