@@ -201,7 +201,7 @@ typedef struct {
      * that reads them (any call with stats, every g4_fmm_force) and
      * g4_tree_info return G4_ENOMEM. */
     uint32_t flags;
-    uint32_t max_stack;  /* deepest traversal stack of the walk (entries; the first 31 are kept in LDS) */
+    uint32_t max_stack;  /* deepest traversal stack of the walk (entries; the first 30 are kept in LDS) */
     /* walk bookkeeping: sibling sets popped, (opened leaf, target) items,
      * particle-pair phases of the lane queue */
     uint64_t w_entry, w_leaf, w_chunk;

@@ -13,7 +13,7 @@
 // device spill area per wavefront (room for the whole stack, so any LDS share
 // is safe), and the wavefront cap of the persistent walk grid.
 #define G4_WALK_STACK (1 + 7 * (G4_MAXLEV - 1) + 8)
-#define G4_WALK_LDS_STACK 31
+#define G4_WALK_LDS_STACK 30
 #define G4_WALK_SPILL G4_WALK_STACK
 #define G4_WALK_MAX_WAVES 8192
 

@@ -263,8 +263,8 @@ struct __attribute__((aligned(16))) VisitRec {
 };
 static_assert(sizeof(VisitRec) == 48, "VisitRec is 48 bytes");
 
-// One wavefront's LDS: 5836 bytes without the potential (7 wavefronts per
-// SIMD fit in the 160 KiB of a CU), 6348 with it.
+// One wavefront's LDS: 5848 bytes without the potential (7 wavefronts per
+// SIMD fit in the 160 KiB of a CU), 6360 with it.
 #define FLAG_OPEN 1
 #define FLAG_USE 2
 template <bool POT>
@@ -279,6 +279,7 @@ struct __attribute__((aligned(16))) WaveLds {
     VisitRec rec[8];               // children of the current entry
     uint8_t flag[8][64];           // flag[j][t]: FLAG_OPEN / FLAG_USE of child j for target t (t in the mask)
     uint8_t rmap[64];              // rank within the entry mask -> lane
+    uint8_t anyopen[8];            // anyopen[j]: some target opened child j, an internal node
     int32_t gbox[6];               // the group's bounding box: lower x y z, upper x y z (offsets from target 0)
     float gamin;                   // its smallest alpha |a| (relative criterion); negative: no group decisions
     uint4 stk[WK_LDS_STK];         // (first node, count, mask lo, mask hi), top of the stack
@@ -677,6 +678,7 @@ __global__ __launch_bounds__(256, WALK_MIN_WAVES(KER, POT, HI)) void k_walk(cons
             v_numleaf = (uint32_t)lane < cmix ? W.rec[lane].numleaf : 0u;
         }
         const uint32_t slots = cmix * k, ubase = (uslots + 63u) & ~63u;
+        if (lane == 0) *reinterpret_cast<uint2 *>(W.anyopen) = make_uint2(0u, 0u);
         wave_sync_lds();
 
         // ---- children every target uses: their (node, target) pairs go straight into the node
@@ -751,6 +753,7 @@ __global__ __launch_bounds__(256, WALK_MIN_WAVES(KER, POT, HI)) void k_walk(cons
             }
             // every (child, target) pair of the entry has exactly one slot: no clearing needed
             if (valid) W.flag[j][t] = (uint8_t)(use ? FLAG_USE : (open ? FLAG_OPEN : 0));
+            if (open && !(R.numleaf & NUM_LEAF)) W.anyopen[j] = 1;
             const uint32_t nu = (uint32_t)__builtin_popcountll(um);
             pm_t += nu;
             u_pm += nu;
@@ -770,21 +773,25 @@ __global__ __launch_bounds__(256, WALK_MIN_WAVES(KER, POT, HI)) void k_walk(cons
         }
         wave_sync_lds();
 
-        // ---- opened internal children become entries; leaves only need counting ----
+        // ---- interaction counts per target (only if asked for) ----
         const bool inm = (m >> lane) & 1ull;
-        for (uint32_t jj = 0; jj < cmix; jj++) {
-            const uint32_t next = lane_val(v_next, jj), nl = lane_val(v_numleaf, jj);
-            const bool leaf = (nl & NUM_LEAF) != 0;
-            const uint32_t num = nl & ~NUM_LEAF;
-            if (leaf && !A.counts) continue;
-            const uint32_t f = W.flag[jj][lane];
-            if (A.counts) {
+        if (A.counts) {
+            for (uint32_t jj = 0; jj < cmix; jj++) {
+                const uint32_t next = lane_val(v_next, jj), nl = lane_val(v_numleaf, jj);
+                const uint32_t num = nl & ~NUM_LEAF;
+                const uint32_t f = W.flag[jj][lane];
                 n_pm += (inm && f == FLAG_USE) ? 1u : 0u;
-                if (leaf && inm && f == FLAG_OPEN) n_pp += num - ((uint32_t)(i - next) < num ? 1u : 0u);
+                if ((nl & NUM_LEAF) && inm && f == FLAG_OPEN) n_pp += num - ((uint32_t)(i - next) < num ? 1u : 0u);
             }
-            if (leaf) continue;
-            const uint64_t om = ballot(f == FLAG_OPEN) & m;
-            if (!om) continue;
+        }
+        // ---- opened internal children become entries ----
+        const uint2 ao = *reinterpret_cast<const uint2 *>(W.anyopen);
+        uint64_t anyb = ((uint64_t)uni(ao.y) << 32) | (uint64_t)uni(ao.x);
+        while (anyb) {
+            const uint32_t jj = (uint32_t)__builtin_ctzll(anyb) >> 3;
+            anyb &= ~(0xffull << (8 * jj));
+            const uint32_t next = lane_val(v_next, jj), num = lane_val(v_numleaf, jj) & ~NUM_LEAF;
+            const uint64_t om = ballot(W.flag[jj][lane] == FLAG_OPEN) & m;
             if (sp < WK_STK) {
                 const uint4 ne = make_uint4(next, num, (uint32_t)om, (uint32_t)(om >> 32));
                 if (lane == 0) {

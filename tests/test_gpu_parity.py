@@ -237,7 +237,7 @@ def test_walk_deep_stack_spills(g, ctx, monkeypatch):
     wp = g.walk_params(kernel=0, criterion=0, theta=0.05, eps0=PLUMMER_EPS)
     acc, pot, cnt = c.ot.walk(kernel=0, criterion=0, theta=0.05, eps0=PLUMMER_EPS, nthreads=16)
     results = []
-    for lds in ("31", "8"):
+    for lds in ("30", "8"):
         monkeypatch.setenv("G4_WALK_LDS_STACK", lds)
         out = g.g4_tree_force(ctx, c.tree, wp, want_pot=True, want_counts=True, want_stats=True)
         print("LDS stack", lds, "max stack", out["stats"]["max_stack"])
