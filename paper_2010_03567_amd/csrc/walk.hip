@@ -256,7 +256,7 @@ struct __attribute__((aligned(16))) VisitRec {
     float crit;         // relative: M l^p; geometric: l^2; +inf at level 0 (the root is never used)
     uint32_t gx, gy, gz;
     int32_t lm1;        // exclusion: cube half-size on the grid minus 1 (-1: no exclusion zone)
-    float hl;           // half side (physical)
+    float hl;           // half side (physical); negative: every target is within r_cut of the cube (no test)
     uint32_t node;      // node index
     uint32_t next;      // first child, or first particle of a leaf
     uint32_t numleaf;   // number of children or particles, NUM_LEAF for a leaf
@@ -318,7 +318,8 @@ __device__ __forceinline__ float crit_rpow(float r2, float rinv)
 
 // The decisions of a visit taken once for every target of the group: 1 if
 // every target uses the node, 2 if every target drops it (beyond r_cut), 0 if
-// the targets must decide one by one.  b0, b1: the group's bounding box on the
+// the targets must decide one by one, 4 if they must but none of them can find
+// the node's cube beyond r_cut (the kernels with a cut-off).  b0, b1: the group's bounding box on the
 // grid as offsets from target 0 (t0); amin: the group's smallest alpha |a|.
 // Each bound evaluates the per-target expression of the visit pass with the
 // box's least (or most) favourable offsets in place of the target's; rounding
@@ -358,9 +359,10 @@ __device__ __forceinline__ uint32_t group_decision(const WalkArgs &A, const WNod
         if (sn > A.rcut2) return 2u;
         if (!(sf <= A.rcut2)) return 0u;
     }
-    if (!outside || !(r2 >= A.h2)) return 0u;
-    if (CRIT == 0) return crit < A.theta2 * r2 ? 1u : 0u;
-    return crit < (amin * crit_rpow<ORD3, HI>(r2, rsq(r2))) * 0.99999f ? 1u : 0u;
+    const uint32_t within = (KER == 1 || KER == 2) ? 4u : 0u;  // no target can drop the node
+    if (!outside || !(r2 >= A.h2)) return within;
+    if (CRIT == 0) return crit < A.theta2 * r2 ? 1u : within;
+    return crit < (amin * crit_rpow<ORD3, HI>(r2, rsq(r2))) * 0.99999f ? 1u : within;
 }
 
 // 64 particle-node interactions from the node ring, one per lane (lanes >= n idle).
@@ -648,8 +650,14 @@ __global__ __launch_bounds__(256, WALK_MIN_WAVES(KER, POT, HI)) void k_walk(cons
             v_numleaf = r.numleaf;
             W.rec[lane] = r;
             const float gamin = W.gamin;
-            if (c * k >= WK_GROUP_MIN_SLOTS && !(A.exclusion & 2) && level > 0 && gamin >= 0.f)
+            if (c * k >= WK_GROUP_MIN_SLOTS && !(A.exclusion & 2) && level > 0 && gamin >= 0.f) {
                 v_dec = group_decision<KER, CRIT, ORD3, HI>(A, nd, r.crit, r.hl, r.lm1, W.tgt[0], W.gbox, gamin);
+                if (v_dec == 4u) {
+                    // left to the targets, none of which can see the cube beyond r_cut
+                    W.rec[lane].hl = -r.hl;
+                    v_dec = 0;
+                }
+            }
         }
         // the children left to the targets get consecutive records, slots and child registers;
         // the node indices of the children every target uses follow them (in the records' node field)
@@ -714,7 +722,7 @@ __global__ __launch_bounds__(256, WALK_MIN_WAVES(KER, POT, HI)) void k_walk(cons
             // exclusion zone; the nearest-edge distance is max(|d| unit - l/2, 0) per axis
             const int32_t gx = (int32_t)(R.gx - T.x), gy = (int32_t)(R.gy - T.y), gz = (int32_t)(R.gz - T.z);
             bool ok = valid;
-            if (KER == 1 || KER == 2) {
+            if ((KER == 1 || KER == 2) && R.hl >= 0.f) {
                 // nearest edge of the node's cube farther than r_cut: drop it
                 const float qx = fmaxf(fmaf(fabsf((float)gx), A.unit, -R.hl), 0.f);
                 const float qy = fmaxf(fmaf(fabsf((float)gy), A.unit, -R.hl), 0.f);
