@@ -85,6 +85,9 @@ def parse():
                     help="curve order of the particles: Morton or Peano-Hilbert (same nodes)")
     ap.add_argument("--sr-table", type=int, default=0,
                     help="intervals of the short-range factor table of the walks (0: erfc/exp per interaction)")
+    ap.add_argument("--profile-fmm", type=int, default=0, metavar="LEAF",
+                    help="only run `steps` calls of the FMM (atomic-sum mode) on the clustered 128^3 box (seed 3) at "
+                         "this leaf size, for counter runs of its kernels")
     ap.add_argument("--profile-walk", choices=("plain", "learned"), default=None,
                     help="only time `steps` steps of this variant at --alpha on the headline box (no reference "
                          "sums, no calibration), for counter runs of the walk")
@@ -354,6 +357,9 @@ def main():
         torch.cuda.synchronize()
         del src, dst
 
+    if args.profile_fmm:
+        print(json.dumps(profile_fmm(g, ctx, args.profile_fmm, args.steps, args.warmup)))
+        return
     head = TreePMCase(g, ctx, args, args.n, args.seed, args.weights)
     if args.profile_walk:
         if args.alpha <= 0:
@@ -659,6 +665,38 @@ def bench_ewald(args, g, ctx, flops):
             "errors_vs_ewald_direct": err, "error_sample": len(tg),
             "fmm": {"workload": "periodic FMM + Ewald, same box, p=3, theta 0.5, leaf 32, atomic-sum mode",
                     "ms_per_step": fmm_ms, "forces_per_s": n / (fmm_ms * 1e-3), "errors_vs_ewald_direct": ferr}}
+
+
+def profile_fmm(g, ctx, leaf, steps, warmup):
+    """FMM calls alone (tree built once) on the clustered 128^3 box of the FMM
+    line, for kernel traces and counters; HIP-event time per call."""
+    import torch
+    import workloads
+    n = SMALL_N
+    r_s, eps0 = treepm_scales(n)
+    ps = workloads.clustered_box(n, seed=3)
+    pos = torch.from_numpy(ps.pos).to(ctx.device)
+    mass = torch.from_numpy(ps.mass.astype(np.float32)).to(ctx.device)
+    tp = g.tree_params(True, 1.0, leaf_max=leaf)
+    x, y, z = g.g4_quantize(ctx, pos, tp)
+    t = g.g4_build_tree(ctx, g.particles(x, y, z, mass), tp)
+    g.g4_compute_multipoles(ctx, t, 3)
+    fp = g.fmm_params(kernel=1, theta=0.5, r_s=r_s, r_cut=4.5 * r_s, eps0=eps0)
+    st = {"factor": 1.0, "fws": None}
+    evs = []
+    for k in range(warmup + steps):
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+        ev[0].record()
+        o = g.g4_fmm_force(ctx, t, fp, list_factor=st["factor"], ws=st["fws"], want_stats=(k == 0))
+        ev[1].record()
+        st["factor"], st["fws"] = o["list_factor"], o["ws"]
+        if k == 0:
+            s0 = o["stats"]
+        if k >= warmup:
+            evs.append(ev)
+    torch.cuda.synchronize()
+    return {"profile_fmm": leaf, "n": n, "steps": steps, "fmm_ms": float(np.mean([e[0].elapsed_time(e[1]) for e in evs])),
+            "per_particle": {"pp": s0["n_pp"] / n, "pn": s0["n_pn"] / n, "nn": s0["n_nn"] / n}}
 
 
 def bench_fmm(args, g, ctx, flops):
