@@ -72,6 +72,33 @@ struct FmmArgs {
 };
 
 // ---------------------------------------------------------------- geometry
+// |d| of an int32 nearest-image offset given as u32 (2^31 for the most negative one)
+__device__ __forceinline__ uint32_t fm_uabs(uint32_t u) { return (int32_t)u < 0 ? 0u - u : u; }
+
+// Separation of two cubes (or of a point and a cube) on the integer grid: centre offsets
+// (b - a, nearest image) against hs, the sum of the half sides.  g2: the squared distance
+// between the nearest faces (physical, only axes with a gap count); returns whether the
+// cubes touch or overlap (|d| <= hs on every axis).  Offsets are at most 2^31 and hs fits
+// 32 bits below the root level, so the test runs in 32-bit integers (a larger hs only
+// arises for two root cubes, which always touch).
+__device__ __forceinline__ bool fm_cube_gap(uint32_t ax, uint32_t ay, uint32_t az, uint32_t bx, uint32_t by,
+                                            uint32_t bz, uint64_t hs64, float unit, float &g2)
+{
+    const uint32_t hs = hs64 > 0xffffffffull ? 0xffffffffu : (uint32_t)hs64;
+    const uint32_t d[3] = {fm_uabs(bx - ax), fm_uabs(by - ay), fm_uabs(bz - az)};
+    bool touching = true;
+    g2 = 0.f;
+#pragma unroll
+    for (int k = 0; k < 3; k++) {
+        if (d[k] > hs) {
+            const float gf = (float)(d[k] - hs) * unit;
+            g2 += gf * gf;
+            touching = false;
+        }
+    }
+    return touching;
+}
+
 struct Ent {
     uint32_t gx, gy, gz;     // integer centre (position for a particle)
     uint32_t cx, cy, cz;     // integer centre of mass
@@ -188,22 +215,9 @@ __device__ Act classify(const FmmArgs &A, uint32_t ea, uint32_t eb)
         X.n_part = 2;
         return X;
     }
-    const int64_t dc[3] = {(int32_t)(b.gx - a.gx), (int32_t)(b.gy - a.gy), (int32_t)(b.gz - a.gz)};
-    const int64_t hs = (int64_t)(a.half + b.half);
-    if (A.kernel == 1) {
-        float g2 = 0.f;
-        for (int k = 0; k < 3; k++) {
-            const int64_t gap = (dc[k] < 0 ? -dc[k] : dc[k]) - hs;
-            if (gap > 0) {
-                const float gf = (float)gap * A.unit;
-                g2 += gf * gf;
-            }
-        }
-        if (g2 > A.rcut2) return X;  // nearest sides beyond r_cut: dropped
-    }
-    bool touching = true;
-    for (int k = 0; k < 3; k++)
-        if ((dc[k] < 0 ? -dc[k] : dc[k]) > hs) touching = false;
+    float g2;
+    const bool touching = fm_cube_gap(a.gx, a.gy, a.gz, b.gx, b.gy, b.gz, a.half + b.half, A.unit, g2);
+    if (A.kernel == 1 && g2 > A.rcut2) return X;  // nearest sides beyond r_cut: dropped
     const float rx = (float)(int32_t)(b.cx - a.cx) * A.unit, ry = (float)(int32_t)(b.cy - a.cy) * A.unit,
                 rz = (float)(int32_t)(b.cz - a.cz) * A.unit;
     const float r2 = rx * rx + ry * ry + rz * rz;
@@ -870,22 +884,10 @@ __device__ __forceinline__ int fm_classify(const FastArgs &A, const WNode &a, co
                                            uint32_t ib, float r[3], float &r2)
 {
     const int la = (int)(a.meta & 0xffu), lb = (int)(b.meta & 0xffu);
-    const int64_t dc[3] = {(int32_t)(b.gx - a.gx), (int32_t)(b.gy - a.gy), (int32_t)(b.gz - a.gz)};
-    const int64_t hs = (int64_t)((1ull << (A.S - la - 1)) + (1ull << (A.S - lb - 1)));
-    if (A.kernel == 1) {
-        float g2 = 0.f;
-        for (int k = 0; k < 3; k++) {
-            const int64_t gap = (dc[k] < 0 ? -dc[k] : dc[k]) - hs;
-            if (gap > 0) {
-                const float gf = (float)gap * A.unit;
-                g2 += gf * gf;
-            }
-        }
-        if (g2 > A.rcut2) return 0;
-    }
-    bool touching = true;
-    for (int k = 0; k < 3; k++)
-        if ((dc[k] < 0 ? -dc[k] : dc[k]) > hs) touching = false;
+    float g2;
+    const bool touching = fm_cube_gap(a.gx, a.gy, a.gz, b.gx, b.gy, b.gz,
+                                      (1ull << (A.S - la - 1)) + (1ull << (A.S - lb - 1)), A.unit, g2);
+    if (A.kernel == 1 && g2 > A.rcut2) return 0;
     r[0] = (float)(int32_t)(b.cx - a.cx) * A.unit;
     r[1] = (float)(int32_t)(b.cy - a.cy) * A.unit;
     r[2] = (float)(int32_t)(b.cz - a.cz) * A.unit;
@@ -1513,23 +1515,9 @@ __global__ __launch_bounds__(256) void k_fast_ln(FastArgs A, uint32_t npairs)
         const bool mine = live && ((gm >> gl) & 1u);
         const int lev = (int)(w.meta & 0xffu);
         // particle (l = 0) against the node: the rules of fm_classify
-        const int64_t dc[3] = {(int32_t)(w.gx - me.x), (int32_t)(w.gy - me.y), (int32_t)(w.gz - me.z)};
-        const int64_t hs = (int64_t)(1ull << (A.S - lev - 1));
-        bool drop = false;
-        if (A.kernel == 1) {
-            float g2 = 0.f;
-            for (int q = 0; q < 3; q++) {
-                const int64_t gap = (dc[q] < 0 ? -dc[q] : dc[q]) - hs;
-                if (gap > 0) {
-                    const float gf = (float)gap * A.unit;
-                    g2 += gf * gf;
-                }
-            }
-            drop = g2 > A.rcut2;
-        }
-        bool touching = true;
-        for (int q = 0; q < 3; q++)
-            if ((dc[q] < 0 ? -dc[q] : dc[q]) > hs) touching = false;
+        float g2;
+        const bool touching = fm_cube_gap(me.x, me.y, me.z, w.gx, w.gy, w.gz, 1ull << (A.S - lev - 1), A.unit, g2);
+        const bool drop = A.kernel == 1 && g2 > A.rcut2;
         const float r[3] = {(float)(int32_t)(w.cx - me.x) * A.unit, (float)(int32_t)(w.cy - me.y) * A.unit,
                             (float)(int32_t)(w.cz - me.z) * A.unit};
         const float r2 = r[0] * r[0] + r[1] * r[1] + r[2] * r[2];
