@@ -1835,10 +1835,13 @@ static int fmm_seed_minima(g4_ctx *ctx, g4_tree *t, const g4_fmm_params *fp, flo
 }
 
 template <int KER, bool POT>
+// up to 4096 blocks of 4 wavefronts: the pairs of a leaf or of a leaf-node pair vary widely in cost,
+// and with more, smaller static shares the last wavefronts finish sooner (measured against 1024,
+// 2048 and 8192)
 static void launch_fast_particles(const FastArgs &A, uint32_t nnodes, uint32_t nln, hipStream_t s)
 {
-    k_fast_pp<KER, POT><<<(unsigned)std::min<uint64_t>(2048, ((uint64_t)nnodes + 3) / 4), 256, 0, s>>>(A, nnodes);
-    if (nln) k_fast_ln<KER, POT><<<(unsigned)std::min<uint64_t>(2048, ((uint64_t)nln + 3) / 4), 256, 0, s>>>(A, nln);
+    k_fast_pp<KER, POT><<<(unsigned)std::min<uint64_t>(4096, ((uint64_t)nnodes + 3) / 4), 256, 0, s>>>(A, nnodes);
+    if (nln) k_fast_ln<KER, POT><<<(unsigned)std::min<uint64_t>(4096, ((uint64_t)nln + 3) / 4), 256, 0, s>>>(A, nln);
 }
 
 static int fmm_fast(g4_ctx *ctx, g4_tree *t, const g4_fmm_params *fp, double factor, void *ws, size_t ws_bytes,
