@@ -107,11 +107,17 @@ def traffic_file(n):
 
 
 def walk_source_sha():
+    """Hash of the walk's sources with comments and blank lines removed (so that
+    a comment edit does not orphan the committed counter summary)."""
     import hashlib
+    import re
     h = hashlib.sha256()
     for f in WALK_SOURCES:
-        with open(os.path.join(ROOT, "paper_2010_03567_amd", "csrc", f), "rb") as fh:
-            h.update(fh.read())
+        with open(os.path.join(ROOT, "paper_2010_03567_amd", "csrc", f)) as fh:
+            src = fh.read()
+        src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+        src = re.sub(r"//[^\n]*", "", src)
+        h.update("\n".join(line.rstrip() for line in src.splitlines() if line.strip()).encode())
     return h.hexdigest()
 
 

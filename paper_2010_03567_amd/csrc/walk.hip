@@ -319,8 +319,9 @@ __device__ __forceinline__ float crit_rpow(float r2, float rinv)
 // The decisions of a visit taken once for every target of the group: 1 if
 // every target uses the node, 2 if every target drops it (beyond r_cut), 0 if
 // the targets must decide one by one, 4 if they must but none of them can find
-// the node's cube beyond r_cut (the kernels with a cut-off).  b0, b1: the group's bounding box on the
-// grid as offsets from target 0 (t0); amin: the group's smallest alpha |a|.
+// the node's cube beyond r_cut (the kernels with a cut-off).  box: the group's
+// bounding box on the grid as offsets from target 0 (t0), lower corner in
+// box[0..2], upper in box[3..5]; amin: the group's smallest alpha |a|.
 // Each bound evaluates the per-target expression of the visit pass with the
 // box's least (or most) favourable offsets in place of the target's; rounding
 // is monotonic in every operation there, so a bound that passes implies the
@@ -622,8 +623,6 @@ __global__ __launch_bounds__(256, WALK_MIN_WAVES(KER, POT, HI)) void k_walk(cons
         // p / k for p < 576 as the float fma(p, 1/k, 1/2k), exact with the hardware reciprocal
         const float invk = rcp((float)k), hinvk = 0.5f * invk;
         if ((m >> lane) & 1ull) W.rmap[lanes_below(m)] = (uint8_t)lane;
-        // lane j < c: child j, and its group decision (bits 0-1: 0 per target, 1 used by every
-        // target, 2 dropped by every target) with its index among the per-target children (bits 2-4)
         uint32_t v_next = 0, v_numleaf = 0;  // lane j < c: child j (after the decisions below: the
                                              // j-th of the children the targets decide one by one)
         uint32_t v_dec = 0;                  // lane j < c: 1 every target uses child j, 2 every target drops it
