@@ -494,7 +494,8 @@ __global__ __launch_bounds__(256, WALK_MIN_WAVES(KER, POT, HI)) void k_walk(cons
         int32_t lo[3] = {act ? (int32_t)(me.x - t0x) : 0, act ? (int32_t)(me.y - t0y) : 0,
                          act ? (int32_t)(me.z - t0z) : 0};
         int32_t hi[3] = {lo[0], lo[1], lo[2]};
-        float am = arel;
+        // a seed that is not a non-negative number (NaN) would make the bound unsafe: no group decisions
+        float am = arel >= 0.f ? arel : -1.f;
         for (int off = 32; off > 0; off >>= 1) {
 #pragma unroll
             for (int a = 0; a < 3; a++) {
@@ -510,7 +511,7 @@ __global__ __launch_bounds__(256, WALK_MIN_WAVES(KER, POT, HI)) void k_walk(cons
                 W.gbox[a] = lo[a];
                 W.gbox[3 + a] = hi[a];
             }
-            W.gamin = ext < (1 << 29) ? (CRIT == 1 ? am : 0.f) : -1.f;
+            W.gamin = ext < (1 << 29) && am >= 0.f ? (CRIT == 1 ? am : 0.f) : -1.f;
         }
     }
     W.acc[0][lane] = 0.0;
