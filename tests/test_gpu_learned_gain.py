@@ -1,9 +1,9 @@
 """What the trained network gains over the method without it: on a clustered
 128^3 box drawn with a seed held out of training (2001; the network was
 trained on seeds 1001-1020), the learned seed (features + MLP) and the plain
-seed (geometric pre-walk) each run the relative walk at the largest alpha of
-the sqrt(2) grid whose 99th-percentile force error against FP64 direct
-summation is <= 1e-3; the learned step must be faster, and the ratio is
+seed (geometric pre-walk) each run the relative walk at the largest alpha
+whose 99th-percentile force error against FP64 direct summation is <= 1e-3
+(a sqrt(2) grid refined by bisection); the learned step must be faster, and the ratio is
 printed.  The step and the calibration are bench.py's own."""
 import types
 
