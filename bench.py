@@ -6,7 +6,7 @@ the relative criterion): the clustered periodic box of 256^3 = 16 777 216
 equal-mass particles drawn with the held-out evaluation seed 2001 (60 % of the
 mass in 2000 Hernquist haloes, 40 % uniform), TreePM split r_s = 1.25 L/256
 scaled to the mean spacing (mesh 512^3 at 256^3), softening L/(40 * 256), leaf
-size 24, p = 3, wavefront groups of 64.
+size 32 (the fastest of 16-40 at this size), p = 3, wavefront groups of 64.
 
 A step is one pass of the whole path: integer mapping -> Morton keys + radix
 sort -> octree -> multipoles -> |a| seed -> relative TreePM short-range walk ->
@@ -81,7 +81,7 @@ def parse():
     ap.add_argument("--no-orders", action="store_true", help="skip the expansion-order (p = 3, 4, 5) comparison")
     ap.add_argument("--err-sample", type=int, default=10000)
     ap.add_argument("--group", type=int, default=64)
-    ap.add_argument("--leaf", type=int, default=24, help="leaf size B of the tree")
+    ap.add_argument("--leaf", type=int, default=32, help="leaf size B of the tree")
     ap.add_argument("--copy-calibration-mb", type=int, default=0,
                     help="also run a plain device copy of this size (HBM counter calibration)")
     ap.add_argument("--keys", choices=("morton", "ph"), default="morton",

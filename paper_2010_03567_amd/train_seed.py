@@ -6,9 +6,14 @@ seed) and keeps log10 |a| of every particle as the target, plus the raw leaf
 features.  The network is then trained full-batch, one snapshot per Adam step,
 with the library's own gradient and Adam kernels (BF16 weights, FP32 master
 copy).  The result is saved as an .npz (bf16 bits, feature standardisation,
-seed shift, metadata).
+seed shift, metadata).  With --tau the loss is the pinball loss at that
+quantile of log10 |a|: a seed below |a| makes the criterion open more nodes
+(more interactions, smaller error), one above it fewer (larger error), so a
+quantile below the median moves the errors to the cheap side.  The committed
+networks (tau 0.2, leaf 32) were made with
 
-    python -m paper_2010_03567_amd.train_seed --n 2097152 --leaf 8 --out paper_2010_03567_amd/weights/seed_mlp_2097152.npz
+    python -m paper_2010_03567_amd.train_seed --n 16777216 --leaf 32 --steps 1500 --tau 0.2 --out paper_2010_03567_amd/weights/seed_mlp_16777216_leaf32.npz
+    python -m paper_2010_03567_amd.train_seed --n 2097152 --leaf 32 --steps 1500 --tau 0.2 --out paper_2010_03567_amd/weights/seed_mlp_2097152_leaf32.npz
 """
 from __future__ import annotations
 

@@ -18,11 +18,11 @@ def test_learned_seed_beats_prewalk_at_equal_p99():
         pytest.skip("no GPU")
     import bench
     import paper_2010_03567_amd.g4hip as g
-    args = types.SimpleNamespace(rcut=7.0, leaf=24, group=64, keys="morton", sr_table=0, no_learned=False,
+    args = types.SimpleNamespace(rcut=7.0, leaf=32, group=64, keys="morton", sr_table=0, no_learned=False,
                                  err_sample=10000)
     ctx = g.Context()
     case = bench.TreePMCase(g, ctx, args, 128 ** 3, 2001)
-    assert case.learned is not None, "no trained weights for 128^3, leaf 24"
+    assert case.learned is not None, "no trained weights for 128^3, leaf 32"
     res = {v: case.variant(v, steps=5, warmup=2) for v in ("plain", "learned")}
     for v, r in res.items():
         assert "ms_per_step" in r, (v, r)
