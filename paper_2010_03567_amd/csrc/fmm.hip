@@ -1410,16 +1410,26 @@ __device__ __forceinline__ void fm_deposit(const FastArgs &A, uint32_t j, float 
     if (POT) atomicAdd(a + 3, (double)fp);
 }
 
-// sum of v over each aligned 16-lane group (a DPP row), in the group's first lane; the
-// other lanes end with partial sums.  Four row shifts with the adds, no LDS traffic; every
-// lane of the wavefront must be active.
-__device__ __forceinline__ float fm_gsum0(float v)
+// sums of the 20 values over each aligned 16-lane group (a DPP row), in the group's first
+// lane; the other lanes end with partial sums.  Row shifts with the adds, no LDS traffic;
+// every lane of the wavefront must be active.  `span` (wavefront-uniform: 4, 8 or 16) bounds
+// the lanes of every group that may hold nonzero values: the shifts that would only add
+// zeros are skipped, which leaves every sum bitwise unchanged.
+__device__ __forceinline__ void fm_gsum20(float v[20], uint32_t span)
 {
-    v += __uint_as_float(fm_from_next<1>(__float_as_uint(v)));
-    v += __uint_as_float(fm_from_next<2>(__float_as_uint(v)));
-    v += __uint_as_float(fm_from_next<4>(__float_as_uint(v)));
-    v += __uint_as_float(fm_from_next<8>(__float_as_uint(v)));
-    return v;
+#pragma unroll
+    for (int q = 0; q < 20; q++) {
+        v[q] += __uint_as_float(fm_from_next<1>(__float_as_uint(v[q])));
+        v[q] += __uint_as_float(fm_from_next<2>(__float_as_uint(v[q])));
+    }
+    if (span > 4) {
+#pragma unroll
+        for (int q = 0; q < 20; q++) v[q] += __uint_as_float(fm_from_next<4>(__float_as_uint(v[q])));
+    }
+    if (span > 8) {
+#pragma unroll
+        for (int q = 0; q < 20; q++) v[q] += __uint_as_float(fm_from_next<8>(__float_as_uint(v[q])));
+    }
 }
 // this lane's group's 16 bits of a wavefront mask
 __device__ __forceinline__ uint32_t fm_gbits(uint64_t m, uint32_t g) { return (uint32_t)(m >> (16 * g)) & 0xffffu; }
@@ -1563,8 +1573,9 @@ __global__ __launch_bounds__(256) void k_fast_ln(FastArgs A, uint32_t npairs)
                 }
                 n_pn++;
             }
-#pragma unroll
-            for (int q = 0; q < 20; q++) pf[q] = fm_gsum0(pf[q]);  // read by lane 0 of the group
+            // only the lanes in im hold nonzero values: within each group, lanes 0-3, 0-7 or all 16
+            const uint32_t span = (im & 0xff00ff00ff00ff00ull) ? 16u : (im & 0xfff0fff0fff0fff0ull) ? 8u : 4u;
+            fm_gsum20(pf, span);  // read by lane 0 of the group
             const bool gi = fm_gbits(im, g) != 0;
             if (gi && gl == 0) {
 #pragma unroll
