@@ -23,7 +23,8 @@ percentile (10^4 random targets, FP64 direct summation on the device) meets the
 bound: the first of a descending sqrt(2) grid that meets it, then three
 bisections in log alpha towards the grid value above it.  `value` is the faster variant that meets it.
 
-Extra keys: the same comparison on the 128^3 box (seed 2), the as-stated
+Extra keys: the same comparison on two more held-out boxes of the headline
+size (seeds 2002 and 2003) and on the 128^3 box (seed 2), the as-stated
 R_cut = 4.5 r_s, alpha = 0.005 line, the total TreePM force (that walk plus
 the long-range PM force on the 256^3 mesh), the FMM at p = 3, theta = 0.5, the
 batched forest of 64 boxes, and the FP64 oracle on the host cores.  Prints one
@@ -70,6 +71,8 @@ def parse():
     ap.add_argument("--no-as-stated", action="store_true")
     ap.add_argument("--no-small", action="store_true", help="skip the 128^3 comparison")
     ap.add_argument("--no-learned", action="store_true")
+    ap.add_argument("--eval-seeds", type=str, default="2002,2003",
+                    help="further held-out seeds of the headline box for the same comparison ('' to skip)")
     ap.add_argument("--weights", type=str, default="", help="learned-seed weights (.npz); default by particle count")
     ap.add_argument("--no-fmm", action="store_true")
     ap.add_argument("--fmm-leaf", type=int, default=32,
@@ -440,6 +443,8 @@ def main():
     cpu_input = (head.ps, head.r_s, head.r_cut, head.eps0, chosen["alpha"])
     head.free()
     del head
+    if args.eval_seeds:
+        result["held_out_seeds"] = held_out_seeds(args, g, ctx)
     if not args.no_small and args.n != SMALL_N:
         small = TreePMCase(g, ctx, args, SMALL_N, SMALL_SEED)
         sc = small.compare(max(5, args.steps), 2, args.alpha)
@@ -472,6 +477,32 @@ def main():
     if not args.no_cpu_baseline:
         result["cpu_baseline"] = cpu_baseline(*cpu_input, args)
     print(json.dumps(result), flush=True)
+
+
+def held_out_seeds(args, g, ctx):
+    """The headline comparison (each variant at its own calibrated alpha) on
+    further boxes of the same size drawn with other held-out seeds: the
+    network, the loss and the leaf size were chosen on the headline box."""
+    out = {}
+    for seed in (int(x) for x in args.eval_seeds.split(",")):
+        case = TreePMCase(g, ctx, args, args.n, seed, args.weights)
+        c = case.compare(5, 2, args.alpha)
+        case.free()
+        del case
+        row = {}
+        for k in ("plain", "learned"):
+            v = c.get(k, {})
+            if "ms_per_step" in v:
+                row[k] = {"alpha": v["alpha"], "ms_per_step": v["ms_per_step"], "errors_vs_direct": v["errors_vs_direct"],
+                          "per_particle": v["per_particle"], "seed_ms": v["phases"]["seed_ms"],
+                          "walk_ms": v["phases"]["walk_ms"]}
+            elif v:
+                row[k] = {"error": v.get("error")}
+        for k in ("speedup_learned_vs_plain", "learned_ceiling_speedup"):
+            if k in c:
+                row[k] = c[k]
+        out[str(seed)] = row
+    return out
 
 
 def bench_orders(args, case):
