@@ -42,26 +42,39 @@ __device__ __forceinline__ float soft_pot(float u, float hinv)
 }
 
 // Long-range pair factors for x = alpha r, needed only inside the softening edge:
-//   lrf(x) = (erf x - 2x e^{-x^2}/sqrt(pi)) / x^3,   erfx(x) = erf(x)/x.
+//   lrf(x) = (erf x - 2x e^{-x^2}/sqrt(pi)) / x^3,   erfx(x) = erf(x)/x,
+// by their Taylor series below x = 0.5 and in closed form above.  Inside the softening
+// length x is usually far below 0.5 (h alpha << 1), so the closed form sits behind a branch
+// on the wavefront's vote and is skipped when no active lane needs it.
 __device__ __forceinline__ float lr_force_x3(float x)
 {
-    if (x < 0.5f) {
-        float x2 = x * x;
-        float s = 1.0f / 3 + x2 * (-1.0f / 5 + x2 * (1.0f / 14 + x2 * (-1.0f / 54 + x2 * (1.0f / 264 - x2 * (1.0f / 1560)))));
-        return 4.0f * INV_SQRTPI * s;
+    const float x2 = x * x;
+    float v = 4.0f * INV_SQRTPI *
+              (1.0f / 3 + x2 * (-1.0f / 5 + x2 * (1.0f / 14 + x2 * (-1.0f / 54 + x2 * (1.0f / 264 - x2 * (1.0f / 1560))))));
+    if (__builtin_amdgcn_ballot_w64(x >= 0.5f)) {
+        // an empty statement that the compiler must assume changes y: it keeps the closed form
+        // inside the branch instead of evaluating it for every lane beside the series
+        float y = x;
+        asm volatile("" : "+v"(y));
+        if (y >= 0.5f) {
+            const float ex = expneg(y * y);
+            const float erfv = 1.0f - erfc_hastings(y, ex);
+            v = (erfv - 2.0f * INV_SQRTPI * y * ex) * rcp(y * y * y);
+        }
     }
-    float ex = expneg(x * x);
-    float erfv = 1.0f - erfc_hastings(x, ex);
-    return (erfv - 2.0f * INV_SQRTPI * x * ex) * rcp(x * x * x);
+    return v;
 }
 __device__ __forceinline__ float erf_over_x(float x)
 {
-    if (x < 0.5f) {
-        float x2 = x * x;
-        float s = 1.0f + x2 * (-1.0f / 3 + x2 * (1.0f / 10 + x2 * (-1.0f / 42 + x2 * (1.0f / 216 - x2 * (1.0f / 1320)))));
-        return 2.0f * INV_SQRTPI * s;
+    const float x2 = x * x;
+    float v = 2.0f * INV_SQRTPI *
+              (1.0f + x2 * (-1.0f / 3 + x2 * (1.0f / 10 + x2 * (-1.0f / 42 + x2 * (1.0f / 216 - x2 * (1.0f / 1320))))));
+    if (__builtin_amdgcn_ballot_w64(x >= 0.5f)) {
+        float y = x;
+        asm volatile("" : "+v"(y));  // as in lr_force_x3
+        if (y >= 0.5f) v = (1.0f - erfc_hastings(y, expneg(y * y))) * rcp(y);
     }
-    return (1.0f - erfc_hastings(x, expneg(x * x))) * rcp(x);
+    return v;
 }
 
 // Pair interaction (softened, optionally short-range): returns the force
@@ -82,7 +95,10 @@ __device__ __forceinline__ void pair_kernel(float r2, float asplit, float h2, fl
         K = (ec + 2.0f * INV_SQRTPI * x * ex) * rinv * rinv2;
         if (POT) W = ec * rinv;
     }
-    if (r2 < h2) {
+    // the softened branch for r < h; a pair at zero separation (a particle with itself) adds no
+    // force whatever K is, so without the potential it takes the plain branch (rinv = 0, K = 0)
+    // and does not pull the whole wavefront into the softened one
+    if (r2 < h2 && (POT || r2 > 0.f)) {
         float r = r2 * rinv;
         float u = r * hinv;
         K = soft_force(u, hinv);
@@ -127,7 +143,7 @@ __device__ __forceinline__ void pair_kernel_tab(float r2, const float4 *__restri
     sr_locate(r, tscale, n, k, u);
     K = sr_eval(tab[n + k], u) * rinv * rinv2;
     if (POT) W = sr_eval(tab[k], u) * rinv;
-    if (r2 < h2) {
+    if (r2 < h2 && (POT || r2 > 0.f)) {  // as in pair_kernel
         float uh = r * hinv;
         K = soft_force(uh, hinv);
         if (POT) W = soft_pot(uh, hinv);
