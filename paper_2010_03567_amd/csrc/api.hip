@@ -398,14 +398,15 @@ static int tree_force_impl(g4_ctx *ctx, g4_tree *tree, const g4_walk_params *wp,
         } else {
             // geometric pre-walk (first-force footnote of eq. eqnrelcriterion): |a| estimate
             // written into the tree's sorted seed buffer; its forces are scratch and go to ax..az
-            st = g4_launch_walk(ctx, tree, wp, kernel, 0, ax, ay, az, nullptr, nullptr, nullptr, tree->aseed, 3);
+            st = g4_launch_walk(ctx, tree, wp, kernel, 0, ax, ay, az, nullptr, nullptr, nullptr, tree->aseed, 3,
+                                stats != nullptr);
         }
         if (st) return st;
         if (seeded && (st = g4_phase_end(ctx, tree, 2))) return st;
     }
     if ((st = g4_phase_begin(ctx, tree, 3))) return st;
     st = g4_launch_walk(ctx, tree, wp, kernel, wp->criterion, ax, ay, az, pot, counts, a_out,
-                        wp->criterion == 0 ? tree->aseed : nullptr, 0);
+                        wp->criterion == 0 ? tree->aseed : nullptr, 0, stats != nullptr);
     if (st) return st;
     if ((st = g4_phase_end(ctx, tree, 3))) return st;
     if (wp->criterion == 0) tree->seed_valid = 1;

@@ -17,7 +17,7 @@ int g4_launch_build_forest(g4_ctx *ctx, g4_tree *t, const g4_particles *p, const
                            uint32_t *bkey1);
 int g4_launch_walk(g4_ctx *ctx, g4_tree *t, const g4_walk_params *wp, int kernel, int criterion,
                    double *ax, double *ay, double *az, double *pot, uint32_t *counts, float *aout_caller,
-                   float *aout_sorted, int stat_slot);
+                   float *aout_sorted, int stat_slot, bool count);
 int g4_launch_export(g4_ctx *ctx, const g4_tree *t, int32_t *level, uint32_t *cell, int64_t *count,
                      int64_t *first, int32_t *leaf, double *mass, double *com, double *q2, double *q3);
 int g4_launch_direct(g4_ctx *ctx, const g4_particles *p, const g4_tree_params *tp, const g4_walk_params *wp,

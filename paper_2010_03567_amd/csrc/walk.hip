@@ -588,7 +588,13 @@ __global__ __launch_bounds__(256, WALK_MIN_WAVES(KER, POT, HI)) void k_walk(cons
                     q_y = T.y;
                     q_z = T.z;
                     q_self = (uint32_t)i0 + q_t;  // sorted index of the target itself
-                    t_pp += q_rem - ((q_self - q_src) < q_rem ? 1u : 0u);
+                    if (A.stat) {
+                        // the pair count only when it is read; the empty statement keeps the
+                        // count behind the branch instead of a select after it
+                        uint32_t nq = q_rem;
+                        asm volatile("" : "+v"(nq));
+                        t_pp += nq - ((q_self - q_src) < nq ? 1u : 0u);
+                    }
                 }
                 lt_h += min((uint32_t)__builtin_popcountll(idle), avail);
             }
@@ -920,7 +926,7 @@ __global__ void k_srtab(float4 *__restrict__ tab, int n)
 
 int g4_launch_walk(g4_ctx *ctx, g4_tree *t, const g4_walk_params *wp, int kernel, int criterion, double *ax,
                    double *ay, double *az, double *pot, uint32_t *counts, float *aout_caller, float *aout_sorted,
-                   int stat_slot)
+                   int stat_slot, bool count)
 {
     WalkArgs A;
     A.parts = t->parts;
@@ -967,7 +973,9 @@ int g4_launch_walk(g4_ctx *ctx, g4_tree *t, const g4_walk_params *wp, int kernel
     A.counts = counts;
     A.aout_caller = aout_caller;
     A.aout_sorted = aout_sorted;
-    A.stat = t->ctr->stat + stat_slot;
+    // interaction and pass counters only when the caller reads them: the kernel then skips
+    // the per-lane counting as well
+    A.stat = count ? t->ctr->stat + stat_slot : nullptr;
     if (t->nbox > 1 && t->items_group != A.group) {
         // work items of a forest: every box cut into groups; largest boxes first so the
         // persistent wavefronts finish together (longest-processing-time order)
@@ -1015,7 +1023,7 @@ int g4_launch_walk(g4_ctx *ctx, g4_tree *t, const g4_walk_params *wp, int kernel
         if (v >= 1 && v <= WK_LDS_STK) A.lds_stk = v;
     }
     if (int st = g4_launch_zero(ctx, A.item_ctr, sizeof(uint32_t))) return st;
-    A.wstat = stat_slot == 0 ? t->ctr->stat + 9 : nullptr;
+    A.wstat = count && stat_slot == 0 ? t->ctr->stat + 9 : nullptr;
     hipStream_t s = ctx->stream;
     const bool P = pot != nullptr;
     if (kernel == 0) {
