@@ -293,9 +293,10 @@ int g4_tree_free(g4_ctx *ctx, g4_tree *tree);
 /* One-sided tree walk (kernel per params).  ax, ay, az: device, n float64,
  * caller order.  pot: device n float64 or NULL.  counts: device n x 2 uint32
  * (particle-particle, particle-node per particle) or NULL.  a_out: device n
- * float32 |a| (caller order) or NULL.  stats: host or NULL (synchronises).
- * A geometric call (criterion 0) also keeps |a| inside the tree for a later
- * relative call with seed_from_tree = 1. */
+ * float32 |a| (caller order) or NULL.  stats: host or NULL (synchronises);
+ * the walk counts interactions and passes only when it is given, so a call
+ * without it runs slightly less work.  A geometric call (criterion 0) also
+ * keeps |a| inside the tree for a later relative call with seed_from_tree = 1. */
 int g4_tree_force(g4_ctx *ctx, g4_tree *tree, const g4_walk_params *wp, double *ax, double *ay, double *az,
                   double *pot, uint32_t *counts, float *a_out, g4_stats *stats);
 
