@@ -287,6 +287,26 @@ def test_group_decisions_change_no_decision(g, ctx, box_case, plummer_case, monk
     np.testing.assert_allclose(grp["pot"].cpu().numpy(), ref["pot"].cpu().numpy(), rtol=1e-9)
 
 
+@pytest.mark.parametrize("criterion", [0, 1])
+def test_walk_without_stats_takes_the_same_decisions(g, ctx, box_case, criterion):
+    """A call without g4_stats skips the interaction counting inside the walk;
+    its per-particle counts and forces equal those of a call with stats, whose
+    counters sum the per-particle counts."""
+    c, kw = box_case, dict(kernel=1, **sr_params(box_case.n))
+    crit = dict(theta=0.7)
+    if criterion == 1:
+        geo = g.g4_tree_force(ctx, c.tree, g.walk_params(criterion=0, theta=0.7, **kw))
+        crit = dict(alpha=0.003, a_seed=torch.sqrt(geo["ax"] ** 2 + geo["ay"] ** 2 + geo["az"] ** 2).float())
+    wp = g.walk_params(criterion=criterion, **crit, **kw)
+    on = g.g4_tree_force(ctx, c.tree, wp, want_counts=True, want_stats=True)
+    off = g.g4_tree_force(ctx, c.tree, wp, want_counts=True)
+    assert torch.equal(on["counts"], off["counts"])
+    cnt = on["counts"].cpu().numpy().astype(np.int64)
+    assert on["stats"]["n_p2p"] == int(cnt[:, 0].sum()) and on["stats"]["n_p2m"] == int(cnt[:, 1].sum())
+    a, b = stack3(off), stack3(on)
+    np.testing.assert_allclose(a, b, rtol=1e-12, atol=1e-15 * np.abs(b).max())
+
+
 def sr_params(n):
     """Config-2 TreePM parameters scaled to n particles in a unit box (same
     r_s and softening relative to the mean spacing)."""
